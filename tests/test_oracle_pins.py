@@ -1,0 +1,455 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Every oracle function is checked here against something other than itself:
+hand-computed worked examples (tests/golden), pure-Python brute force on tiny
+inputs, exact rational arithmetic, closed forms of the estimator, statistical
+properties of the estimator over Haar-random rotations, and the reduction of
+the whole search to exact kNN.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+# ---------------------------------------------------------------- fixtures
+
+def _load(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["worked_d4_identity.json", "worked_d4_hadamard.json"])
+def test_worked_example(golden_dir, name):
+    """Sec. 2.2.1-2.2.2 worked by hand (see the fixture's note)."""
+    g = _load(golden_dir, name)
+    D, bq = g["D"], g["bq"]
+    P = np.array(g["P"], np.float64)
+    c = np.array(g["c"], np.float32)[None, :]
+    x = np.array(g["x"], np.float32)[None, :]
+    q = np.array(g["q"], np.float32)
+    codes, n_x, alpha = O.encode(x, c, np.array([0]), P)
+    assert codes.tolist() == [g["code_bytes"]]
+    assert n_x[0] == pytest.approx(g["n_x"], rel=1e-7)
+    assert alpha[0] == pytest.approx(g["alpha"], rel=1e-7)
+    r = O.rotate(q, P) - O.rotate(c[0], P)
+    qu, vl, delta, squ = O.quantize(r, bq)
+    assert qu.tolist() == g["qu"]
+    assert vl == pytest.approx(g["v_l"], abs=1e-15)
+    assert delta == pytest.approx(g["delta"], rel=1e-15)
+    assert squ == g["sum_qu"]
+    E, ip, pop = O.est_terms(codes, qu, vl, delta, D)
+    assert ip.tolist() == [g["ip"]] and pop.tolist() == [g["pop"]]
+    assert E[0] == pytest.approx(g["E"], rel=1e-14)
+    assert float(r @ r) == pytest.approx(g["rnorm2"], rel=1e-15)
+    est = O.estimate(float(r @ r), E, n_x, alpha, D)
+    # factors are stored as FP32, so d_hat^2 carries their rounding
+    assert est[0] == pytest.approx(g["d_hat2"], rel=1e-6)
+    s = O.s_hat_unquantized(P, codes, (q - c[0]) / np.linalg.norm(q - c[0]), alpha, D)
+    qn = float(np.linalg.norm(q.astype(np.float64) - c[0]))
+    est_unq = qn ** 2 + float(n_x[0]) ** 2 - 2 * qn * float(n_x[0]) * s[0]
+    assert est_unq == pytest.approx(g["d_hat2_unquantized"], rel=1e-6)
+    assert float(np.sum((q.astype(np.float64) - x[0]) ** 2)) == g["d2_exact"]
+
+
+# ---------------------------------------------------------------- IVF build
+
+def test_assign_is_bruteforce_argmin_with_ties():
+    """Sec. 2.1.2: each vector goes to its nearest centroid; ties -> lowest id."""
+    rng = np.random.default_rng(1)
+    X = rng.integers(-3, 4, size=(60, 3)).astype(np.float32)
+    C = rng.integers(-3, 4, size=(9, 3)).astype(np.float32)
+    C[5] = C[2]                          # an exact duplicate centroid: ties
+    a, dmin = O.assign(X, C)
+    for i in range(len(X)):
+        best, bj = None, None
+        for j in range(len(C)):
+            d = sum((float(X[i, t]) - float(C[j, t])) ** 2 for t in range(3))
+            if best is None or d < best:
+                best, bj = d, j
+        assert a[i] == bj and dmin[i] == best
+    assert not np.any(a == 5)
+
+
+def test_kmeanspp_picks_training_points_and_spreads():
+    rng = np.random.default_rng(2)
+    A = rng.normal(0, 1e-3, size=(20, 4))
+    B = rng.normal(0, 1e-3, size=(20, 4)) + 1e6
+    T = np.concatenate([A, B])
+    for s in range(20):
+        C = O.kmeanspp_init(T, 2, np.random.default_rng(s))
+        for c in C:
+            assert np.any(np.all(T == c, axis=1))
+        # D^2 sampling must take the second centre from the far cluster
+        assert (C[0, 0] > 1e5) != (C[1, 0] > 1e5)
+
+
+def test_kmeans_objective_monotone_and_means():
+    """Lloyd iterations never increase the objective; the result's centroids are
+    the means of their assigned points (a fixed point)."""
+    rng = np.random.default_rng(3)
+    centres = rng.normal(0, 1, size=(8, 6))
+    X = (centres[rng.integers(0, 8, 800)] + 0.3 * rng.normal(size=(800, 6))).astype(np.float32)
+    trace = []
+    C = O.kmeans(X, 8, np.random.default_rng(0), iters=50, restarts=2, trace=trace)
+    for run in trace:
+        assert all(b <= a * (1 + 1e-12) for a, b in zip(run, run[1:]))
+    a, _ = O.assign(X, C)
+    for j in range(8):
+        m = a == j
+        assert m.any()
+        np.testing.assert_allclose(C[j], X[m].astype(np.float64).mean(axis=0), atol=1e-9)
+
+
+def test_kmeans_recovers_separated_mixture():
+    """Textbook special case: well-separated components are found exactly."""
+    rng = np.random.default_rng(4)
+    centres = np.eye(5) * 100.0
+    lab = rng.integers(0, 5, 500)
+    X = (centres[lab] + 0.01 * rng.normal(size=(500, 5))).astype(np.float32)
+    C = O.kmeans(X, 5, np.random.default_rng(1), iters=25, restarts=3)
+    d = O.sqdist(C, centres)
+    assert np.all(np.min(d, axis=1) < 0.01)
+    assert len(set(np.argmin(d, axis=1))) == 5
+
+
+def test_kmeans_empty_cluster_reseed():
+    """An empty cluster is moved onto the point farthest from its centroid."""
+    T = np.array([[0.0], [1.0], [10.0]])
+    C0 = np.array([[0.5], [100.0]])
+    a, dmin = O.assign(T, C0)
+    assert (a == 1).sum() == 0
+    C1 = O.lloyd_update(T, a, C0, dmin)
+    assert C1[1, 0] == 10.0
+    assert C1[0, 0] == pytest.approx(11.0 / 3.0)
+
+
+@pytest.mark.parametrize("d", [8, 16, 96, 128])
+def test_rotation_is_orthogonal(d):
+    """Sec. 2.2.1: P is orthogonal, so it preserves norms (used in Sec. 3.2.2)."""
+    P = O.random_orthogonal(d, np.random.default_rng(d))
+    assert np.max(np.abs(P.T @ P - np.eye(d))) <= 1e-12
+    P32 = P.astype(np.float32).astype(np.float64)
+    assert np.max(np.abs(P32.T @ P32 - np.eye(d))) <= 1e-6
+    q = np.random.default_rng(5).normal(size=(50, d))
+    nq = np.linalg.norm(q, axis=1)
+    assert np.all(np.abs(np.linalg.norm(O.rotate(q, P32), axis=1) - nq) <= 1e-6 * nq)
+
+
+def test_rotation_is_haar():
+    """Haar-random columns are uniform on the sphere: E[P_ij^2] = 1/D, and the
+    determinant takes both signs."""
+    d = 8
+    sq, dets = [], []
+    for s in range(800):
+        P = O.random_orthogonal(d, np.random.default_rng(1000 + s))
+        sq.append(P[0, 0] ** 2)
+        dets.append(np.sign(np.linalg.det(P)))
+    m = np.mean(sq)
+    se = np.std(sq) / math.sqrt(len(sq))
+    assert abs(m - 1.0 / d) < 4 * se
+    assert 0.4 < np.mean(np.array(dets) > 0) < 0.6
+
+
+# ---------------------------------------------------------------- encoding
+
+def test_pack_bits_lsb_first():
+    bits = np.zeros((1, 12), np.uint8)
+    bits[0, [0, 3, 8, 11]] = 1
+    assert O.pack_bits(bits).tolist() == [[0b00001001, 0b00001001]]
+    np.testing.assert_array_equal(O.unpack_bits(O.pack_bits(bits), 12), bits)
+
+
+@pytest.mark.parametrize("d", [16, 96, 128, 960])
+def test_alpha_identity_and_range(d):
+    """Eq. rabitq-alpha: <P b / sqrt(D), u_x> equals ||P^T u_x||_1 / sqrt(D),
+    and alpha lies in [1/sqrt(D), 1]; for Gaussian residuals its mean is near
+    sqrt(2/pi)."""
+    rng = np.random.default_rng(d)
+    P = O.random_orthogonal(d, rng) if d <= 128 else np.linalg.qr(rng.normal(size=(d, d)))[0]
+    X = rng.normal(size=(400, d)).astype(np.float32)
+    C = np.zeros((1, d), np.float32)
+    codes, n_x, alpha = O.encode(X, C, np.zeros(400, np.int64), P)
+    b = 2.0 * O.unpack_bits(codes, d).astype(np.float64) - 1.0
+    u = X.astype(np.float64) / np.linalg.norm(X.astype(np.float64), axis=1, keepdims=True)
+    lhs = np.einsum("ij,ij->i", (P @ b.T).T / math.sqrt(d), u)
+    np.testing.assert_allclose(lhs, alpha.astype(np.float64), rtol=1e-6)
+    assert np.all(alpha >= 1 / math.sqrt(d) - 1e-7) and np.all(alpha <= 1 + 1e-7)
+    assert abs(alpha.mean() - math.sqrt(2 / math.pi)) < 0.03
+    np.testing.assert_allclose(n_x, np.linalg.norm(X.astype(np.float64), axis=1), rtol=1e-7)
+
+
+def test_encode_degenerate_zero_residual():
+    """n_x = 0 (a vector equal to its centroid): alpha = 1, all-ones code."""
+    d = 16
+    P = O.random_orthogonal(d, np.random.default_rng(0))
+    X = np.ones((2, d), np.float32)
+    X[1, 0] = 2.0
+    codes, n_x, alpha = O.encode(X, np.ones((1, d), np.float32), np.zeros(2, np.int64), P)
+    assert n_x[0] == 0.0 and alpha[0] == 1.0
+    assert codes[0].tolist() == [255, 255]
+    assert n_x[1] == 1.0
+
+
+def test_encode_sign_matches_rotation_bruteforce():
+    """Codes are the signs of P^T (x - c), written out as plain loops."""
+    d = 12
+    rng = np.random.default_rng(7)
+    P = O.random_orthogonal(d, rng)
+    X = rng.normal(size=(5, d)).astype(np.float32)
+    C = rng.normal(size=(2, d)).astype(np.float32)
+    a = np.array([0, 1, 1, 0, 1])
+    codes, _, _ = O.encode(X, C, a, P)
+    for i in range(5):
+        z = [sum(P[t, j] * (float(X[i, t]) - float(C[a[i], t])) for t in range(d)) for j in range(d)]
+        byte = [0] * 2
+        for j in range(d):
+            if z[j] >= 0:
+                byte[j >> 3] |= 1 << (j & 7)
+        assert codes[i].tolist() == byte
+
+
+# ---------------------------------------------------------------- query side
+
+def test_quantize_bounds_and_degenerate():
+    rng = np.random.default_rng(8)
+    for bq in (1, 2, 4, 8):
+        top = (1 << bq) - 1
+        r = rng.normal(size=128)
+        qu, vl, delta, squ = O.quantize(r, bq)
+        assert qu.min() == 0 and qu.max() == top
+        assert vl == r.min() and delta == pytest.approx((r.max() - r.min()) / top)
+        assert np.all(np.abs(r - (vl + delta * qu)) <= delta / 2 * (1 + 1e-12))
+        assert squ == qu.sum()
+    qu, vl, delta, squ = O.quantize(np.full(16, 3.5), 4)
+    assert delta == 0.0 and vl == 3.5 and squ == 0 and not qu.any()
+
+
+def test_quantize_round_half_up_bruteforce():
+    """Rounding is floor(y + 1/2), checked against exact rationals."""
+    r = np.array([0.0, 1.0, 2.0, 3.0, 0.5, 1.5, 2.5, 0.25], np.float64)
+    qu, vl, delta, _ = O.quantize(r, 2)          # Delta = 1
+    exp = [math.floor(Fraction(v) + Fraction(1, 2)) for v in r]
+    assert qu.tolist() == exp
+
+
+def test_integer_ip_two_routes_and_bruteforce():
+    """Sec. 2.2.2: the bitwise (bit-plane popcount) route and a dense product of
+    small integers give the same integer inner products, equal to a pure-Python
+    double loop."""
+    rng = np.random.default_rng(9)
+    for d in (8, 13, 96, 128, 960):
+        bits = rng.integers(0, 2, size=(40, d)).astype(np.uint8)
+        codes = O.pack_bits(bits)
+        for bq in (1, 4, 8):
+            qu = rng.integers(0, 1 << bq, size=d)
+            a = O.ip_dense(codes, qu, d)
+            b = O.ip_bitplanes(codes, qu, d, bq)
+            np.testing.assert_array_equal(a, b)
+            if d <= 13:
+                for i in range(40):
+                    assert a[i] == sum(int(bits[i, t]) * int(qu[t]) for t in range(d))
+
+
+def test_E_identity_exact_rationals():
+    """E = sum_d b_d (v_l + Delta qu_d) = 2 Delta ip + 2 v_l pop - Delta sum(qu) - D v_l,
+    in exact rational arithmetic; the oracle's FP64 E agrees to rounding."""
+    rng = np.random.default_rng(10)
+    d, bq = 24, 4
+    for _ in range(20):
+        bits = rng.integers(0, 2, size=(1, d)).astype(np.uint8)
+        codes = O.pack_bits(bits)
+        r = rng.normal(size=d)
+        qu, vl, delta, squ = O.quantize(r, bq)
+        Fv, Fd = Fraction(vl), Fraction(delta)
+        lhs = sum((2 * int(bits[0, t]) - 1) * (Fv + Fd * int(qu[t])) for t in range(d))
+        ip = sum(int(bits[0, t]) * int(qu[t]) for t in range(d))
+        pop = int(bits.sum())
+        rhs = 2 * Fd * ip + 2 * Fv * pop - Fd * squ - d * Fv
+        assert lhs == rhs
+        E, ip_o, pop_o = O.est_terms(codes, qu, vl, delta, d)
+        assert ip_o[0] == ip and pop_o[0] == pop
+        assert abs(E[0] - float(lhs)) <= 1e-12 * (abs(vl) * d + delta * 15 * d)
+
+
+def test_quantisation_error_bound():
+    """|E - sum_d b_d r_d| <= D Delta / 2 (each dimension is off by <= Delta/2)."""
+    rng = np.random.default_rng(11)
+    d = 128
+    bits = rng.integers(0, 2, size=(200, d)).astype(np.uint8)
+    codes = O.pack_bits(bits)
+    b = 2.0 * bits - 1.0
+    for _ in range(10):
+        r = rng.normal(size=d) * rng.uniform(0.1, 10)
+        qu, vl, delta, _ = O.quantize(r, 4)
+        E, _, _ = O.est_terms(codes, qu, vl, delta, d)
+        assert np.all(np.abs(E - b @ r) <= d * delta / 2 * (1 + 1e-12))
+
+
+def test_estimator_exact_on_ray():
+    """Closed form of Eqs. rabitq-ip-estimator / approx-dist: if q lies on the
+    ray c + t (x - c), then P^T u_q = sign(t) P^T u_x, so <b, z_q> =
+    sign(t) ||z_x||_1 and s_hat = sign(t) exactly: d_hat^2 equals the exact
+    d^2 = (||q-c|| - sign(t) ||x-c||)^2. With q = x, d_hat^2 = 0."""
+    d = 64
+    rng = np.random.default_rng(12)
+    P = O.random_orthogonal(d, rng)
+    c = rng.normal(size=(1, d)).astype(np.float32)
+    x = rng.normal(size=(1, d)).astype(np.float32)
+    codes, n_x, alpha = O.encode(x, c, np.array([0]), P)
+    for t in (-2.0, -0.5, 0.3, 1.0, 3.0):
+        q = c[0].astype(np.float64) + t * (x[0].astype(np.float64) - c[0])
+        qn = np.linalg.norm(q - c[0])
+        s = O.s_hat_unquantized(P, codes, (q - c[0]) / qn, alpha.astype(np.float64), d)
+        # alpha is stored in FP32, so s_hat is sign(t) to FP32 precision
+        assert s[0] == pytest.approx(math.copysign(1.0, t), rel=1e-6)
+        exact = float(np.sum((q - x[0].astype(np.float64)) ** 2))
+        est = qn ** 2 + float(n_x[0]) ** 2 - 2 * qn * float(n_x[0]) * s[0]
+        assert est == pytest.approx(exact, rel=1e-5, abs=1e-5 * (qn ** 2 + float(n_x[0]) ** 2))
+        # and through the quantised pipeline with many bits the error is tiny
+        r = O.rotate(q, P) - O.rotate(c[0].astype(np.float64), P)
+        qu, vl, delta, _ = O.quantize(r, 20)
+        E, _, _ = O.est_terms(codes, qu, vl, delta, d)
+        est_q = O.estimate(float(r @ r), E, n_x, alpha, d)[0]
+        assert est_q == pytest.approx(exact, abs=1e-4 * (qn ** 2 + float(n_x[0]) ** 2))
+
+
+def _pair_with_cos(d, cos, rng):
+    u = rng.normal(size=d)
+    u /= np.linalg.norm(u)
+    w = rng.normal(size=d)
+    w -= (w @ u) * u
+    w /= np.linalg.norm(w)
+    return u, cos * u + math.sqrt(1 - cos * cos) * w
+
+
+def test_estimator_unbiased_and_sqrt_d_error():
+    """RaBitQ's guarantees (cited in Sec. 2.2): over Haar-random P the
+    estimator s_hat of <u_x, u_q> is unbiased, and its error shrinks as
+    O(1/sqrt(D)): std(s_hat - s) sqrt(D) is flat across D."""
+    rng = np.random.default_rng(13)
+    scaled = []
+    trials = 700
+    for d in (32, 64, 128):
+        ux, uq = _pair_with_cos(d, 0.6, rng)
+        errs = []
+        for t in range(trials):
+            P = O.random_orthogonal(d, rng)
+            codes, _, alpha = O.encode(ux[None, :].astype(np.float32), np.zeros((1, d), np.float32),
+                                       np.array([0]), P)
+            z = ux @ P
+            alpha64 = np.sum(np.abs(z)) / (math.sqrt(d) * np.linalg.norm(z))
+            s = O.s_hat_unquantized(P, codes, uq, np.array([alpha64]), d)[0]
+            errs.append(s - float(ux @ uq))
+        errs = np.array(errs)
+        se = errs.std() / math.sqrt(trials)
+        assert abs(errs.mean()) <= 3.5 * se, (d, errs.mean(), se)
+        scaled.append(errs.std() * math.sqrt(d))
+    assert max(scaled) / min(scaled) < 1.15 ** 2, scaled
+
+
+# ---------------------------------------------------------------- selection
+
+def test_probe_bruteforce_with_ties():
+    rng = np.random.default_rng(14)
+    C = rng.integers(-2, 3, size=(30, 3)).astype(np.float32)
+    for _ in range(10):
+        q = rng.integers(-2, 3, size=3).astype(np.float32)
+        ids, dist = O.probe(q, C, 7)
+        full = sorted(((sum((float(q[t]) - float(C[j, t])) ** 2 for t in range(3)), j)
+                       for j in range(30)))
+        assert ids.tolist() == [j for _, j in full[:7]]
+        assert dist.tolist() == [v for v, _ in full[:7]]
+
+
+def test_topk_lex_and_padding():
+    rng = np.random.default_rng(15)
+    v = rng.integers(0, 5, size=50).astype(np.float64)
+    ids = rng.permutation(50)
+    tv, ti = O.topk_lex(v, ids, 12)
+    ref = sorted(zip(v.tolist(), ids.tolist()))[:12]
+    assert list(zip(tv.tolist(), ti.tolist())) == ref
+    tv, ti = O.topk_lex(v[:3], ids[:3], 5)
+    assert ti[3:].tolist() == [-1, -1] and np.all(np.isinf(tv[3:]))
+
+
+def test_bruteforce_knn_loops():
+    rng = np.random.default_rng(16)
+    X = rng.integers(0, 4, size=(40, 3)).astype(np.float32)
+    Q = rng.integers(0, 4, size=(5, 3)).astype(np.float32)
+    ids, d = O.brute_force_knn(X, Q, 6, chunk=7)
+    for qi in range(5):
+        full = sorted((sum((float(Q[qi, t]) - float(X[i, t])) ** 2 for t in range(3)), i)
+                      for i in range(40))[:6]
+        assert ids[qi].tolist() == [i for _, i in full]
+        assert d[qi].tolist() == [v for v, _ in full]
+
+
+def test_rerank_bruteforce():
+    rng = np.random.default_rng(17)
+    X = rng.normal(size=(30, 5)).astype(np.float32)
+    q = rng.normal(size=5).astype(np.float32)
+    cand = np.array([3, 7, 1, 29, 11, -1, -1])
+    d, i = O.rerank(q, X, cand, 3)
+    full = sorted((float(np.sum((X[j].astype(np.float64) - q) ** 2)), j) for j in [3, 7, 1, 29, 11])
+    assert i.tolist() == [j for _, j in full[:3]]
+    d, i = O.rerank(q, X, cand, 8)
+    assert i[5:].tolist() == [-1, -1, -1]
+
+
+# ---------------------------------------------------------------- whole search
+
+def test_search_reduces_to_exact_knn():
+    """With every list probed and every candidate re-ranked, IVF-RaBitQ search
+    is exact kNN (Sec. 2.1.1 problem definition)."""
+    rng = np.random.default_rng(18)
+    X = rng.normal(size=(600, 16)).astype(np.float32)
+    Q = rng.normal(size=(8, 16)).astype(np.float32)
+    idx = O.build(X, 8, rng=np.random.default_rng(0), kmeans_iters=5, kmeans_restarts=1)
+    ids, d = O.search(idx, X, Q, nprobe=8, k=10, rerank_n=600)
+    ids_bf, d_bf = O.brute_force_knn(X, Q, 10)
+    np.testing.assert_array_equal(ids, ids_bf)
+    np.testing.assert_allclose(d, d_bf, rtol=1e-12)
+
+
+def test_search_stages_consistent():
+    """Stage outputs agree with the stand-alone definitions: probes are the
+    nprobe nearest lists; every candidate set is the lexicographic top-R of all
+    estimated distances of the probed lists."""
+    rng = np.random.default_rng(19)
+    X = rng.normal(size=(900, 32)).astype(np.float32)
+    Q = rng.normal(size=(4, 32)).astype(np.float32)
+    idx = O.build(X, 12, rng=np.random.default_rng(1), kmeans_iters=5, kmeans_restarts=1)
+    ids, d, st = O.search(idx, X, Q, nprobe=4, k=5, rerank_n=40, stages=True)
+    for qi in range(4):
+        full = sorted((float(np.sum((idx.centroids[j].astype(np.float64) - Q[qi]) ** 2)), j)
+                      for j in range(12))
+        assert st["probes"][qi].tolist() == [j for _, j in full[:4]]
+        allv = np.concatenate([pl["est"] for pl in st["per_list"][qi]])
+        alli = np.concatenate([pl["ids"] for pl in st["per_list"][qi]])
+        ref = sorted(zip(allv.tolist(), alli.tolist()))[:40]
+        assert st["cand_ids"][qi].tolist() == [i for _, i in ref]
+        # every probed list's members are assigned to it
+        for j, pl in zip(st["probes"][qi], st["per_list"][qi]):
+            assert np.all(idx.assign[pl["ids"]] == j)
+    assert np.all(np.diff(d, axis=1) >= 0)
+
+
+def test_recall_small_mixture():
+    """A quality check on a small Gaussian mixture: recall@10 is high once
+    enough candidates are re-ranked."""
+    from synth import get, database, queries
+    w = get("mixture128", n=20_000, nq=20, nlist=64)
+    X = database(w)
+    Q = queries(w)
+    idx = O.build(X, 64, rng=np.random.default_rng(0), kmeans_iters=10, kmeans_restarts=1)
+    ids, _ = O.search(idx, X, Q, nprobe=8, k=10, rerank_n=200)
+    gt, _ = O.brute_force_knn(X, Q, 10)
+    rec = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids.tolist(), gt.tolist())])
+    assert rec >= 0.9, rec
