@@ -1,0 +1,182 @@
+/*
+ * rbq.h — C ABI of librbq, an IVF-RaBitQ vector search library for AMD
+ * MI355X (gfx950).
+ *
+ * The library builds an IVF index whose lists hold 1-bit RaBitQ codes plus two
+ * FP32 factors per vector (Sec. 2.2.1), and answers batches of k-nearest-
+ * neighbour queries under squared L2 distance (Sec. 2.1.1) in the paper's
+ * search phases (Sec. 3.1.2): probe the nprobe nearest lists, estimate the
+ * distance of every vector in them from its code (Eqs. rabitq-ip-estimator,
+ * approx-dist), keep the rerank_n best estimates, re-rank those by exact
+ * distance and return the k best.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an rbq_status; nothing throws across the ABI.
+ *     On failure rbq_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread).
+ *   - Argument errors return RBQ_EINVAL before any side effect.
+ *   - Pointers marked "host or device" may point to host memory or to device
+ *     memory of the index's GPU; the library tells them apart with
+ *     hipPointerGetAttributes. The caller owns every buffer it passes.
+ *   - Matrices are row-major, float32, rows of d values, no padding.
+ *   - Distances are squared L2. Results rank by (distance, id) ascending; when
+ *     fewer than k candidates exist the rest is padded with id -1 and
+ *     distance +inf.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Calls on
+ *     one index may run concurrently on distinct streams. When a call returns,
+ *     host outputs are complete; device outputs are complete in stream order.
+ */
+#ifndef RBQ_H
+#define RBQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBQ_OK = 0,
+  RBQ_EINVAL = -1,   /* bad argument; nothing was changed */
+  RBQ_ENOMEM = -2,   /* device or pinned host allocation failed */
+  RBQ_EDEVICE = -3,  /* a HIP runtime call failed */
+  RBQ_ESTATE = -4,   /* object in the wrong state (e.g. server stopped) */
+  RBQ_EAGAIN = -5    /* try again later (serving queue full) */
+} rbq_status;
+
+typedef struct rbq_index rbq_index; /* opaque; owns its device and host copies */
+
+/* Index construction parameters (Sec. 3.1.1). Fill with rbq_build_params_init. */
+typedef struct {
+  int32_t nlist;           /* number of IVF lists, 1..n */
+  int32_t bq;              /* query quantisation bits B_q, 1..8 (default 4) */
+  uint64_t seed;           /* seeds the library's own random draws */
+  int32_t kmeans_iters;    /* Lloyd iterations limit (default 25) */
+  int32_t kmeans_restarts; /* k-means runs, lowest objective kept (default 3) */
+  int64_t train_n;         /* k-means training rows; 0 = min(n, 256*nlist) */
+  const float* rotation;   /* optional host d*d orthogonal P, row-major; NULL:
+                              the library draws a Haar-random P from `seed` */
+  const float* centroids;  /* optional host nlist*d centroids; NULL: k-means */
+  const int32_t* assignment; /* optional host n list ids in [0,nlist); NULL:
+                              nearest centroid */
+  int32_t vectors_on_host; /* 0: keep the raw vectors in HBM and re-rank on the
+                              GPU; 1: keep them in pinned host memory and
+                              re-rank on host cores (Sec. 3.3.4) */
+  int32_t host_threads;    /* host re-rank threads (0 = hardware concurrency) */
+  int32_t reserved[6];     /* must be zero */
+} rbq_build_params;
+
+void rbq_build_params_init(rbq_build_params* p);
+
+/*
+ * Build an index over x (host or device, n*d float32), Sec. 3.1.1: IVF
+ * centroids (given or k-means on a training sample, Phases 1-2), assignment of
+ * every vector to its nearest centroid (Sec. 2.1.2), random orthogonal P, and
+ * the RaBitQ encoding of each vector against its centroid (Phase 3;
+ * Eqs. normalized-residual, quantize, rabitq-alpha). The index copies x.
+ * Errors: EINVAL for n < 1, d < 1, nlist outside [1,n], bq outside [1,8],
+ * non-finite inputs, a bad assignment; ENOMEM; EDEVICE.
+ */
+rbq_status rbq_build_index(const float* x, int64_t n, int32_t d, const rbq_build_params* p,
+                           rbq_index** out);
+
+rbq_status rbq_free_index(rbq_index* idx);
+
+typedef struct {
+  int64_t n;
+  int32_t d, nlist, bq, vectors_on_host;
+  int64_t max_list_len;      /* largest list */
+  int64_t device_bytes;      /* device memory held by the index */
+  int64_t code_bytes;        /* packed codes + factors on the device */
+} rbq_index_info;
+
+rbq_status rbq_get_info(const rbq_index* idx, rbq_index_info* info);
+
+/*
+ * Search a batch (Sec. 3.1.2 Phases 1-5). q: host or device nq*d float32.
+ * ids: host or device nq*k int64; sqdist: host or device nq*k float32.
+ * Requires 1 <= nprobe <= min(nlist, 2048), 1 <= k <= rerank_n <= 2048,
+ * nq >= 0 (nq = 0 is a no-op). Errors: EINVAL for argument errors, ENOMEM,
+ * EDEVICE. The library allocates per-call device scratch, reused across calls.
+ */
+rbq_status rbq_search(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+                      int32_t rerank_n, int64_t* ids, float* sqdist, void* stream);
+
+/* Canonical exports (host dst, exactly `bytes` long), all in vector-id order. */
+enum {
+  RBQ_EXPORT_CENTROIDS = 1,  /* nlist*d float32 */
+  RBQ_EXPORT_ROTATION = 2,   /* d*d float32, row-major P (z = P^T r) */
+  RBQ_EXPORT_ASSIGN = 3,     /* n int32 list ids */
+  RBQ_EXPORT_CODES = 4,      /* n*ceil(d/8) uint8, LSB-first: dim j in byte j>>3 bit j&7 */
+  RBQ_EXPORT_FACTORS = 5,    /* n*2 float32: (n_x = ||x-c||, alpha_x) */
+  RBQ_EXPORT_LIST_SIZES = 6  /* nlist int64 */
+};
+rbq_status rbq_export(const rbq_index* idx, int32_t what, void* dst, size_t bytes);
+
+/*
+ * Stage-by-stage search for parity checks: the same kernels as rbq_search,
+ * with optional injected inputs and per-stage outputs. All pointers here are
+ * HOST pointers; NULL skips the item. Layouts (pair = query*nprobe + rank):
+ *   inject_probes  nq*nprobe int32     probed lists used instead of probing
+ *   inject_qu      nq*nprobe*d uint8   quantised residual qu (needs scalars)
+ *   inject_scalars nq*nprobe*3 float32 (||r||^2, v_l, Delta) per pair
+ *   probes         nq*nprobe int32;  probe_score nq*nprobe float32
+ *                  (||c||^2 - 2<q,c>, the ranking score; ||q||^2 omitted)
+ *   qrot           nq*d float32 (P^T q)
+ *   qu             nq*nprobe*d uint8; scalars nq*nprobe*4 float32
+ *                  (||r||^2, v_l, Delta, sum qu)
+ *   ip, est        nq*nprobe*max_list_len int32 / float32: per probed list,
+ *                  the integer inner product and estimated d_hat^2 of its
+ *                  vectors in ascending-id order (unused slots zero)
+ *   cand_ids, cand_est nq*rerank_n int64 / float32: the coarse top-rerank_n
+ *   ids, sqdist    nq*k final results
+ */
+typedef struct {
+  const int32_t* inject_probes;
+  const uint8_t* inject_qu;
+  const float* inject_scalars;
+  int32_t* probes;
+  float* probe_score;
+  float* qrot;
+  uint8_t* qu;
+  float* scalars;
+  int32_t* ip;
+  float* est;
+  int64_t* cand_ids;
+  float* cand_est;
+  int64_t* ids;
+  float* sqdist;
+} rbq_debug_io;
+
+rbq_status rbq_search_debug(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+                            int32_t rerank_n, rbq_debug_io* io);
+
+/* Stage timing with HIP events recorded on each call's stream. While timing
+ * is enabled every rbq_search adds its stage times to running sums; reading
+ * them waits for the recorded events. rbq_set_timing(idx, 1) clears the sums
+ * and enables timing; rbq_set_timing(idx, 0) disables it. Stages:
+ * probe (score GEMM + top-nprobe), rotate (P^T q GEMM), quant (residual
+ * quantisation), scan (the code-scan kernel alone), merge (per-query top-R),
+ * rerank (exact re-rank); total spans probe..rerank. */
+typedef struct {
+  int64_t searches;          /* timed searches summed */
+  float probe_ms, rotate_ms, quant_ms, scan_ms, merge_ms, rerank_ms, total_ms;
+  int64_t scanned_vectors;   /* sum over (query, probed list) of list sizes */
+  int64_t scan_bytes;        /* scanned_vectors * (4*ceil(d/32) + 8): codes + 2 factors */
+} rbq_timings;
+
+rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled);
+rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t);
+
+/* Persist / restore an index (versioned binary with per-section checksums). */
+rbq_status rbq_save(const rbq_index* idx, const char* path);
+rbq_status rbq_load(const char* path, rbq_index** out);
+
+const char* rbq_last_error(void);
+const char* rbq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBQ_H */

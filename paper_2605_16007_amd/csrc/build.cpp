@@ -1,0 +1,365 @@
+// Index construction (Sec. 3.1.1): k-means centroids (Phases 1-2: random
+// k-means++ seeding, GPU assignment, host centroid update), assignment of every
+// vector, random orthogonal P, list layout, and the RaBitQ encoding (Phase 3).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "host_math.hpp"
+#include "index.hpp"
+
+namespace rbq {
+
+Workspace::~Workspace() {
+  if (done) (void)hipEventDestroy(done);
+  if (base) (void)hipFree(base);
+}
+
+void DevBuf::alloc(size_t b) {
+  reset();
+  if (b == 0) b = 256;
+  RBQ_HIP(hipMalloc(&p, b));
+  bytes = b;
+}
+
+void DevBuf::reset() {
+  if (p) {
+    (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes) {
+  std::unique_ptr<Workspace> got;
+  {
+    std::lock_guard<std::mutex> g(idx->ws_mu);
+    // prefer the smallest idle workspace that is big enough
+    size_t best = (size_t)-1;
+    for (size_t i = 0; i < idx->ws_free.size(); ++i) {
+      auto& w = idx->ws_free[i];
+      if (hipEventQuery(w->done) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      if (w->cap >= bytes && (best == (size_t)-1 || w->cap < idx->ws_free[best]->cap)) best = i;
+    }
+    if (best == (size_t)-1) {
+      for (size_t i = 0; i < idx->ws_free.size(); ++i)
+        if (hipEventQuery(idx->ws_free[i]->done) == hipSuccess) {
+          best = i;
+          break;
+        }
+      (void)hipGetLastError();
+    }
+    if (best != (size_t)-1) {
+      got = std::move(idx->ws_free[best]);
+      idx->ws_free.erase(idx->ws_free.begin() + best);
+    }
+  }
+  if (got && got->cap >= bytes) return got;
+  got.reset();  // idle but too small: its last use has completed
+  got = std::make_unique<Workspace>();
+  RBQ_HIP(hipMalloc(reinterpret_cast<void**>(&got->base), bytes));
+  got->cap = bytes;
+  RBQ_HIP(hipEventCreateWithFlags(&got->done, hipEventDisableTiming));
+  return got;
+}
+
+void ws_release(rbq_index* idx, std::unique_ptr<Workspace> ws, hipStream_t s) {
+  if (!ws) return;
+  RBQ_HIP(hipEventRecord(ws->done, s));
+  std::lock_guard<std::mutex> g(idx->ws_mu);
+  idx->ws_free.push_back(std::move(ws));
+}
+
+namespace {
+
+struct StreamGuard {
+  hipStream_t s = nullptr;
+  StreamGuard() { RBQ_HIP(hipStreamCreate(&s)); }
+  ~StreamGuard() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+};
+
+__global__ void k_count_nonfinite(const float* X, int64_t rows, int d, int ld, unsigned* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = rows * d;
+  unsigned bad = 0;
+  for (int64_t e = t; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / d;
+    const float v = X[r * ld + (e - r * d)];
+    bad += !isfinite(v);
+  }
+  if (bad) atomicAdd(out, bad);
+}
+
+// Device k-means (Sec. 3.1.1 Phases 1-2). Returns nlist x ld host centroids.
+std::vector<float> kmeans_gpu(const float* Xd, int64_t n, int d, int ld, int nlist,
+                              const rbq_build_params& p, Rng& rng, hipStream_t s) {
+  const int64_t tn = p.train_n > 0 ? std::min<int64_t>(n, p.train_n)
+                                   : std::min<int64_t>(n, (int64_t)256 * nlist);
+  RBQ_CHECK(tn >= nlist, "k-means training sample is smaller than nlist");
+  const int iters = p.kmeans_iters > 0 ? p.kmeans_iters : 25;
+  const int restarts = p.kmeans_restarts > 0 ? p.kmeans_restarts : 3;
+  const std::vector<int64_t> sample = sample_without_replacement(n, tn, rng);
+
+  DevBuf didx, T, dC, dcn, keys, mind, bsum, pick;
+  didx.alloc(tn * sizeof(int64_t));
+  T.alloc((size_t)tn * ld * sizeof(float));
+  RBQ_HIP(hipMemcpyAsync(didx.p, sample.data(), tn * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  launch_gather_rows(s, Xd, ld, didx.as<int64_t>(), tn, T.as<float>(), ld);
+  std::vector<float> hT((size_t)tn * ld);
+  RBQ_HIP(hipMemcpyAsync(hT.data(), T.p, hT.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+  RBQ_HIP(hipStreamSynchronize(s));
+  std::vector<double> tnorm(tn);
+  for (int64_t t = 0; t < tn; ++t) {
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) acc += (double)hT[t * ld + k] * hT[t * ld + k];
+    tnorm[t] = acc;
+  }
+  const int64_t nb = (tn + 255) / 256;
+  dC.alloc((size_t)nlist * ld * sizeof(float));
+  dcn.alloc(nlist * sizeof(float));
+  keys.alloc(tn * sizeof(uint64_t));
+  mind.alloc(tn * sizeof(float));
+  bsum.alloc(nb * sizeof(double));
+  pick.alloc(sizeof(int64_t));
+
+  std::vector<float> hC((size_t)nlist * ld, 0.f), best;
+  std::vector<float> hcn(nlist);
+  std::vector<uint64_t> hk(tn);
+  std::vector<int32_t> a(tn), prev;
+  std::vector<double> dist(tn);
+  double best_obj = INFINITY;
+
+  auto assign_train = [&]() -> double {
+    for (int j = 0; j < nlist; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < d; ++k) acc += (double)hC[(size_t)j * ld + k] * hC[(size_t)j * ld + k];
+      hcn[j] = (float)acc;
+    }
+    RBQ_HIP(hipMemcpyAsync(dC.p, hC.data(), hC.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    RBQ_HIP(hipMemcpyAsync(dcn.p, hcn.data(), nlist * sizeof(float), hipMemcpyHostToDevice, s));
+    launch_assign_argmin(s, T.as<float>(), ld, dC.as<float>(), ld, dcn.as<float>(), (int)tn, nlist,
+                         ld, keys.as<uint64_t>());
+    RBQ_HIP(hipMemcpyAsync(hk.data(), keys.p, tn * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    RBQ_HIP(hipStreamSynchronize(s));
+    double obj = 0.0;
+    for (int64_t t = 0; t < tn; ++t) {
+      a[t] = (int32_t)(uint32_t)hk[t];
+      dist[t] = std::max(0.0, (double)f32_ord((uint32_t)(hk[t] >> 32)) + tnorm[t]);
+      obj += dist[t];
+    }
+    return obj;
+  };
+
+  for (int rs = 0; rs < restarts; ++rs) {
+    // k-means++ seeding on the device: first centre uniform, then D(x)^2 sampling
+    RBQ_HIP(hipMemsetAsync(dC.p, 0, dC.bytes, s));
+    const int64_t first = (int64_t)rng.below((uint64_t)tn);
+    RBQ_HIP(hipMemcpyAsync(pick.p, &first, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    launch_copy_row(s, T.as<float>(), ld, pick.as<int64_t>(), dC.as<float>(), d);
+    launch_kpp_update(s, T.as<float>(), ld, tn, d, pick.as<int64_t>(), mind.as<float>(),
+                      bsum.as<double>(), 1);
+    for (int j = 1; j < nlist; ++j) {
+      launch_kpp_choose(s, mind.as<float>(), bsum.as<double>(), tn, rng.uniform(), pick.as<int64_t>());
+      launch_copy_row(s, T.as<float>(), ld, pick.as<int64_t>(), dC.as<float>() + (size_t)j * ld, d);
+      launch_kpp_update(s, T.as<float>(), ld, tn, d, pick.as<int64_t>(), mind.as<float>(),
+                        bsum.as<double>(), 0);
+    }
+    RBQ_HIP(hipMemcpyAsync(hC.data(), dC.p, hC.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    RBQ_HIP(hipStreamSynchronize(s));
+    prev.clear();
+    for (int it = 0; it < iters; ++it) {
+      assign_train();
+      if (!prev.empty() && prev == a) break;
+      lloyd_update(hT.data(), tn, d, ld, a.data(), dist.data(), nlist, hC.data());
+      prev = a;
+    }
+    const double obj = assign_train();
+    if (obj < best_obj) {
+      best_obj = obj;
+      best = hC;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params& p) {
+  auto idx = std::make_unique<rbq_index>();
+  RBQ_HIP(hipGetDevice(&idx->device));
+  idx->n = n;
+  idx->d = d;
+  idx->ld = (int)round_up(d, 4);
+  idx->nlist = p.nlist;
+  idx->bq = p.bq;
+  idx->bqs = p.bq <= 4 ? 4 : 8;
+  idx->W = (d + 31) / 32;
+  idx->vectors_on_host = p.vectors_on_host;
+  idx->host_threads = p.host_threads;
+  const int ld = idx->ld, nlist = p.nlist, W = idx->W;
+  StreamGuard sg;
+  hipStream_t s = sg.s;
+  Rng rng(p.seed);
+
+  // raw vectors on the device, rows padded to ld with zeros
+  DevBuf tmpX;
+  DevBuf& Xd = idx->vectors_on_host ? tmpX : idx->X;
+  Xd.alloc((size_t)n * ld * sizeof(float));
+  if (ld != d) RBQ_HIP(hipMemsetAsync(Xd.p, 0, Xd.bytes, s));
+  RBQ_HIP(hipMemcpy2DAsync(Xd.p, ld * sizeof(float), x, d * sizeof(float), d * sizeof(float), n,
+                           hipMemcpyDefault, s));
+  {
+    DevBuf bad;
+    bad.alloc(sizeof(unsigned));
+    RBQ_HIP(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(1024), dim3(256), 0, s, Xd.as<float>(), n, d, ld,
+                       bad.as<unsigned>());
+    RBQ_HIP(hipGetLastError());
+    unsigned hb = 0;
+    RBQ_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    RBQ_HIP(hipStreamSynchronize(s));
+    RBQ_CHECK(hb == 0, "input vectors contain NaN or Inf");
+  }
+
+  // centroids
+  std::vector<float> hCld((size_t)nlist * ld, 0.f);
+  if (p.centroids) {
+    for (int j = 0; j < nlist; ++j)
+      for (int k = 0; k < d; ++k) {
+        const float v = p.centroids[(size_t)j * d + k];
+        RBQ_CHECK(std::isfinite(v), "centroids contain NaN or Inf");
+        hCld[(size_t)j * ld + k] = v;
+      }
+  } else {
+    hCld = kmeans_gpu(Xd.as<float>(), n, d, ld, nlist, p, rng, s);
+  }
+  idx->hC.resize((size_t)nlist * d);
+  for (int j = 0; j < nlist; ++j)
+    for (int k = 0; k < d; ++k) idx->hC[(size_t)j * d + k] = hCld[(size_t)j * ld + k];
+  idx->C.alloc(hCld.size() * sizeof(float));
+  RBQ_HIP(hipMemcpyAsync(idx->C.p, hCld.data(), hCld.size() * sizeof(float), hipMemcpyHostToDevice, s));
+
+  // rotation P (row-major), stored transposed: Pt[i][k] = P[k][i]
+  idx->hP.resize((size_t)d * d);
+  if (p.rotation) {
+    for (size_t t = 0; t < idx->hP.size(); ++t) {
+      RBQ_CHECK(std::isfinite(p.rotation[t]), "rotation contains NaN or Inf");
+      idx->hP[t] = p.rotation[t];
+    }
+  } else {
+    Rng prng(p.seed ^ 0x5D1E5EEDull);
+    const std::vector<double> P64 = haar_orthogonal(d, prng);
+    for (size_t t = 0; t < P64.size(); ++t) idx->hP[t] = (float)P64[t];
+  }
+  std::vector<float> hPt((size_t)d * ld, 0.f);
+  for (int k = 0; k < d; ++k)
+    for (int i = 0; i < d; ++i) hPt[(size_t)i * ld + k] = idx->hP[(size_t)k * d + i];
+  idx->Pt.alloc(hPt.size() * sizeof(float));
+  RBQ_HIP(hipMemcpyAsync(idx->Pt.p, hPt.data(), hPt.size() * sizeof(float), hipMemcpyHostToDevice, s));
+
+  // rotated centroids and squared norms (FP64 sums, stored FP32)
+  idx->Crot.alloc((size_t)nlist * ld * sizeof(float));
+  idx->cnorm.alloc(nlist * sizeof(float));
+  RBQ_HIP(hipMemsetAsync(idx->Crot.p, 0, idx->Crot.bytes, s));
+  launch_rotate_rows_f64(s, idx->C.as<float>(), ld, idx->Pt.as<float>(), ld, nlist, d,
+                         idx->Crot.as<float>(), ld, idx->cnorm.as<float>());
+
+  // assignment: given, or nearest centroid on the GPU
+  idx->h_assign.resize(n);
+  if (p.assignment) {
+    for (int64_t i = 0; i < n; ++i) {
+      RBQ_CHECK(p.assignment[i] >= 0 && p.assignment[i] < nlist, "assignment out of range");
+      idx->h_assign[i] = p.assignment[i];
+    }
+  } else {
+    DevBuf keys;
+    keys.alloc(n * sizeof(uint64_t));
+    launch_assign_argmin(s, Xd.as<float>(), ld, idx->C.as<float>(), ld, idx->cnorm.as<float>(),
+                         (int)n, nlist, ld, keys.as<uint64_t>());
+    std::vector<uint64_t> hk(n);
+    RBQ_HIP(hipMemcpyAsync(hk.data(), keys.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    RBQ_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) idx->h_assign[i] = (int32_t)(uint32_t)hk[i];
+  }
+
+  // lists: stable counting sort by list id (ids ascend inside each list), each
+  // list padded to whole 64-vector micro-blocks
+  std::vector<int64_t> cnt(nlist, 0);
+  for (int64_t i = 0; i < n; ++i) ++cnt[idx->h_assign[i]];
+  idx->h_list_len.resize(nlist);
+  idx->h_list_mb.resize(nlist);
+  int64_t nmb = 0;
+  for (int j = 0; j < nlist; ++j) {
+    idx->h_list_len[j] = (int32_t)cnt[j];
+    idx->h_list_mb[j] = (int32_t)nmb;
+    nmb += ceil_div(cnt[j], MB);
+    idx->max_list_len = std::max<int64_t>(idx->max_list_len, cnt[j]);
+  }
+  RBQ_CHECK(nmb * MB < (int64_t)INT32_MAX, "index too large for 32-bit positions");
+  idx->nmb = nmb;
+  idx->h_pos2id.assign(nmb * MB, -1);
+  std::vector<int32_t> mb_list(nmb);
+  {
+    std::vector<int64_t> fill(nlist);
+    for (int j = 0; j < nlist; ++j) {
+      fill[j] = (int64_t)idx->h_list_mb[j] * MB;
+      for (int64_t m = idx->h_list_mb[j]; m < idx->h_list_mb[j] + ceil_div(cnt[j], MB); ++m) mb_list[m] = j;
+    }
+    for (int64_t i = 0; i < n; ++i) idx->h_pos2id[fill[idx->h_assign[i]]++] = (int32_t)i;
+  }
+  idx->list_len.alloc(nlist * sizeof(int32_t));
+  idx->list_mb.alloc(nlist * sizeof(int32_t));
+  idx->pos2id.alloc(idx->h_pos2id.size() * sizeof(int32_t));
+  DevBuf dmb;
+  dmb.alloc(std::max<int64_t>(1, nmb) * sizeof(int32_t));
+  RBQ_HIP(hipMemcpyAsync(idx->list_len.p, idx->h_list_len.data(), nlist * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  RBQ_HIP(hipMemcpyAsync(idx->list_mb.p, idx->h_list_mb.data(), nlist * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  RBQ_HIP(hipMemcpyAsync(idx->pos2id.p, idx->h_pos2id.data(), idx->h_pos2id.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, s));
+  if (nmb) RBQ_HIP(hipMemcpyAsync(dmb.p, mb_list.data(), nmb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+
+  // RaBitQ encoding of every micro-block
+  const size_t rec = (size_t)(W + 2) * MB;
+  idx->blocks.alloc(std::max<int64_t>(1, nmb) * rec * sizeof(uint32_t));
+  idx->nx.alloc(std::max<int64_t>(1, nmb) * MB * sizeof(float));
+  idx->alpha.alloc(std::max<int64_t>(1, nmb) * MB * sizeof(float));
+  const int64_t step = 1 << 20;
+  for (int64_t m0 = 0; m0 < nmb; m0 += step)
+    launch_encode(s, Xd.as<float>(), ld, idx->C.as<float>(), ld, idx->Pt.as<float>(), ld,
+                  idx->pos2id.as<int32_t>(), dmb.as<int32_t>(), m0, std::min(nmb, m0 + step), d, W,
+                  idx->blocks.as<uint32_t>(), idx->nx.as<float>(), idx->alpha.as<float>());
+
+  if (idx->vectors_on_host) {
+    RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&idx->hostX), (size_t)n * d * sizeof(float),
+                          hipHostMallocDefault));
+    RBQ_HIP(hipMemcpy2DAsync(idx->hostX, d * sizeof(float), Xd.p, ld * sizeof(float),
+                             d * sizeof(float), n, hipMemcpyDeviceToHost, s));
+  }
+  RBQ_HIP(hipStreamSynchronize(s));
+  return idx.release();
+}
+
+}  // namespace rbq
+
+rbq_index::~rbq_index() {
+  if (hostX) (void)hipHostFree(hostX);
+}

@@ -1,0 +1,56 @@
+// Shared helpers of librbq: status plumbing and order-preserving sort keys.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "rbq.h"
+
+namespace rbq {
+
+// An error that crosses back to the C ABI as a status plus message.
+struct Error : std::runtime_error {
+  rbq_status status;
+  Error(rbq_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] inline void fail(rbq_status s, const std::string& m) { throw Error(s, m); }
+
+#define RBQ_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      ::rbq::fail(e_ == hipErrorOutOfMemory ? RBQ_ENOMEM : RBQ_EDEVICE,                     \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                       \
+  } while (0)
+
+#define RBQ_CHECK(cond, msg)                        \
+  do {                                              \
+    if (!(cond)) ::rbq::fail(RBQ_EINVAL, (msg));    \
+  } while (0)
+
+// Order-preserving map float -> uint32 (ascending floats give ascending keys;
+// -0.0 sorts just below +0.0). Selection runs on 64-bit keys
+// (ordered value << 32 | tie), so ties break by the low word.
+__host__ __device__ inline uint32_t ord_f32(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float f32_ord(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+__host__ __device__ inline uint64_t key64(float v, uint32_t tie) {
+  return (static_cast<uint64_t>(ord_f32(v)) << 32) | tie;
+}
+constexpr uint64_t KEY_NONE = ~0ull;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+}  // namespace rbq

@@ -1,0 +1,120 @@
+// The index object behind the opaque rbq_index handle, and the per-call
+// device workspaces.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "rbq.h"
+
+namespace rbq {
+
+// A device scratch area reused across calls. `done` is recorded on the stream
+// of the call that last used it; the area is handed out again only once that
+// event has completed, so concurrent calls on distinct streams never share one.
+struct Workspace {
+  char* base = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  ~Workspace();
+};
+
+// Carves aligned sub-buffers out of a workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(char* b) : base(b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Device memory owned by the index; freed with it.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  void alloc(size_t b);
+  void reset();
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace rbq
+
+struct rbq_index {
+  int device = 0;
+  int64_t n = 0;
+  int d = 0, ld = 0, nlist = 0, bq = 4, bqs = 4, W = 0;
+  int vectors_on_host = 0;
+  int host_threads = 0;
+  int64_t nmb = 0;            // micro-blocks over all lists
+  int64_t max_list_len = 0;
+
+  // device arrays
+  rbq::DevBuf X;       // n x ld raw vectors in id order (vectors_on_host == 0)
+  rbq::DevBuf C;       // nlist x ld centroids
+  rbq::DevBuf Crot;    // nlist x ld rotated centroids P^T c
+  rbq::DevBuf cnorm;   // nlist, ||c||^2
+  rbq::DevBuf Pt;      // d x ld, row i = column i of P
+  rbq::DevBuf blocks;  // nmb micro-block records
+  rbq::DevBuf list_mb, list_len, pos2id;
+  rbq::DevBuf nx, alpha;  // per position, for export
+
+  // host copies
+  std::vector<float> hC;          // nlist x d
+  std::vector<float> hP;          // d x d row-major
+  std::vector<int32_t> h_assign;  // n
+  std::vector<int32_t> h_list_len, h_list_mb, h_pos2id;
+  float* hostX = nullptr;         // pinned n x d when vectors_on_host
+
+  // per-call scratch
+  std::mutex ws_mu;
+  std::vector<std::unique_ptr<rbq::Workspace>> ws_free;
+
+  // stage timing: sums over the timed searches since timing was enabled.
+  // Each timed search leaves its 7 stage events in `pending`; they are read
+  // (and destroyed) by rbq_get_timings, so no search waits for them.
+  std::atomic<int> timing{0};
+  std::mutex timing_mu;
+  rbq_timings last{};
+  std::vector<std::array<hipEvent_t, 7>> pending;
+  rbq::DevBuf tcounter;  // device sum of scanned vectors
+
+  ~rbq_index();
+};
+
+namespace rbq {
+
+std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes);
+void ws_release(rbq_index* idx, std::unique_ptr<Workspace> ws, hipStream_t s);
+
+bool is_device_ptr(const void* p);
+
+rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params& p);
+
+struct SearchIO {
+  const rbq_debug_io* dbg = nullptr;  // stage injection / outputs (host pointers)
+};
+void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
+            float* dist, hipStream_t s, const SearchIO& io);
+
+void export_item(const rbq_index* idx, int what, void* dst, size_t bytes);
+void save_index(const rbq_index* idx, const char* path);
+rbq_index* load_index(const char* path);
+
+}  // namespace rbq

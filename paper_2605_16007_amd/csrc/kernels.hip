@@ -1,0 +1,890 @@
+// HIP kernels of librbq for gfx950 (CDNA4, wave64).
+//
+// Search path (Sec. 3.1.2): probe GEMM + top-nprobe (Phase 1), query rotation
+// GEMM, B_q-bit query quantisation, 1-bit code scan with the estimator fused
+// (Phase 3; Eqs. rabitq-ip-estimator, approx-dist), per-query top-R selection
+// (Phase 4) and exact re-rank (Phase 5). Build path (Sec. 3.1.1): k-means
+// assignment GEMM with fused argmin and the RaBitQ encoder (Phase 3).
+#include <cfloat>
+#include <cmath>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rbq {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ inline uint32_t lane_prefix(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
+}
+
+__device__ inline float wave_sum(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ inline float wave_min(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline float wave_max(float v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ inline int wave_sum_i(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Ascending bitonic sort of n (power of two) 64-bit keys in LDS by the whole
+// workgroup. Ends with a barrier.
+__device__ void bitonic_sort_lds(uint64_t* a, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < (n >> 1); t += blockDim.x) {
+        const int i = 2 * t - (t & (stride - 1));
+        const int j = i + stride;
+        const uint64_t x = a[i], y = a[j];
+        const bool up = (i & size) == 0;
+        if ((x > y) == up) {
+          a[i] = y;
+          a[j] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Inclusive prefix sum over a 256-thread workgroup. wsum: 4 words of LDS.
+__device__ uint32_t block_incl_scan_256(uint32_t v, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off);
+    if (lane >= off) v += t;
+  }
+  if (lane == 63) wsum[wave] = v;
+  __syncthreads();
+  uint32_t add = 0;
+  for (int w = 0; w < wave; ++w) add += wsum[w];
+  __syncthreads();
+  return v + add;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// FP32 GEMM on MFMA (v_mfma_f32_16x16x4f32). 64x64 block tile, K step 16,
+// four waves of 32x32. Lane layout: A(i,k) in lane i+16k, B(k,j) in lane
+// j+16k, result (i,j) in lane j+16*(i/4), register i%4.
+// ---------------------------------------------------------------------------
+
+__device__ inline void gemm_tile_load(const float* __restrict__ A, int lda, const float* __restrict__ B,
+                                      int ldb, int M, int N, int K, int m0, int n0, int k0,
+                                      float (*As)[17], float (*Bs)[17]) {
+  const int tid = threadIdx.x;
+  const int lr = tid >> 2, lc = (tid & 3) * 4;
+  float4 av = make_float4(0.f, 0.f, 0.f, 0.f), bv = av;
+  const int gk = k0 + lc;
+  if (m0 + lr < M && gk < K) av = *reinterpret_cast<const float4*>(A + (size_t)(m0 + lr) * lda + gk);
+  if (n0 + lr < N && gk < K) bv = *reinterpret_cast<const float4*>(B + (size_t)(n0 + lr) * ldb + gk);
+  __syncthreads();
+  As[lr][lc + 0] = av.x; As[lr][lc + 1] = av.y; As[lr][lc + 2] = av.z; As[lr][lc + 3] = av.w;
+  Bs[lr][lc + 0] = bv.x; Bs[lr][lc + 1] = bv.y; Bs[lr][lc + 2] = bv.z; Bs[lr][lc + 3] = bv.w;
+  __syncthreads();
+}
+
+__device__ inline void gemm_tile_mma(float (*As)[17], float (*Bs)[17], int wm, int wn, v4f (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int kk = s * 4 + (lane >> 4);
+    const float a0 = As[wm + (lane & 15)][kk], a1 = As[wm + 16 + (lane & 15)][kk];
+    const float b0 = Bs[wn + (lane & 15)][kk], b1 = Bs[wn + 16 + (lane & 15)][kk];
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_tn(const float* __restrict__ A, int lda,
+                                                 const float* __restrict__ B, int ldb,
+                                                 float* __restrict__ C, int ldc, int M, int N, int K,
+                                                 const float* __restrict__ bnorm) {
+  __shared__ float As[64][17];
+  __shared__ float Bs[64][17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4f acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    gemm_tile_load(A, lda, B, ldb, M, N, K, m0, n0, k0, As, Bs);
+    gemm_tile_mma(As, Bs, wm, wn, acc);
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + ti * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn + tj * 16 + (lane & 15);
+        if (row < M && col < N) {
+          float v = acc[ti][tj][r];
+          if (MODE == 1) v = bnorm[col] - 2.0f * v;
+          C[(size_t)row * ldc + col] = v;
+        }
+      }
+}
+
+void launch_gemm_tn(hipStream_t s, int mode, const float* A, int lda, const float* B, int ldb,
+                    float* C, int ldc, int M, int N, int K, const float* bnorm) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_gemm_tn<0>, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, bnorm);
+  else
+    hipLaunchKernelGGL(k_gemm_tn<1>, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, bnorm);
+  RBQ_HIP(hipGetLastError());
+}
+
+// Nearest centroid per row: each workgroup owns 64 rows of A and walks every
+// 64-column tile of B, keeping the running minimum of key64(score, column).
+__global__ __launch_bounds__(256) void k_assign_argmin(const float* __restrict__ A, int lda,
+                                                       const float* __restrict__ B, int ldb,
+                                                       const float* __restrict__ bnorm, int M, int N,
+                                                       int K, uint64_t* __restrict__ out) {
+  __shared__ float As[64][17];
+  __shared__ float Bs[64][17];
+  __shared__ unsigned long long best[64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  if (tid < 64) best[tid] = KEY_NONE;
+  __syncthreads();
+  for (int n0 = 0; n0 < N; n0 += 64) {
+    v4f acc[2][2];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      gemm_tile_load(A, lda, B, ldb, M, N, K, m0, n0, k0, As, Bs);
+      gemm_tile_mma(As, Bs, wm, wn, acc);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = wm + ti * 16 + 4 * (lane >> 4) + r;
+        unsigned long long kb = KEY_NONE;
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          const int col = n0 + wn + tj * 16 + (lane & 15);
+          if (col < N) {
+            const unsigned long long kk = key64(bnorm[col] - 2.0f * acc[ti][tj][r], (uint32_t)col);
+            kb = kk < kb ? kk : kb;
+          }
+        }
+        for (int off = 1; off < 16; off <<= 1) {
+          const unsigned long long o = __shfl_xor(kb, off);
+          kb = o < kb ? o : kb;
+        }
+        if ((lane & 15) == 0) atomicMin(&best[rl], kb);
+      }
+  }
+  __syncthreads();
+  if (tid < 64 && m0 + tid < M) out[m0 + tid] = best[tid];
+}
+
+void launch_assign_argmin(hipStream_t s, const float* A, int lda, const float* B, int ldb,
+                          const float* bnorm, int M, int N, int K, uint64_t* out) {
+  if (M <= 0) return;
+  hipLaunchKernelGGL(k_assign_argmin, dim3((M + 63) / 64), dim3(256), 0, s, A, lda, B, ldb, bnorm,
+                     M, N, K, out);
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Row top-k: exact selection of the k smallest 64-bit keys of each row by an
+// MSB-first radix select (8-bit digits, early exit once the boundary bucket is
+// taken whole), compaction, and an LDS bitonic sort of the k survivors.
+// ---------------------------------------------------------------------------
+
+constexpr int TOPK_CACHE = 4096;   // rows up to this many keys are staged in LDS
+
+template <bool FROM_SCORE>
+__global__ __launch_bounds__(256) void k_row_topk(const float* __restrict__ score,
+                                                  const uint64_t* __restrict__ keys, int64_t ld,
+                                                  int ncols, int k, int KP,
+                                                  uint64_t* __restrict__ out_keys,
+                                                  int32_t* __restrict__ out_low,
+                                                  float* __restrict__ out_val) {
+  extern __shared__ uint64_t smem[];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t s_digit, s_rem, s_bucket, s_cnt;
+  const int tid = threadIdx.x;
+  const int64_t row = blockIdx.x;
+  const bool cached = ncols <= TOPK_CACHE;
+  uint64_t* cache = smem;
+  uint64_t* sel = smem + (cached ? ncols : 0);
+  auto src = [&](int c) -> uint64_t {
+    if (FROM_SCORE) return key64(score[row * ld + c], (uint32_t)c);
+    return keys[row * ld + c];
+  };
+  auto get = [&](int c) -> uint64_t { return cached ? cache[c] : src(c); };
+  if (cached)
+    for (int c = tid; c < ncols; c += 256) cache[c] = src(c);
+  __syncthreads();
+
+  const bool take_all = ncols <= k;
+  uint64_t prefix = 0, pmask = 0;
+  uint32_t rem = (uint32_t)k;
+  if (!take_all) {
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hist[tid] = 0;
+      __syncthreads();
+      for (int c = tid; c < ncols; c += 256) {
+        const uint64_t key = get(c);
+        if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      const uint32_t h = hist[tid];
+      const uint32_t incl = block_incl_scan_256(h, wsum);
+      const uint32_t excl = incl - h;
+      if (excl < rem && rem <= incl) {
+        s_digit = (uint32_t)tid;
+        s_rem = rem - excl;
+        s_bucket = h;
+      }
+      __syncthreads();
+      prefix |= (uint64_t)s_digit << shift;
+      pmask |= 0xFFull << shift;
+      rem = s_rem;
+      const uint32_t bucket = s_bucket;
+      __syncthreads();
+      if (bucket == rem) break;
+    }
+  }
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+  if (take_all) {
+    for (int c = tid; c < ncols; c += 256) sel[atomicAdd(&s_cnt, 1u)] = get(c);
+  } else {
+    for (int c = tid; c < ncols; c += 256) {
+      const uint64_t key = get(c);
+      if (key < prefix) sel[atomicAdd(&s_cnt, 1u)] = key;
+    }
+    __syncthreads();
+    const uint64_t hi = prefix | ~pmask;
+    for (int c = tid; c < ncols; c += 256) {
+      const uint64_t key = get(c);
+      if (key >= prefix && key <= hi) {
+        const uint32_t p = atomicAdd(&s_cnt, 1u);
+        if (p < (uint32_t)k) sel[p] = key;
+      }
+    }
+  }
+  __syncthreads();
+  const int cnt = min((int)s_cnt, k);
+  for (int i = cnt + tid; i < KP; i += 256) sel[i] = KEY_NONE;
+  __syncthreads();
+  bitonic_sort_lds(sel, KP);
+  for (int i = tid; i < k; i += 256) {
+    const uint64_t v = sel[i];
+    if (out_keys) out_keys[row * k + i] = v;
+    if (out_low) out_low[row * k + i] = v == KEY_NONE ? -1 : (int32_t)(uint32_t)v;
+    if (out_val) out_val[row * k + i] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
+  }
+}
+
+static int pow2_at_least(int n) {
+  int p = 2;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+void launch_row_topk(hipStream_t s, const float* score, const uint64_t* keys, int rows, int64_t ld,
+                     int ncols, int k, uint64_t* out_keys, int32_t* out_low, float* out_val) {
+  if (rows <= 0) return;
+  RBQ_CHECK(k >= 1 && k <= MAX_SEL, "selection size out of range");
+  const int KP = pow2_at_least(k);
+  const size_t lds = ((ncols <= TOPK_CACHE ? ncols : 0) + KP) * sizeof(uint64_t);
+  if (score)
+    hipLaunchKernelGGL(k_row_topk<true>, dim3(rows), dim3(256), lds, s, score, keys, ld, ncols, k,
+                       KP, out_keys, out_low, out_val);
+  else
+    hipLaunchKernelGGL(k_row_topk<false>, dim3(rows), dim3(256), lds, s, score, keys, ld, ncols, k,
+                       KP, out_keys, out_low, out_val);
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Query quantisation: one wave per (query, probe) pair. r = P^T q - P^T c_j,
+// v_l = min r, Delta = (max r - v_l)/(2^bq - 1), qu = floor((r - v_l)/Delta
+// + 1/2) clamped; bit-planes by wave ballots (64 dims per ballot = 2 words).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, int ldq,
+                                               const float* __restrict__ crot, int ldc,
+                                               const int32_t* __restrict__ probes, int nq, int nprobe,
+                                               int d, int W, int bq, int bqs,
+                                               uint32_t* __restrict__ planes,
+                                               uint8_t* __restrict__ qu_out, float4* __restrict__ scal,
+                                               const uint8_t* __restrict__ inj_qu,
+                                               const float* __restrict__ inj_scal) {
+  const int lane = threadIdx.x & 63;
+  const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pair >= (int64_t)nq * nprobe) return;  // uniform per wave
+  const int64_t i = pair / nprobe;
+  const int j = max(probes[pair], 0);  // probes are always valid list ids; never index below 0
+  const float* qr = qrot + i * ldq;
+  const float* cr = crot + (int64_t)j * ldc;
+  const int nch = (W * 32 + 63) / 64;
+  float rmin = INFINITY, rmax = -INFINITY, ss = 0.f;
+  for (int t = 0; t < nch; ++t) {
+    const int dd = t * 64 + lane;
+    if (dd < d) {
+      const float r = qr[dd] - cr[dd];
+      rmin = fminf(rmin, r);
+      rmax = fmaxf(rmax, r);
+      ss += r * r;
+    }
+  }
+  rmin = wave_min(rmin);
+  rmax = wave_max(rmax);
+  ss = wave_sum(ss);
+  float vl, delta, rn2;
+  if (inj_scal) {
+    rn2 = inj_scal[pair * 3 + 0];
+    vl = inj_scal[pair * 3 + 1];
+    delta = inj_scal[pair * 3 + 2];
+  } else {
+    rn2 = ss;
+    vl = rmin;
+    delta = (rmax - rmin) / (float)((1 << bq) - 1);
+  }
+  const float inv = delta > 0.f ? 1.0f / delta : 0.f;
+  const uint32_t top = (1u << bq) - 1u;
+  int sq = 0;
+  for (int t = 0; t < nch; ++t) {
+    const int dd = t * 64 + lane;
+    uint32_t q = 0;
+    if (dd < d) {
+      if (inj_qu) {
+        q = inj_qu[pair * d + dd];
+      } else {
+        const float r = qr[dd] - cr[dd];
+        const float y = (r - vl) * inv;
+        const float f = floorf(y + 0.5f);
+        q = f <= 0.f ? 0u : (f >= (float)top ? top : (uint32_t)f);
+      }
+    }
+    sq += (int)q;
+    if (qu_out && dd < W * 32) qu_out[pair * (W * 32) + dd] = (uint8_t)q;
+    for (int b = 0; b < bq; ++b) {
+      const uint64_t m = __ballot((q >> b) & 1u);
+      if (lane == 0) {
+        const int w0 = 2 * t;
+        planes[(pair * W + w0) * bqs + b] = (uint32_t)m;
+        if (w0 + 1 < W) planes[(pair * W + w0 + 1) * bqs + b] = (uint32_t)(m >> 32);
+      }
+    }
+  }
+  if (lane == 0)
+    for (int w = 0; w < W; ++w)
+      for (int b = bq; b < bqs; ++b) planes[(pair * W + w) * bqs + b] = 0u;
+  sq = wave_sum_i(sq);
+  if (lane == 0) scal[pair] = make_float4(rn2, vl, delta, (float)sq);
+}
+
+void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, int ldc,
+                  const int32_t* probes, int nq, int nprobe, int d, int W, int bq, int bqs,
+                  uint32_t* planes, uint8_t* qu, float4* scal, const uint8_t* inj_qu,
+                  const float* inj_scal) {
+  const int64_t pairs = (int64_t)nq * nprobe;
+  if (pairs <= 0) return;
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, s, qrot, ldq, crot,
+                     ldc, probes, nq, nprobe, d, W, bq, bqs, planes, qu, scal, inj_qu, inj_scal);
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Code scan (query-major popcount form). One workgroup per (query, probe)
+// item, ordered probe-rank-major so that every query's nearest lists are
+// scanned first. Each lane takes one vector of a 64-vector micro-block:
+//   ip  = sum_t 2^t popcount(code & plane_t)      (exact integer)
+//   pop = popcount(code)
+//   E   = v_l (2 pop - D) + Delta (2 ip - sum qu)  (= sum_d b_d (v_l + Delta qu_d))
+//   d_hat^2 = ||r||^2 + n_x^2 - 2 n_x E / (sqrt(D) alpha_x)
+// with the two per-vector factors stored folded (n_x^2, -2 n_x/(sqrt(D) alpha)).
+// Candidates below the running threshold go to an LDS buffer that is cut back
+// to the best R whenever it could overflow; the item's final R-th estimate
+// tightens the query's global bound (the IVF-aware pruning of Sec. 3.3.3).
+// ---------------------------------------------------------------------------
+
+__device__ void sel_compact(uint64_t* sel, int cap, int R, int* s_n, uint64_t* s_thr) {
+  const int n = *s_n;
+  for (int t = n + threadIdx.x; t < cap; t += blockDim.x) sel[t] = KEY_NONE;
+  __syncthreads();
+  bitonic_sort_lds(sel, cap);
+  if (threadIdx.x == 0 && n >= R) {
+    *s_thr = sel[R - 1];
+    *s_n = R;
+  }
+  __syncthreads();
+}
+
+template <int WT, int BQT, bool DUMP>
+__global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
+  extern __shared__ uint64_t sel[];
+  __shared__ int s_n;
+  __shared__ uint64_t s_thr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int W = WT > 0 ? WT : a.L.W;
+  const int BQ = BQT > 0 ? BQT : a.Q.bqs;
+  const int bqs = a.Q.bqs;
+  const int it = blockIdx.x;
+  const int p = it / a.nq, i = it - p * a.nq;
+  const int64_t pair = (int64_t)i * a.nprobe + p;
+  const int j = a.probes[pair];
+  const int len = j >= 0 ? a.L.list_len[j] : 0, mb0 = j >= 0 ? a.L.list_mb[j] : 0;
+  const int nmb = (len + 63) >> 6;
+  const int R = a.R;
+  const uint32_t* planes = a.Q.planes + pair * W * bqs;
+  const float4 sc = a.Q.scal[pair];
+  const float rn2 = sc.x, vl = sc.y, delta = sc.z;
+  const int sumqu = (int)sc.w;
+  const int D = a.L.d;
+  if (tid == 0) {
+    s_n = 0;
+    s_thr = a.qthr ? ((static_cast<uint64_t>(a.qthr[i]) << 32) | 0xFFFFFFFFull) : KEY_NONE;
+  }
+  __syncthreads();
+  const size_t rec = (size_t)(W + 2) * 64;
+  for (int base = 0; base < nmb; base += 4) {
+    const int m = base + wave;
+    uint64_t key = KEY_NONE;
+    if (m < nmb) {
+      const uint32_t* blk = a.L.blocks + (size_t)(mb0 + m) * rec;
+      int acc[BQT > 0 ? BQT : 8];
+      for (int t = 0; t < BQ; ++t) acc[t] = 0;
+      int pop = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint32_t c = blk[w * 64 + lane];
+        pop += __popc(c);
+#pragma unroll
+        for (int t = 0; t < BQ; ++t) acc[t] += __popc(c & planes[w * bqs + t]);
+      }
+      int ip = 0;
+      for (int t = 0; t < BQ; ++t) ip += acc[t] << t;
+      const float fadd = __uint_as_float(blk[W * 64 + lane]);
+      const float fmul = __uint_as_float(blk[(W + 1) * 64 + lane]);
+      const float E = vl * (float)(2 * pop - D) + delta * (float)(2 * ip - sumqu);
+      const float est = rn2 + fadd + fmul * E;
+      const int v = (m << 6) + lane;
+      if (v < len) {
+        key = key64(est, (uint32_t)((mb0 << 6) + v));
+        if (DUMP) {
+          a.dump_ip[pair * a.maxlen + v] = ip;
+          a.dump_est[pair * a.maxlen + v] = est;
+        }
+      }
+    }
+    const uint64_t thr = s_thr;
+    const bool pass = key < thr;
+    const uint64_t mask = __ballot(pass);
+    if (mask) {
+      int off = 0;
+      if (lane == 0) off = atomicAdd(&s_n, (int)__popcll(mask));
+      off = __shfl(off, 0);
+      if (pass) sel[off + (int)lane_prefix(mask)] = key;
+    }
+    __syncthreads();
+    const int nn = s_n;
+    __syncthreads();  // every thread has read the count before the next appends
+    if (nn > cap - 256) sel_compact(sel, cap, R, &s_n, &s_thr);
+  }
+  __syncthreads();
+  const int n = s_n;
+  int P = 2;
+  while (P < n) P <<= 1;
+  for (int t = n + tid; t < P; t += 256) sel[t] = KEY_NONE;
+  __syncthreads();
+  bitonic_sort_lds(sel, P);
+  const int nout = n < R ? n : R;
+  for (int r = tid; r < R; r += 256) {
+    uint64_t kk = KEY_NONE;
+    if (r < nout) {
+      const uint64_t sv = sel[r];
+      const int id = a.L.pos2id[(uint32_t)sv];
+      kk = (sv & 0xFFFFFFFF00000000ull) | (uint32_t)id;
+    }
+    a.out[pair * R + r] = kk;
+  }
+  if (a.qthr && tid == 0 && n >= R) atomicMin(&a.qthr[i], (uint32_t)(sel[R - 1] >> 32));
+}
+
+template <int WT, int BQT>
+static void scan_dispatch(hipStream_t s, const ScanArgs& a, int cap, bool dump) {
+  const unsigned items = (unsigned)((int64_t)a.nq * a.nprobe);
+  const size_t lds = (size_t)cap * sizeof(uint64_t);
+  if (dump)
+    hipLaunchKernelGGL((k_scan_popc<WT, BQT, true>), dim3(items), dim3(256), lds, s, a, cap);
+  else
+    hipLaunchKernelGGL((k_scan_popc<WT, BQT, false>), dim3(items), dim3(256), lds, s, a, cap);
+}
+
+void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
+  if ((int64_t)a.nq * a.nprobe <= 0) return;
+  const int cap = pow2_at_least(a.R + 256);
+  const bool dump = a.dump_ip != nullptr;
+  const int bq4 = a.Q.bqs == 4;
+  if (bq4 && a.L.W == 4)
+    scan_dispatch<4, 4>(s, a, cap, dump);
+  else if (bq4 && a.L.W == 3)
+    scan_dispatch<3, 4>(s, a, cap, dump);
+  else if (bq4 && a.L.W == 30)
+    scan_dispatch<30, 4>(s, a, cap, dump);
+  else
+    scan_dispatch<0, 0>(s, a, cap, dump);
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Exact re-rank (Phase 5 on the GPU): per query, the R candidates' raw vectors
+// are gathered (one wave per candidate), ||q - x||^2 is summed in FP32 and the
+// k best (distance, id) pairs are kept.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int ldq,
+                                                const float* __restrict__ X, int ldx, int d,
+                                                const uint64_t* __restrict__ cand, int R, int k,
+                                                int KP, int64_t* __restrict__ ids,
+                                                float* __restrict__ dist) {
+  extern __shared__ uint64_t ck[];
+  float* qs = reinterpret_cast<float*>(ck + KP);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i = blockIdx.x;
+  for (int t = tid; t < d; t += 256) qs[t] = q[i * ldq + t];
+  for (int t = R + tid; t < KP; t += 256) ck[t] = KEY_NONE;
+  __syncthreads();
+  for (int c = wave; c < R; c += 4) {
+    const uint64_t key = cand[i * R + c];
+    uint64_t out = KEY_NONE;
+    if (key != KEY_NONE) {
+      const uint32_t id = (uint32_t)key;
+      const float* x = X + (size_t)id * ldx;
+      float acc = 0.f;
+      for (int t = lane; t < d; t += 64) {
+        const float df = qs[t] - x[t];
+        acc += df * df;
+      }
+      acc = wave_sum(acc);
+      out = key64(acc, id);
+    }
+    if (lane == 0) ck[c] = out;
+  }
+  __syncthreads();
+  bitonic_sort_lds(ck, KP);
+  for (int r = tid; r < k; r += 256) {
+    const uint64_t v = ck[r];
+    ids[i * k + r] = v == KEY_NONE ? -1 : (int64_t)(uint32_t)v;
+    dist[i * k + r] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
+  }
+}
+
+void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int ldx, int d,
+                   const uint64_t* cand, int nq, int R, int k, int64_t* ids, float* dist) {
+  if (nq <= 0) return;
+  const int KP = pow2_at_least(R);
+  const size_t lds = KP * sizeof(uint64_t) + (size_t)d * sizeof(float);
+  hipLaunchKernelGGL(k_rerank, dim3(nq), dim3(256), lds, s, q, ldq, X, ldx, d, cand, R, k, KP, ids,
+                     dist);
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// RaBitQ encoder (Sec. 3.1.1 Phase 3, Sec. 3.2.2) in FP64: one workgroup per
+// micro-block of 64 list positions. The residual norm n_x is taken from
+// r = x - c directly (an orthogonal P preserves it, so it need not wait for
+// the rotation); z = P^T r; code bit = [z >= 0]; alpha = ||z||_1/(sqrt(D) n_x).
+// Writes the micro-block record (codes, n_x^2, -2 n_x/(sqrt(D) alpha)) and the
+// unfolded (n_x, alpha) for export.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_encode(const float* __restrict__ X, int ldx,
+                                                const float* __restrict__ C, int ldc,
+                                                const float* __restrict__ Pt, int ldp,
+                                                const int32_t* __restrict__ pos2id,
+                                                const int32_t* __restrict__ mb_list, int64_t mb_begin,
+                                                int d, int W, uint32_t* __restrict__ blocks,
+                                                float* __restrict__ nx_out,
+                                                float* __restrict__ alpha_out) {
+  extern __shared__ uint32_t bits[];          // [W][64]
+  __shared__ double rs[64][33];
+  __shared__ double part[4][64];
+  __shared__ double l1part[4][64];
+  const int tid = threadIdx.x;
+  const int v = tid & 63;
+  const int g = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t mb = mb_begin + blockIdx.x;
+  const int j = mb_list[mb];
+  const float* cj = C + (int64_t)j * ldc;
+  for (int t = tid; t < W * 64; t += 256) bits[t] = 0u;
+  {  // ||x - c||^2 in FP64, four interleaved partial sums per vector
+    const int id = pos2id[mb * 64 + v];
+    double s2 = 0.0;
+    if (id >= 0) {
+      const float* x = X + (int64_t)id * ldx;
+      for (int t = g; t < d; t += 4) {
+        const double r = (double)x[t] - (double)cj[t];
+        s2 += r * r;
+      }
+    }
+    part[g][v] = s2;
+  }
+  double l1 = 0.0;
+  const int lr = tid >> 2, lc = (tid & 3) * 8;
+  const int idl = pos2id[mb * 64 + lr];
+  for (int i0 = 0; i0 < d; i0 += 128) {
+    double acc[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) acc[t] = 0.0;
+    for (int d0 = 0; d0 < d; d0 += 32) {
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int dd = d0 + lc + c;
+        double r = 0.0;
+        if (idl >= 0 && dd < d) r = (double)X[(int64_t)idl * ldx + dd] - (double)cj[dd];
+        rs[lr][lc + c] = r;
+      }
+      __syncthreads();
+      const int dmax = min(32, d - d0);
+      for (int dd = 0; dd < dmax; ++dd) {
+        const double rv = rs[v][dd];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+          const int oi = i0 + g + 4 * t;
+          if (oi < d) acc[t] += rv * (double)Pt[(int64_t)oi * ldp + d0 + dd];
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int oi = i0 + g + 4 * t;
+      if (oi < d) {
+        if (acc[t] >= 0.0) atomicOr(&bits[(oi >> 5) * 64 + v], 1u << (oi & 31));
+        l1 += fabs(acc[t]);
+      }
+    }
+  }
+  l1part[g][v] = l1;
+  __syncthreads();
+  const int64_t pos = mb * 64 + v;
+  const int id = pos2id[pos];
+  const size_t rec = (size_t)(W + 2) * 64;
+  uint32_t* out = blocks + mb * rec;
+  for (int t = tid; t < W * 64; t += 256) {
+    const int vv = t & 63;
+    out[t] = pos2id[mb * 64 + vv] >= 0 ? bits[t] : 0u;
+  }
+  if (g == 0) {
+    float fadd = INFINITY, fmul = 0.f, nxf = 0.f, alf = 1.f;
+    if (id >= 0) {
+      const double n2 = part[0][v] + part[1][v] + part[2][v] + part[3][v];
+      const double nx = sqrt(n2);
+      const double L1 = l1part[0][v] + l1part[1][v] + l1part[2][v] + l1part[3][v];
+      const double alpha = nx > 0.0 ? L1 / (sqrt((double)d) * nx) : 1.0;
+      fadd = (float)(nx * nx);
+      fmul = (float)(-2.0 * nx / (sqrt((double)d) * alpha));
+      nxf = (float)nx;
+      alf = (float)alpha;
+    }
+    out[W * 64 + v] = __float_as_uint(fadd);
+    out[(W + 1) * 64 + v] = __float_as_uint(fmul);
+    nx_out[pos] = nxf;
+    alpha_out[pos] = alf;
+  }
+}
+
+void launch_encode(hipStream_t s, const float* X, int ldx, const float* C, int ldc, const float* Pt,
+                   int ldp, const int32_t* pos2id, const int32_t* mb_list, int64_t mb_begin,
+                   int64_t mb_end, int d, int W, uint32_t* blocks, float* nx_out,
+                   float* alpha_out) {
+  const int64_t n = mb_end - mb_begin;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_encode, dim3((unsigned)n), dim3(256), (size_t)W * 64 * sizeof(uint32_t), s,
+                     X, ldx, C, ldc, Pt, ldp, pos2id, mb_list, mb_begin, d, W, blocks, nx_out,
+                     alpha_out);
+  RBQ_HIP(hipGetLastError());
+}
+
+__global__ void k_rotate_rows_f64(const float* __restrict__ A, int lda, const float* __restrict__ Pt,
+                                  int ldp, int rows, int d, float* __restrict__ out, int ldo,
+                                  float* __restrict__ nrm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)rows * d) return;
+  const int64_t r = t / d;
+  const int i = (int)(t - r * d);
+  const float* a = A + r * lda;
+  const float* p = Pt + (int64_t)i * ldp;
+  double acc = 0.0;
+  for (int k = 0; k < d; ++k) acc += (double)a[k] * (double)p[k];
+  out[r * ldo + i] = (float)acc;
+  if (nrm && i == 0) {
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += (double)a[k] * (double)a[k];
+    nrm[r] = (float)s;
+  }
+}
+
+void launch_rotate_rows_f64(hipStream_t s, const float* A, int lda, const float* Pt, int ldp,
+                            int rows, int d, float* out, int ldo, float* nrm) {
+  const int64_t n = (int64_t)rows * d;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_rotate_rows_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, lda,
+                     Pt, ldp, rows, d, out, ldo, nrm);
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels.
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+void launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  RBQ_HIP(hipGetLastError());
+}
+void launch_fill_u64(hipStream_t s, uint64_t* p, uint64_t v, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  RBQ_HIP(hipGetLastError());
+}
+
+__global__ void k_gather_rows(const float* __restrict__ X, int ldx, const int64_t* __restrict__ idx,
+                              int64_t n, float* __restrict__ out, int ldo) {
+  const int64_t r = blockIdx.x;
+  if (r >= n) return;
+  const float* src = X + idx[r] * ldx;
+  for (int t = threadIdx.x; t < ldo; t += blockDim.x) out[r * ldo + t] = src[t];
+}
+void launch_gather_rows(hipStream_t s, const float* X, int ldx, const int64_t* idx, int64_t n,
+                        float* out, int ldo) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)n), dim3(128), 0, s, X, ldx, idx, n, out, ldo);
+  RBQ_HIP(hipGetLastError());
+}
+
+// k-means++ seeding on the device. mind[t] holds the squared distance of row t
+// to its nearest chosen centre; blocksum[b] the FP64 sum of block b's mind.
+__global__ __launch_bounds__(256) void k_kpp_update(const float* __restrict__ T, int ldt, int64_t n,
+                                                    int d, const int64_t* __restrict__ pick,
+                                                    float* __restrict__ mind,
+                                                    double* __restrict__ blocksum, int first) {
+  __shared__ double red[256];
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const float* c = T + (*pick) * ldt;
+  double v = 0.0;
+  if (t < n) {
+    const float* x = T + t * ldt;
+    float acc = 0.f;
+    for (int k = 0; k < d; ++k) {
+      const float df = x[k] - c[k];
+      acc += df * df;
+    }
+    const float m = first ? acc : fminf(mind[t], acc);
+    mind[t] = m;
+    v = m;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0];
+}
+
+void launch_kpp_update(hipStream_t s, const float* T, int ldt, int64_t n, int d, const int64_t* pick,
+                       float* mind, double* blocksum, int first) {
+  hipLaunchKernelGGL(k_kpp_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, T, ldt, n, d,
+                     pick, mind, blocksum, first);
+  RBQ_HIP(hipGetLastError());
+}
+
+// Samples row t with probability mind[t] / sum(mind): locates u * total in the
+// running sums (blocks first, then rows inside the block), in a fixed order.
+__global__ __launch_bounds__(256) void k_kpp_choose(const float* __restrict__ mind,
+                                                    const double* __restrict__ blocksum, int64_t n,
+                                                    double u, int64_t* __restrict__ pick) {
+  __shared__ double part[256];
+  __shared__ double pre[257];
+  const int tid = threadIdx.x;
+  const int64_t nb = (n + 255) / 256;
+  const int64_t per = (nb + 255) / 256;
+  const int64_t b0 = tid * per, b1 = min(nb, b0 + per);
+  double s = 0.0;
+  for (int64_t b = b0; b < b1; ++b) s += blocksum[b];
+  part[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    pre[0] = 0.0;
+    for (int t = 0; t < 256; ++t) pre[t + 1] = pre[t] + part[t];
+    const double total = pre[256];
+    int64_t choice = 0;
+    if (!(total > 0.0)) {
+      choice = min(n - 1, (int64_t)(u * (double)n));
+    } else {
+      const double target = u * total;
+      int t = 0;
+      while (t < 255 && pre[t + 1] <= target) ++t;
+      double acc = pre[t];
+      int64_t b = min((int64_t)t * per, nb - 1);
+      const int64_t bend = min(nb, b + per);
+      while (b + 1 < bend && acc + blocksum[b] <= target) acc += blocksum[b++];
+      int64_t r = b * 256;
+      const int64_t rend = min(n, r + 256);
+      while (r + 1 < rend && acc + (double)mind[r] <= target) acc += (double)mind[r++];
+      // never pick a row whose weight is zero
+      while (r < rend - 1 && mind[r] == 0.f) ++r;
+      choice = min(r, n - 1);
+    }
+    *pick = choice;
+  }
+}
+
+void launch_kpp_choose(hipStream_t s, const float* mind, const double* blocksum, int64_t n, double u,
+                       int64_t* pick) {
+  hipLaunchKernelGGL(k_kpp_choose, dim3(1), dim3(256), 0, s, mind, blocksum, n, u, pick);
+  RBQ_HIP(hipGetLastError());
+}
+
+__global__ void k_copy_row(const float* __restrict__ T, int ldt, const int64_t* __restrict__ pick,
+                           float* __restrict__ dst, int d) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < d) dst[t] = T[(*pick) * ldt + t];
+}
+void launch_copy_row(hipStream_t s, const float* T, int ldt, const int64_t* pick, float* dst, int d) {
+  hipLaunchKernelGGL(k_copy_row, dim3((d + 255) / 256), dim3(256), 0, s, T, ldt, pick, dst, d);
+  RBQ_HIP(hipGetLastError());
+}
+
+}  // namespace rbq

@@ -1,0 +1,98 @@
+// Kernel launchers of librbq (host-callable; every kernel is in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rbq {
+
+constexpr int MB = 64;            // vectors per micro-block (one wave64 lane each)
+constexpr int MAX_SEL = 2048;     // largest k of a selection (nprobe, rerank_n)
+
+// Device view of the lists of an index.
+struct ListsView {
+  const uint32_t* blocks;  // micro-block records: W*64 code words, 64 f_add, 64 f_mul
+  const int32_t* list_mb;  // [nlist] first micro-block of each list
+  const int32_t* list_len; // [nlist] vectors per list
+  const int32_t* pos2id;   // [nmb*64] vector id at each position, -1 for padding
+  int W;                   // 32-bit code words per vector, ceil(d/32)
+  int d;
+};
+
+// Per-(query, probe) quantised query: bit-planes [W][BQS] u32, qu bytes [W*32],
+// scalars (||r||^2, v_l, Delta, sum qu).
+struct PairsView {
+  const uint32_t* planes;
+  const float4* scal;
+  int bqs;                 // plane slots per word (bq rounded up to 4)
+};
+
+// C[m][n] = sum_k A[m][k] B[n][k] (mode 0) or bnorm[n] - 2 sum_k A B (mode 1).
+// Requires lda, ldb % 4 == 0 and 16-byte aligned rows.
+void launch_gemm_tn(hipStream_t s, int mode, const float* A, int lda, const float* B, int ldb,
+                    float* C, int ldc, int M, int N, int K, const float* bnorm);
+
+// out[m] = min_n key64(bnorm[n] - 2 <A_m, B_n>, n): nearest row of B per row of A.
+void launch_assign_argmin(hipStream_t s, const float* A, int lda, const float* B, int ldb,
+                          const float* bnorm, int M, int N, int K, uint64_t* out);
+
+// Per row: the k smallest 64-bit keys, ascending. Keys come from a float matrix
+// (tie = column) when `score` is set, else from a key matrix. Optional outputs:
+// out_keys [rows][k], out_low (low word as int32), out_val (high word as float).
+void launch_row_topk(hipStream_t s, const float* score, const uint64_t* keys, int rows,
+                     int64_t ld, int ncols, int k, uint64_t* out_keys, int32_t* out_low,
+                     float* out_val);
+
+// Residual r = qrot_i - crot_j for every (query, probe) pair, B_q-bit
+// quantisation, bit-planes and scalars; or pack injected qu / scalars.
+void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, int ldc,
+                  const int32_t* probes, int nq, int nprobe, int d, int W, int bq, int bqs,
+                  uint32_t* planes, uint8_t* qu, float4* scal, const uint8_t* inj_qu,
+                  const float* inj_scal);
+
+// Code scan with fused estimator and streaming top-R per (query, probe) item.
+struct ScanArgs {
+  ListsView L;
+  PairsView Q;
+  const int32_t* probes;   // [nq][nprobe]
+  int nq, nprobe, R;
+  uint32_t* qthr;          // [nq] ordered-float bound on each query's R-th estimate (or null)
+  uint64_t* out;           // [nq][nprobe][R] keys (est, id)
+  int32_t* dump_ip;        // debug: [nq][nprobe][maxlen] (or null)
+  float* dump_est;
+  int64_t maxlen;
+};
+void launch_scan_popc(hipStream_t s, const ScanArgs& a);
+
+// Exact re-rank: per query, gather the candidates' raw vectors, exact squared
+// L2 in FP32, top-k by (distance, id).
+void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int ldx, int d,
+                   const uint64_t* cand, int nq, int R, int k, int64_t* ids, float* dist);
+
+// RaBitQ encoder (FP64): one launch encodes micro-blocks [mb_begin, mb_end).
+void launch_encode(hipStream_t s, const float* X, int ldx, const float* C, int ldc,
+                   const float* Pt, int ldp, const int32_t* pos2id, const int32_t* mb_list,
+                   int64_t mb_begin, int64_t mb_end, int d, int W, uint32_t* blocks,
+                   float* nx_out, float* alpha_out);
+
+// out[r][i] = sum_d A[r][d] P[d][i] in FP64, rounded to FP32 (Pt = P^T rows);
+// also nrm[r] = ||A_r||^2 (FP64 -> FP32) if nrm is set.
+void launch_rotate_rows_f64(hipStream_t s, const float* A, int lda, const float* Pt, int ldp,
+                            int rows, int d, float* out, int ldo, float* nrm);
+
+void launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n);
+void launch_fill_u64(hipStream_t s, uint64_t* p, uint64_t v, int64_t n);
+void launch_gather_rows(hipStream_t s, const float* X, int ldx, const int64_t* idx, int64_t n,
+                        float* out, int ldo);
+
+// k-means++ on the device: one step adds centre j (row `pick` of T) and updates
+// the running min distances and per-block sums; the choose step samples the
+// next centre with probability proportional to the min distance.
+void launch_kpp_update(hipStream_t s, const float* T, int ldt, int64_t n, int d,
+                       const int64_t* pick, float* mind, double* blocksum, int first);
+void launch_kpp_choose(hipStream_t s, const float* mind, const double* blocksum, int64_t n,
+                       double u, int64_t* pick);
+void launch_copy_row(hipStream_t s, const float* T, int ldt, const int64_t* pick, float* dst,
+                     int d);
+
+}  // namespace rbq

@@ -1,0 +1,238 @@
+// Batched search (Sec. 3.1.2): Phase 1 probe, query rotation and B_q-bit
+// quantisation, Phase 3 code scan with the fused estimator, Phase 4 top-R,
+// Phase 5 exact re-rank.
+#include <algorithm>
+#include <array>
+#include <cstring>
+
+#include "index.hpp"
+
+namespace rbq {
+
+namespace {
+
+__global__ void k_count_scanned(const int32_t* probes, const int32_t* list_len, int64_t pairs,
+                                unsigned long long* acc) {
+  __shared__ unsigned long long part[256];
+  unsigned long long s = 0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < pairs; t += (int64_t)gridDim.x * 256)
+    s += (unsigned long long)list_len[probes[t]];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(acc, part[0]);
+}
+
+struct Bufs {
+  float* qpad = nullptr;
+  float* score = nullptr;
+  int32_t* probes = nullptr;
+  float* pscore = nullptr;
+  float* qrot = nullptr;
+  uint32_t* planes = nullptr;
+  uint8_t* qu = nullptr;
+  float4* scal = nullptr;
+  uint8_t* inj_qu = nullptr;
+  float* inj_scal = nullptr;
+  uint32_t* qthr = nullptr;
+  uint64_t* cand = nullptr;
+  uint64_t* merged = nullptr;
+  int32_t* dump_ip = nullptr;
+  float* dump_est = nullptr;
+  int64_t* ids = nullptr;
+  float* dist = nullptr;
+};
+
+}  // namespace
+
+}  // namespace rbq
+
+namespace rbq {
+
+void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
+            float* dist, hipStream_t s, const SearchIO& io) {
+  if (nq == 0) return;
+  RBQ_HIP(hipSetDevice(idx->device));
+  const int d = idx->d, ld = idx->ld, nlist = idx->nlist, W = idx->W, bqs = idx->bqs;
+  const rbq_debug_io* dbg = io.dbg;
+  const bool qdev = is_device_ptr(q);
+  const bool need_qcopy = !qdev || ld != d || (reinterpret_cast<uintptr_t>(q) & 15);
+  const bool ids_dev = ids && is_device_ptr(ids);
+  const bool dist_dev = dist && is_device_ptr(dist);
+  const int64_t pairs = nq * nprobe;
+  const bool inj_probes = dbg && dbg->inject_probes;
+  const bool inj_qu = dbg && dbg->inject_qu;
+  const bool dumps = dbg && (dbg->ip || dbg->est);
+  const int64_t maxlen = std::max<int64_t>(1, idx->max_list_len);
+  const bool timed = idx->timing.load() != 0;
+  RBQ_CHECK(!idx->vectors_on_host, "host-resident raw vectors: re-rank on host is not available in this build");
+
+  auto layout = [&](Carver& c, Bufs& b) {
+    if (need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
+    if (!inj_probes) b.score = c.take<float>((size_t)nq * nlist);
+    b.probes = c.take<int32_t>(pairs);
+    if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
+    b.qrot = c.take<float>((size_t)nq * ld);
+    b.planes = c.take<uint32_t>((size_t)pairs * W * bqs);
+    if (dbg && dbg->qu) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
+    b.scal = c.take<float4>(pairs);
+    if (inj_qu) {
+      b.inj_qu = c.take<uint8_t>((size_t)pairs * d);
+      b.inj_scal = c.take<float>((size_t)pairs * 3);
+    }
+    b.qthr = c.take<uint32_t>(nq);
+    b.cand = c.take<uint64_t>((size_t)pairs * R);
+    b.merged = nprobe > 1 ? c.take<uint64_t>((size_t)nq * R) : nullptr;
+    if (dumps) {
+      b.dump_ip = c.take<int32_t>((size_t)pairs * maxlen);
+      b.dump_est = c.take<float>((size_t)pairs * maxlen);
+    }
+    if (!ids_dev) b.ids = c.take<int64_t>((size_t)nq * k);
+    if (!dist_dev) b.dist = c.take<float>((size_t)nq * k);
+  };
+  Bufs b;
+  {
+    Carver dry(nullptr);
+    layout(dry, b);
+    b = Bufs();
+    auto ws = ws_acquire(idx, dry.off + 256);
+    Carver c(ws->base);
+    layout(c, b);
+
+    hipEvent_t ev[7] = {};
+    if (timed)
+      for (auto& e : ev) RBQ_HIP(hipEventCreate(&e));
+    auto mark = [&](int i) {
+      if (timed) RBQ_HIP(hipEventRecord(ev[i], s));
+    };
+
+    const float* qd = q;
+    if (need_qcopy) {
+      if (ld != d) RBQ_HIP(hipMemsetAsync(b.qpad, 0, (size_t)nq * ld * sizeof(float), s));
+      RBQ_HIP(hipMemcpy2DAsync(b.qpad, ld * sizeof(float), q, d * sizeof(float), d * sizeof(float),
+                               nq, hipMemcpyDefault, s));
+      qd = b.qpad;
+    }
+    mark(0);
+    // Phase 1: probe scores ||c||^2 - 2<q,c> on MFMA, then top-nprobe per query
+    if (inj_probes) {
+      for (int64_t t = 0; t < pairs; ++t)
+        RBQ_CHECK(dbg->inject_probes[t] >= 0 && dbg->inject_probes[t] < nlist, "injected probe out of range");
+      RBQ_HIP(hipMemcpyAsync(b.probes, dbg->inject_probes, pairs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    } else {
+      launch_gemm_tn(s, 1, qd, ld, idx->C.as<float>(), ld, b.score, nlist, (int)nq, nlist, ld,
+                     idx->cnorm.as<float>());
+      launch_row_topk(s, b.score, nullptr, (int)nq, nlist, nlist, nprobe, nullptr, b.probes, b.pscore);
+    }
+    mark(1);
+    // query rotation q' = P^T q (row form q P) on MFMA
+    launch_gemm_tn(s, 0, qd, ld, idx->Pt.as<float>(), ld, b.qrot, ld, (int)nq, d, ld, nullptr);
+    mark(2);
+    // residual quantisation per (query, probe)
+    if (inj_qu) {
+      RBQ_HIP(hipMemcpyAsync(b.inj_qu, dbg->inject_qu, (size_t)pairs * d, hipMemcpyHostToDevice, s));
+      RBQ_CHECK(dbg->inject_scalars != nullptr, "inject_qu needs inject_scalars");
+      RBQ_HIP(hipMemcpyAsync(b.inj_scal, dbg->inject_scalars, (size_t)pairs * 3 * sizeof(float),
+                             hipMemcpyHostToDevice, s));
+    }
+    launch_fill_u32(s, b.qthr, 0xFFFFFFFFu, nq);
+    if (dumps) {
+      RBQ_HIP(hipMemsetAsync(b.dump_ip, 0, (size_t)pairs * maxlen * sizeof(int32_t), s));
+      RBQ_HIP(hipMemsetAsync(b.dump_est, 0, (size_t)pairs * maxlen * sizeof(float), s));
+    }
+    launch_quant(s, b.qrot, ld, idx->Crot.as<float>(), ld, b.probes, (int)nq, nprobe, d, W, idx->bq,
+                 bqs, b.planes, b.qu, b.scal, b.inj_qu, b.inj_scal);
+    mark(3);
+    // Phase 3 + local part of Phase 4: code scan, estimator, per-item top-R
+    ScanArgs sa;
+    sa.L = ListsView{idx->blocks.as<uint32_t>(), idx->list_mb.as<int32_t>(), idx->list_len.as<int32_t>(),
+                     idx->pos2id.as<int32_t>(), W, d};
+    sa.Q = PairsView{b.planes, b.scal, bqs};
+    sa.probes = b.probes;
+    sa.nq = (int)nq;
+    sa.nprobe = nprobe;
+    sa.R = R;
+    sa.qthr = b.qthr;
+    sa.out = b.cand;
+    sa.dump_ip = b.dump_ip;
+    sa.dump_est = b.dump_est;
+    sa.maxlen = maxlen;
+    launch_scan_popc(s, sa);
+    mark(4);
+    // Phase 4: per-query merge of the items' top-R
+    const uint64_t* top = b.cand;
+    if (nprobe > 1) {
+      launch_row_topk(s, nullptr, b.cand, (int)nq, (int64_t)nprobe * R, nprobe * R, R, b.merged,
+                      nullptr, nullptr);
+      top = b.merged;
+    }
+    mark(5);
+    // Phase 5: exact re-rank of the top-R on the GPU
+    int64_t* ids_out = ids_dev ? ids : b.ids;
+    float* dist_out = dist_dev ? dist : b.dist;
+    launch_rerank(s, qd, ld, idx->X.as<float>(), ld, d, top, (int)nq, R, k, ids_out, dist_out);
+    mark(6);
+    if (timed) {
+      hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
+                         idx->list_len.as<int32_t>(), pairs,
+                         idx->tcounter.as<unsigned long long>());
+      RBQ_HIP(hipGetLastError());
+    }
+
+    // host-side outputs
+    if (ids && !ids_dev)
+      RBQ_HIP(hipMemcpyAsync(ids, b.ids, (size_t)nq * k * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (dist && !dist_dev)
+      RBQ_HIP(hipMemcpyAsync(dist, b.dist, (size_t)nq * k * sizeof(float), hipMemcpyDeviceToHost, s));
+    std::vector<uint64_t> hm;
+    if (dbg) {
+      if (dbg->probes)
+        RBQ_HIP(hipMemcpyAsync(dbg->probes, b.probes, pairs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      if (dbg->probe_score && b.pscore)
+        RBQ_HIP(hipMemcpyAsync(dbg->probe_score, b.pscore, pairs * sizeof(float), hipMemcpyDeviceToHost, s));
+      if (dbg->qrot)
+        RBQ_HIP(hipMemcpy2DAsync(dbg->qrot, d * sizeof(float), b.qrot, ld * sizeof(float),
+                                 d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
+      if (dbg->qu)
+        RBQ_HIP(hipMemcpy2DAsync(dbg->qu, d, b.qu, W * 32, d, pairs, hipMemcpyDeviceToHost, s));
+      if (dbg->scalars)
+        RBQ_HIP(hipMemcpyAsync(dbg->scalars, b.scal, pairs * sizeof(float4), hipMemcpyDeviceToHost, s));
+      if (dbg->ip)
+        RBQ_HIP(hipMemcpyAsync(dbg->ip, b.dump_ip, (size_t)pairs * maxlen * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+      if (dbg->est)
+        RBQ_HIP(hipMemcpyAsync(dbg->est, b.dump_est, (size_t)pairs * maxlen * sizeof(float),
+                               hipMemcpyDeviceToHost, s));
+      if (dbg->cand_ids || dbg->cand_est) {
+        hm.resize((size_t)nq * R);
+        RBQ_HIP(hipMemcpyAsync(hm.data(), top, hm.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+      }
+      if (dbg->ids)
+        RBQ_HIP(hipMemcpyAsync(dbg->ids, ids_out, (size_t)nq * k * sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+      if (dbg->sqdist)
+        RBQ_HIP(hipMemcpyAsync(dbg->sqdist, dist_out, (size_t)nq * k * sizeof(float), hipMemcpyDeviceToHost, s));
+    }
+    ws_release(idx, std::move(ws), s);
+    if (timed) {
+      std::lock_guard<std::mutex> g(idx->timing_mu);
+      std::array<hipEvent_t, 7> a;
+      for (int i = 0; i < 7; ++i) a[i] = ev[i];
+      idx->pending.push_back(a);
+    }
+    const bool host_out = (ids && !ids_dev) || (dist && !dist_dev) || dbg;
+    if (host_out) RBQ_HIP(hipStreamSynchronize(s));
+    if (dbg && !hm.empty()) {
+      for (size_t t = 0; t < hm.size(); ++t) {
+        const uint64_t v = hm[t];
+        if (dbg->cand_ids) dbg->cand_ids[t] = v == KEY_NONE ? -1 : (int64_t)(uint32_t)v;
+        if (dbg->cand_est) dbg->cand_est[t] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
+      }
+    }
+  }
+}
+
+}  // namespace rbq

@@ -1,0 +1,276 @@
+"""Python binding of librbq (ctypes). Argument marshalling only: every step of
+index construction and search runs in the library's HIP kernels.
+
+Arrays may be NumPy (host) or torch tensors (host or GPU); torch is used for
+device memory and streams only. The library must be built
+(``python -m paper_2605_16007_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbq.so")
+
+RBQ_OK, RBQ_EINVAL, RBQ_ENOMEM, RBQ_EDEVICE, RBQ_ESTATE, RBQ_EAGAIN = 0, -1, -2, -3, -4, -5
+EXPORT = {"centroids": 1, "rotation": 2, "assign": 3, "codes": 4, "factors": 5, "list_sizes": 6}
+
+# every symbol declared in include/rbq.h
+SYMBOLS = [
+    "rbq_build_params_init", "rbq_build_index", "rbq_free_index", "rbq_get_info", "rbq_search",
+    "rbq_export", "rbq_search_debug", "rbq_set_timing", "rbq_get_timings", "rbq_save",
+    "rbq_load", "rbq_last_error", "rbq_version",
+]
+
+
+class BuildParams(C.Structure):
+    _fields_ = [("nlist", C.c_int32), ("bq", C.c_int32), ("seed", C.c_uint64),
+                ("kmeans_iters", C.c_int32), ("kmeans_restarts", C.c_int32),
+                ("train_n", C.c_int64), ("rotation", C.c_void_p), ("centroids", C.c_void_p),
+                ("assignment", C.c_void_p), ("vectors_on_host", C.c_int32),
+                ("host_threads", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class IndexInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("nlist", C.c_int32), ("bq", C.c_int32),
+                ("vectors_on_host", C.c_int32), ("max_list_len", C.c_int64),
+                ("device_bytes", C.c_int64), ("code_bytes", C.c_int64)]
+
+
+class DebugIO(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "inject_probes", "inject_qu", "inject_scalars", "probes", "probe_score", "qrot", "qu",
+        "scalars", "ip", "est", "cand_ids", "cand_est", "ids", "sqdist")]
+
+
+class Timings(C.Structure):
+    _fields_ = [("searches", C.c_int64), ("probe_ms", C.c_float), ("rotate_ms", C.c_float),
+                ("quant_ms", C.c_float), ("scan_ms", C.c_float), ("merge_ms", C.c_float),
+                ("rerank_ms", C.c_float), ("total_ms", C.c_float),
+                ("scanned_vectors", C.c_int64), ("scan_bytes", C.c_int64)]
+
+
+class RbqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"librbq status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2605_16007_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.rbq_build_params_init.argtypes = [C.POINTER(BuildParams)]
+        L.rbq_build_params_init.restype = None
+        L.rbq_build_index.argtypes = [vp, i64, i32, C.POINTER(BuildParams), C.POINTER(vp)]
+        L.rbq_free_index.argtypes = [vp]
+        L.rbq_get_info.argtypes = [vp, C.POINTER(IndexInfo)]
+        L.rbq_search.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp]
+        L.rbq_export.argtypes = [vp, i32, vp, C.c_size_t]
+        L.rbq_search_debug.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(DebugIO)]
+        L.rbq_set_timing.argtypes = [vp, i32]
+        L.rbq_get_timings.argtypes = [vp, C.POINTER(Timings)]
+        L.rbq_save.argtypes = [vp, C.c_char_p]
+        L.rbq_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+        L.rbq_last_error.restype = C.c_char_p
+        L.rbq_last_error.argtypes = []
+        L.rbq_version.restype = C.c_char_p
+        L.rbq_version.argtypes = []
+        for name in SYMBOLS:
+            if name not in ("rbq_build_params_init", "rbq_last_error", "rbq_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != RBQ_OK:
+        raise RbqError(status, lib().rbq_last_error().decode())
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    """Address of a contiguous NumPy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if _is_torch(a):
+        assert a.is_contiguous(), "tensor must be contiguous"
+        return a.data_ptr()
+    assert isinstance(a, np.ndarray) and a.flags.c_contiguous, "array must be C-contiguous"
+    return a.ctypes.data
+
+
+def _stream_of(t, stream):
+    if stream is not None:
+        return stream
+    if _is_torch(t) and t.is_cuda:
+        import torch
+        return torch.cuda.current_stream(t.device).cuda_stream
+    return None
+
+
+class Index:
+    """An IVF-RaBitQ index held by librbq on the current GPU."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+
+    # ---------------------------------------------------------------- build
+    @classmethod
+    def build(cls, x, nlist, *, bq=4, seed=0, kmeans_iters=25, kmeans_restarts=3, train_n=0,
+              rotation=None, centroids=None, assignment=None, vectors_on_host=False,
+              host_threads=0):
+        if _is_torch(x):
+            assert str(x.dtype) == "torch.float32"
+        else:
+            x = np.ascontiguousarray(x, np.float32)
+        n, d = x.shape
+        p = BuildParams()
+        lib().rbq_build_params_init(C.byref(p))
+        p.nlist, p.bq, p.seed = int(nlist), int(bq), int(seed)
+        p.kmeans_iters, p.kmeans_restarts, p.train_n = int(kmeans_iters), int(kmeans_restarts), int(train_n)
+        keep = []
+        if rotation is not None:
+            rotation = np.ascontiguousarray(rotation, np.float32)
+            keep.append(rotation)
+            p.rotation = rotation.ctypes.data
+        if centroids is not None:
+            centroids = np.ascontiguousarray(centroids, np.float32)
+            keep.append(centroids)
+            p.centroids = centroids.ctypes.data
+        if assignment is not None:
+            assignment = np.ascontiguousarray(assignment, np.int32)
+            keep.append(assignment)
+            p.assignment = assignment.ctypes.data
+        p.vectors_on_host = int(bool(vectors_on_host))
+        p.host_threads = int(host_threads)
+        h = C.c_void_p()
+        _check(lib().rbq_build_index(_ptr(x), n, d, C.byref(p), C.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        _check(lib().rbq_load(os.fsencode(path), C.byref(h)))
+        return cls(h.value)
+
+    def save(self, path):
+        _check(lib().rbq_save(self._h, os.fsencode(path)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().rbq_free_index(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- info / export
+    def info(self) -> dict:
+        i = IndexInfo()
+        _check(lib().rbq_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in IndexInfo._fields_}
+
+    def export(self, what: str) -> np.ndarray:
+        inf = self.info()
+        n, d, nlist = inf["n"], inf["d"], inf["nlist"]
+        shape, dt = {
+            "centroids": ((nlist, d), np.float32), "rotation": ((d, d), np.float32),
+            "assign": ((n,), np.int32), "codes": ((n, (d + 7) // 8), np.uint8),
+            "factors": ((n, 2), np.float32), "list_sizes": ((nlist,), np.int64),
+        }[what]
+        out = np.empty(shape, dt)
+        _check(lib().rbq_export(self._h, EXPORT[what], out.ctypes.data, out.nbytes))
+        return out
+
+    # ---------------------------------------------------------------- search
+    def search(self, q, nprobe, k, rerank_n, ids=None, dists=None, stream=None):
+        """Top-k (ids int64, squared distances float32) per query. With a GPU
+        tensor ``q`` the outputs are GPU tensors on the caller's stream."""
+        if _is_torch(q):
+            import torch
+            nq = q.shape[0]
+            if ids is None:
+                ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
+            if dists is None:
+                dists = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        else:
+            q = np.ascontiguousarray(q, np.float32)
+            nq = q.shape[0]
+            if ids is None:
+                ids = np.empty((nq, k), np.int64)
+            if dists is None:
+                dists = np.empty((nq, k), np.float32)
+        s = _stream_of(q, stream)
+        _check(lib().rbq_search(self._h, _ptr(q), nq, int(nprobe), int(k), int(rerank_n),
+                                _ptr(ids), _ptr(dists), s))
+        return ids, dists
+
+    def search_debug(self, q, nprobe, k, rerank_n, *, inject_probes=None, inject_qu=None,
+                     inject_scalars=None):
+        """Stage-by-stage search (host arrays). Returns a dict of every stage's
+        output; see rbq_search_debug in include/rbq.h for the layouts."""
+        q = np.ascontiguousarray(q, np.float32)
+        nq, d = q.shape
+        maxlen = max(1, self.info()["max_list_len"])
+        pairs = nq * nprobe
+        out = {
+            "probes": np.zeros((nq, nprobe), np.int32),
+            "probe_score": np.zeros((nq, nprobe), np.float32),
+            "qrot": np.zeros((nq, d), np.float32),
+            "qu": np.zeros((nq, nprobe, d), np.uint8),
+            "scalars": np.zeros((nq, nprobe, 4), np.float32),
+            "ip": np.zeros((nq, nprobe, maxlen), np.int32),
+            "est": np.zeros((nq, nprobe, maxlen), np.float32),
+            "cand_ids": np.zeros((nq, rerank_n), np.int64),
+            "cand_est": np.zeros((nq, rerank_n), np.float32),
+            "ids": np.zeros((nq, k), np.int64),
+            "sqdist": np.zeros((nq, k), np.float32),
+        }
+        io = DebugIO()
+        keep = []
+        if inject_probes is not None:
+            a = np.ascontiguousarray(inject_probes, np.int32).reshape(pairs)
+            keep.append(a)
+            io.inject_probes = a.ctypes.data
+            del out["probe_score"]
+        if inject_qu is not None:
+            a = np.ascontiguousarray(inject_qu, np.uint8).reshape(pairs * d)
+            b = np.ascontiguousarray(inject_scalars, np.float32).reshape(pairs * 3)
+            keep += [a, b]
+            io.inject_qu, io.inject_scalars = a.ctypes.data, b.ctypes.data
+        for key, arr in out.items():
+            setattr(io, key, arr.ctypes.data)
+        _check(lib().rbq_search_debug(self._h, q.ctypes.data, nq, int(nprobe), int(k),
+                                      int(rerank_n), C.byref(io)))
+        return out
+
+    # ---------------------------------------------------------------- timing
+    def set_timing(self, enabled: bool):
+        _check(lib().rbq_set_timing(self._h, int(bool(enabled))))
+
+    def timings(self) -> dict:
+        t = Timings()
+        _check(lib().rbq_get_timings(self._h, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in Timings._fields_}
+
+
+def version() -> str:
+    return lib().rbq_version().decode()

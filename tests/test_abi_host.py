@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/rbq.h declares, and rejects bad arguments with RBQ_EINVAL before
+touching a GPU (so these run on a machine without one)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_16007_amd import rbq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rbq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbq_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(rbq.SYMBOLS)
+
+
+def test_library_exports_every_symbol():
+    L = rbq.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert "gfx950" in rbq.version()
+
+
+def _params(**kw):
+    p = rbq.BuildParams()
+    rbq.lib().rbq_build_params_init(C.byref(p))
+    p.nlist = 4
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_params_defaults():
+    p = _params()
+    assert p.bq == 4 and p.kmeans_iters == 25 and p.kmeans_restarts == 3 and p.train_n == 0
+
+
+@pytest.mark.parametrize("n,d,kw,msg", [
+    (0, 8, {}, "n must"),
+    (10, 0, {}, "d must"),
+    (10, 8, {"nlist": 11}, "nlist"),
+    (10, 8, {"nlist": 0}, "nlist"),
+    (10, 8, {"bq": 0}, "bq"),
+    (10, 8, {"bq": 9}, "bq"),
+    (10, 8, {"vectors_on_host": 2}, "vectors_on_host"),
+])
+def test_build_rejects_bad_arguments(n, d, kw, msg):
+    L = rbq.lib()
+    x = np.zeros((max(n, 1), max(d, 1)), np.float32)
+    p = _params(**kw)
+    h = C.c_void_p()
+    st = L.rbq_build_index(x.ctypes.data, n, d, C.byref(p), C.byref(h))
+    assert st == rbq.RBQ_EINVAL
+    assert msg in L.rbq_last_error().decode()
+    assert not h.value
+
+
+def test_build_rejects_nonzero_reserved():
+    L = rbq.lib()
+    x = np.zeros((10, 8), np.float32)
+    p = _params()
+    p.reserved[3] = 1
+    h = C.c_void_p()
+    assert L.rbq_build_index(x.ctypes.data, 10, 8, C.byref(p), C.byref(h)) == rbq.RBQ_EINVAL
+
+
+def test_null_arguments():
+    L = rbq.lib()
+    x = np.zeros((10, 8), np.float32)
+    p = _params()
+    h = C.c_void_p()
+    assert L.rbq_build_index(None, 10, 8, C.byref(p), C.byref(h)) == rbq.RBQ_EINVAL
+    assert L.rbq_build_index(x.ctypes.data, 10, 8, None, C.byref(h)) == rbq.RBQ_EINVAL
+    assert L.rbq_build_index(x.ctypes.data, 10, 8, C.byref(p), None) == rbq.RBQ_EINVAL
+    ids = np.zeros(10, np.int64)
+    dist = np.zeros(10, np.float32)
+    assert L.rbq_search(None, x.ctypes.data, 1, 1, 1, 1, ids.ctypes.data, dist.ctypes.data, None) == rbq.RBQ_EINVAL
+    assert "index is NULL" in L.rbq_last_error().decode()
+    assert L.rbq_free_index(None) == rbq.RBQ_EINVAL
+    assert L.rbq_export(None, 1, x.ctypes.data, 4) == rbq.RBQ_EINVAL
+    assert L.rbq_set_timing(None, 1) == rbq.RBQ_EINVAL
+    t = rbq.Timings()
+    assert L.rbq_get_timings(None, C.byref(t)) == rbq.RBQ_EINVAL
+    assert L.rbq_save(None, b"/tmp/x") == rbq.RBQ_EINVAL
+    assert L.rbq_load(None, C.byref(h)) == rbq.RBQ_EINVAL
+    info = rbq.IndexInfo()
+    assert L.rbq_get_info(None, C.byref(info)) == rbq.RBQ_EINVAL
+
+
+def test_struct_sizes_match_header_layout():
+    # natural C layout of the public structs (x86-64 / LP64)
+    assert C.sizeof(rbq.BuildParams) == 4 + 4 + 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4 + 6 * 4
+    assert C.sizeof(rbq.DebugIO) == 14 * 8
+    assert C.sizeof(rbq.Timings) == 8 + 7 * 4 + 4 + 2 * 8
+    assert C.sizeof(rbq.IndexInfo) == 8 + 4 * 4 + 3 * 8
