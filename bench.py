@@ -1,0 +1,327 @@
+#!/usr/bin/env python3
+"""Benchmark of batched IVF-RaBitQ search on one MI355X.
+
+Workload (default ``sift10m``): 10M x 128 integer-valued skewed vectors,
+nlist 4096, batches of 1024 queries, B_q 4, k 10, rerank 100. A step is one
+pass of the whole search path over one batch: probe GEMM + top-nprobe, query
+rotation, residual quantisation, code scan with the fused estimator, per-query
+top-R, exact re-rank. nprobe is the smallest of the workload's values (32, 64,
+128) whose recall@10 reaches 0.95 (measured against exact kNN before timing).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QPS at recall@10>=0.95 (1 GPU), code-scan HBM GB/s vs peak, p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------- CPU baseline
+
+_CPU_STATE = {}
+
+
+def _oracle_chunk(task):
+    """Worker: the oracle's search of one chunk of queries (one BLAS thread)."""
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    i, nprobe, k, R = task
+    st = _CPU_STATE
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        O.search(st["idx"], st["X"], st["Q"][st["chunks"][i]], nprobe, k, R)
+        return time.perf_counter() - t
+
+
+class CpuBaseline:
+    """The oracle as it stands, on the host cores, over a bounded sample.
+
+    Sample: the first ``nqueries`` queries of the batch, searched by the oracle
+    on an oracle-built index over the first 1M database rows with nlist scaled
+    so that lists hold as many vectors as in the full workload (N / nlist);
+    each query therefore probes and scans the same number of vectors as on the
+    full index. Index construction is not timed. The worker processes are
+    forked here, before the GPU is used, and run the sample later at the
+    operating point the GPU run settles on.
+    """
+
+    def __init__(self, w, Q, nqueries, cores):
+        import multiprocessing as mp
+        import oracle as O
+        from synth import database
+        self.w, self.nqueries, self.cores = w, nqueries, cores
+        self.n_sub = min(w.n, 1_000_000)
+        self.nlist_sub = max(1, int(round(w.nlist * self.n_sub / w.n)))
+        t = time.perf_counter()
+        Xs = database(w, 0, self.n_sub)
+        rng = np.random.default_rng(0)
+        C = O.kmeans(Xs, self.nlist_sub, rng, iters=3, restarts=1, train_n=64 * self.nlist_sub)
+        idx = O.build(Xs, self.nlist_sub, bq=w.bq, centroids=C, rng=rng)
+        log(f"[cpu_baseline] oracle index over {self.n_sub} rows, nlist {self.nlist_sub}: "
+            f"{time.perf_counter() - t:.1f}s")
+        self.chunks = np.array_split(np.arange(nqueries), cores)
+        _CPU_STATE.update(idx=idx, X=Xs, Q=Q[:nqueries], chunks=self.chunks)
+        self.pool = mp.get_context("fork").Pool(cores)
+
+    def run(self, nprobe, k, R):
+        # the sub-index has nlist_sub lists: beyond that, time nprobe = nlist_sub
+        # and scale by the number of vectors scanned per query (extrapolated)
+        npc = min(nprobe, self.nlist_sub)
+        scale = npc / nprobe
+        t = time.perf_counter()
+        per = self.pool.map(_oracle_chunk, [(i, npc, k, R) for i in range(len(self.chunks))])
+        wall = time.perf_counter() - t
+        one_core = len(self.chunks[0]) / per[0] * scale if per[0] > 0 else None
+        w = self.w
+        value = self.nqueries / wall * scale
+        log(f"[cpu_baseline] nprobe {npc} rerank {R}: {self.nqueries / wall:.1f} q/s on "
+            f"{self.cores} cores; reported {value:.2f} q/s at nprobe {nprobe}")
+        extra = "" if scale == 1 else (
+            f"; timed at nprobe {npc} (every list of the sub-index) and scaled by {scale:.4f} "
+            f"to nprobe {nprobe} in proportion to vectors scanned (extrapolated)")
+        return {
+            "value": value, "unit": "queries/s", "cores": self.cores, "kind": "oracle",
+            "sample": (f"first {self.nqueries} queries of the batch; oracle index over the first "
+                       f"{self.n_sub} rows with nlist {self.nlist_sub} (same {w.n // w.nlist} "
+                       f"vectors per list on average as the full workload; centroids from 3 "
+                       f"Lloyd iterations), nprobe {nprobe}, k {k}, rerank {R}; FP64 NumPy, one "
+                       f"BLAS thread per worker process; index construction not timed{extra}"),
+            "extrapolated": scale != 1, "one_core_qps": one_core, "wall_s": wall,
+        }
+
+    def close(self):
+        self.pool.close()
+        self.pool.join()
+
+
+# ----------------------------------------------------------------- ground truth
+
+def exact_knn_gpu(Xt, Qt, X_host, Q_host, k, shortlist=64, chunk=1 << 20):
+    """Exact kNN for recall: FP32 GEMM shortlist on the GPU with plain torch
+    ops, then FP64 re-ranking of the shortlist on the host."""
+    import torch
+    nq = Qt.shape[0]
+    qn = (Qt * Qt).sum(1, keepdim=True)
+    best_v = torch.full((nq, 0), float("inf"), device=Qt.device)
+    best_i = torch.zeros((nq, 0), dtype=torch.int64, device=Qt.device)
+    for s in range(0, Xt.shape[0], chunk):
+        xb = Xt[s:s + chunk]
+        d = qn - 2.0 * (Qt @ xb.T) + (xb * xb).sum(1)[None, :]
+        v, i = torch.topk(d, min(shortlist, xb.shape[0]), dim=1, largest=False)
+        best_v = torch.cat([best_v, v], 1)
+        best_i = torch.cat([best_i, i + s], 1)
+        v, o = torch.topk(best_v, min(shortlist, best_v.shape[1]), dim=1, largest=False)
+        best_v, best_i = v, torch.gather(best_i, 1, o)
+    cand = best_i.cpu().numpy()
+    gt = np.empty((nq, k), np.int64)
+    for q in range(nq):
+        c = cand[q]
+        dd = np.sum((X_host[c].astype(np.float64) - Q_host[q].astype(np.float64)) ** 2, axis=1)
+        o = np.lexsort((c, dd))[:k]
+        gt[q] = c[o]
+    return gt
+
+
+def recall(ids, gt):
+    k = gt.shape[1]
+    return float(np.mean([len(set(a[:k]) & set(b)) / k for a, b in zip(ids.tolist(), gt.tolist())]))
+
+
+# ----------------------------------------------------------------- main
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sift10m")
+    ap.add_argument("--nprobe", type=int, default=0,
+                    help="fix nprobe (default: smallest workload value reaching recall@10 >= 0.95)")
+    ap.add_argument("--n", type=int, default=0, help="database rows (default: the workload's)")
+    ap.add_argument("--batches", type=int, default=4, help="distinct query batches cycled")
+    ap.add_argument("--latency-iters", type=int, default=50)
+    ap.add_argument("--cpu-queries", type=int, default=128)
+    ap.add_argument("--cpu-cores", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures the search path on one GPU only; this build runs no "
+              "multi-GPU configuration (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from synth import get, database, queries
+    w = get(args.workload)
+    if args.n:
+        w = w.with_(n=args.n, nlist=max(1, int(round(w.nlist * args.n / w.n))))
+    nb = args.batches
+    t = time.perf_counter()
+    X = database(w)
+    Qall = queries(w, w.nq * nb)
+    log(f"[data] {w.name}: {w.n} x {w.d} + {nb} x {w.nq} queries in {time.perf_counter() - t:.1f}s")
+
+    cpu_pool = None
+    if not args.no_cpu_baseline:
+        # forked before the GPU is touched
+        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+        cpu_pool = CpuBaseline(w, Qall[:w.nq], args.cpu_queries, cores)
+
+    import torch
+    from paper_2605_16007_amd import Index
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = time.perf_counter()
+    idx = Index.build(X, w.nlist, bq=w.bq, seed=w.seed)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    info = idx.info()
+    log(f"[build] {build_s:.1f}s, max list {info['max_list_len']}, codes {info['code_bytes'] / 1e6:.1f} MB")
+
+    Qb = [torch.from_numpy(Qall[i * w.nq:(i + 1) * w.nq]).to(dev) for i in range(nb)]
+    Xt = torch.from_numpy(X).to(dev)
+    gt = exact_knn_gpu(Xt, Qb[0], X, Qall[:w.nq], w.k)
+    del Xt
+    torch.cuda.empty_cache()
+
+    # Operating point: the listed (nprobe, rerank_n) first; if none reaches
+    # recall@10 >= 0.95, wider probes and longer re-rank lists are tried, and
+    # the fastest point that reaches it is timed.
+    assign = idx.export("assign")
+    gt_lists = assign[gt]
+
+    def probe_recall(npb):
+        pr = idx.search_debug(Qall[:w.nq], npb, w.k, w.rerank_n, want={"probes"})["probes"]
+        return float(np.mean([np.isin(gl, p).mean() for gl, p in zip(gt_lists, pr)]))
+
+    def eval_point(npb, R):
+        ids, _ = idx.search(Qb[0], npb, w.k, R)
+        torch.cuda.synchronize()
+        return recall(ids.cpu().numpy(), gt)
+
+    def quick_qps(npb, R, steps=8):
+        ids_ = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
+        dd_ = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
+        idx.search(Qb[0], npb, w.k, R, ids=ids_, dists=dd_)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s in range(steps):
+            idx.search(Qb[s % nb], npb, w.k, R, ids=ids_, dists=dd_)
+        torch.cuda.synchronize()
+        return w.nq * steps / (time.perf_counter() - t)
+
+    rec, prec = {}, {}
+    points = [(p, w.rerank_n) for p in ((args.nprobe,) if args.nprobe else w.nprobe)]
+    for pt in points:
+        rec[pt] = eval_point(*pt)
+        prec[pt[0]] = probe_recall(pt[0])
+        log(f"[recall] nprobe {pt[0]} rerank {pt[1]}: recall@{w.k} = {rec[pt]:.4f} "
+            f"(probe recall {prec[pt[0]]:.4f})")
+    ok = [pt for pt in points if rec[pt] >= 0.95]
+    if not ok and not args.nprobe:
+        top = min(w.nlist, 2048)
+        wider = [p for p in (256, 512, 1024, 2048) if max(w.nprobe) < p <= top]
+        for npb in wider:
+            prec[npb] = probe_recall(npb)
+            for R in sorted({w.rerank_n, 2 * w.rerank_n, 5 * w.rerank_n, 10 * w.rerank_n}):
+                R = min(R, 2048)
+                pt = (npb, R)
+                rec[pt] = eval_point(*pt)
+                log(f"[recall] nprobe {npb} rerank {R}: recall@{w.k} = {rec[pt]:.4f} "
+                    f"(probe recall {prec[npb]:.4f})")
+                if rec[pt] >= 0.95:
+                    ok.append(pt)
+                    break
+    if ok:
+        qq = {pt: quick_qps(*pt) for pt in ok}
+        nprobe, R = max(ok, key=lambda pt: qq[pt])
+        log("[choose] " + ", ".join(f"{pt}: {q:.0f} q/s" for pt, q in qq.items()))
+    else:
+        nprobe, R = max(rec, key=lambda pt: rec[pt])
+        log(f"[choose] no point reached recall 0.95; timing the best one {(nprobe, R)}")
+    listed_qps = {f"{p}": quick_qps(p, w.rerank_n) for p in w.nprobe} if not args.nprobe else {}
+
+    ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
+    dd = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
+    for s in range(args.warmup):
+        idx.search(Qb[s % nb], nprobe, w.k, R, ids=ids, dists=dd)
+    torch.cuda.synchronize()
+    idx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        idx.search(Qb[s % nb], nprobe, w.k, R, ids=ids, dists=dd)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = idx.timings()
+    idx.set_timing(False)
+    ms_step = elapsed * 1e3 / args.steps
+    qps = w.nq * args.steps / elapsed
+
+    # latency per batch (one synchronised batch at a time)
+    lat = []
+    for s in range(args.latency_iters):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        idx.search(Qb[s % nb], nprobe, w.k, R, ids=ids, dists=dd)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    cpu = cpu_pool.run(nprobe, w.k, R) if cpu_pool else None
+    if cpu_pool:
+        cpu_pool.close()
+
+    ns = max(1, tm["searches"])
+    scan_ms = tm["scan_ms"] / ns
+    scan_bytes = tm["scan_bytes"] / ns
+    achieved = scan_bytes / (scan_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 popcount + fp32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,
+                   "batch": w.nq, "k": w.k, "rerank_n": R, "bq": w.bq,
+                   "parallelism": "none (1 GPU)"},
+        "recall_at_10": rec[(nprobe, R)],
+        "recall_by_point": {f"nprobe={p},rerank={r}": v for (p, r), v in rec.items()},
+        "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
+        "qps_at_listed_nprobe": listed_qps,
+        "p50_ms": p50,
+        "p99_ms": p99,
+        "stage_ms": {s: tm[f"{s}_ms"] / ns for s in
+                     ("probe", "rotate", "quant", "scan", "merge", "rerank", "total")},
+        "roofline": {"kernel": "k_scan_popc", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "bytes_per_launch": scan_bytes, "avg_launch_ms": scan_ms},
+        "cpu_baseline": cpu,
+        "build_s": build_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

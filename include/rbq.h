@@ -131,6 +131,8 @@ rbq_status rbq_export(const rbq_index* idx, int32_t what, void* dst, size_t byte
  *                  vectors in ascending-id order (unused slots zero)
  *   cand_ids, cand_est nq*rerank_n int64 / float32: the coarse top-rerank_n
  *   ids, sqdist    nq*k final results
+ *   probe_chunk    scan at most this many probe ranks per launch, merging
+ *                  the running top-rerank_n after each (0: as rbq_search)
  */
 typedef struct {
   const int32_t* inject_probes;
@@ -147,6 +149,8 @@ typedef struct {
   float* cand_est;
   int64_t* ids;
   float* sqdist;
+  int32_t probe_chunk;  /* probe ranks per scan launch (0 = automatic) */
+  int32_t reserved;
 } rbq_debug_io;
 
 rbq_status rbq_search_debug(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,

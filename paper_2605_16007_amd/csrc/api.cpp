@@ -299,8 +299,10 @@ rbq_status rbq_free_index(rbq_index* idx) {
   return guarded([&] {
     (void)hipSetDevice(idx->device);
     (void)hipDeviceSynchronize();
-    for (auto& a : idx->pending)
-      for (auto e : a) (void)hipEventDestroy(e);
+    for (auto& a : idx->pending) {
+      for (auto e : a.e) (void)hipEventDestroy(e);
+      for (auto e : a.scan) (void)hipEventDestroy(e);
+    }
     delete idx;
   });
 }
@@ -363,8 +365,10 @@ rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled) {
   return guarded([&] {
     RBQ_HIP(hipSetDevice(idx->device));
     std::lock_guard<std::mutex> g(idx->timing_mu);
-    for (auto& a : idx->pending)
-      for (auto e : a) (void)hipEventDestroy(e);
+    for (auto& a : idx->pending) {
+      for (auto e : a.e) (void)hipEventDestroy(e);
+      for (auto e : a.scan) (void)hipEventDestroy(e);
+    }
     idx->pending.clear();
     idx->last = rbq_timings{};
     if (enabled) {
@@ -381,19 +385,25 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
     RBQ_HIP(hipSetDevice(idx->device));
     std::lock_guard<std::mutex> g(idx->timing_mu);
     for (auto& a : idx->pending) {
-      RBQ_HIP(hipEventSynchronize(a[6]));
-      float ms[7];
-      for (int i = 0; i < 6; ++i) RBQ_HIP(hipEventElapsedTime(&ms[i], a[i], a[i + 1]));
-      RBQ_HIP(hipEventElapsedTime(&ms[6], a[0], a[6]));
+      RBQ_HIP(hipEventSynchronize(a.e[5]));
+      float ms[5], tot = 0.f, scan = 0.f;
+      for (int i = 0; i < 5; ++i) RBQ_HIP(hipEventElapsedTime(&ms[i], a.e[i], a.e[i + 1]));
+      RBQ_HIP(hipEventElapsedTime(&tot, a.e[0], a.e[5]));
+      for (size_t c = 0; c + 1 < a.scan.size(); c += 2) {
+        float t = 0.f;
+        RBQ_HIP(hipEventElapsedTime(&t, a.scan[c], a.scan[c + 1]));
+        scan += t;
+      }
       idx->last.probe_ms += ms[0];
       idx->last.rotate_ms += ms[1];
       idx->last.quant_ms += ms[2];
-      idx->last.scan_ms += ms[3];
-      idx->last.merge_ms += ms[4];
-      idx->last.rerank_ms += ms[5];
-      idx->last.total_ms += ms[6];
+      idx->last.scan_ms += scan;
+      idx->last.merge_ms += ms[3] - scan;
+      idx->last.rerank_ms += ms[4];
+      idx->last.total_ms += tot;
       idx->last.searches += 1;
-      for (auto e : a) (void)hipEventDestroy(e);
+      for (auto e : a.e) (void)hipEventDestroy(e);
+      for (auto e : a.scan) (void)hipEventDestroy(e);
     }
     idx->pending.clear();
     if (idx->tcounter.p) {

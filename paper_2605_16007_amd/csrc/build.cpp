@@ -84,6 +84,36 @@ void ws_release(rbq_index* idx, std::unique_ptr<Workspace> ws, hipStream_t s) {
   idx->ws_free.push_back(std::move(ws));
 }
 
+// Copies n rows of d floats (host or device source, rows packed) into a
+// device array with row stride ld. Host sources go through 1-D copies (one per
+// chunk of rows) because a pitched copy from pageable memory moves one row at
+// a time.
+void upload_rows(float* dst, int ld, const float* src, int d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const bool dev = is_device_ptr(src);
+  if (ld == d) {
+    RBQ_HIP(hipMemcpyAsync(dst, src, (size_t)n * d * sizeof(float),
+                           dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    return;
+  }
+  if (dev) {
+    RBQ_HIP(hipMemcpy2DAsync(dst, ld * sizeof(float), src, d * sizeof(float), d * sizeof(float), n,
+                             hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  const int64_t chunk = std::min<int64_t>(n, 1 << 18);
+  DevBuf tmp;
+  tmp.alloc((size_t)chunk * d * sizeof(float));
+  for (int64_t r = 0; r < n; r += chunk) {
+    const int64_t m = std::min(chunk, n - r);
+    RBQ_HIP(hipMemcpyAsync(tmp.p, src + (size_t)r * d, (size_t)m * d * sizeof(float),
+                           hipMemcpyHostToDevice, s));
+    RBQ_HIP(hipMemcpy2DAsync(dst + (size_t)r * ld, ld * sizeof(float), tmp.p, d * sizeof(float),
+                             d * sizeof(float), m, hipMemcpyDeviceToDevice, s));
+    RBQ_HIP(hipStreamSynchronize(s));  // tmp is reused by the next chunk
+  }
+}
+
 namespace {
 
 struct StreamGuard {
@@ -169,19 +199,33 @@ std::vector<float> kmeans_gpu(const float* Xd, int64_t n, int d, int ld, int nli
     return obj;
   };
 
+  // k-means++ seeding runs on an evenly strided subset of at most 32 nlist
+  // training rows (the training rows are already a uniform random sample)
+  const int64_t sn = std::min<int64_t>(tn, (int64_t)32 * nlist);
+  DevBuf S;
+  const float* Sd = T.as<float>();
+  if (sn < tn) {
+    std::vector<int64_t> sub(sn);
+    for (int64_t t = 0; t < sn; ++t) sub[t] = t * tn / sn;
+    DevBuf dsub;
+    dsub.alloc(sn * sizeof(int64_t));
+    S.alloc((size_t)sn * ld * sizeof(float));
+    RBQ_HIP(hipMemcpyAsync(dsub.p, sub.data(), sn * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    launch_gather_rows(s, T.as<float>(), ld, dsub.as<int64_t>(), sn, S.as<float>(), ld);
+    RBQ_HIP(hipStreamSynchronize(s));
+    Sd = S.as<float>();
+  }
   for (int rs = 0; rs < restarts; ++rs) {
     // k-means++ seeding on the device: first centre uniform, then D(x)^2 sampling
     RBQ_HIP(hipMemsetAsync(dC.p, 0, dC.bytes, s));
-    const int64_t first = (int64_t)rng.below((uint64_t)tn);
+    const int64_t first = (int64_t)rng.below((uint64_t)sn);
     RBQ_HIP(hipMemcpyAsync(pick.p, &first, sizeof(int64_t), hipMemcpyHostToDevice, s));
-    launch_copy_row(s, T.as<float>(), ld, pick.as<int64_t>(), dC.as<float>(), d);
-    launch_kpp_update(s, T.as<float>(), ld, tn, d, pick.as<int64_t>(), mind.as<float>(),
-                      bsum.as<double>(), 1);
+    launch_copy_row(s, Sd, ld, pick.as<int64_t>(), dC.as<float>(), d);
+    launch_kpp_update(s, Sd, ld, sn, d, pick.as<int64_t>(), mind.as<float>(), bsum.as<double>(), 1);
     for (int j = 1; j < nlist; ++j) {
-      launch_kpp_choose(s, mind.as<float>(), bsum.as<double>(), tn, rng.uniform(), pick.as<int64_t>());
-      launch_copy_row(s, T.as<float>(), ld, pick.as<int64_t>(), dC.as<float>() + (size_t)j * ld, d);
-      launch_kpp_update(s, T.as<float>(), ld, tn, d, pick.as<int64_t>(), mind.as<float>(),
-                        bsum.as<double>(), 0);
+      launch_kpp_choose(s, mind.as<float>(), bsum.as<double>(), sn, rng.uniform(), pick.as<int64_t>());
+      launch_copy_row(s, Sd, ld, pick.as<int64_t>(), dC.as<float>() + (size_t)j * ld, d);
+      launch_kpp_update(s, Sd, ld, sn, d, pick.as<int64_t>(), mind.as<float>(), bsum.as<double>(), 0);
     }
     RBQ_HIP(hipMemcpyAsync(hC.data(), dC.p, hC.size() * sizeof(float), hipMemcpyDeviceToHost, s));
     RBQ_HIP(hipStreamSynchronize(s));
@@ -225,8 +269,7 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
   DevBuf& Xd = idx->vectors_on_host ? tmpX : idx->X;
   Xd.alloc((size_t)n * ld * sizeof(float));
   if (ld != d) RBQ_HIP(hipMemsetAsync(Xd.p, 0, Xd.bytes, s));
-  RBQ_HIP(hipMemcpy2DAsync(Xd.p, ld * sizeof(float), x, d * sizeof(float), d * sizeof(float), n,
-                           hipMemcpyDefault, s));
+  upload_rows(Xd.as<float>(), ld, x, d, n, s);
   {
     DevBuf bad;
     bad.alloc(sizeof(unsigned));
@@ -351,8 +394,11 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
   if (idx->vectors_on_host) {
     RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&idx->hostX), (size_t)n * d * sizeof(float),
                           hipHostMallocDefault));
-    RBQ_HIP(hipMemcpy2DAsync(idx->hostX, d * sizeof(float), Xd.p, ld * sizeof(float),
-                             d * sizeof(float), n, hipMemcpyDeviceToHost, s));
+    if (ld == d)
+      RBQ_HIP(hipMemcpyAsync(idx->hostX, Xd.p, (size_t)n * d * sizeof(float), hipMemcpyDeviceToHost, s));
+    else
+      RBQ_HIP(hipMemcpy2DAsync(idx->hostX, d * sizeof(float), Xd.p, ld * sizeof(float),
+                               d * sizeof(float), n, hipMemcpyDeviceToHost, s));
   }
   RBQ_HIP(hipStreamSynchronize(s));
   return idx.release();

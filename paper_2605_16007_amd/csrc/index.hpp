@@ -16,6 +16,12 @@
 
 namespace rbq {
 
+// HIP events of one timed search (read back lazily by rbq_get_timings).
+struct TimingRec {
+  hipEvent_t e[6] = {};           // start, probe, rotate, quant, scan+merge, rerank
+  std::vector<hipEvent_t> scan;   // (start, end) around every scan launch
+};
+
 // A device scratch area reused across calls. `done` is recorded on the stream
 // of the call that last used it; the area is handed out again only once that
 // event has completed, so concurrent calls on distinct streams never share one.
@@ -87,12 +93,12 @@ struct rbq_index {
   std::vector<std::unique_ptr<rbq::Workspace>> ws_free;
 
   // stage timing: sums over the timed searches since timing was enabled.
-  // Each timed search leaves its 7 stage events in `pending`; they are read
+  // Each timed search leaves its stage events in `pending`; they are read
   // (and destroyed) by rbq_get_timings, so no search waits for them.
   std::atomic<int> timing{0};
   std::mutex timing_mu;
   rbq_timings last{};
-  std::vector<std::array<hipEvent_t, 7>> pending;
+  std::vector<rbq::TimingRec> pending;
   rbq::DevBuf tcounter;  // device sum of scanned vectors
 
   ~rbq_index();
@@ -104,6 +110,7 @@ std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes);
 void ws_release(rbq_index* idx, std::unique_ptr<Workspace> ws, hipStream_t s);
 
 bool is_device_ptr(const void* p);
+void upload_rows(float* dst, int ld, const float* src, int d, int64_t n, hipStream_t s);
 
 rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params& p);
 

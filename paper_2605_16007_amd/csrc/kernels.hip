@@ -220,11 +220,11 @@ constexpr int TOPK_CACHE = 4096;   // rows up to this many keys are staged in LD
 
 template <bool FROM_SCORE>
 __global__ __launch_bounds__(256) void k_row_topk(const float* __restrict__ score,
-                                                  const uint64_t* __restrict__ keys, int64_t ld,
+                                                  const uint64_t* keys, int64_t ld,
                                                   int ncols, int k, int KP,
-                                                  uint64_t* __restrict__ out_keys,
+                                                  uint64_t* out_keys,
                                                   int32_t* __restrict__ out_low,
-                                                  float* __restrict__ out_val) {
+                                                  float* __restrict__ out_val, int64_t ldo) {
   extern __shared__ uint64_t smem[];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[4];
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void k_row_topk(const float* __restrict__ scor
   bitonic_sort_lds(sel, KP);
   for (int i = tid; i < k; i += 256) {
     const uint64_t v = sel[i];
-    if (out_keys) out_keys[row * k + i] = v;
+    if (out_keys) out_keys[row * ldo + i] = v;
     if (out_low) out_low[row * k + i] = v == KEY_NONE ? -1 : (int32_t)(uint32_t)v;
     if (out_val) out_val[row * k + i] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
   }
@@ -311,17 +311,19 @@ static int pow2_at_least(int n) {
 }
 
 void launch_row_topk(hipStream_t s, const float* score, const uint64_t* keys, int rows, int64_t ld,
-                     int ncols, int k, uint64_t* out_keys, int32_t* out_low, float* out_val) {
+                     int ncols, int k, uint64_t* out_keys, int32_t* out_low, float* out_val,
+                     int64_t ldo) {
   if (rows <= 0) return;
+  if (ldo <= 0) ldo = k;
   RBQ_CHECK(k >= 1 && k <= MAX_SEL, "selection size out of range");
   const int KP = pow2_at_least(k);
   const size_t lds = ((ncols <= TOPK_CACHE ? ncols : 0) + KP) * sizeof(uint64_t);
   if (score)
     hipLaunchKernelGGL(k_row_topk<true>, dim3(rows), dim3(256), lds, s, score, keys, ld, ncols, k,
-                       KP, out_keys, out_low, out_val);
+                       KP, out_keys, out_low, out_val, ldo);
   else
     hipLaunchKernelGGL(k_row_topk<false>, dim3(rows), dim3(256), lds, s, score, keys, ld, ncols, k,
-                       KP, out_keys, out_low, out_val);
+                       KP, out_keys, out_low, out_val, ldo);
   RBQ_HIP(hipGetLastError());
 }
 
@@ -451,7 +453,8 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
   const int BQ = BQT > 0 ? BQT : a.Q.bqs;
   const int bqs = a.Q.bqs;
   const int it = blockIdx.x;
-  const int p = it / a.nq, i = it - p * a.nq;
+  const int pr = it / a.nq, i = it - pr * a.nq;
+  const int p = a.p0 + pr;
   const int64_t pair = (int64_t)i * a.nprobe + p;
   const int j = a.probes[pair];
   const int len = j >= 0 ? a.L.list_len[j] : 0, mb0 = j >= 0 ? a.L.list_mb[j] : 0;
@@ -527,14 +530,14 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
       const int id = a.L.pos2id[(uint32_t)sv];
       kk = (sv & 0xFFFFFFFF00000000ull) | (uint32_t)id;
     }
-    a.out[pair * R + r] = kk;
+    a.out[(int64_t)i * a.out_ld + (int64_t)R * (1 + pr) + r] = kk;
   }
   if (a.qthr && tid == 0 && n >= R) atomicMin(&a.qthr[i], (uint32_t)(sel[R - 1] >> 32));
 }
 
 template <int WT, int BQT>
 static void scan_dispatch(hipStream_t s, const ScanArgs& a, int cap, bool dump) {
-  const unsigned items = (unsigned)((int64_t)a.nq * a.nprobe);
+  const unsigned items = (unsigned)((int64_t)a.nq * a.pn);
   const size_t lds = (size_t)cap * sizeof(uint64_t);
   if (dump)
     hipLaunchKernelGGL((k_scan_popc<WT, BQT, true>), dim3(items), dim3(256), lds, s, a, cap);
@@ -543,7 +546,7 @@ static void scan_dispatch(hipStream_t s, const ScanArgs& a, int cap, bool dump) 
 }
 
 void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
-  if ((int64_t)a.nq * a.nprobe <= 0) return;
+  if ((int64_t)a.nq * a.pn <= 0) return;
   const int cap = pow2_at_least(a.R + 256);
   const bool dump = a.dump_ip != nullptr;
   const int bq4 = a.Q.bqs == 4;
@@ -565,9 +568,9 @@ void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int ldq,
-                                                const float* __restrict__ X, int ldx, int d,
-                                                const uint64_t* __restrict__ cand, int R, int k,
-                                                int KP, int64_t* __restrict__ ids,
+                                                const float* __restrict__ X, int64_t n, int ldx, int d,
+                                                const uint64_t* __restrict__ cand, int64_t ldc,
+                                                int R, int k, int KP, int64_t* __restrict__ ids,
                                                 float* __restrict__ dist) {
   extern __shared__ uint64_t ck[];
   float* qs = reinterpret_cast<float*>(ck + KP);
@@ -577,9 +580,9 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   for (int t = R + tid; t < KP; t += 256) ck[t] = KEY_NONE;
   __syncthreads();
   for (int c = wave; c < R; c += 4) {
-    const uint64_t key = cand[i * R + c];
+    const uint64_t key = cand[i * ldc + c];
     uint64_t out = KEY_NONE;
-    if (key != KEY_NONE) {
+    if (key != KEY_NONE && (int64_t)(uint32_t)key < n) {  // ids outside [0, n) are never read
       const uint32_t id = (uint32_t)key;
       const float* x = X + (size_t)id * ldx;
       float acc = 0.f;
@@ -601,13 +604,14 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   }
 }
 
-void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int ldx, int d,
-                   const uint64_t* cand, int nq, int R, int k, int64_t* ids, float* dist) {
+void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64_t n, int ldx,
+                   int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
+                   float* dist) {
   if (nq <= 0) return;
   const int KP = pow2_at_least(R);
   const size_t lds = KP * sizeof(uint64_t) + (size_t)d * sizeof(float);
-  hipLaunchKernelGGL(k_rerank, dim3(nq), dim3(256), lds, s, q, ldq, X, ldx, d, cand, R, k, KP, ids,
-                     dist);
+  hipLaunchKernelGGL(k_rerank, dim3(nq), dim3(256), lds, s, q, ldq, X, n, ldx, d, cand, ldc, R, k,
+                     KP, ids, dist);
   RBQ_HIP(hipGetLastError());
 }
 
@@ -768,6 +772,21 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = v;
 }
+// p[r * ld + c] = v for r < rows, c < cols
+__global__ void k_fill_rows_u64(uint64_t* p, int64_t ld, int64_t rows, int cols, uint64_t v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * cols) return;
+  const int64_t r = t / cols;
+  p[r * ld + (t - r * cols)] = v;
+}
+void launch_fill_rows_u64(hipStream_t s, uint64_t* p, int64_t ld, int64_t rows, int cols, uint64_t v) {
+  const int64_t n = rows * cols;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_rows_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, ld, rows,
+                     cols, v);
+  RBQ_HIP(hipGetLastError());
+}
+
 void launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
@@ -794,33 +813,34 @@ void launch_gather_rows(hipStream_t s, const float* X, int ldx, const int64_t* i
 }
 
 // k-means++ seeding on the device. mind[t] holds the squared distance of row t
-// to its nearest chosen centre; blocksum[b] the FP64 sum of block b's mind.
+// to its nearest chosen centre; blocksum[b] the FP64 sum of mind over rows
+// [256 b, 256 b + 256). One wave per row: lanes stride the dimensions, so every
+// load instruction reads one contiguous span of the row.
 __global__ __launch_bounds__(256) void k_kpp_update(const float* __restrict__ T, int ldt, int64_t n,
                                                     int d, const int64_t* __restrict__ pick,
                                                     float* __restrict__ mind,
                                                     double* __restrict__ blocksum, int first) {
-  __shared__ double red[256];
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float* c = T + (*pick) * ldt;
-  double v = 0.0;
-  if (t < n) {
+  double part = 0.0;
+  for (int rr = 0; rr < 64; ++rr) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + wave * 64 + rr;
+    if (t >= n) break;
     const float* x = T + t * ldt;
     float acc = 0.f;
-    for (int k = 0; k < d; ++k) {
+    for (int k = lane; k < d; k += 64) {
       const float df = x[k] - c[k];
       acc += df * df;
     }
+    acc = wave_sum(acc);
     const float m = first ? acc : fminf(mind[t], acc);
-    mind[t] = m;
-    v = m;
+    if (lane == 0) mind[t] = m;
+    part += (double)m;
   }
-  red[threadIdx.x] = v;
+  if (lane == 0) red[wave] = part;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 void launch_kpp_update(hipStream_t s, const float* T, int ldt, int64_t n, int d, const int64_t* pick,

@@ -39,9 +39,11 @@ void launch_assign_argmin(hipStream_t s, const float* A, int lda, const float* B
 // Per row: the k smallest 64-bit keys, ascending. Keys come from a float matrix
 // (tie = column) when `score` is set, else from a key matrix. Optional outputs:
 // out_keys [rows][k], out_low (low word as int32), out_val (high word as float).
+// out_keys rows have stride ldo (>= k); an output row may overlap its own input
+// row (every read of a row precedes every write).
 void launch_row_topk(hipStream_t s, const float* score, const uint64_t* keys, int rows,
                      int64_t ld, int ncols, int k, uint64_t* out_keys, int32_t* out_low,
-                     float* out_val);
+                     float* out_val, int64_t ldo = 0);
 
 // Residual r = qrot_i - crot_j for every (query, probe) pair, B_q-bit
 // quantisation, bit-planes and scalars; or pack injected qu / scalars.
@@ -56,8 +58,10 @@ struct ScanArgs {
   PairsView Q;
   const int32_t* probes;   // [nq][nprobe]
   int nq, nprobe, R;
+  int p0, pn;              // this launch scans probe ranks [p0, p0 + pn)
+  int64_t out_ld;          // keys per query row of `out`; item (i, p) writes at i*out_ld + R*(1+p-p0)
   uint32_t* qthr;          // [nq] ordered-float bound on each query's R-th estimate (or null)
-  uint64_t* out;           // [nq][nprobe][R] keys (est, id)
+  uint64_t* out;           // candidate rows (est, id) keys
   int32_t* dump_ip;        // debug: [nq][nprobe][maxlen] (or null)
   float* dump_est;
   int64_t maxlen;
@@ -66,8 +70,9 @@ void launch_scan_popc(hipStream_t s, const ScanArgs& a);
 
 // Exact re-rank: per query, gather the candidates' raw vectors, exact squared
 // L2 in FP32, top-k by (distance, id).
-void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int ldx, int d,
-                   const uint64_t* cand, int nq, int R, int k, int64_t* ids, float* dist);
+void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64_t n, int ldx,
+                   int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
+                   float* dist);
 
 // RaBitQ encoder (FP64): one launch encodes micro-blocks [mb_begin, mb_end).
 void launch_encode(hipStream_t s, const float* X, int ldx, const float* C, int ldc,
@@ -82,6 +87,7 @@ void launch_rotate_rows_f64(hipStream_t s, const float* A, int lda, const float*
 
 void launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n);
 void launch_fill_u64(hipStream_t s, uint64_t* p, uint64_t v, int64_t n);
+void launch_fill_rows_u64(hipStream_t s, uint64_t* p, int64_t ld, int64_t rows, int cols, uint64_t v);
 void launch_gather_rows(hipStream_t s, const float* X, int ldx, const int64_t* idx, int64_t n,
                         float* out, int ldo);
 

@@ -39,7 +39,6 @@ struct Bufs {
   float* inj_scal = nullptr;
   uint32_t* qthr = nullptr;
   uint64_t* cand = nullptr;
-  uint64_t* merged = nullptr;
   int32_t* dump_ip = nullptr;
   float* dump_est = nullptr;
   int64_t* ids = nullptr;
@@ -70,6 +69,14 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
   const bool timed = idx->timing.load() != 0;
   RBQ_CHECK(!idx->vectors_on_host, "host-resident raw vectors: re-rank on host is not available in this build");
 
+  // Probe ranks are scanned in chunks of `pch`: each item writes its top-R
+  // after the query's running top-R (first R keys of its candidate row), and a
+  // merge after each chunk folds the row back into its first R keys. This
+  // bounds the candidate buffer at ~512 MB whatever nprobe and R are.
+  const int64_t budget = (int64_t)512 << 20;
+  int pch = (int)std::max<int64_t>(1, std::min<int64_t>(nprobe, budget / std::max<int64_t>(1, nq * R * 8) - 1));
+  if (dbg && dbg->probe_chunk > 0) pch = std::min(pch, (int)dbg->probe_chunk);
+  const int64_t cand_ld = (int64_t)R * (1 + pch);
   auto layout = [&](Carver& c, Bufs& b) {
     if (need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
     if (!inj_probes) b.score = c.take<float>((size_t)nq * nlist);
@@ -84,8 +91,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       b.inj_scal = c.take<float>((size_t)pairs * 3);
     }
     b.qthr = c.take<uint32_t>(nq);
-    b.cand = c.take<uint64_t>((size_t)pairs * R);
-    b.merged = nprobe > 1 ? c.take<uint64_t>((size_t)nq * R) : nullptr;
+    b.cand = c.take<uint64_t>((size_t)nq * R * (1 + pch));
     if (dumps) {
       b.dump_ip = c.take<int32_t>((size_t)pairs * maxlen);
       b.dump_est = c.take<float>((size_t)pairs * maxlen);
@@ -102,18 +108,24 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     Carver c(ws->base);
     layout(c, b);
 
-    hipEvent_t ev[7] = {};
+    // stage events: start, probe, rotate, quant, scan+merge loop, rerank; plus
+    // a (start, end) pair around every scan launch
+    TimingRec tr;
+    auto newev = [&]() {
+      hipEvent_t e;
+      RBQ_HIP(hipEventCreate(&e));
+      return e;
+    };
     if (timed)
-      for (auto& e : ev) RBQ_HIP(hipEventCreate(&e));
+      for (auto& e : tr.e) e = newev();
     auto mark = [&](int i) {
-      if (timed) RBQ_HIP(hipEventRecord(ev[i], s));
+      if (timed) RBQ_HIP(hipEventRecord(tr.e[i], s));
     };
 
     const float* qd = q;
     if (need_qcopy) {
       if (ld != d) RBQ_HIP(hipMemsetAsync(b.qpad, 0, (size_t)nq * ld * sizeof(float), s));
-      RBQ_HIP(hipMemcpy2DAsync(b.qpad, ld * sizeof(float), q, d * sizeof(float), d * sizeof(float),
-                               nq, hipMemcpyDefault, s));
+      upload_rows(b.qpad, ld, q, d, nq, s);
       qd = b.qpad;
     }
     mark(0);
@@ -146,7 +158,8 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     launch_quant(s, b.qrot, ld, idx->Crot.as<float>(), ld, b.probes, (int)nq, nprobe, d, W, idx->bq,
                  bqs, b.planes, b.qu, b.scal, b.inj_qu, b.inj_scal);
     mark(3);
-    // Phase 3 + local part of Phase 4: code scan, estimator, per-item top-R
+    // Phase 3 + Phase 4: code scan with the estimator and per-item top-R,
+    // then the per-query merge, one chunk of probe ranks at a time
     ScanArgs sa;
     sa.L = ListsView{idx->blocks.as<uint32_t>(), idx->list_mb.as<int32_t>(), idx->list_len.as<int32_t>(),
                      idx->pos2id.as<int32_t>(), W, d};
@@ -155,26 +168,37 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     sa.nq = (int)nq;
     sa.nprobe = nprobe;
     sa.R = R;
+    sa.out_ld = cand_ld;
     sa.qthr = b.qthr;
     sa.out = b.cand;
     sa.dump_ip = b.dump_ip;
     sa.dump_est = b.dump_est;
     sa.maxlen = maxlen;
-    launch_scan_popc(s, sa);
-    mark(4);
-    // Phase 4: per-query merge of the items' top-R
-    const uint64_t* top = b.cand;
-    if (nprobe > 1) {
-      launch_row_topk(s, nullptr, b.cand, (int)nq, (int64_t)nprobe * R, nprobe * R, R, b.merged,
-                      nullptr, nullptr);
-      top = b.merged;
+    launch_fill_rows_u64(s, b.cand, cand_ld, nq, R, KEY_NONE);  // every row's running top-R starts empty
+    for (int p0 = 0; p0 < nprobe; p0 += pch) {
+      sa.p0 = p0;
+      sa.pn = std::min(pch, nprobe - p0);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        e0 = newev();
+        e1 = newev();
+        tr.scan.push_back(e0);
+        tr.scan.push_back(e1);
+        RBQ_HIP(hipEventRecord(e0, s));
+      }
+      launch_scan_popc(s, sa);
+      if (timed) RBQ_HIP(hipEventRecord(e1, s));
+      launch_row_topk(s, nullptr, b.cand, (int)nq, cand_ld, R * (1 + sa.pn), R, b.cand, nullptr,
+                      nullptr, cand_ld);
     }
-    mark(5);
+    const uint64_t* top = b.cand;
+    mark(4);
     // Phase 5: exact re-rank of the top-R on the GPU
     int64_t* ids_out = ids_dev ? ids : b.ids;
     float* dist_out = dist_dev ? dist : b.dist;
-    launch_rerank(s, qd, ld, idx->X.as<float>(), ld, d, top, (int)nq, R, k, ids_out, dist_out);
-    mark(6);
+    launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
+                  ids_out, dist_out);
+    mark(5);
     if (timed) {
       hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
                          idx->list_len.as<int32_t>(), pairs,
@@ -208,7 +232,8 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
                                hipMemcpyDeviceToHost, s));
       if (dbg->cand_ids || dbg->cand_est) {
         hm.resize((size_t)nq * R);
-        RBQ_HIP(hipMemcpyAsync(hm.data(), top, hm.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        RBQ_HIP(hipMemcpy2DAsync(hm.data(), R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
+                                 R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
       }
       if (dbg->ids)
         RBQ_HIP(hipMemcpyAsync(dbg->ids, ids_out, (size_t)nq * k * sizeof(int64_t),
@@ -219,9 +244,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     ws_release(idx, std::move(ws), s);
     if (timed) {
       std::lock_guard<std::mutex> g(idx->timing_mu);
-      std::array<hipEvent_t, 7> a;
-      for (int i = 0; i < 7; ++i) a[i] = ev[i];
-      idx->pending.push_back(a);
+      idx->pending.push_back(std::move(tr));
     }
     const bool host_out = (ids && !ids_dev) || (dist && !dist_dev) || dbg;
     if (host_out) RBQ_HIP(hipStreamSynchronize(s));

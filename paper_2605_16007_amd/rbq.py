@@ -43,7 +43,8 @@ class IndexInfo(C.Structure):
 class DebugIO(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "inject_probes", "inject_qu", "inject_scalars", "probes", "probe_score", "qrot", "qu",
-        "scalars", "ip", "est", "cand_ids", "cand_est", "ids", "sqdist")]
+        "scalars", "ip", "est", "cand_ids", "cand_est", "ids", "sqdist")] + [
+        ("probe_chunk", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Timings(C.Structure):
@@ -69,6 +70,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2605_16007_amd.build`")
+        # torch ships its own HIP runtime under the same soname; load it first
+        # so that librbq and torch share one runtime in this process
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.rbq_build_params_init.argtypes = [C.POINTER(BuildParams)]
@@ -223,13 +230,18 @@ class Index:
                                 _ptr(ids), _ptr(dists), s))
         return ids, dists
 
+    DEBUG_OUTPUTS = ("probes", "probe_score", "qrot", "qu", "scalars", "ip", "est", "cand_ids",
+                     "cand_est", "ids", "sqdist")
+
     def search_debug(self, q, nprobe, k, rerank_n, *, inject_probes=None, inject_qu=None,
-                     inject_scalars=None):
-        """Stage-by-stage search (host arrays). Returns a dict of every stage's
-        output; see rbq_search_debug in include/rbq.h for the layouts."""
+                     inject_scalars=None, want=None, probe_chunk=0):
+        """Stage-by-stage search (host arrays). Returns a dict of the stage
+        outputs named in ``want`` (default: all); see rbq_search_debug in
+        include/rbq.h for the layouts."""
         q = np.ascontiguousarray(q, np.float32)
         nq, d = q.shape
-        maxlen = max(1, self.info()["max_list_len"])
+        want = set(self.DEBUG_OUTPUTS if want is None else want)
+        maxlen = max(1, self.info()["max_list_len"]) if want & {"ip", "est"} else 1
         pairs = nq * nprobe
         out = {
             "probes": np.zeros((nq, nprobe), np.int32),
@@ -244,13 +256,14 @@ class Index:
             "ids": np.zeros((nq, k), np.int64),
             "sqdist": np.zeros((nq, k), np.float32),
         }
+        out = {key: v for key, v in out.items() if key in want}
         io = DebugIO()
         keep = []
         if inject_probes is not None:
             a = np.ascontiguousarray(inject_probes, np.int32).reshape(pairs)
             keep.append(a)
             io.inject_probes = a.ctypes.data
-            del out["probe_score"]
+            out.pop("probe_score", None)
         if inject_qu is not None:
             a = np.ascontiguousarray(inject_qu, np.uint8).reshape(pairs * d)
             b = np.ascontiguousarray(inject_scalars, np.float32).reshape(pairs * 3)
@@ -258,6 +271,7 @@ class Index:
             io.inject_qu, io.inject_scalars = a.ctypes.data, b.ctypes.data
         for key, arr in out.items():
             setattr(io, key, arr.ctypes.data)
+        io.probe_chunk = int(probe_chunk)
         _check(lib().rbq_search_debug(self._h, q.ctypes.data, nq, int(nprobe), int(k),
                                       int(rerank_n), C.byref(io)))
         return out
