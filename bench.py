@@ -232,12 +232,11 @@ def main():
             f"(probe recall {prec[pt[0]]:.4f})")
     ok = [pt for pt in points if rec[pt] >= 0.95]
     if not ok and not args.nprobe:
-        top = min(w.nlist, 2048)
+        top = min(w.nlist, 4096)
         wider = [p for p in (256, 512, 1024, 2048) if max(w.nprobe) < p <= top]
         for npb in wider:
             prec[npb] = probe_recall(npb)
-            for R in sorted({w.rerank_n, 2 * w.rerank_n, 5 * w.rerank_n, 10 * w.rerank_n}):
-                R = min(R, 2048)
+            for R in sorted({min(3840, f * w.rerank_n) for f in (1, 2, 5, 10, 20, 40)}):
                 pt = (npb, R)
                 rec[pt] = eval_point(*pt)
                 log(f"[recall] nprobe {npb} rerank {R}: recall@{w.k} = {rec[pt]:.4f} "

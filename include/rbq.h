@@ -96,7 +96,7 @@ rbq_status rbq_get_info(const rbq_index* idx, rbq_index_info* info);
 /*
  * Search a batch (Sec. 3.1.2 Phases 1-5). q: host or device nq*d float32.
  * ids: host or device nq*k int64; sqdist: host or device nq*k float32.
- * Requires 1 <= nprobe <= min(nlist, 2048), 1 <= k <= rerank_n <= 2048,
+ * Requires 1 <= nprobe <= min(nlist, 4096), 1 <= k <= rerank_n <= 3840,
  * nq >= 0 (nq = 0 is a no-op). Errors: EINVAL for argument errors, ENOMEM,
  * EDEVICE. The library allocates per-call device scratch, reused across calls.
  */

@@ -41,8 +41,8 @@ void check_search_args(const rbq_index* idx, const float* q, int64_t nq, int32_t
   RBQ_CHECK(nq >= 0, "nq must be >= 0");
   RBQ_CHECK(nq == 0 || q != nullptr, "queries are NULL");
   RBQ_CHECK(nprobe >= 1 && nprobe <= idx->nlist, "nprobe must be in [1, nlist]");
-  RBQ_CHECK(nprobe <= rbq::MAX_SEL, "nprobe must be <= 2048");
-  RBQ_CHECK(rerank_n >= 1 && rerank_n <= rbq::MAX_SEL, "rerank_n must be in [1, 2048]");
+  RBQ_CHECK(nprobe <= rbq::MAX_SEL, "nprobe must be <= 4096");
+  RBQ_CHECK(rerank_n >= 1 && rerank_n <= rbq::MAX_R, "rerank_n must be in [1, 3840]");
   RBQ_CHECK(k >= 1 && k <= rerank_n, "k must be in [1, rerank_n]");
   RBQ_CHECK(nq * (int64_t)nprobe <= (int64_t)INT32_MAX, "nq * nprobe too large");
 }

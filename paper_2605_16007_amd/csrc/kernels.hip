@@ -5,6 +5,7 @@
 // (Phase 3; Eqs. rabitq-ip-estimator, approx-dist), per-query top-R selection
 // (Phase 4) and exact re-rank (Phase 5). Build path (Sec. 3.1.1): k-means
 // assignment GEMM with fused argmin and the RaBitQ encoder (Phase 3).
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -216,27 +217,27 @@ void launch_assign_argmin(hipStream_t s, const float* A, int lda, const float* B
 // taken whole), compaction, and an LDS bitonic sort of the k survivors.
 // ---------------------------------------------------------------------------
 
-constexpr int TOPK_CACHE = 4096;   // rows up to this many keys are staged in LDS
-
 template <bool FROM_SCORE>
-__global__ __launch_bounds__(256) void k_row_topk(const float* __restrict__ score,
-                                                  const uint64_t* keys, int64_t ld,
-                                                  int ncols, int k, int KP,
-                                                  uint64_t* out_keys,
-                                                  int32_t* __restrict__ out_low,
-                                                  float* __restrict__ out_val, int64_t ldo) {
+__global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
   extern __shared__ uint64_t smem[];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t s_digit, s_rem, s_bucket, s_cnt;
   const int tid = threadIdx.x;
   const int64_t row = blockIdx.x;
-  const bool cached = ncols <= TOPK_CACHE;
+  const int k = a.k, KP = a.KP;
+  int ncols = a.ncols;
+  if (a.rowcnt) {  // pool mode: the row holds k running keys then rowcnt[row] new ones
+    const uint32_t extra = a.rowcnt[row];
+    if (extra == 0) return;
+    ncols = k + (int)extra;
+  }
+  const bool cached = ncols <= a.cache_cap;
   uint64_t* cache = smem;
-  uint64_t* sel = smem + (cached ? ncols : 0);
+  uint64_t* sel = smem + a.cache_cap;
   auto src = [&](int c) -> uint64_t {
-    if (FROM_SCORE) return key64(score[row * ld + c], (uint32_t)c);
-    return keys[row * ld + c];
+    if (FROM_SCORE) return key64(a.score[row * a.ld + c], (uint32_t)c);
+    return a.keys[row * a.ld + c];
   };
   auto get = [&](int c) -> uint64_t { return cached ? cache[c] : src(c); };
   if (cached)
@@ -298,9 +299,13 @@ __global__ __launch_bounds__(256) void k_row_topk(const float* __restrict__ scor
   bitonic_sort_lds(sel, KP);
   for (int i = tid; i < k; i += 256) {
     const uint64_t v = sel[i];
-    if (out_keys) out_keys[row * ldo + i] = v;
-    if (out_low) out_low[row * k + i] = v == KEY_NONE ? -1 : (int32_t)(uint32_t)v;
-    if (out_val) out_val[row * k + i] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
+    if (a.out_keys) a.out_keys[row * a.ldo + i] = v;
+    if (a.out_low) a.out_low[row * k + i] = v == KEY_NONE ? -1 : (int32_t)(uint32_t)v;
+    if (a.out_val) a.out_val[row * k + i] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
+  }
+  if (tid == 0) {
+    if (a.rowcnt) a.rowcnt[row] = 0;
+    if (a.qthr && sel[k - 1] != KEY_NONE) atomicMin(&a.qthr[row], (uint32_t)(sel[k - 1] >> 32));
   }
 }
 
@@ -310,20 +315,20 @@ static int pow2_at_least(int n) {
   return p;
 }
 
-void launch_row_topk(hipStream_t s, const float* score, const uint64_t* keys, int rows, int64_t ld,
-                     int ncols, int k, uint64_t* out_keys, int32_t* out_low, float* out_val,
-                     int64_t ldo) {
+void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   if (rows <= 0) return;
-  if (ldo <= 0) ldo = k;
-  RBQ_CHECK(k >= 1 && k <= MAX_SEL, "selection size out of range");
-  const int KP = pow2_at_least(k);
-  const size_t lds = ((ncols <= TOPK_CACHE ? ncols : 0) + KP) * sizeof(uint64_t);
-  if (score)
-    hipLaunchKernelGGL(k_row_topk<true>, dim3(rows), dim3(256), lds, s, score, keys, ld, ncols, k,
-                       KP, out_keys, out_low, out_val, ldo);
+  RBQ_CHECK(a.k >= 1 && a.k <= MAX_SEL, "selection size out of range");
+  a.KP = pow2_at_least(a.k);
+  if (a.ldo <= 0) a.ldo = a.k;
+  const int maxcols = a.rowcnt ? a.k + a.max_extra : a.ncols;
+  // stage a row in LDS when it fits next to the sort buffer (48 KB in all)
+  const int room = (int)((48 << 10) / sizeof(uint64_t)) - a.KP;
+  a.cache_cap = std::max(0, std::min(maxcols, room));
+  const size_t lds = (size_t)(a.cache_cap + a.KP) * sizeof(uint64_t);
+  if (a.score)
+    hipLaunchKernelGGL(k_row_topk<true>, dim3(rows), dim3(256), lds, s, a);
   else
-    hipLaunchKernelGGL(k_row_topk<false>, dim3(rows), dim3(256), lds, s, score, keys, ld, ncols, k,
-                       KP, out_keys, out_low, out_val, ldo);
+    hipLaunchKernelGGL(k_row_topk<false>, dim3(rows), dim3(256), lds, s, a);
   RBQ_HIP(hipGetLastError());
 }
 
@@ -522,15 +527,17 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
   for (int t = n + tid; t < P; t += 256) sel[t] = KEY_NONE;
   __syncthreads();
   bitonic_sort_lds(sel, P);
+  // append this item's survivors (at most R) to the query's pool; the pool
+  // holds R * (probe ranks in this launch) keys, so it cannot overflow
   const int nout = n < R ? n : R;
-  for (int r = tid; r < R; r += 256) {
-    uint64_t kk = KEY_NONE;
-    if (r < nout) {
-      const uint64_t sv = sel[r];
-      const int id = a.L.pos2id[(uint32_t)sv];
-      kk = (sv & 0xFFFFFFFF00000000ull) | (uint32_t)id;
-    }
-    a.out[(int64_t)i * a.out_ld + (int64_t)R * (1 + pr) + r] = kk;
+  __shared__ int s_base;
+  if (tid == 0) s_base = nout ? (int)atomicAdd(&a.pcnt[i], (uint32_t)nout) : 0;
+  __syncthreads();
+  uint64_t* dst = a.out + (int64_t)i * a.out_ld + R + s_base;
+  for (int r = tid; r < nout; r += 256) {
+    const uint64_t sv = sel[r];
+    const int id = a.L.pos2id[(uint32_t)sv];
+    dst[r] = (sv & 0xFFFFFFFF00000000ull) | (uint32_t)id;
   }
   if (a.qthr && tid == 0 && n >= R) atomicMin(&a.qthr[i], (uint32_t)(sel[R - 1] >> 32));
 }

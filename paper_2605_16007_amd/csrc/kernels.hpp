@@ -7,7 +7,8 @@
 namespace rbq {
 
 constexpr int MB = 64;            // vectors per micro-block (one wave64 lane each)
-constexpr int MAX_SEL = 2048;     // largest k of a selection (nprobe, rerank_n)
+constexpr int MAX_SEL = 4096;     // largest k of a selection (nprobe)
+constexpr int MAX_R = 3840;       // largest rerank_n (scan buffer R + 256 <= 4096 keys)
 
 // Device view of the lists of an index.
 struct ListsView {
@@ -36,14 +37,29 @@ void launch_gemm_tn(hipStream_t s, int mode, const float* A, int lda, const floa
 void launch_assign_argmin(hipStream_t s, const float* A, int lda, const float* B, int ldb,
                           const float* bnorm, int M, int N, int K, uint64_t* out);
 
-// Per row: the k smallest 64-bit keys, ascending. Keys come from a float matrix
-// (tie = column) when `score` is set, else from a key matrix. Optional outputs:
-// out_keys [rows][k], out_low (low word as int32), out_val (high word as float).
-// out_keys rows have stride ldo (>= k); an output row may overlap its own input
-// row (every read of a row precedes every write).
-void launch_row_topk(hipStream_t s, const float* score, const uint64_t* keys, int rows,
-                     int64_t ld, int ncols, int k, uint64_t* out_keys, int32_t* out_low,
-                     float* out_val, int64_t ldo = 0);
+// Per row: the k smallest 64-bit keys, ascending (MSB-first radix select, then
+// an LDS bitonic sort of the survivors). Keys come from a float matrix (tie =
+// column) when `score` is set, else from a key matrix. Pool mode (rowcnt set):
+// row r holds its k running keys followed by rowcnt[r] new ones; rows with no
+// new keys are skipped, rowcnt[r] is reset to 0 and qthr[r] (if set) is
+// lowered to the k-th key's value. An output row may overlap its input row:
+// every read of a row precedes every write.
+struct TopkArgs {
+  const float* score = nullptr;
+  const uint64_t* keys = nullptr;
+  int64_t ld = 0;              // input row stride
+  int ncols = 0;               // keys per row (non-pool mode)
+  int k = 0;
+  uint64_t* out_keys = nullptr;
+  int64_t ldo = 0;             // output row stride (0: k)
+  int32_t* out_low = nullptr;  // [rows][k] low word as int32 (-1 for none)
+  float* out_val = nullptr;    // [rows][k] high word as float (+inf for none)
+  uint32_t* rowcnt = nullptr;
+  int max_extra = 0;           // largest rowcnt (pool mode)
+  uint32_t* qthr = nullptr;
+  int KP = 0, cache_cap = 0;   // set by the launcher
+};
+void launch_row_topk(hipStream_t s, TopkArgs a, int rows);
 
 // Residual r = qrot_i - crot_j for every (query, probe) pair, B_q-bit
 // quantisation, bit-planes and scalars; or pack injected qu / scalars.
@@ -59,7 +75,8 @@ struct ScanArgs {
   const int32_t* probes;   // [nq][nprobe]
   int nq, nprobe, R;
   int p0, pn;              // this launch scans probe ranks [p0, p0 + pn)
-  int64_t out_ld;          // keys per query row of `out`; item (i, p) writes at i*out_ld + R*(1+p-p0)
+  int64_t out_ld;          // keys per query row of `out`: R running keys, then the pool
+  uint32_t* pcnt;          // [nq] keys appended to each query's pool
   uint32_t* qthr;          // [nq] ordered-float bound on each query's R-th estimate (or null)
   uint64_t* out;           // candidate rows (est, id) keys
   int32_t* dump_ip;        // debug: [nq][nprobe][maxlen] (or null)

@@ -38,6 +38,7 @@ struct Bufs {
   uint8_t* inj_qu = nullptr;
   float* inj_scal = nullptr;
   uint32_t* qthr = nullptr;
+  uint32_t* pcnt = nullptr;
   uint64_t* cand = nullptr;
   int32_t* dump_ip = nullptr;
   float* dump_est = nullptr;
@@ -69,13 +70,18 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
   const bool timed = idx->timing.load() != 0;
   RBQ_CHECK(!idx->vectors_on_host, "host-resident raw vectors: re-rank on host is not available in this build");
 
-  // Probe ranks are scanned in chunks of `pch`: each item writes its top-R
-  // after the query's running top-R (first R keys of its candidate row), and a
-  // merge after each chunk folds the row back into its first R keys. This
-  // bounds the candidate buffer at ~512 MB whatever nprobe and R are.
+  // Probe ranks are scanned in chunks: each scan item appends at most R
+  // survivors to its query's pool (row layout: R running keys, then the pool),
+  // and a merge after each chunk folds the pool into the running top-R and
+  // lowers the query's threshold to its exact R-th estimate, so later chunks
+  // keep only candidates that can still enter the top-R (the IVF-aware pruning
+  // of Sec. 3.3.3). Chunk sizes double from `first` (enough items to fill the
+  // GPU) up to `pch`, the most probe ranks whose worst-case pool fits ~512 MB;
+  // a pool never holds more than R keys per probe rank of its chunk.
   const int64_t budget = (int64_t)512 << 20;
   int pch = (int)std::max<int64_t>(1, std::min<int64_t>(nprobe, budget / std::max<int64_t>(1, nq * R * 8) - 1));
-  if (dbg && dbg->probe_chunk > 0) pch = std::min(pch, (int)dbg->probe_chunk);
+  int first = (int)std::min<int64_t>(pch, std::max<int64_t>(1, (2048 + nq - 1) / nq));
+  if (dbg && dbg->probe_chunk > 0) pch = first = std::min(pch, (int)dbg->probe_chunk);
   const int64_t cand_ld = (int64_t)R * (1 + pch);
   auto layout = [&](Carver& c, Bufs& b) {
     if (need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
@@ -91,7 +97,8 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       b.inj_scal = c.take<float>((size_t)pairs * 3);
     }
     b.qthr = c.take<uint32_t>(nq);
-    b.cand = c.take<uint64_t>((size_t)nq * R * (1 + pch));
+    b.pcnt = c.take<uint32_t>(nq);
+    b.cand = c.take<uint64_t>((size_t)nq * cand_ld);
     if (dumps) {
       b.dump_ip = c.take<int32_t>((size_t)pairs * maxlen);
       b.dump_est = c.take<float>((size_t)pairs * maxlen);
@@ -137,7 +144,14 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     } else {
       launch_gemm_tn(s, 1, qd, ld, idx->C.as<float>(), ld, b.score, nlist, (int)nq, nlist, ld,
                      idx->cnorm.as<float>());
-      launch_row_topk(s, b.score, nullptr, (int)nq, nlist, nlist, nprobe, nullptr, b.probes, b.pscore);
+      TopkArgs ta;
+      ta.score = b.score;
+      ta.ld = nlist;
+      ta.ncols = nlist;
+      ta.k = nprobe;
+      ta.out_low = b.probes;
+      ta.out_val = b.pscore;
+      launch_row_topk(s, ta, (int)nq);
     }
     mark(1);
     // query rotation q' = P^T q (row form q P) on MFMA
@@ -174,10 +188,20 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     sa.dump_ip = b.dump_ip;
     sa.dump_est = b.dump_est;
     sa.maxlen = maxlen;
-    launch_fill_rows_u64(s, b.cand, cand_ld, nq, R, KEY_NONE);  // every row's running top-R starts empty
-    for (int p0 = 0; p0 < nprobe; p0 += pch) {
+    launch_fill_rows_u64(s, b.cand, cand_ld, nq, R, KEY_NONE);  // running top-R starts empty
+    launch_fill_u32(s, b.pcnt, 0u, nq);
+    sa.pcnt = b.pcnt;
+    TopkArgs ma;
+    ma.keys = b.cand;
+    ma.ld = cand_ld;
+    ma.k = R;
+    ma.out_keys = b.cand;
+    ma.ldo = cand_ld;
+    ma.rowcnt = b.pcnt;
+    ma.qthr = b.qthr;
+    for (int p0 = 0, pn = first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, pch)) {
       sa.p0 = p0;
-      sa.pn = std::min(pch, nprobe - p0);
+      sa.pn = pn = std::min(pn, nprobe - p0);
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {
         e0 = newev();
@@ -188,8 +212,8 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       }
       launch_scan_popc(s, sa);
       if (timed) RBQ_HIP(hipEventRecord(e1, s));
-      launch_row_topk(s, nullptr, b.cand, (int)nq, cand_ld, R * (1 + sa.pn), R, b.cand, nullptr,
-                      nullptr, cand_ld);
+      ma.max_extra = R * pn;
+      launch_row_topk(s, ma, (int)nq);
     }
     const uint64_t* top = b.cand;
     mark(4);

@@ -171,6 +171,6 @@ def test_search_rejects_bad_arguments_on_gpu_index():
     from paper_2605_16007_amd import RbqError
     X, Q, idx = make_case(3000, 16, 8, 4, seed=12)
     lib = lib_index(X, idx)
-    for args in ((0, 5, 10), (9, 5, 10), (4, 11, 10), (4, 0, 10), (4, 5, 2049)):
+    for args in ((0, 5, 10), (9, 5, 10), (4, 11, 10), (4, 0, 10), (4, 5, 3841)):
         with pytest.raises(RbqError, match="status -1"):
             lib.search(Q, *args)
