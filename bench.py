@@ -280,6 +280,14 @@ def main():
         lat.append((time.perf_counter() - t) * 1e3)
     p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
+    # the two scan forms at the chosen point
+    variants = {}
+    for name, mode in (("popcount_query_major", 1), ("mfma_list_major", 0)):
+        idx.set_option("scan", mode)
+        variants[name] = quick_qps(nprobe, R, steps=10)
+    idx.set_option("scan", 0)
+    log("[variants] " + ", ".join(f"{k_}: {v:.0f} q/s" for k_, v in variants.items()))
+
     cpu = cpu_pool.run(nprobe, w.k, R) if cpu_pool else None
     if cpu_pool:
         cpu_pool.close()
@@ -308,6 +316,7 @@ def main():
         "recall_by_point": {f"nprobe={p},rerank={r}": v for (p, r), v in rec.items()},
         "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
         "qps_at_listed_nprobe": listed_qps,
+        "qps_by_scan_form": variants,
         "p50_ms": p50,
         "p99_ms": p99,
         "stage_ms": {s: tm[f"{s}_ms"] / ns for s in

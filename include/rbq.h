@@ -173,6 +173,20 @@ typedef struct {
 rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled);
 rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t);
 
+/* Tuning options of an index (apply to later searches on any thread).
+ *   RBQ_OPT_SCAN        0: choose per chunk of probe ranks (default),
+ *                       1: query-major popcount scan only,
+ *                       2: list-major int8-MFMA scan wherever allowed
+ *                          (every chunk after the first; d <= 256)
+ *   RBQ_OPT_GROUP_MIN   with RBQ_OPT_SCAN 0, a chunk uses the list-major scan
+ *                       when nq * (probe ranks in the chunk) >= value * nlist
+ *                       (default 4: a list is probed by >= 4 queries on average)
+ *   RBQ_OPT_POOL_CAP    cap on the per-query pool of the list-major scan
+ *                       (0 = the workspace bound; small values exercise the
+ *                       overflow path, which stays exact) */
+enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3 };
+rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
+
 /* Persist / restore an index (versioned binary with per-section checksums). */
 rbq_status rbq_save(const rbq_index* idx, const char* path);
 rbq_status rbq_load(const char* path, rbq_index** out);

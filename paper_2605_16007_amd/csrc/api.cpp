@@ -194,6 +194,7 @@ rbq_index* load_index(const char* path) {
   RBQ_CHECK(f && h.n > 0 && h.d > 0 && h.nlist > 0 && h.bq >= 1 && h.bq <= 8, "bad index header");
   auto idx = std::make_unique<rbq_index>();
   RBQ_HIP(hipGetDevice(&idx->device));
+  RBQ_HIP(hipDeviceGetAttribute(&idx->num_cus, hipDeviceAttributeMultiprocessorCount, idx->device));
   idx->n = h.n;
   idx->d = h.d;
   idx->ld = (int)round_up(h.d, 4);
@@ -415,6 +416,26 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
     }
     *t = idx->last;
   });
+}
+
+rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value) {
+  if (!idx) return invalid("index is NULL");
+  switch (option) {
+    case RBQ_OPT_SCAN:
+      if (value < 0 || value > 2) return invalid("RBQ_OPT_SCAN must be 0, 1 or 2");
+      idx->opt_scan.store((int)value);
+      return RBQ_OK;
+    case RBQ_OPT_GROUP_MIN:
+      if (value < 1 || value > (1 << 20)) return invalid("RBQ_OPT_GROUP_MIN must be in [1, 2^20]");
+      idx->opt_group_min.store((int)value);
+      return RBQ_OK;
+    case RBQ_OPT_POOL_CAP:
+      if (value < 0) return invalid("RBQ_OPT_POOL_CAP must be >= 0");
+      idx->opt_pool_cap.store(value);
+      return RBQ_OK;
+    default:
+      return invalid("unknown option");
+  }
 }
 
 rbq_status rbq_save(const rbq_index* idx, const char* path) {

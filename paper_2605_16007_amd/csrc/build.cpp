@@ -250,6 +250,7 @@ std::vector<float> kmeans_gpu(const float* Xd, int64_t n, int d, int ld, int nli
 rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params& p) {
   auto idx = std::make_unique<rbq_index>();
   RBQ_HIP(hipGetDevice(&idx->device));
+  RBQ_HIP(hipDeviceGetAttribute(&idx->num_cus, hipDeviceAttributeMultiprocessorCount, idx->device));
   idx->n = n;
   idx->d = d;
   idx->ld = (int)round_up(d, 4);

@@ -88,6 +88,12 @@ struct rbq_index {
   std::vector<int32_t> h_list_len, h_list_mb, h_pos2id;
   float* hostX = nullptr;         // pinned n x d when vectors_on_host
 
+  // options (rbq_set_option) and device facts
+  std::atomic<int> opt_scan{0};
+  std::atomic<int> opt_group_min{4};
+  std::atomic<int64_t> opt_pool_cap{0};
+  int num_cus = 256;
+
   // per-call scratch
   std::mutex ws_mu;
   std::vector<std::unique_ptr<rbq::Workspace>> ws_free;

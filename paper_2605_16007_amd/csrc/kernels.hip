@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
   const int k = a.k, KP = a.KP;
   int ncols = a.ncols;
   if (a.rowcnt) {  // pool mode: the row holds k running keys then rowcnt[row] new ones
-    const uint32_t extra = a.rowcnt[row];
+    const uint32_t extra = min(a.rowcnt[row], (uint32_t)a.max_extra);
     if (extra == 0) return;
     ncols = k + (int)extra;
   }
@@ -460,6 +460,7 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
   const int it = blockIdx.x;
   const int pr = it / a.nq, i = it - pr * a.nq;
   const int p = a.p0 + pr;
+  if (a.qmask && a.qmask[i] == 0u) return;  // uniform over the workgroup
   const int64_t pair = (int64_t)i * a.nprobe + p;
   const int j = a.probes[pair];
   const int len = j >= 0 ? a.L.list_len[j] : 0, mb0 = j >= 0 ? a.L.list_mb[j] : 0;

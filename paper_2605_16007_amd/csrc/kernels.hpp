@@ -77,6 +77,7 @@ struct ScanArgs {
   int p0, pn;              // this launch scans probe ranks [p0, p0 + pn)
   int64_t out_ld;          // keys per query row of `out`: R running keys, then the pool
   uint32_t* pcnt;          // [nq] keys appended to each query's pool
+  const uint32_t* qmask;   // if set, only queries with qmask[i] != 0 are scanned
   uint32_t* qthr;          // [nq] ordered-float bound on each query's R-th estimate (or null)
   uint64_t* out;           // candidate rows (est, id) keys
   int32_t* dump_ip;        // debug: [nq][nprobe][maxlen] (or null)
@@ -84,6 +85,33 @@ struct ScanArgs {
   int64_t maxlen;
 };
 void launch_scan_popc(hipStream_t s, const ScanArgs& a);
+
+// List-major grouped scan on int8 MFMA (kernels_group.hip).
+struct GroupArgs {
+  ListsView L;
+  const uint8_t* qu;       // [pairs][W*32] quantised residuals
+  const float4* scal;      // [pairs] (||r||^2, v_l, Delta, sum qu)
+  int nq, nprobe, R, nlist, G;
+  const int32_t* slots;    // chunk pairs grouped by list
+  const int32_t* pair_off; // [nlist+1]
+  const int32_t* item_off; // [nlist+1] items per list: ceil(pairs / G)
+  const int4* items;       // per item: (list, first slot, pairs)
+  uint32_t* item_counter;  // work-queue cursor, zero before the launch
+  const uint32_t* qthr;    // per-query threshold (ordered float of d_hat^2)
+  uint64_t* pool;          // candidate rows: R running keys then the pool
+  int64_t pool_ld;
+  int cap;                 // pool capacity per query
+  uint32_t* pcnt;          // [nq] pool fill
+  uint32_t* overflow;      // [nq] set when a query's pool overflowed
+  uint32_t* any_overflow;  // set with any overflow flag
+};
+int group_k_steps(int d);
+void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, int p0, int pn,
+                      int nlist, int G, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
+                      int32_t* fill, int32_t* slots, int4* items);
+void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups);
+void launch_reset_masked(hipStream_t s, const uint32_t* mask, uint64_t* rows, int64_t ld, int R,
+                         uint32_t* qthr, uint32_t* pcnt, int nq);
 
 // Exact re-rank: per query, gather the candidates' raw vectors, exact squared
 // L2 in FP32, top-k by (distance, id).

@@ -3,6 +3,7 @@
 // Phase 5 exact re-rank.
 #include <algorithm>
 #include <array>
+#include <vector>
 #include <cstring>
 
 #include "index.hpp"
@@ -39,6 +40,15 @@ struct Bufs {
   float* inj_scal = nullptr;
   uint32_t* qthr = nullptr;
   uint32_t* pcnt = nullptr;
+  uint8_t* qu8 = nullptr;
+  int32_t* gcnt = nullptr;
+  int32_t* gfill = nullptr;
+  int32_t* pair_off = nullptr;
+  int32_t* item_off = nullptr;
+  int32_t* slots = nullptr;
+  int4* items = nullptr;
+  uint32_t* overflow = nullptr;
+  uint32_t* counter = nullptr;
   uint64_t* cand = nullptr;
   int32_t* dump_ip = nullptr;
   float* dump_est = nullptr;
@@ -83,6 +93,47 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
   int first = (int)std::min<int64_t>(pch, std::max<int64_t>(1, (2048 + nq - 1) / nq));
   if (dbg && dbg->probe_chunk > 0) pch = first = std::min(pch, (int)dbg->probe_chunk);
   const int64_t cand_ld = (int64_t)R * (1 + pch);
+  // Chunk schedule. The list-major MFMA scan is used for the whole search
+  // when d <= 256 and the batch probes each list several times on average
+  // (nq * nprobe >= group_min * nlist), or always with RBQ_OPT_SCAN = 2.
+  // Its chunks double the prefix already scanned, so with the threshold at
+  // the exact R-th estimate of that prefix a pool expects about R survivors
+  // per chunk; the first chunk is sized so that even all of its candidates
+  // fit. A query whose pool overflows anyway is searched again, from
+  // scratch, by the query-major scan (exact; checked once per search).
+  // Query-major chunks double up to `pch`, whose worst case (R keys per
+  // item) always fits.
+  const int scan_mode = idx->opt_scan.load();
+  const int group_min = idx->opt_group_min.load();
+  int64_t pool_cap = (int64_t)R * pch;
+  if (idx->opt_pool_cap.load() > 0) pool_cap = std::min<int64_t>(pool_cap, idx->opt_pool_cap.load());
+  // (per-vector dumps of the debug entry point come from the query-major scan)
+  const bool any_group = scan_mode != 1 && !dumps && group_k_steps(d) <= 4 &&
+                         (scan_mode == 2 || nq * (int64_t)nprobe >= (int64_t)group_min * nlist);
+  struct Chunk {
+    int p0, pn;
+  };
+  std::vector<Chunk> chunks, qm_chunks;
+  for (int p0 = 0, pn = first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, pch)) {
+    pn = std::min(pn, nprobe - p0);
+    qm_chunks.push_back({p0, pn});
+  }
+  if (any_group) {
+    // first chunk: about 2R candidates per query on average, and never more
+    // than the pool holds even for the longest lists
+    const int64_t maxl = std::max<int64_t>(1, idx->max_list_len);
+    const int64_t avgl = std::max<int64_t>(1, idx->n / nlist);
+    int pn = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nprobe, pool_cap / maxl,
+                                                          ceil_div(2 * (int64_t)R, avgl)}));
+    if (dbg && dbg->probe_chunk > 0) pn = std::min(pn, (int)dbg->probe_chunk);
+    for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, p0)) {
+      pn = std::min(pn, nprobe - p0);
+      chunks.push_back({p0, pn});
+    }
+  } else {
+    chunks = qm_chunks;
+  }
+  const int64_t max_chunk_pairs = pairs;
   auto layout = [&](Carver& c, Bufs& b) {
     if (need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
     if (!inj_probes) b.score = c.take<float>((size_t)nq * nlist);
@@ -90,7 +141,17 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
     b.qrot = c.take<float>((size_t)nq * ld);
     b.planes = c.take<uint32_t>((size_t)pairs * W * bqs);
-    if (dbg && dbg->qu) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
+    if ((dbg && dbg->qu) || any_group) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
+    if (any_group) {
+      b.gcnt = c.take<int32_t>(nlist);
+      b.gfill = c.take<int32_t>(nlist);
+      b.pair_off = c.take<int32_t>(nlist + 1);
+      b.item_off = c.take<int32_t>(nlist + 1);
+      b.slots = c.take<int32_t>(max_chunk_pairs);
+      b.items = c.take<int4>(max_chunk_pairs / 64 + nlist + 1);
+      b.overflow = c.take<uint32_t>(nq);
+      b.counter = c.take<uint32_t>(2);
+    }
     b.scal = c.take<float4>(pairs);
     if (inj_qu) {
       b.inj_qu = c.take<uint8_t>((size_t)pairs * d);
@@ -190,7 +251,30 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     sa.maxlen = maxlen;
     launch_fill_rows_u64(s, b.cand, cand_ld, nq, R, KEY_NONE);  // running top-R starts empty
     launch_fill_u32(s, b.pcnt, 0u, nq);
+    if (any_group) launch_fill_u32(s, b.overflow, 0u, nq);
     sa.pcnt = b.pcnt;
+    sa.qmask = nullptr;
+    GroupArgs ga;
+    ga.L = sa.L;
+    ga.qu = b.qu;
+    ga.scal = b.scal;
+    ga.nq = (int)nq;
+    ga.nprobe = nprobe;
+    ga.R = R;
+    ga.nlist = nlist;
+    ga.G = 64;
+    ga.slots = b.slots;
+    ga.pair_off = b.pair_off;
+    ga.item_off = b.item_off;
+    ga.items = b.items;
+    ga.item_counter = b.counter;
+    ga.any_overflow = b.counter + 1;
+    ga.qthr = b.qthr;
+    ga.pool = b.cand;
+    ga.pool_ld = cand_ld;
+    ga.cap = (int)pool_cap;
+    ga.pcnt = b.pcnt;
+    ga.overflow = b.overflow;
     TopkArgs ma;
     ma.keys = b.cand;
     ma.ld = cand_ld;
@@ -199,21 +283,56 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     ma.ldo = cand_ld;
     ma.rowcnt = b.pcnt;
     ma.qthr = b.qthr;
-    for (int p0 = 0, pn = first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, pch)) {
-      sa.p0 = p0;
-      sa.pn = pn = std::min(pn, nprobe - p0);
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (timed) {
-        e0 = newev();
-        e1 = newev();
-        tr.scan.push_back(e0);
-        tr.scan.push_back(e1);
-        RBQ_HIP(hipEventRecord(e0, s));
+    auto scan_qm_chunks = [&]() {
+      for (const auto& ch : qm_chunks) {
+        sa.p0 = ch.p0;
+        sa.pn = ch.pn;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+          e0 = newev();
+          e1 = newev();
+          tr.scan.push_back(e0);
+          tr.scan.push_back(e1);
+          RBQ_HIP(hipEventRecord(e0, s));
+        }
+        launch_scan_popc(s, sa);
+        if (timed) RBQ_HIP(hipEventRecord(e1, s));
+        ma.max_extra = R * ch.pn;
+        launch_row_topk(s, ma, (int)nq);
       }
-      launch_scan_popc(s, sa);
-      if (timed) RBQ_HIP(hipEventRecord(e1, s));
-      ma.max_extra = R * pn;
-      launch_row_topk(s, ma, (int)nq);
+    };
+    if (!any_group) {
+      scan_qm_chunks();
+    } else {
+      launch_fill_u32(s, b.counter + 1, 0u, 1);
+      for (const auto& ch : chunks) {
+        launch_group_map(s, b.probes, (int)nq, nprobe, ch.p0, ch.pn, nlist, ga.G, b.gcnt,
+                         b.pair_off, b.item_off, b.gfill, b.slots, b.items);
+        launch_fill_u32(s, b.counter, 0u, 1);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed) {
+          e0 = newev();
+          e1 = newev();
+          tr.scan.push_back(e0);
+          tr.scan.push_back(e1);
+          RBQ_HIP(hipEventRecord(e0, s));
+        }
+        launch_scan_group(s, ga, 8 * idx->num_cus);
+        if (timed) RBQ_HIP(hipEventRecord(e1, s));
+        ma.max_extra = (int)pool_cap;
+        launch_row_topk(s, ma, (int)nq);
+      }
+      // one check per search: queries whose pool overflowed are searched
+      // again by the query-major scan
+      uint32_t any = 0;
+      RBQ_HIP(hipMemcpyAsync(&any, b.counter + 1, sizeof(any), hipMemcpyDeviceToHost, s));
+      RBQ_HIP(hipStreamSynchronize(s));
+      if (any) {
+        launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
+        sa.qmask = b.overflow;
+        scan_qm_chunks();
+        sa.qmask = nullptr;
+      }
     }
     const uint64_t* top = b.cand;
     mark(4);

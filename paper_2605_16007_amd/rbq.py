@@ -22,8 +22,9 @@ EXPORT = {"centroids": 1, "rotation": 2, "assign": 3, "codes": 4, "factors": 5, 
 SYMBOLS = [
     "rbq_build_params_init", "rbq_build_index", "rbq_free_index", "rbq_get_info", "rbq_search",
     "rbq_export", "rbq_search_debug", "rbq_set_timing", "rbq_get_timings", "rbq_save",
-    "rbq_load", "rbq_last_error", "rbq_version",
+    "rbq_load", "rbq_last_error", "rbq_version", "rbq_set_option",
 ]
+OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3}
 
 
 class BuildParams(C.Structure):
@@ -88,6 +89,7 @@ def lib():
         L.rbq_search_debug.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(DebugIO)]
         L.rbq_set_timing.argtypes = [vp, i32]
         L.rbq_get_timings.argtypes = [vp, C.POINTER(Timings)]
+        L.rbq_set_option.argtypes = [vp, i32, i64]
         L.rbq_save.argtypes = [vp, C.c_char_p]
         L.rbq_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.rbq_last_error.restype = C.c_char_p
@@ -275,6 +277,11 @@ class Index:
         _check(lib().rbq_search_debug(self._h, q.ctypes.data, nq, int(nprobe), int(k),
                                       int(rerank_n), C.byref(io)))
         return out
+
+    def set_option(self, name: str, value: int):
+        """Tuning knobs: scan (0 auto, 1 query-major popcount, 2 list-major
+        MFMA), group_min, pool_cap; see rbq_set_option in include/rbq.h."""
+        _check(lib().rbq_set_option(self._h, OPTIONS[name], int(value)))
 
     # ---------------------------------------------------------------- timing
     def set_timing(self, enabled: bool):

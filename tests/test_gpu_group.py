@@ -1,0 +1,103 @@
+"""GPU tests of the list-major int8-MFMA scan.
+
+Its estimator epilogue is the same expression as the query-major popcount
+scan's and the selection is exact, so both scans must return identical
+candidates and results; with the oracle's probes, qu and scalars injected the
+candidates must also match the oracle's (same rule as test_gpu_parity P6).
+A tiny pool capacity forces the overflow path (restore + query-major redo).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests._parity import est_scale, lib_index, make_case, set_diff_ok
+
+pytestmark = pytest.mark.gpu
+
+WANT = {"cand_ids", "cand_est", "ids", "sqdist"}
+
+SHAPES = [
+    # name, n, d, nlist, nq, nprobe, k, R, kind, bq
+    ("g128", 20_000, 128, 16, 150, 12, 10, 100, "mixture", 4),
+    ("g96", 12_000, 96, 12, 70, 9, 10, 60, "unit_mixture", 4),
+    ("g40_bq8", 9_000, 40, 10, 90, 7, 5, 40, "mixture", 8),
+    ("g13", 4_000, 13, 8, 33, 6, 5, 30, "mixture", 2),
+    ("g256", 6_000, 256, 8, 40, 5, 10, 80, "gamma_int", 4),
+]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", params=list(enumerate(SHAPES)), ids=[s[0] for s in SHAPES])
+def gcase(request):
+    seed, (name, n, d, nlist, nq, nprobe, k, R, kind, bq) = request.param
+    _say(f"[group {name}] n={n} d={d} nlist={nlist} nq={nq} nprobe={nprobe} R={R} bq={bq}")
+    X, Q, idx = make_case(n, d, nlist, nq, seed=100 + seed, kind=kind)
+    idx.bq = bq
+    lib = lib_index(X, idx, bq=bq)
+    return dict(name=name, X=X, Q=Q, idx=idx, lib=lib, nprobe=nprobe, k=k, R=R, d=d)
+
+
+def _run(lib, Q, nprobe, k, R, scan, pool_cap=0, **kw):
+    lib.set_option("scan", scan)
+    lib.set_option("pool_cap", pool_cap)
+    try:
+        return lib.search_debug(Q, nprobe, k, R, want=WANT, **kw)
+    finally:
+        lib.set_option("scan", 0)
+        lib.set_option("pool_cap", 0)
+
+
+def test_group_equals_query_major(gcase):
+    lib, Q = gcase["lib"], gcase["Q"]
+    a = _run(lib, Q, gcase["nprobe"], gcase["k"], gcase["R"], scan=1)
+    b = _run(lib, Q, gcase["nprobe"], gcase["k"], gcase["R"], scan=2)
+    for key in WANT:
+        np.testing.assert_array_equal(b[key], a[key], err_msg=key)
+
+
+@pytest.mark.parametrize("cap", [1, 37])
+def test_group_overflow_path_is_exact(gcase, cap):
+    lib, Q = gcase["lib"], gcase["Q"]
+    a = _run(lib, Q, gcase["nprobe"], gcase["k"], gcase["R"], scan=1)
+    b = _run(lib, Q, gcase["nprobe"], gcase["k"], gcase["R"], scan=2, pool_cap=cap)
+    for key in WANT:
+        np.testing.assert_array_equal(b[key], a[key], err_msg=f"{key} cap {cap}")
+
+
+def test_group_candidates_match_oracle(gcase):
+    """Oracle probes, qu and scalars injected; list-major scan; P6 rule."""
+    lib, Q, X, idx = gcase["lib"], gcase["Q"], gcase["X"], gcase["idx"]
+    nprobe, k, R, d = gcase["nprobe"], gcase["k"], gcase["R"], gcase["d"]
+    _, _, st = O.search(idx, X, Q, nprobe, k, R, stages=True)
+    nq = len(Q)
+    probes = np.array(st["probes"], np.int32)
+    qu = np.zeros((nq, nprobe, d), np.uint8)
+    sc = np.zeros((nq, nprobe, 3), np.float32)
+    for qi in range(nq):
+        for p in range(nprobe):
+            qu[qi, p] = st["qu"][qi][p]
+            sc[qi, p] = (st["rnorm2"][qi][p], st["vl"][qi][p], st["delta"][qi][p])
+    out = _run(lib, Q, nprobe, k, R, scan=2, inject_probes=probes, inject_qu=qu, inject_scalars=sc)
+    for qi in range(nq):
+        val, tol = {}, {}
+        for p, pl in enumerate(st["per_list"][qi]):
+            S = est_scale(st["rnorm2"][qi][p], st["vl"][qi][p], st["delta"][qi][p],
+                          st["sumqu"][qi][p], pl["ip"], pl["pop"], idx.n_x[pl["ids"]],
+                          idx.alpha[pl["ids"]], d)
+            for i, e, s in zip(pl["ids"].tolist(), pl["est"].tolist(), S.tolist()):
+                val[i], tol[i] = e, 2e-5 * s
+        ref = st["cand_ids"][qi]
+        rv = ref[ref >= 0]
+        boundary = val[int(rv[-1])] if len(rv) else math.inf
+        bad = set_diff_ok(out["cand_ids"][qi], ref, lambda x: val[x], boundary, lambda x: tol[x])
+        assert not bad, (qi, bad[:5])
+        g = out["cand_ids"][qi]
+        for i, e in zip(g[g >= 0].tolist(), out["cand_est"][qi].tolist()):
+            assert abs(e - val[i]) <= tol[i]
