@@ -296,7 +296,23 @@ __global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
   const int cnt = min((int)s_cnt, k);
   for (int i = cnt + tid; i < KP; i += 256) sel[i] = KEY_NONE;
   __syncthreads();
-  bitonic_sort_lds(sel, KP);
+  uint64_t kth;  // the k-th smallest key (KEY_NONE if fewer than k)
+  if (a.sorted) {
+    bitonic_sort_lds(sel, KP);
+    kth = sel[k - 1];
+  } else {  // the selected keys in any order; their maximum is the k-th
+    uint64_t mx = 0;
+    for (int i = tid; i < k; i += 256) mx = sel[i] > mx ? sel[i] : mx;
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_xor(mx, off);
+      mx = o > mx ? o : mx;
+    }
+    __shared__ uint64_t s_mx[4];
+    if ((tid & 63) == 0) s_mx[tid >> 6] = mx;
+    __syncthreads();
+    kth = s_mx[0];
+    for (int w = 1; w < 4; ++w) kth = s_mx[w] > kth ? s_mx[w] : kth;
+  }
   for (int i = tid; i < k; i += 256) {
     const uint64_t v = sel[i];
     if (a.out_keys) a.out_keys[row * a.ldo + i] = v;
@@ -305,7 +321,7 @@ __global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
   }
   if (tid == 0) {
     if (a.rowcnt) a.rowcnt[row] = 0;
-    if (a.qthr && sel[k - 1] != KEY_NONE) atomicMin(&a.qthr[row], (uint32_t)(sel[k - 1] >> 32));
+    if (a.qthr && kth != KEY_NONE) atomicMin(&a.qthr[row], (uint32_t)(kth >> 32));
   }
 }
 
@@ -571,42 +587,119 @@ void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
 
 // ---------------------------------------------------------------------------
 // Exact re-rank (Phase 5 on the GPU): per query, the R candidates' raw vectors
-// are gathered (one wave per candidate), ||q - x||^2 is summed in FP32 and the
-// k best (distance, id) pairs are kept.
+// are gathered (16 lanes per candidate, float4 loads, four candidates per wave
+// in flight), ||q - x||^2 is summed in FP32, and the k best (distance, id)
+// keys are selected by an MSB-first radix select and sorted.
 // ---------------------------------------------------------------------------
+
+// The k smallest of n 64-bit keys held in LDS (whole workgroup): after the
+// call, sel[0..k) holds them ascending. hist: 256 words, wsum: 4 words,
+// sel: KP = pow2 >= k keys.
+__device__ void lds_select_sorted(const uint64_t* keys, int n, int k, int KP, uint64_t* sel,
+                                  uint32_t* hist, uint32_t* wsum, uint32_t* s_misc) {
+  const int tid = threadIdx.x;
+  uint64_t prefix = 0, pmask = 0;
+  uint32_t rem = (uint32_t)k;
+  const bool take_all = n <= k;
+  if (!take_all) {
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      hist[tid] = 0;
+      __syncthreads();
+      for (int c = tid; c < n; c += 256) {
+        const uint64_t key = keys[c];
+        if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+      }
+      __syncthreads();
+      const uint32_t h = hist[tid];
+      const uint32_t incl = block_incl_scan_256(h, wsum);
+      const uint32_t excl = incl - h;
+      if (excl < rem && rem <= incl) {
+        s_misc[0] = (uint32_t)tid;
+        s_misc[1] = rem - excl;
+        s_misc[2] = h;
+      }
+      __syncthreads();
+      prefix |= (uint64_t)s_misc[0] << shift;
+      pmask |= 0xFFull << shift;
+      rem = s_misc[1];
+      const uint32_t bucket = s_misc[2];
+      __syncthreads();
+      if (bucket == rem) break;
+    }
+  }
+  if (tid == 0) s_misc[3] = 0;
+  __syncthreads();
+  if (take_all) {
+    for (int c = tid; c < n; c += 256) sel[atomicAdd(&s_misc[3], 1u)] = keys[c];
+  } else {
+    for (int c = tid; c < n; c += 256)
+      if (keys[c] < prefix) sel[atomicAdd(&s_misc[3], 1u)] = keys[c];
+    __syncthreads();
+    const uint64_t hi = prefix | ~pmask;
+    for (int c = tid; c < n; c += 256) {
+      const uint64_t key = keys[c];
+      if (key >= prefix && key <= hi) {
+        const uint32_t p = atomicAdd(&s_misc[3], 1u);
+        if (p < (uint32_t)k) sel[p] = key;
+      }
+    }
+  }
+  __syncthreads();
+  const int cnt = min((int)s_misc[3], k);
+  for (int i = cnt + tid; i < KP; i += 256) sel[i] = KEY_NONE;
+  __syncthreads();
+  bitonic_sort_lds(sel, KP);
+}
 
 __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int ldq,
                                                 const float* __restrict__ X, int64_t n, int ldx, int d,
                                                 const uint64_t* __restrict__ cand, int64_t ldc,
                                                 int R, int k, int KP, int64_t* __restrict__ ids,
                                                 float* __restrict__ dist) {
+  // [R] candidate keys, then [KP] selection keys; KP < 0 means no separate
+  // selection buffer: ck holds -KP (pow2 >= R) keys and is sorted in place
   extern __shared__ uint64_t ck[];
-  float* qs = reinterpret_cast<float*>(ck + KP);
+  uint64_t* sel = ck + (KP > 0 ? R : -KP);
+  float4* qs = reinterpret_cast<float4*>(sel + (KP > 0 ? KP : 0));  // the query, ldx/4 float4
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t s_misc[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sub = lane >> 4, sl = lane & 15;  // candidate slot in the wave, lane in the slot
   const int64_t i = blockIdx.x;
-  for (int t = tid; t < d; t += 256) qs[t] = q[i * ldq + t];
-  for (int t = R + tid; t < KP; t += 256) ck[t] = KEY_NONE;
+  const int nf4 = ldx >> 2;
+  for (int t = tid; t < nf4; t += 256)
+    qs[t] = (t * 4 < d) ? reinterpret_cast<const float4*>(q + i * ldq)[t] : make_float4(0, 0, 0, 0);
   __syncthreads();
-  for (int c = wave; c < R; c += 4) {
-    const uint64_t key = cand[i * ldc + c];
-    uint64_t out = KEY_NONE;
-    if (key != KEY_NONE && (int64_t)(uint32_t)key < n) {  // ids outside [0, n) are never read
-      const uint32_t id = (uint32_t)key;
-      const float* x = X + (size_t)id * ldx;
-      float acc = 0.f;
-      for (int t = lane; t < d; t += 64) {
-        const float df = qs[t] - x[t];
-        acc += df * df;
+  // 16 candidates per workgroup round: wave w, slot s takes candidate 16 r + 4 w + s
+  for (int c0 = 0; c0 < R; c0 += 16) {
+    const int c = c0 + 4 * wave + sub;
+    uint64_t key = c < R ? cand[i * ldc + c] : KEY_NONE;
+    const bool ok = key != KEY_NONE && (int64_t)(uint32_t)key < n;  // ids outside [0, n) are never read
+    float acc = 0.f;
+    if (ok) {
+      const float4* x = reinterpret_cast<const float4*>(X + (size_t)(uint32_t)key * ldx);
+      for (int f = sl; f < nf4; f += 16) {
+        const float4 xv = x[f], qv = qs[f];
+        const float a0 = qv.x - xv.x, a1 = qv.y - xv.y, a2 = qv.z - xv.z, a3 = qv.w - xv.w;
+        acc += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
       }
-      acc = wave_sum(acc);
-      out = key64(acc, id);
     }
-    if (lane == 0) ck[c] = out;
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (sl == 0 && c < R) ck[c] = ok ? key64(acc, (uint32_t)key) : KEY_NONE;
   }
   __syncthreads();
-  bitonic_sort_lds(ck, KP);
+  if (KP > 0) {
+    lds_select_sorted(ck, R, k, KP, sel, hist, wsum, s_misc);
+  } else {  // large k: sort all candidates in place (ck holds pow2 >= R keys)
+    const int KR = -KP;
+    for (int t = R + tid; t < KR; t += 256) ck[t] = KEY_NONE;
+    __syncthreads();
+    bitonic_sort_lds(ck, KR);
+    sel = ck;
+  }
   for (int r = tid; r < k; r += 256) {
-    const uint64_t v = ck[r];
+    const uint64_t v = sel[r];
     ids[i * k + r] = v == KEY_NONE ? -1 : (int64_t)(uint32_t)v;
     dist[i * k + r] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
   }
@@ -616,8 +709,14 @@ void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64
                    int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
                    float* dist) {
   if (nq <= 0) return;
-  const int KP = pow2_at_least(R);
-  const size_t lds = KP * sizeof(uint64_t) + (size_t)d * sizeof(float);
+  RBQ_CHECK(ldx % 4 == 0 && ldq % 4 == 0, "rows must be padded to 4 floats");
+  int KP = pow2_at_least(k);
+  size_t lds = (size_t)(R + KP) * sizeof(uint64_t) + (size_t)ldx * sizeof(float);
+  if (lds > (size_t)(60 << 10)) {
+    KP = -pow2_at_least(R);
+    lds = (size_t)(-KP) * sizeof(uint64_t) + (size_t)ldx * sizeof(float);
+  }
+  RBQ_CHECK(lds <= (size_t)(64 << 10), "re-rank needs too much LDS for this d and rerank_n");
   hipLaunchKernelGGL(k_rerank, dim3(nq), dim3(256), lds, s, q, ldq, X, n, ldx, d, cand, ldc, R, k,
                      KP, ids, dist);
   RBQ_HIP(hipGetLastError());

@@ -57,6 +57,7 @@ struct TopkArgs {
   uint32_t* rowcnt = nullptr;
   int max_extra = 0;           // largest rowcnt (pool mode)
   uint32_t* qthr = nullptr;
+  bool sorted = true;          // false: the k keys in any order (pool merges)
   int KP = 0, cache_cap = 0;   // set by the launcher
 };
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows);

@@ -122,8 +122,8 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   __shared__ float4 sSc[GMAX];                // (||r||^2, v_l, Delta, sum qu) per query slot
   __shared__ float sThr[GMAX];                // threshold on d_hat^2 per query slot
   __shared__ int32_t sQ[GMAX];                // query id per slot
-  __shared__ uint32_t sCode[4][2 * KSMAX][64];  // per wave: the micro-block's code words
-  __shared__ float sPop[4][64], sAdd[4][64], sMul[4][64];
+  __shared__ uint32_t sCode[4][2 * KS][64];  // per wave: the micro-block's code words
+  __shared__ __align__(16) float sPop[4][64], sAdd[4][64], sMul[4][64];
   __shared__ uint64_t sStage[4][STAGE];        // per wave: survivors (est, position)
   __shared__ uint8_t sStageQ[4][STAGE];        // their query slot
   __shared__ uint32_t sFcnt[4][GMAX], sFbase[4][GMAX];  // per wave: flush counts and bases
@@ -198,6 +198,20 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
       sB[n][t][l] = v;
     }
     __syncthreads();
+    // this lane's query (column lane & 15 of each 16-query tile): scalars in
+    // registers for the whole item; an empty slot gets a NaN threshold
+    float qrn2[GMAX / 16], qvl[GMAX / 16], qdelta[GMAX / 16], qthr[GMAX / 16];
+    int qsum[GMAX / 16];
+#pragma unroll
+    for (int n = 0; n < GMAX / 16; ++n) {
+      const int q = 16 * n + (lane & 15);
+      const float4 sc = sSc[q];
+      qrn2[n] = sc.x;
+      qvl[n] = sc.y;
+      qdelta[n] = sc.z;
+      qsum[n] = (int)sc.w;
+      qthr[n] = q < count ? sThr[q] : NAN;
+    }
     const int len = a.L.list_len[j], mb0 = a.L.list_mb[j];
     const int nmb = (len + 63) >> 6;
     const size_t rec = (size_t)(W + 2) * 64;
@@ -238,36 +252,46 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
           const uint32_t word = sCode[wave][2 * t + (lg >> 1)][vrow];
           A[t] = unpack16((word >> (16 * (lg & 1))) & 0xFFFFu);
         }
-        for (int n = 0; n < nt; ++n) {
+        // the four vectors of this lane's result rows: 16 m + 4 lg + r
+        const float4 fadd4 = *reinterpret_cast<const float4*>(&sAdd[wave][16 * m + 4 * lg]);
+        const float4 pop4 = *reinterpret_cast<const float4*>(&sPop[wave][16 * m + 4 * lg]);
+        const float4 fmul4 = *reinterpret_cast<const float4*>(&sMul[wave][16 * m + 4 * lg]);
+        const float fadd[4] = {fadd4.x, fadd4.y, fadd4.z, fadd4.w};
+        const float popt[4] = {pop4.x, pop4.y, pop4.z, pop4.w};
+        const float fmul[4] = {fmul4.x, fmul4.y, fmul4.z, fmul4.w};
+#pragma unroll
+        for (int n = 0; n < GMAX / 16; ++n) {
+          if (n >= nt) break;
           v4i acc = {0, 0, 0, 0};
 #pragma unroll
           for (int t = 0; t < KS; ++t)
             acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t], sB[n][t][lane], acc, 0, 0, 0);
-          const int q = 16 * n + (lane & 15);
-          const bool qok = q < count;
-          const float4 sc = sSc[q & (GMAX - 1)];
-          const float thr = sThr[q & (GMAX - 1)];
-          const int sumqu = (int)sc.w;
+          float est[4];
+          bool pass[4];
+          bool anyp = false;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int v = 16 * m + 4 * lg + r;
-            const float fadd = sAdd[wave][v];
-            const float E = sc.y * sPop[wave][v] + sc.z * (float)(2 * acc[r] - sumqu);
-            const float est = sc.x + fadd + sMul[wave][v] * E;
-            const bool pass = qok && est <= thr;  // NaN (padding lanes) never passes
-            const uint64_t mask = __ballot(pass);
-            if (mask) {  // wave-uniform: append to this wave's stage
-              if (pass) {
+            const float E = qvl[n] * popt[r] + qdelta[n] * (float)(2 * acc[r] - qsum[n]);
+            est[r] = qrn2[n] + fadd[r] + fmul[r] * E;
+            pass[r] = est[r] <= qthr[n];  // NaN (padding lanes, empty slots) never passes
+            anyp |= pass[r];
+          }
+          if (__ballot(anyp)) {  // rare: stage the survivors of this tile
+            const int q = 16 * n + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const uint64_t mask = __ballot(pass[r]);
+              if (pass[r]) {
                 const int e = stage_n + (int)lane_prefix(mask);
-                sStage[wave][e] = key64(est, (uint32_t)((mb0 + mb) * 64 + v));
+                sStage[wave][e] = key64(est[r], (uint32_t)((mb0 + mb) * 64 + 16 * m + 4 * lg + r));
                 sStageQ[wave][e] = (uint8_t)q;
               }
               stage_n += (int)__popcll(mask);
-              if (stage_n > STAGE - 64) {
-                __builtin_amdgcn_wave_barrier();
-                flush(stage_n);
-                stage_n = 0;
-              }
+            }
+            if (stage_n > STAGE - 256) {
+              __builtin_amdgcn_wave_barrier();
+              flush(stage_n);
+              stage_n = 0;
             }
           }
         }

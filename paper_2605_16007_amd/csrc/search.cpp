@@ -283,6 +283,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     ma.ldo = cand_ld;
     ma.rowcnt = b.pcnt;
     ma.qthr = b.qthr;
+    ma.sorted = false;
     auto scan_qm_chunks = [&]() {
       for (const auto& ch : qm_chunks) {
         sa.p0 = ch.p0;
@@ -335,6 +336,16 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       }
     }
     const uint64_t* top = b.cand;
+    if (dbg && (dbg->cand_ids || dbg->cand_est)) {  // the debug output lists candidates ascending
+      TopkArgs so;
+      so.keys = b.cand;
+      so.ld = cand_ld;
+      so.ncols = R;
+      so.k = R;
+      so.out_keys = b.cand;
+      so.ldo = cand_ld;
+      launch_row_topk(s, so, (int)nq);
+    }
     mark(4);
     // Phase 5: exact re-rank of the top-R on the GPU
     int64_t* ids_out = ids_dev ? ids : b.ids;

@@ -174,3 +174,19 @@ def test_search_rejects_bad_arguments_on_gpu_index():
     for args in ((0, 5, 10), (9, 5, 10), (4, 11, 10), (4, 0, 10), (4, 5, 3841)):
         with pytest.raises(RbqError, match="status -1"):
             lib.search(Q, *args)
+
+
+def test_large_k_rerank():
+    """k = rerank_n at the largest allowed size (the re-rank sorts all
+    candidates in place) and a large k below it (radix select path)."""
+    _say("[edge] large k")
+    X, Q, idx = make_case(6000, 32, 4, 5, seed=13)
+    lib = lib_index(X, idx)
+    for k, R in ((3840, 3840), (2900, 3000)):
+        ids, dd = lib.search(Q, 4, k, R)
+        ref_ids, ref_d = O.search(idx, X, Q, 4, k, R)
+        for qi in range(len(Q)):
+            g = ids[qi]
+            assert np.all(np.diff(dd[qi][g >= 0]) >= 0)
+            common = len(set(g.tolist()) & set(ref_ids[qi].tolist()))
+            assert common >= k - 5, (k, qi, common)
