@@ -2,11 +2,12 @@
 """Benchmark of batched IVF-RaBitQ search on one MI355X.
 
 Workload (default ``sift10m``): 10M x 128 integer-valued skewed vectors,
-nlist 4096, batches of 1024 queries, B_q 4, k 10, rerank 100. A step is one
-pass of the whole search path over one batch: probe GEMM + top-nprobe, query
-rotation, residual quantisation, code scan with the fused estimator, per-query
-top-R, exact re-rank. nprobe is the smallest of the workload's values (32, 64,
-128) whose recall@10 reaches 0.95 (measured against exact kNN before timing).
+nlist 4096, batches of 1024 queries, B_q 4, k 10. A step is one pass of the
+whole search path over one batch: probe GEMM + top-nprobe, query rotation,
+residual quantisation, code scan with the fused estimator, per-query top-R,
+exact re-rank. The operating point (nprobe, rerank_n) is the fastest measured
+point whose recall@10 against exact kNN reaches 0.95: the workload's listed
+points first, then a wider grid; ``--nprobe``/``--rerank`` fix it instead.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -25,6 +26,36 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QPS at recall@10>=0.95 (1 GPU), code-scan HBM GB/s vs peak, p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
+# 32-bit VALU lane-ops of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed FP32)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU operations the estimator epilogue needs per (query, vector) once the
+# integer inner product is known: 2 ip - sum(qu), int->float, two products and
+# a sum for E, (||r||^2 + n_x^2), the factor product and its sum, the threshold
+# compare
+EPILOGUE_OPS = 9
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_scan_group_sift10m_pmc.md")
+GROUP_SRC = os.path.join(ROOT, "paper_2605_16007_amd", "csrc", "kernels_group.hip")
+
+
+def pmc_traffic(workload, nprobe, rerank):
+    """HBM bytes per k_scan_group launch from the committed PMC summary, if the
+    kernel source has not changed since the counters were taken and they were
+    taken at this workload and operating point."""
+    import hashlib
+    import re
+    try:
+        text = open(PMC_SUMMARY).read()
+        sha = hashlib.sha256(open(GROUP_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    o = re.search(r"operating_point:\s*(\S+)\s+nprobe=(\d+)\s+rerank=(\d+)", text)
+    if not m or not t or not o or m.group(1) != sha:
+        return None
+    if (o.group(1), int(o.group(2)), int(o.group(3))) != (workload, nprobe, rerank):
+        return None
+    return float(t.group(1))
 
 
 def log(*a):
@@ -151,7 +182,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sift10m")
     ap.add_argument("--nprobe", type=int, default=0,
-                    help="fix nprobe (default: smallest workload value reaching recall@10 >= 0.95)")
+                    help="fix nprobe (default: the fastest point reaching recall@10 >= 0.95)")
+    ap.add_argument("--rerank", type=int, default=0, help="fix rerank_n (with --nprobe)")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="finish with one device-to-device copy of this size (PMC calibration)")
     ap.add_argument("--n", type=int, default=0, help="database rows (default: the workload's)")
     ap.add_argument("--batches", type=int, default=4, help="distinct query batches cycled")
     ap.add_argument("--latency-iters", type=int, default=50)
@@ -224,7 +258,7 @@ def main():
         return w.nq * steps / (time.perf_counter() - t)
 
     rec, prec = {}, {}
-    points = [(p, w.rerank_n) for p in ((args.nprobe,) if args.nprobe else w.nprobe)]
+    points = [(p, args.rerank or w.rerank_n) for p in ((args.nprobe,) if args.nprobe else w.nprobe)]
     for pt in points:
         rec[pt] = eval_point(*pt)
         prec[pt[0]] = probe_recall(pt[0])
@@ -244,7 +278,9 @@ def main():
                 if rec[pt] >= 0.95:
                     ok.append(pt)
                     break
-    if ok:
+    if args.nprobe:
+        nprobe, R = points[0]
+    elif ok:
         qq = {pt: quick_qps(*pt) for pt in ok}
         nprobe, R = max(ok, key=lambda pt: qq[pt])
         log("[choose] " + ", ".join(f"{pt}: {q:.0f} q/s" for pt, q in qq.items()))
@@ -293,9 +329,40 @@ def main():
         cpu_pool.close()
 
     ns = max(1, tm["searches"])
-    scan_ms = tm["scan_ms"] / ns
-    scan_bytes = tm["scan_bytes"] / ns
-    achieved = scan_bytes / (scan_ms * 1e-3) / 1e9
+    scan_s = tm["scan_ms"] / ns * 1e-3
+    if tm["group_launches"] > 0:
+        # list-major int8-MFMA scan: bound by the VALU epilogue
+        launches = tm["group_launches"] / ns
+        ops = tm["scanned_vectors"] / ns * EPILOGUE_OPS
+        achieved = ops / scan_s / 1e12
+        traffic = pmc_traffic(w.name, nprobe, R)
+        roofline = {"kernel": "k_scan_group", "bound": "alu", "achieved": achieved,
+                    "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                    "traffic": traffic,
+                    "launches_per_step": launches,
+                    "avg_launch_ms": scan_s * 1e3 / launches,
+                    "estimates_per_launch": tm["scanned_vectors"] / ns / launches,
+                    "read_bytes_per_launch": tm["read_bytes"] / ns / launches,
+                    "read_gbs": tm["read_bytes"] / ns / scan_s / 1e9,
+                    "schedule_gbs_effective": tm["scan_bytes"] / ns / scan_s / 1e9}
+    else:
+        launches = max(1, tm["popc_launches"]) / ns
+        achieved = tm["read_bytes"] / ns / scan_s / 1e9
+        roofline = {"kernel": "k_scan_popc", "bound": "hbm", "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": None, "launches_per_step": launches,
+                    "avg_launch_ms": scan_s * 1e3 / launches,
+                    "bytes_per_launch": tm["read_bytes"] / ns / launches}
+    if args.calibrate_copy_gib > 0:
+        nb = int(args.calibrate_copy_gib * (1 << 30)) // 4
+        a = torch.ones(nb, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[calibrate] copied {nb * 4} bytes device to device")
+        del a, b
+
     line = {
         "metric": METRIC,
         "value": qps,
@@ -307,7 +374,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32 popcount + fp32",
+        "dtype": "i8 MFMA / u32 popcount + fp32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,
                    "batch": w.nq, "k": w.k, "rerank_n": R, "bq": w.bq,
@@ -321,10 +388,7 @@ def main():
         "p99_ms": p99,
         "stage_ms": {s: tm[f"{s}_ms"] / ns for s in
                      ("probe", "rotate", "quant", "scan", "merge", "rerank", "total")},
-        "roofline": {"kernel": "k_scan_popc", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
-                     "bytes_per_launch": scan_bytes, "avg_launch_ms": scan_ms},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "build_s": build_s,
     }

@@ -166,8 +166,14 @@ rbq_status rbq_search_debug(rbq_index* idx, const float* q, int64_t nq, int32_t 
 typedef struct {
   int64_t searches;          /* timed searches summed */
   float probe_ms, rotate_ms, quant_ms, scan_ms, merge_ms, rerank_ms, total_ms;
-  int64_t scanned_vectors;   /* sum over (query, probed list) of list sizes */
-  int64_t scan_bytes;        /* scanned_vectors * (4*ceil(d/32) + 8): codes + 2 factors */
+  int64_t scanned_vectors;   /* sum over (query, probed list) of list sizes: the
+                                estimated distances computed */
+  int64_t scan_bytes;        /* scanned_vectors * (4*ceil(d/32) + 8): code and factor
+                                bytes if every (query, list) pair read its list */
+  int64_t read_bytes;        /* code and factor bytes the scan kernels' schedule reads
+                                (list-major items read a list once per item) */
+  int64_t group_launches;    /* list-major scan launches summed */
+  int64_t popc_launches;     /* query-major scan launches summed */
 } rbq_timings;
 
 rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled);

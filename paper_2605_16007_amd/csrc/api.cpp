@@ -373,8 +373,8 @@ rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled) {
     idx->pending.clear();
     idx->last = rbq_timings{};
     if (enabled) {
-      if (!idx->tcounter.p) idx->tcounter.alloc(sizeof(unsigned long long));
-      RBQ_HIP(hipMemset(idx->tcounter.p, 0, sizeof(unsigned long long)));
+      if (!idx->tcounter.p) idx->tcounter.alloc(2 * sizeof(unsigned long long));
+      RBQ_HIP(hipMemset(idx->tcounter.p, 0, 2 * sizeof(unsigned long long)));
     }
     idx->timing.store(enabled ? 1 : 0);
   });
@@ -403,16 +403,19 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
       idx->last.rerank_ms += ms[4];
       idx->last.total_ms += tot;
       idx->last.searches += 1;
+      idx->last.group_launches += a.group;
+      idx->last.popc_launches += a.popc;
       for (auto e : a.e) (void)hipEventDestroy(e);
       for (auto e : a.scan) (void)hipEventDestroy(e);
     }
     idx->pending.clear();
     if (idx->tcounter.p) {
-      unsigned long long c = 0;
+      unsigned long long c[2] = {0, 0};
       RBQ_HIP(hipDeviceSynchronize());
-      RBQ_HIP(hipMemcpy(&c, idx->tcounter.p, sizeof(c), hipMemcpyDeviceToHost));
-      idx->last.scanned_vectors = (int64_t)c;
-      idx->last.scan_bytes = (int64_t)c * (idx->W * 4 + 8);
+      RBQ_HIP(hipMemcpy(c, idx->tcounter.p, sizeof(c), hipMemcpyDeviceToHost));
+      idx->last.scanned_vectors = (int64_t)c[0];
+      idx->last.scan_bytes = (int64_t)c[0] * (idx->W * 4 + 8);
+      idx->last.read_bytes = (int64_t)c[1];
     }
     *t = idx->last;
   });

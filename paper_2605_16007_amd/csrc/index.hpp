@@ -20,6 +20,7 @@ namespace rbq {
 struct TimingRec {
   hipEvent_t e[6] = {};           // start, probe, rotate, quant, scan+merge, rerank
   std::vector<hipEvent_t> scan;   // (start, end) around every scan launch
+  int64_t group = 0, popc = 0;    // scan launches of each form
 };
 
 // A device scratch area reused across calls. `done` is recorded on the stream
@@ -105,7 +106,7 @@ struct rbq_index {
   std::mutex timing_mu;
   rbq_timings last{};
   std::vector<rbq::TimingRec> pending;
-  rbq::DevBuf tcounter;  // device sum of scanned vectors
+  rbq::DevBuf tcounter;  // device sums: [0] scanned vectors, [1] record bytes read
 
   ~rbq_index();
 };

@@ -12,13 +12,44 @@ namespace rbq {
 
 namespace {
 
-__global__ void k_count_scanned(const int32_t* probes, const int32_t* list_len, int64_t pairs,
-                                unsigned long long* acc) {
+// Timing counters: acc[0] += sum of list sizes over the pairs of probe ranks
+// [p0, p0 + pn); acc[1] += their padded record bytes when `qm` (each
+// query-major item reads its whole list).
+__global__ void k_count_scanned(const int32_t* probes, const int32_t* list_len, int nq, int nprobe,
+                                int p0, int pn, int rec_bytes, int qm, unsigned long long* acc) {
+  __shared__ unsigned long long part[2][256];
+  unsigned long long s = 0, b = 0;
+  const int64_t pairs = (int64_t)nq * pn;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < pairs; t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t / pn;
+    const int len = list_len[probes[i * nprobe + p0 + (t - i * pn)]];
+    s += (unsigned long long)len;
+    if (qm) b += (unsigned long long)((len + 63) / 64) * 64 * rec_bytes;
+  }
+  part[0][threadIdx.x] = s;
+  part[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      part[0][threadIdx.x] += part[0][threadIdx.x + off];
+      part[1][threadIdx.x] += part[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&acc[0], part[0][0]);
+    atomicAdd(&acc[1], part[1][0]);
+  }
+}
+
+// acc += padded record bytes of every list-major item (items x list bytes)
+__global__ void k_count_group_bytes(const int32_t* cnt, const int32_t* list_len, int nlist, int G,
+                                    int rec_bytes, unsigned long long* acc) {
   __shared__ unsigned long long part[256];
-  unsigned long long s = 0;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < pairs; t += (int64_t)gridDim.x * 256)
-    s += (unsigned long long)list_len[probes[t]];
-  part[threadIdx.x] = s;
+  unsigned long long b = 0;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < nlist; j += gridDim.x * 256)
+    b += (unsigned long long)((cnt[j] + G - 1) / G) * ((list_len[j] + 63) / 64) * 64 * rec_bytes;
+  part[threadIdx.x] = b;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
@@ -78,6 +109,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
   const bool dumps = dbg && (dbg->ip || dbg->est);
   const int64_t maxlen = std::max<int64_t>(1, idx->max_list_len);
   const bool timed = idx->timing.load() != 0;
+  const int rec_bytes = W * 4 + 8;  // code words and two factors per vector
   RBQ_CHECK(!idx->vectors_on_host, "host-resident raw vectors: re-rank on host is not available in this build");
 
   // Probe ranks are scanned in chunks: each scan item appends at most R
@@ -297,7 +329,16 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
           RBQ_HIP(hipEventRecord(e0, s));
         }
         launch_scan_popc(s, sa);
-        if (timed) RBQ_HIP(hipEventRecord(e1, s));
+        if (timed) {
+          RBQ_HIP(hipEventRecord(e1, s));
+          tr.popc += 1;
+          if (!sa.qmask) {  // (the redo of overflowed queries is not counted)
+            hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
+                               idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 1,
+                               idx->tcounter.as<unsigned long long>());
+            RBQ_HIP(hipGetLastError());
+          }
+        }
         ma.max_extra = R * ch.pn;
         launch_row_topk(s, ma, (int)nq);
       }
@@ -319,7 +360,17 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
           RBQ_HIP(hipEventRecord(e0, s));
         }
         launch_scan_group(s, ga, 8 * idx->num_cus);
-        if (timed) RBQ_HIP(hipEventRecord(e1, s));
+        if (timed) {
+          RBQ_HIP(hipEventRecord(e1, s));
+          tr.group += 1;
+          hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
+                             idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 0,
+                             idx->tcounter.as<unsigned long long>());
+          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s, b.gcnt,
+                             idx->list_len.as<int32_t>(), nlist, ga.G, rec_bytes,
+                             idx->tcounter.as<unsigned long long>() + 1);
+          RBQ_HIP(hipGetLastError());
+        }
         ma.max_extra = (int)pool_cap;
         launch_row_topk(s, ma, (int)nq);
       }
@@ -353,12 +404,6 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
                   ids_out, dist_out);
     mark(5);
-    if (timed) {
-      hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
-                         idx->list_len.as<int32_t>(), pairs,
-                         idx->tcounter.as<unsigned long long>());
-      RBQ_HIP(hipGetLastError());
-    }
 
     // host-side outputs
     if (ids && !ids_dev)

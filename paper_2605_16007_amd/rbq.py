@@ -52,7 +52,9 @@ class Timings(C.Structure):
     _fields_ = [("searches", C.c_int64), ("probe_ms", C.c_float), ("rotate_ms", C.c_float),
                 ("quant_ms", C.c_float), ("scan_ms", C.c_float), ("merge_ms", C.c_float),
                 ("rerank_ms", C.c_float), ("total_ms", C.c_float),
-                ("scanned_vectors", C.c_int64), ("scan_bytes", C.c_int64)]
+                ("scanned_vectors", C.c_int64), ("scan_bytes", C.c_int64),
+                ("read_bytes", C.c_int64), ("group_launches", C.c_int64),
+                ("popc_launches", C.c_int64)]
 
 
 class RbqError(RuntimeError):
