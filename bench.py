@@ -175,6 +175,52 @@ def recall(ids, gt):
 
 # ----------------------------------------------------------------- main
 
+def serve_compare(idx, w, args):
+    """Open-loop Poisson traces on the resident index: the continuous-batching
+    server against plain one-query-at-a-time search (rbq_search, nq = 1, in
+    arrival order), both driven by the library's native replay. Per request
+    nprobe ~ U{8, 16, ..., 256}, k ~ U{10, 100}, rerank_n = 10 k. The two return
+    identical results (checked here), so their recall is equal."""
+    from paper_2605_16007_amd import Server
+    from synth import arrivals, queries
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    counts = [max(64, min(args.serve_max, int(r * args.serve_seconds))) for r in rates]
+    Qs = queries(w, max(counts))
+    out = {"workload": f"{w.name} index, Poisson arrivals, nprobe U{{8..256 step 8}}, "
+                       f"k U{{10,100}}, rerank_n 10k",
+           "server": {"lanes": 2, "max_batch": 1024, "mem_budget_gib": 1.0}, "rates": {}}
+
+    def summary(n, arr, lat):
+        done = arr + lat
+        return {"qps": n / float(done.max() - arr[0]), "p50_ms": float(np.percentile(lat, 50)) * 1e3,
+                "p99_ms": float(np.percentile(lat, 99)) * 1e3}
+
+    with Server(idx, lanes=2, max_batch=1024, max_nprobe=256, max_k=100, max_rerank=1000,
+                mem_budget=1 << 30) as srv:
+        t, npb, kk = arrivals(rates[0], 256, seed=99)
+        srv.replay(Qs[:256], npb, kk, 10 * kk, np.zeros(256))  # warm-up
+        idx.replay_plain(Qs[:32], npb[:32], kk[:32], 10 * kk[:32], np.zeros(32))
+        for ri, (rate, n) in enumerate(zip(rates, counts)):
+            t, npb, kk = arrivals(rate, n, seed=ri)
+            t = t - t[0]
+            before = srv.stats()
+            ids_s, d_s, lat_s = srv.replay(Qs[:n], npb, kk, 10 * kk, t)
+            after = srv.stats()
+            ids_p, d_p, lat_p = idx.replay_plain(Qs[:n], npb, kk, 10 * kk, t)
+            batches = after["batches"] - before["batches"]
+            rec = {"requests": n, "trace_s": float(t[-1]),
+                   "server": dict(summary(n, t, lat_s), mean_batch=n / max(1, batches)),
+                   "plain": summary(n, t, lat_p),
+                   "identical_results": bool(np.array_equal(ids_s, ids_p) and np.array_equal(d_s, d_p))}
+            out["rates"][str(int(rate))] = rec
+            log(f"[serving] {rate:.0f} q/s x {n}: server {rec['server']['qps']:.0f} q/s "
+                f"p50 {rec['server']['p50_ms']:.2f} p99 {rec['server']['p99_ms']:.2f} ms "
+                f"(batch {rec['server']['mean_batch']:.1f}); plain {rec['plain']['qps']:.0f} q/s "
+                f"p50 {rec['plain']['p50_ms']:.2f} p99 {rec['plain']['p99_ms']:.2f} ms; "
+                f"identical {rec['identical_results']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +238,11 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=128)
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
+                    help="Poisson arrival rates (queries/s) of the serving comparison; '' skips it")
+    ap.add_argument("--serve-seconds", type=float, default=0.5,
+                    help="seconds of arrivals per rate (capped by --serve-max)")
+    ap.add_argument("--serve-max", type=int, default=8000, help="most requests per rate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures the search path on one GPU only; this build runs no "
@@ -324,6 +375,8 @@ def main():
     idx.set_option("scan", 0)
     log("[variants] " + ", ".join(f"{k_}: {v:.0f} q/s" for k_, v in variants.items()))
 
+    serving = serve_compare(idx, w, args) if args.serve_rates else None
+
     cpu = cpu_pool.run(nprobe, w.k, R) if cpu_pool else None
     if cpu_pool:
         cpu_pool.close()
@@ -389,6 +442,7 @@ def main():
         "stage_ms": {s: tm[f"{s}_ms"] / ns for s in
                      ("probe", "rotate", "quant", "scan", "merge", "rerank", "total")},
         "roofline": roofline,
+        "serving": serving,
         "cpu_baseline": cpu,
         "build_s": build_s,
     }

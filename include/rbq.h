@@ -103,6 +103,20 @@ rbq_status rbq_get_info(const rbq_index* idx, rbq_index_info* info);
 rbq_status rbq_search(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
                       int32_t rerank_n, int64_t* ids, float* sqdist, void* stream);
 
+/*
+ * Mixed batch: the batch-processing search of Sec. 3.1.2 in which query i uses
+ * its own nprobe[i], k[i] and rerank_n[i] (host int32 arrays of nq, each in the
+ * ranges rbq_search accepts). Query i's result is the same as rbq_search of
+ * that query alone with its parameters: probing, estimates, the top-rerank_n
+ * selection and the re-rank are per query, and no kernel's arithmetic depends
+ * on the rest of the batch. ids / sqdist (host or device) hold nq rows of
+ * k_stride (>= every k[i]) values; row i has its k[i] results, then
+ * (-1, +inf).
+ */
+rbq_status rbq_search_mixed(rbq_index* idx, const float* q, int64_t nq, const int32_t* nprobe,
+                            const int32_t* k, const int32_t* rerank_n, int32_t k_stride,
+                            int64_t* ids, float* sqdist, void* stream);
+
 /* Canonical exports (host dst, exactly `bytes` long), all in vector-id order. */
 enum {
   RBQ_EXPORT_CENTROIDS = 1,  /* nlist*d float32 */
@@ -178,6 +192,101 @@ typedef struct {
 
 rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled);
 rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t);
+
+/*
+ * Serving loop: continuous batching over a resident index (the batch
+ * processing of Sec. 3.1.2 with requests that arrive one at a time).
+ *
+ * Requests are submitted one query at a time, from any host thread, each with
+ * its own nprobe, k and rerank_n. A server runs `lanes` host threads, each with
+ * its own HIP stream and a device workspace of mem_budget bytes allocated at
+ * creation. A lane that is free takes the oldest waiting requests, in arrival
+ * order, for as long as the batch stays within max_batch queries and its
+ * workspace need (probe scores, quantised residuals and candidate rows, which
+ * grow with the batch's size, nprobe and rerank_n) within mem_budget; runs them
+ * as one mixed batch (rbq_search_mixed); and publishes each request's result.
+ * Requests that arrive while batches are on the device join the next batch a
+ * lane forms, and with lanes > 1 that batch is launched while earlier ones
+ * still run, so their kernels overlap on the device. Each result equals that
+ * of rbq_search of the query alone with its own parameters.
+ *
+ * A server must be destroyed before its index. rbq_submit / rbq_poll /
+ * rbq_wait may be called concurrently from several threads.
+ */
+typedef struct rbq_server rbq_server; /* opaque */
+
+typedef struct {
+  int32_t lanes;        /* batches in flight at once, 1..8 (default 2) */
+  int32_t max_batch;    /* queries per batch, 1..65536 (default 1024) */
+  int32_t queue_cap;    /* requests held at once, waiting, running or finished
+                           but not yet collected, 1..2^22 (default 65536) */
+  int32_t max_nprobe;   /* largest nprobe of a request (0 = default: min(nlist, 256)) */
+  int32_t max_k;        /* largest k (default 100) */
+  int32_t max_rerank;   /* largest rerank_n (default 1000) */
+  int64_t mem_budget;   /* device workspace bytes per lane (default 1 GiB) */
+  int32_t reserved[8];  /* must be zero */
+} rbq_server_params;
+
+typedef struct {
+  int64_t submitted;      /* requests accepted by rbq_submit */
+  int64_t rejected;       /* rbq_submit calls refused with RBQ_EAGAIN */
+  int64_t completed;      /* results published (including failed batches) */
+  int64_t batches;        /* batches run */
+  int64_t max_batch_seen; /* largest batch run */
+  int64_t budget_cuts;    /* batches closed because the next request would have
+                             taken the workspace need past mem_budget */
+  int64_t reserved[2];
+} rbq_server_stats;
+
+rbq_status rbq_server_params_init(rbq_server_params* p);
+/* Allocates the lanes' streams, workspaces and pinned staging buffers and
+ * starts the lane threads. ENOMEM if an allocation fails. */
+rbq_status rbq_server_create(rbq_index* idx, const rbq_server_params* p, rbq_server** out);
+/* Queues one query (host pointer, d floats, copied before return). EINVAL for
+ * parameters outside the server's limits, ENOMEM if the request alone needs
+ * more than mem_budget, EAGAIN when queue_cap requests are held, ESTATE after
+ * destroy began. */
+rbq_status rbq_submit(rbq_server* srv, const float* q, int32_t nprobe, int32_t k, int32_t rerank_n,
+                      uint64_t* ticket);
+/* Non-blocking. *done = 0: not finished, outputs untouched. *done = 1: ids and
+ * sqdist (host, the request's k values) hold the result and the ticket is
+ * released. If the request's batch failed, its status is returned instead
+ * (with the message) and the ticket is released. latency_ns (optional)
+ * receives submit-to-result time. EINVAL for an unknown or released ticket. */
+rbq_status rbq_poll(rbq_server* srv, uint64_t ticket, int64_t* ids, float* sqdist, int32_t* done,
+                    int64_t* latency_ns);
+/* As rbq_poll, waiting up to timeout_us (< 0: no limit); EAGAIN on time-out. */
+rbq_status rbq_wait(rbq_server* srv, uint64_t ticket, int64_t* ids, float* sqdist,
+                    int64_t timeout_us, int64_t* latency_ns);
+rbq_status rbq_server_get_stats(rbq_server* srv, rbq_server_stats* st);
+/* Finishes every queued and running request, stops the lanes and frees the
+ * server (uncollected results are dropped). */
+rbq_status rbq_server_destroy(rbq_server* srv);
+
+/* An open-loop arrival trace and where its results go (all host memory). */
+typedef struct {
+  const float* q;          /* n*d queries */
+  const int32_t* nprobe;   /* n values each */
+  const int32_t* k;
+  const int32_t* rerank_n;
+  const double* arrival_s; /* n non-decreasing arrival times, seconds after the start */
+  int64_t* ids;            /* n*k_stride results, padded with (-1, +inf) past k[i] */
+  float* sqdist;
+  double* latency_s;       /* n: time the result was ready minus arrival time */
+  int64_t n;
+  int32_t k_stride;        /* >= every k[i] */
+  int32_t reserved;        /* must be zero */
+} rbq_replay_io;
+
+/* Replays the trace through the server: request i is submitted at its arrival
+ * time (if the queue is full, as soon as a request has been collected; its
+ * latency still counts from the arrival time) and collected by a second host
+ * thread. Returns when every result is in. */
+rbq_status rbq_server_replay(rbq_server* srv, const rbq_replay_io* io);
+/* The same trace served one query at a time, in arrival order, by rbq_search
+ * with nq = 1 on one stream of the calling thread (the plain per-query form
+ * the serving loop is compared with). */
+rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
 
 /* Tuning options of an index (apply to later searches on any thread).
  *   RBQ_OPT_SCAN        0: choose per chunk of probe ranks (default),

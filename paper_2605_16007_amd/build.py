@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librbq.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "kernels_group.hip", "build.cpp", "search.cpp", "api.cpp", "host_math.cpp"]
+SOURCES = ["kernels.hip", "kernels_group.hip", "build.cpp", "search.cpp", "server.cpp", "api.cpp",
+           "host_math.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

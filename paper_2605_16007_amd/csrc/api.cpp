@@ -1,5 +1,6 @@
 // The C ABI of librbq: argument validation, status codes and thread-local
 // error messages around the C++ implementation.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -7,6 +8,7 @@
 #include <string>
 
 #include "index.hpp"
+#include "server.hpp"
 
 namespace {
 
@@ -334,6 +336,35 @@ rbq_status rbq_search(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe
   });
 }
 
+rbq_status rbq_search_mixed(rbq_index* idx, const float* q, int64_t nq, const int32_t* nprobe,
+                            const int32_t* k, const int32_t* rerank_n, int32_t k_stride,
+                            int64_t* ids, float* sqdist, void* stream) {
+  return guarded([&] {
+    RBQ_CHECK(idx != nullptr, "index is NULL");
+    RBQ_CHECK(nq >= 0, "nq must be >= 0");
+    if (nq == 0) return;
+    RBQ_CHECK(q && nprobe && k && rerank_n && ids && sqdist, "an argument is NULL");
+    RBQ_CHECK(k_stride >= 1, "k_stride must be >= 1");
+    int np = 0, R = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+      RBQ_CHECK(nprobe[i] >= 1 && nprobe[i] <= std::min(idx->nlist, rbq::MAX_SEL),
+                "nprobe[i] must be in [1, min(nlist, 4096)]");
+      RBQ_CHECK(rerank_n[i] >= 1 && rerank_n[i] <= rbq::MAX_R, "rerank_n[i] must be in [1, 3840]");
+      RBQ_CHECK(k[i] >= 1 && k[i] <= rerank_n[i] && k[i] <= k_stride,
+                "k[i] must be in [1, min(rerank_n[i], k_stride)]");
+      np = std::max(np, nprobe[i]);
+      R = std::max(R, rerank_n[i]);
+    }
+    RBQ_CHECK(k_stride <= R, "k_stride must be <= the largest rerank_n");
+    RBQ_CHECK(nq * (int64_t)np <= (int64_t)INT32_MAX, "nq * nprobe too large");
+    rbq::SearchIO io;
+    io.q_nprobe = nprobe;
+    io.q_k = k;
+    io.q_R = rerank_n;
+    rbq::search(idx, q, nq, np, k_stride, R, ids, sqdist, static_cast<hipStream_t>(stream), io);
+  });
+}
+
 rbq_status rbq_search_debug(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
                             int32_t rerank_n, rbq_debug_io* io) {
   return guarded([&] {
@@ -450,6 +481,81 @@ rbq_status rbq_load(const char* path, rbq_index** out) {
   if (!path || !out) return invalid("NULL argument");
   *out = nullptr;
   return guarded([&] { *out = rbq::load_index(path); });
+}
+
+rbq_status rbq_server_params_init(rbq_server_params* p) {
+  if (!p) return invalid("params is NULL");
+  rbq::server_params_default(p);
+  return RBQ_OK;
+}
+
+rbq_status rbq_server_create(rbq_index* idx, const rbq_server_params* p, rbq_server** out) {
+  return guarded([&] {
+    RBQ_CHECK(idx != nullptr && p != nullptr && out != nullptr, "an argument is NULL");
+    *out = nullptr;
+    *out = rbq::server_create(idx, *p);
+  });
+}
+
+rbq_status rbq_submit(rbq_server* srv, const float* q, int32_t nprobe, int32_t k, int32_t rerank_n,
+                      uint64_t* ticket) {
+  rbq_status st = RBQ_OK;
+  const rbq_status g = guarded([&] {
+    RBQ_CHECK(srv != nullptr, "server is NULL");
+    st = rbq::server_submit(srv, q, nprobe, k, rerank_n, ticket);
+    if (st == RBQ_EAGAIN) g_err = "request queue is full";
+  });
+  return g != RBQ_OK ? g : st;
+}
+
+rbq_status rbq_poll(rbq_server* srv, uint64_t ticket, int64_t* ids, float* sqdist, int32_t* done,
+                    int64_t* latency_ns) {
+  return guarded([&] {
+    RBQ_CHECK(srv != nullptr && done != nullptr, "server or done is NULL");
+    RBQ_CHECK(ids != nullptr && sqdist != nullptr, "outputs are NULL");
+    *done = 0;
+    *done = rbq::server_collect(srv, ticket, ids, sqdist, 0, nullptr, latency_ns);
+  });
+}
+
+rbq_status rbq_wait(rbq_server* srv, uint64_t ticket, int64_t* ids, float* sqdist,
+                    int64_t timeout_us, int64_t* latency_ns) {
+  int got = 0;
+  const rbq_status g = guarded([&] {
+    RBQ_CHECK(srv != nullptr, "server is NULL");
+    RBQ_CHECK(ids != nullptr && sqdist != nullptr, "outputs are NULL");
+    got = rbq::server_collect(srv, ticket, ids, sqdist, timeout_us, nullptr, latency_ns);
+    if (!got) g_err = "timed out";
+  });
+  return g != RBQ_OK ? g : (got ? RBQ_OK : RBQ_EAGAIN);
+}
+
+rbq_status rbq_server_get_stats(rbq_server* srv, rbq_server_stats* st) {
+  return guarded([&] {
+    RBQ_CHECK(srv != nullptr && st != nullptr, "an argument is NULL");
+    rbq::server_stats(srv, st);
+  });
+}
+
+rbq_status rbq_server_destroy(rbq_server* srv) {
+  return guarded([&] {
+    RBQ_CHECK(srv != nullptr, "server is NULL");
+    rbq::server_destroy(srv);
+  });
+}
+
+rbq_status rbq_server_replay(rbq_server* srv, const rbq_replay_io* io) {
+  return guarded([&] {
+    RBQ_CHECK(srv != nullptr && io != nullptr, "an argument is NULL");
+    rbq::server_replay(srv, *io);
+  });
+}
+
+rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io) {
+  return guarded([&] {
+    RBQ_CHECK(idx != nullptr && io != nullptr, "an argument is NULL");
+    rbq::replay_plain(idx, *io);
+  });
 }
 
 const char* rbq_last_error(void) { return g_err.c_str(); }

@@ -123,7 +123,22 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
 
 struct SearchIO {
   const rbq_debug_io* dbg = nullptr;  // stage injection / outputs (host pointers)
+  // mixed batches (host arrays of nq): query i probes q_nprobe[i] <= nprobe
+  // lists, keeps q_R[i] <= R candidates and returns q_k[i] <= k results (its
+  // output row, of stride k, is padded with (-1, +inf))
+  const int32_t* q_nprobe = nullptr;
+  const int32_t* q_k = nullptr;
+  const int32_t* q_R = nullptr;
+  int64_t pool_budget = 0;  // bytes for the candidate rows (0: 512 MB)
+  // caller-owned device scratch (else the index's pool); not reused by the
+  // caller before the search's stream has passed this call
+  char* ws_base = nullptr;
+  size_t ws_cap = 0;
 };
+// Workspace bytes of a mixed search of nq queries (nprobe, k, R the batch's
+// largest, scanned_pairs the sum of per-query nprobe) with that pool budget.
+size_t search_workspace_bytes(const rbq_index* idx, int64_t nq, int nprobe, int k, int R,
+                              int64_t scanned_pairs, int64_t pool_budget);
 void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
             float* dist, hipStream_t s, const SearchIO& io);
 

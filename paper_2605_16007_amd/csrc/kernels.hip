@@ -225,12 +225,12 @@ __global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
   __shared__ uint32_t s_digit, s_rem, s_bucket, s_cnt;
   const int tid = threadIdx.x;
   const int64_t row = blockIdx.x;
-  const int k = a.k, KP = a.KP;
+  const int k = a.rowk ? a.rowk[row] : a.k, KP = a.KP;
   int ncols = a.ncols;
   if (a.rowcnt) {  // pool mode: the row holds k running keys then rowcnt[row] new ones
     const uint32_t extra = min(a.rowcnt[row], (uint32_t)a.max_extra);
     if (extra == 0) return;
-    ncols = k + (int)extra;
+    ncols = a.k + (int)extra;
   }
   const bool cached = ncols <= a.cache_cap;
   uint64_t* cache = smem;
@@ -655,7 +655,8 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
                                                 const float* __restrict__ X, int64_t n, int ldx, int d,
                                                 const uint64_t* __restrict__ cand, int64_t ldc,
                                                 int R, int k, int KP, int64_t* __restrict__ ids,
-                                                float* __restrict__ dist) {
+                                                float* __restrict__ dist,
+                                                const int32_t* __restrict__ rowk) {
   // [R] candidate keys, then [KP] selection keys; KP < 0 means no separate
   // selection buffer: ck holds -KP (pow2 >= R) keys and is sorted in place
   extern __shared__ uint64_t ck[];
@@ -667,6 +668,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = lane >> 4, sl = lane & 15;  // candidate slot in the wave, lane in the slot
   const int64_t i = blockIdx.x;
+  const int kr = rowk ? rowk[i] : k;  // this row's k (<= k)
   const int nf4 = ldx >> 2;
   for (int t = tid; t < nf4; t += 256)
     qs[t] = (t * 4 < d) ? reinterpret_cast<const float4*>(q + i * ldq)[t] : make_float4(0, 0, 0, 0);
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   }
   __syncthreads();
   if (KP > 0) {
-    lds_select_sorted(ck, R, k, KP, sel, hist, wsum, s_misc);
+    lds_select_sorted(ck, R, kr, KP, sel, hist, wsum, s_misc);
   } else {  // large k: sort all candidates in place (ck holds pow2 >= R keys)
     const int KR = -KP;
     for (int t = R + tid; t < KR; t += 256) ck[t] = KEY_NONE;
@@ -699,7 +701,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
     sel = ck;
   }
   for (int r = tid; r < k; r += 256) {
-    const uint64_t v = sel[r];
+    const uint64_t v = r < kr ? sel[r] : KEY_NONE;
     ids[i * k + r] = v == KEY_NONE ? -1 : (int64_t)(uint32_t)v;
     dist[i * k + r] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
   }
@@ -707,7 +709,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
 
 void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64_t n, int ldx,
                    int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
-                   float* dist) {
+                   float* dist, const int32_t* rowk) {
   if (nq <= 0) return;
   RBQ_CHECK(ldx % 4 == 0 && ldq % 4 == 0, "rows must be padded to 4 floats");
   int KP = pow2_at_least(k);
@@ -718,7 +720,22 @@ void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64
   }
   RBQ_CHECK(lds <= (size_t)(64 << 10), "re-rank needs too much LDS for this d and rerank_n");
   hipLaunchKernelGGL(k_rerank, dim3(nq), dim3(256), lds, s, q, ldq, X, n, ldx, d, cand, ldc, R, k,
-                     KP, ids, dist);
+                     KP, ids, dist, rowk);
+  RBQ_HIP(hipGetLastError());
+}
+
+__global__ void k_mask_probes(int32_t* probes, int nq, int nprobe, const int32_t* qnp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nq * nprobe) return;
+  const int64_t i = t / nprobe;
+  if ((int)(t - i * nprobe) >= qnp[i]) probes[t] = -1;
+}
+
+void launch_mask_probes(hipStream_t s, int32_t* probes, int nq, int nprobe, const int32_t* qnp) {
+  const int64_t n = (int64_t)nq * nprobe;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mask_probes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, probes, nq,
+                     nprobe, qnp);
   RBQ_HIP(hipGetLastError());
 }
 

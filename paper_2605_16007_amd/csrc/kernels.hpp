@@ -57,6 +57,7 @@ struct TopkArgs {
   uint32_t* rowcnt = nullptr;
   int max_extra = 0;           // largest rowcnt (pool mode)
   uint32_t* qthr = nullptr;
+  const int32_t* rowk = nullptr;  // per-row selection size (<= k); slots past it are untouched
   bool sorted = true;          // false: the k keys in any order (pool merges)
   int KP = 0, cache_cap = 0;   // set by the launcher
 };
@@ -115,10 +116,15 @@ void launch_reset_masked(hipStream_t s, const uint32_t* mask, uint64_t* rows, in
                          uint32_t* qthr, uint32_t* pcnt, int nq);
 
 // Exact re-rank: per query, gather the candidates' raw vectors, exact squared
-// L2 in FP32, top-k by (distance, id).
+// L2 in FP32, top-k by (distance, id). Output rows have stride k; with rowk
+// set, row i keeps its best rowk[i] (<= k) and pads the rest with (-1, +inf).
 void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64_t n, int ldx,
                    int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
-                   float* dist);
+                   float* dist, const int32_t* rowk = nullptr);
+
+// probes[i][p] = -1 for p >= qnp[i] (a query that probes fewer lists than the
+// batch's widest one); scans and maps skip such pairs.
+void launch_mask_probes(hipStream_t s, int32_t* probes, int nq, int nprobe, const int32_t* qnp);
 
 // RaBitQ encoder (FP64): one launch encodes micro-blocks [mb_begin, mb_end).
 void launch_encode(hipStream_t s, const float* X, int ldx, const float* C, int ldc,

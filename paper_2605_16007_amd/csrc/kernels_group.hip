@@ -36,7 +36,8 @@ __global__ void k_grp_hist(const int32_t* __restrict__ probes, int nq, int nprob
   if (t >= (int64_t)nq * pn) return;
   const int64_t i = t / pn;
   const int p = p0 + (int)(t - i * pn);
-  atomicAdd(&cnt[probes[i * nprobe + p]], 1);
+  const int j = probes[i * nprobe + p];
+  if (j >= 0) atomicAdd(&cnt[j], 1);  // (-1: the query probes fewer lists)
 }
 
 // Exclusive prefix sums over lists of the pair counts and of the item counts
@@ -100,7 +101,7 @@ __global__ void k_grp_scatter(const int32_t* __restrict__ probes, int nq, int np
   const int p = p0 + (int)(t - i * pn);
   const int64_t pair = i * nprobe + p;
   const int j = probes[pair];
-  slots[pair_off[j] + atomicAdd(&fill[j], 1)] = (int32_t)pair;
+  if (j >= 0) slots[pair_off[j] + atomicAdd(&fill[j], 1)] = (int32_t)pair;
 }
 
 __device__ inline uint32_t lane_prefix(uint64_t mask) {

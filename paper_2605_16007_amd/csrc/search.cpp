@@ -22,7 +22,8 @@ __global__ void k_count_scanned(const int32_t* probes, const int32_t* list_len, 
   const int64_t pairs = (int64_t)nq * pn;
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < pairs; t += (int64_t)gridDim.x * 256) {
     const int64_t i = t / pn;
-    const int len = list_len[probes[i * nprobe + p0 + (t - i * pn)]];
+    const int j = probes[i * nprobe + p0 + (t - i * pn)];
+    const int len = j >= 0 ? list_len[j] : 0;
     s += (unsigned long long)len;
     if (qm) b += (unsigned long long)((len + 63) / 64) * 64 * rec_bytes;
   }
@@ -85,7 +86,129 @@ struct Bufs {
   float* dump_est = nullptr;
   int64_t* ids = nullptr;
   float* dist = nullptr;
+  int32_t* spec = nullptr;  // mixed batches: [3][nq] nprobe, k, rerank_n per query
 };
+
+struct Chunk {
+  int p0, pn;
+};
+
+// What a search call does and needs, fixed before any launch.
+struct Plan {
+  int64_t nq = 0, pairs = 0, maxlen = 1;
+  int nprobe = 0, k = 0, R = 0;
+  int pch = 1, first = 1;
+  int64_t cand_ld = 0, pool_cap = 0;
+  bool need_qcopy = true, ids_dev = false, dist_dev = false;
+  bool inj_probes = false, inj_qu = false, dumps = false, mixed = false, any_group = false;
+  const rbq_debug_io* dbg = nullptr;
+  std::vector<Chunk> chunks, qm_chunks;
+};
+
+constexpr int64_t kDefaultPoolBudget = (int64_t)512 << 20;
+
+// Probe ranks are scanned in chunks: each scan item appends at most R
+// survivors to its query's pool (row layout: R running keys, then the pool),
+// and a merge after each chunk folds the pool into the running top-R and
+// lowers the query's threshold to its exact R-th estimate, so later chunks
+// keep only candidates that can still enter the top-R (the IVF-aware pruning
+// of Sec. 3.3.3). Query-major chunks double from `first` (enough items to fill
+// the GPU) up to `pch`, the most probe ranks whose worst-case pool (R keys per
+// item) fits the pool budget.
+//
+// The list-major MFMA scan is used for the whole search when d <= 256 and the
+// batch probes each list several times on average (pairs >= group_min *
+// nlist), or always with RBQ_OPT_SCAN = 2. Its chunks double the prefix
+// already scanned, so with the threshold at the exact R-th estimate of that
+// prefix a pool expects about R survivors per chunk; the first chunk is sized
+// so that even all of its candidates fit. A query whose pool overflows anyway
+// is searched again, from scratch, by the query-major scan (exact; checked
+// once per search).
+Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64_t scanned_pairs,
+               int64_t pool_budget, const rbq_debug_io* dbg) {
+  Plan P;
+  P.nq = nq;
+  P.nprobe = nprobe;
+  P.k = k;
+  P.R = R;
+  P.pairs = nq * nprobe;
+  P.dbg = dbg;
+  P.maxlen = std::max<int64_t>(1, idx->max_list_len);
+  P.inj_probes = dbg && dbg->inject_probes;
+  P.inj_qu = dbg && dbg->inject_qu;
+  P.dumps = dbg && (dbg->ip || dbg->est);
+  const int64_t budget = pool_budget > 0 ? pool_budget : kDefaultPoolBudget;
+  P.pch = (int)std::max<int64_t>(
+      1, std::min<int64_t>(nprobe, budget / std::max<int64_t>(1, nq * R * 8) - 1));
+  P.first = (int)std::min<int64_t>(P.pch, std::max<int64_t>(1, (2048 + nq - 1) / nq));
+  if (dbg && dbg->probe_chunk > 0) P.pch = P.first = std::min(P.pch, (int)dbg->probe_chunk);
+  P.cand_ld = (int64_t)R * (1 + P.pch);
+  const int scan_mode = idx->opt_scan.load();
+  const int group_min = idx->opt_group_min.load();
+  P.pool_cap = (int64_t)R * P.pch;
+  if (idx->opt_pool_cap.load() > 0) P.pool_cap = std::min<int64_t>(P.pool_cap, idx->opt_pool_cap.load());
+  // (per-vector dumps of the debug entry point come from the query-major scan)
+  P.any_group = scan_mode != 1 && !P.dumps && group_k_steps(idx->d) <= 4 &&
+                (scan_mode == 2 || scanned_pairs >= (int64_t)group_min * idx->nlist);
+  for (int p0 = 0, pn = P.first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, P.pch)) {
+    pn = std::min(pn, nprobe - p0);
+    P.qm_chunks.push_back({p0, pn});
+  }
+  if (P.any_group) {
+    // first chunk: about 2R candidates per query on average, and never more
+    // than the pool holds even for the longest lists
+    const int64_t maxl = std::max<int64_t>(1, idx->max_list_len);
+    const int64_t avgl = std::max<int64_t>(1, idx->n / idx->nlist);
+    int pn = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nprobe, P.pool_cap / maxl,
+                                                          ceil_div(2 * (int64_t)R, avgl)}));
+    if (dbg && dbg->probe_chunk > 0) pn = std::min(pn, (int)dbg->probe_chunk);
+    for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, p0)) {
+      pn = std::min(pn, nprobe - p0);
+      P.chunks.push_back({p0, pn});
+    }
+  } else {
+    P.chunks = P.qm_chunks;
+  }
+  return P;
+}
+
+void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
+  const int64_t nq = P.nq, pairs = P.pairs;
+  const int ld = idx->ld, nlist = idx->nlist, W = idx->W, d = idx->d;
+  const rbq_debug_io* dbg = P.dbg;
+  if (P.need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
+  if (!P.inj_probes) b.score = c.take<float>((size_t)nq * nlist);
+  b.probes = c.take<int32_t>(pairs);
+  if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
+  b.qrot = c.take<float>((size_t)nq * ld);
+  b.planes = c.take<uint32_t>((size_t)pairs * W * idx->bqs);
+  if ((dbg && dbg->qu) || P.any_group) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
+  if (P.any_group) {
+    b.gcnt = c.take<int32_t>(nlist);
+    b.gfill = c.take<int32_t>(nlist);
+    b.pair_off = c.take<int32_t>(nlist + 1);
+    b.item_off = c.take<int32_t>(nlist + 1);
+    b.slots = c.take<int32_t>(pairs);
+    b.items = c.take<int4>(pairs / 64 + nlist + 1);
+    b.overflow = c.take<uint32_t>(nq);
+    b.counter = c.take<uint32_t>(2);
+  }
+  b.scal = c.take<float4>(pairs);
+  if (P.inj_qu) {
+    b.inj_qu = c.take<uint8_t>((size_t)pairs * d);
+    b.inj_scal = c.take<float>((size_t)pairs * 3);
+  }
+  b.qthr = c.take<uint32_t>(nq);
+  b.pcnt = c.take<uint32_t>(nq);
+  b.cand = c.take<uint64_t>((size_t)nq * P.cand_ld);
+  if (P.dumps) {
+    b.dump_ip = c.take<int32_t>((size_t)pairs * P.maxlen);
+    b.dump_est = c.take<float>((size_t)pairs * P.maxlen);
+  }
+  if (!P.ids_dev) b.ids = c.take<int64_t>((size_t)nq * P.k);
+  if (!P.dist_dev) b.dist = c.take<float>((size_t)nq * P.k);
+  if (P.mixed) b.spec = c.take<int32_t>((size_t)nq * 3);
+}
 
 }  // namespace
 
@@ -93,120 +216,79 @@ struct Bufs {
 
 namespace rbq {
 
+size_t search_workspace_bytes(const rbq_index* idx, int64_t nq, int nprobe, int k, int R,
+                              int64_t scanned_pairs, int64_t pool_budget) {
+  Plan P = make_plan(idx, nq, nprobe, k, R, scanned_pairs, pool_budget, nullptr);
+  P.mixed = true;
+  Carver dry(nullptr);
+  Bufs b;
+  layout(idx, P, dry, b);
+  return dry.off + 256;
+}
+
 void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
             float* dist, hipStream_t s, const SearchIO& io) {
   if (nq == 0) return;
   RBQ_HIP(hipSetDevice(idx->device));
   const int d = idx->d, ld = idx->ld, nlist = idx->nlist, W = idx->W, bqs = idx->bqs;
   const rbq_debug_io* dbg = io.dbg;
+  const bool mixed = io.q_nprobe != nullptr;
+  RBQ_CHECK(!idx->vectors_on_host, "host-resident raw vectors: re-rank on host is not available in this build");
+  int64_t scanned_pairs = nq * (int64_t)nprobe;
+  if (mixed) {
+    RBQ_CHECK(io.q_k && io.q_R, "mixed batch needs nprobe, k and rerank_n per query");
+    scanned_pairs = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+      RBQ_CHECK(io.q_nprobe[i] >= 1 && io.q_nprobe[i] <= nprobe, "per-query nprobe out of range");
+      RBQ_CHECK(io.q_R[i] >= 1 && io.q_R[i] <= R, "per-query rerank_n out of range");
+      RBQ_CHECK(io.q_k[i] >= 1 && io.q_k[i] <= k && io.q_k[i] <= io.q_R[i], "per-query k out of range");
+      scanned_pairs += io.q_nprobe[i];
+    }
+  }
+  Plan P = make_plan(idx, nq, nprobe, k, R, scanned_pairs, io.pool_budget, dbg);
+  P.mixed = mixed;
   const bool qdev = is_device_ptr(q);
-  const bool need_qcopy = !qdev || ld != d || (reinterpret_cast<uintptr_t>(q) & 15);
-  const bool ids_dev = ids && is_device_ptr(ids);
-  const bool dist_dev = dist && is_device_ptr(dist);
-  const int64_t pairs = nq * nprobe;
-  const bool inj_probes = dbg && dbg->inject_probes;
-  const bool inj_qu = dbg && dbg->inject_qu;
-  const bool dumps = dbg && (dbg->ip || dbg->est);
-  const int64_t maxlen = std::max<int64_t>(1, idx->max_list_len);
+  P.need_qcopy = !qdev || ld != d || (reinterpret_cast<uintptr_t>(q) & 15);
+  P.ids_dev = ids && is_device_ptr(ids);
+  P.dist_dev = dist && is_device_ptr(dist);
+  const bool need_qcopy = P.need_qcopy, ids_dev = P.ids_dev, dist_dev = P.dist_dev;
+  const int64_t pairs = P.pairs;
+  const bool inj_probes = P.inj_probes, inj_qu = P.inj_qu, dumps = P.dumps;
+  const int64_t maxlen = P.maxlen;
   const bool timed = idx->timing.load() != 0;
   const int rec_bytes = W * 4 + 8;  // code words and two factors per vector
-  RBQ_CHECK(!idx->vectors_on_host, "host-resident raw vectors: re-rank on host is not available in this build");
-
-  // Probe ranks are scanned in chunks: each scan item appends at most R
-  // survivors to its query's pool (row layout: R running keys, then the pool),
-  // and a merge after each chunk folds the pool into the running top-R and
-  // lowers the query's threshold to its exact R-th estimate, so later chunks
-  // keep only candidates that can still enter the top-R (the IVF-aware pruning
-  // of Sec. 3.3.3). Chunk sizes double from `first` (enough items to fill the
-  // GPU) up to `pch`, the most probe ranks whose worst-case pool fits ~512 MB;
-  // a pool never holds more than R keys per probe rank of its chunk.
-  const int64_t budget = (int64_t)512 << 20;
-  int pch = (int)std::max<int64_t>(1, std::min<int64_t>(nprobe, budget / std::max<int64_t>(1, nq * R * 8) - 1));
-  int first = (int)std::min<int64_t>(pch, std::max<int64_t>(1, (2048 + nq - 1) / nq));
-  if (dbg && dbg->probe_chunk > 0) pch = first = std::min(pch, (int)dbg->probe_chunk);
-  const int64_t cand_ld = (int64_t)R * (1 + pch);
-  // Chunk schedule. The list-major MFMA scan is used for the whole search
-  // when d <= 256 and the batch probes each list several times on average
-  // (nq * nprobe >= group_min * nlist), or always with RBQ_OPT_SCAN = 2.
-  // Its chunks double the prefix already scanned, so with the threshold at
-  // the exact R-th estimate of that prefix a pool expects about R survivors
-  // per chunk; the first chunk is sized so that even all of its candidates
-  // fit. A query whose pool overflows anyway is searched again, from
-  // scratch, by the query-major scan (exact; checked once per search).
-  // Query-major chunks double up to `pch`, whose worst case (R keys per
-  // item) always fits.
-  const int scan_mode = idx->opt_scan.load();
-  const int group_min = idx->opt_group_min.load();
-  int64_t pool_cap = (int64_t)R * pch;
-  if (idx->opt_pool_cap.load() > 0) pool_cap = std::min<int64_t>(pool_cap, idx->opt_pool_cap.load());
-  // (per-vector dumps of the debug entry point come from the query-major scan)
-  const bool any_group = scan_mode != 1 && !dumps && group_k_steps(d) <= 4 &&
-                         (scan_mode == 2 || nq * (int64_t)nprobe >= (int64_t)group_min * nlist);
-  struct Chunk {
-    int p0, pn;
-  };
-  std::vector<Chunk> chunks, qm_chunks;
-  for (int p0 = 0, pn = first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, pch)) {
-    pn = std::min(pn, nprobe - p0);
-    qm_chunks.push_back({p0, pn});
-  }
-  if (any_group) {
-    // first chunk: about 2R candidates per query on average, and never more
-    // than the pool holds even for the longest lists
-    const int64_t maxl = std::max<int64_t>(1, idx->max_list_len);
-    const int64_t avgl = std::max<int64_t>(1, idx->n / nlist);
-    int pn = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nprobe, pool_cap / maxl,
-                                                          ceil_div(2 * (int64_t)R, avgl)}));
-    if (dbg && dbg->probe_chunk > 0) pn = std::min(pn, (int)dbg->probe_chunk);
-    for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, p0)) {
-      pn = std::min(pn, nprobe - p0);
-      chunks.push_back({p0, pn});
-    }
-  } else {
-    chunks = qm_chunks;
-  }
-  const int64_t max_chunk_pairs = pairs;
-  auto layout = [&](Carver& c, Bufs& b) {
-    if (need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
-    if (!inj_probes) b.score = c.take<float>((size_t)nq * nlist);
-    b.probes = c.take<int32_t>(pairs);
-    if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
-    b.qrot = c.take<float>((size_t)nq * ld);
-    b.planes = c.take<uint32_t>((size_t)pairs * W * bqs);
-    if ((dbg && dbg->qu) || any_group) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
-    if (any_group) {
-      b.gcnt = c.take<int32_t>(nlist);
-      b.gfill = c.take<int32_t>(nlist);
-      b.pair_off = c.take<int32_t>(nlist + 1);
-      b.item_off = c.take<int32_t>(nlist + 1);
-      b.slots = c.take<int32_t>(max_chunk_pairs);
-      b.items = c.take<int4>(max_chunk_pairs / 64 + nlist + 1);
-      b.overflow = c.take<uint32_t>(nq);
-      b.counter = c.take<uint32_t>(2);
-    }
-    b.scal = c.take<float4>(pairs);
-    if (inj_qu) {
-      b.inj_qu = c.take<uint8_t>((size_t)pairs * d);
-      b.inj_scal = c.take<float>((size_t)pairs * 3);
-    }
-    b.qthr = c.take<uint32_t>(nq);
-    b.pcnt = c.take<uint32_t>(nq);
-    b.cand = c.take<uint64_t>((size_t)nq * cand_ld);
-    if (dumps) {
-      b.dump_ip = c.take<int32_t>((size_t)pairs * maxlen);
-      b.dump_est = c.take<float>((size_t)pairs * maxlen);
-    }
-    if (!ids_dev) b.ids = c.take<int64_t>((size_t)nq * k);
-    if (!dist_dev) b.dist = c.take<float>((size_t)nq * k);
-  };
+  const int64_t cand_ld = P.cand_ld;
+  const int64_t pool_cap = P.pool_cap;
+  const bool any_group = P.any_group;
+  const std::vector<Chunk>& chunks = P.chunks;
+  const std::vector<Chunk>& qm_chunks = P.qm_chunks;
   Bufs b;
   {
     Carver dry(nullptr);
-    layout(dry, b);
+    layout(idx, P, dry, b);
     b = Bufs();
-    auto ws = ws_acquire(idx, dry.off + 256);
-    Carver c(ws->base);
-    layout(c, b);
+    std::unique_ptr<Workspace> ws;
+    char* base = io.ws_base;
+    if (base) {
+      RBQ_CHECK(dry.off + 256 <= io.ws_cap, "caller workspace too small for this batch");
+      base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
+    } else {
+      ws = ws_acquire(idx, dry.off + 256);
+      base = ws->base;
+    }
+    Carver c(base);
+    layout(idx, P, c, b);
+    const int32_t* d_np = nullptr;
+    const int32_t* d_k = nullptr;
+    const int32_t* d_R = nullptr;
+    if (mixed) {
+      RBQ_HIP(hipMemcpyAsync(b.spec, io.q_nprobe, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      RBQ_HIP(hipMemcpyAsync(b.spec + nq, io.q_k, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      RBQ_HIP(hipMemcpyAsync(b.spec + 2 * nq, io.q_R, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      d_np = b.spec;
+      d_k = b.spec + nq;
+      d_R = b.spec + 2 * nq;
+    }
 
     // stage events: start, probe, rotate, quant, scan+merge loop, rerank; plus
     // a (start, end) pair around every scan launch
@@ -246,6 +328,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       ta.out_val = b.pscore;
       launch_row_topk(s, ta, (int)nq);
     }
+    if (mixed) launch_mask_probes(s, b.probes, (int)nq, nprobe, d_np);
     mark(1);
     // query rotation q' = P^T q (row form q P) on MFMA
     launch_gemm_tn(s, 0, qd, ld, idx->Pt.as<float>(), ld, b.qrot, ld, (int)nq, d, ld, nullptr);
@@ -315,6 +398,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     ma.ldo = cand_ld;
     ma.rowcnt = b.pcnt;
     ma.qthr = b.qthr;
+    ma.rowk = d_R;
     ma.sorted = false;
     auto scan_qm_chunks = [&]() {
       for (const auto& ch : qm_chunks) {
@@ -395,6 +479,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       so.k = R;
       so.out_keys = b.cand;
       so.ldo = cand_ld;
+      so.rowk = d_R;
       launch_row_topk(s, so, (int)nq);
     }
     mark(4);
@@ -402,7 +487,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
     int64_t* ids_out = ids_dev ? ids : b.ids;
     float* dist_out = dist_dev ? dist : b.dist;
     launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
-                  ids_out, dist_out);
+                  ids_out, dist_out, d_k);
     mark(5);
 
     // host-side outputs
@@ -440,7 +525,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       if (dbg->sqdist)
         RBQ_HIP(hipMemcpyAsync(dbg->sqdist, dist_out, (size_t)nq * k * sizeof(float), hipMemcpyDeviceToHost, s));
     }
-    ws_release(idx, std::move(ws), s);
+    if (ws) ws_release(idx, std::move(ws), s);
     if (timed) {
       std::lock_guard<std::mutex> g(idx->timing_mu);
       idx->pending.push_back(std::move(tr));

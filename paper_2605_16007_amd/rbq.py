@@ -22,7 +22,9 @@ EXPORT = {"centroids": 1, "rotation": 2, "assign": 3, "codes": 4, "factors": 5, 
 SYMBOLS = [
     "rbq_build_params_init", "rbq_build_index", "rbq_free_index", "rbq_get_info", "rbq_search",
     "rbq_export", "rbq_search_debug", "rbq_set_timing", "rbq_get_timings", "rbq_save",
-    "rbq_load", "rbq_last_error", "rbq_version", "rbq_set_option",
+    "rbq_load", "rbq_last_error", "rbq_version", "rbq_set_option", "rbq_search_mixed",
+    "rbq_server_params_init", "rbq_server_create", "rbq_submit", "rbq_poll", "rbq_wait",
+    "rbq_server_get_stats", "rbq_server_destroy", "rbq_server_replay", "rbq_replay_plain",
 ]
 OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3}
 
@@ -55,6 +57,24 @@ class Timings(C.Structure):
                 ("scanned_vectors", C.c_int64), ("scan_bytes", C.c_int64),
                 ("read_bytes", C.c_int64), ("group_launches", C.c_int64),
                 ("popc_launches", C.c_int64)]
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("max_batch", C.c_int32), ("queue_cap", C.c_int32),
+                ("max_nprobe", C.c_int32), ("max_k", C.c_int32), ("max_rerank", C.c_int32),
+                ("mem_budget", C.c_int64), ("reserved", C.c_int32 * 8)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("rejected", C.c_int64), ("completed", C.c_int64),
+                ("batches", C.c_int64), ("max_batch_seen", C.c_int64),
+                ("budget_cuts", C.c_int64), ("reserved", C.c_int64 * 2)]
+
+
+class ReplayIO(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "q", "nprobe", "k", "rerank_n", "arrival_s", "ids", "sqdist", "latency_s")] + [
+        ("n", C.c_int64), ("k_stride", C.c_int32), ("reserved", C.c_int32)]
 
 
 class RbqError(RuntimeError):
@@ -98,6 +118,16 @@ def lib():
         L.rbq_last_error.argtypes = []
         L.rbq_version.restype = C.c_char_p
         L.rbq_version.argtypes = []
+        L.rbq_search_mixed.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp, vp, vp]
+        L.rbq_server_params_init.argtypes = [C.POINTER(ServerParams)]
+        L.rbq_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
+        L.rbq_submit.argtypes = [vp, vp, i32, i32, i32, C.POINTER(C.c_uint64)]
+        L.rbq_poll.argtypes = [vp, C.c_uint64, vp, vp, C.POINTER(i32), C.POINTER(i64)]
+        L.rbq_wait.argtypes = [vp, C.c_uint64, vp, vp, i64, C.POINTER(i64)]
+        L.rbq_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.rbq_server_destroy.argtypes = [vp]
+        L.rbq_server_replay.argtypes = [vp, C.POINTER(ReplayIO)]
+        L.rbq_replay_plain.argtypes = [vp, C.POINTER(ReplayIO)]
         for name in SYMBOLS:
             if name not in ("rbq_build_params_init", "rbq_last_error", "rbq_version"):
                 getattr(L, name).restype = C.c_int
@@ -234,6 +264,34 @@ class Index:
                                 _ptr(ids), _ptr(dists), s))
         return ids, dists
 
+    def search_mixed(self, q, nprobe, k, rerank_n, stream=None):
+        """Mixed batch: query i with its own nprobe[i], k[i], rerank_n[i]. Returns
+        (ids, dists) of shape (nq, max k); row i is padded with (-1, inf) past
+        k[i]. Outputs follow ``q`` (NumPy or torch on q's device)."""
+        nq = q.shape[0]
+        nprobe = np.ascontiguousarray(np.broadcast_to(nprobe, (nq,)), np.int32)
+        k = np.ascontiguousarray(np.broadcast_to(k, (nq,)), np.int32)
+        rerank_n = np.ascontiguousarray(np.broadcast_to(rerank_n, (nq,)), np.int32)
+        ks = int(k.max()) if nq else 1
+        if _is_torch(q):
+            import torch
+            ids = torch.empty((nq, ks), dtype=torch.int64, device=q.device)
+            dists = torch.empty((nq, ks), dtype=torch.float32, device=q.device)
+        else:
+            q = np.ascontiguousarray(q, np.float32)
+            ids = np.empty((nq, ks), np.int64)
+            dists = np.empty((nq, ks), np.float32)
+        s = _stream_of(q, stream)
+        _check(lib().rbq_search_mixed(self._h, _ptr(q), nq, nprobe.ctypes.data, k.ctypes.data,
+                                      rerank_n.ctypes.data, ks, _ptr(ids), _ptr(dists), s))
+        return ids, dists
+
+    def replay_plain(self, q, nprobe, k, rerank_n, arrival_s):
+        """Serve an open-loop trace one query at a time (rbq_search, nq = 1) in
+        arrival order; returns (ids, dists, latency_s)."""
+        return _replay(lambda io: lib().rbq_replay_plain(self._h, C.byref(io)),
+                       q, nprobe, k, rerank_n, arrival_s)
+
     DEBUG_OUTPUTS = ("probes", "probe_score", "qrot", "qu", "scalars", "ip", "est", "cand_ids",
                      "cand_est", "ids", "sqdist")
 
@@ -297,3 +355,102 @@ class Index:
 
 def version() -> str:
     return lib().rbq_version().decode()
+
+
+def _replay(call, q, nprobe, k, rerank_n, arrival_s):
+    q = np.ascontiguousarray(q, np.float32)
+    n = q.shape[0]
+    nprobe = np.ascontiguousarray(np.broadcast_to(nprobe, (n,)), np.int32)
+    k = np.ascontiguousarray(np.broadcast_to(k, (n,)), np.int32)
+    rerank_n = np.ascontiguousarray(np.broadcast_to(rerank_n, (n,)), np.int32)
+    arrival_s = np.ascontiguousarray(arrival_s, np.float64)
+    assert arrival_s.shape == (n,)
+    ks = int(k.max()) if n else 1
+    ids = np.empty((n, ks), np.int64)
+    dists = np.empty((n, ks), np.float32)
+    lat = np.empty(n, np.float64)
+    io = ReplayIO()
+    io.q, io.nprobe, io.k, io.rerank_n = q.ctypes.data, nprobe.ctypes.data, k.ctypes.data, rerank_n.ctypes.data
+    io.arrival_s, io.ids, io.sqdist, io.latency_s = (arrival_s.ctypes.data, ids.ctypes.data,
+                                                     dists.ctypes.data, lat.ctypes.data)
+    io.n, io.k_stride = n, ks
+    _check(call(io))
+    return ids, dists, lat
+
+
+class Server:
+    """Continuous-batching serving loop over a resident index (rbq_server_*).
+    The index must outlive the server."""
+
+    def __init__(self, index: Index, *, lanes=2, max_batch=1024, queue_cap=65536, max_nprobe=0,
+                 max_k=100, max_rerank=1000, mem_budget=1 << 30):
+        p = ServerParams()
+        _check(lib().rbq_server_params_init(C.byref(p)))
+        p.lanes, p.max_batch, p.queue_cap = int(lanes), int(max_batch), int(queue_cap)
+        p.max_nprobe, p.max_k, p.max_rerank = int(max_nprobe), int(max_k), int(max_rerank)
+        p.mem_budget = int(mem_budget)
+        h = C.c_void_p()
+        _check(lib().rbq_server_create(index._h, C.byref(p), C.byref(h)))
+        self._h = h
+        self._index = index  # keeps the index alive
+
+    def submit(self, q, nprobe, k, rerank_n):
+        """Queue one query (host, d floats). Returns its ticket, or None when
+        the queue is full (RBQ_EAGAIN)."""
+        q = np.ascontiguousarray(q, np.float32).reshape(-1)
+        t = C.c_uint64()
+        st = lib().rbq_submit(self._h, q.ctypes.data, int(nprobe), int(k), int(rerank_n), C.byref(t))
+        if st == RBQ_EAGAIN:
+            return None
+        _check(st)
+        return t.value
+
+    def poll(self, ticket, k):
+        """(ids, dists, latency_ns) when finished, else None."""
+        ids = np.empty(k, np.int64)
+        dists = np.empty(k, np.float32)
+        done = C.c_int32()
+        lat = C.c_int64()
+        _check(lib().rbq_poll(self._h, ticket, ids.ctypes.data, dists.ctypes.data, C.byref(done),
+                              C.byref(lat)))
+        return (ids, dists, lat.value) if done.value else None
+
+    def wait(self, ticket, k, timeout_us=-1):
+        """Block for the result; (ids, dists, latency_ns), or None on time-out."""
+        ids = np.empty(k, np.int64)
+        dists = np.empty(k, np.float32)
+        lat = C.c_int64()
+        st = lib().rbq_wait(self._h, ticket, ids.ctypes.data, dists.ctypes.data, int(timeout_us),
+                            C.byref(lat))
+        if st == RBQ_EAGAIN:
+            return None
+        _check(st)
+        return ids, dists, lat.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().rbq_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_ if f != "reserved"}
+
+    def replay(self, q, nprobe, k, rerank_n, arrival_s):
+        """Open-loop replay of an arrival trace through the server; returns
+        (ids, dists, latency_s) with latency from each arrival time."""
+        return _replay(lambda io: lib().rbq_server_replay(self._h, C.byref(io)),
+                       q, nprobe, k, rerank_n, arrival_s)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(lib().rbq_server_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -102,3 +102,42 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(rbq.DebugIO) == 14 * 8 + 8
     assert C.sizeof(rbq.Timings) == 8 + 7 * 4 + 4 + 5 * 8
     assert C.sizeof(rbq.IndexInfo) == 8 + 4 * 4 + 3 * 8
+    assert C.sizeof(rbq.ServerParams) == 6 * 4 + 8 + 8 * 4
+    assert C.sizeof(rbq.ServerStats) == 8 * 8
+    assert C.sizeof(rbq.ReplayIO) == 8 * 8 + 8 + 4 + 4
+
+
+def test_server_params_defaults():
+    p = rbq.ServerParams()
+    assert rbq.lib().rbq_server_params_init(C.byref(p)) == rbq.RBQ_OK
+    assert (p.lanes, p.max_batch, p.queue_cap, p.max_nprobe, p.max_k, p.max_rerank) == (
+        2, 1024, 65536, 0, 100, 1000)
+    assert p.mem_budget == 1 << 30 and list(p.reserved) == [0] * 8
+    assert rbq.lib().rbq_server_params_init(None) == rbq.RBQ_EINVAL
+
+
+def test_serving_and_mixed_null_arguments():
+    L = rbq.lib()
+    p = rbq.ServerParams()
+    L.rbq_server_params_init(C.byref(p))
+    h = C.c_void_p()
+    assert L.rbq_server_create(None, C.byref(p), C.byref(h)) == rbq.RBQ_EINVAL
+    assert not h.value
+    q = np.zeros(8, np.float32)
+    t = C.c_uint64()
+    assert L.rbq_submit(None, q.ctypes.data, 1, 1, 1, C.byref(t)) == rbq.RBQ_EINVAL
+    ids = np.zeros(4, np.int64)
+    dist = np.zeros(4, np.float32)
+    done = C.c_int32()
+    assert L.rbq_poll(None, 0, ids.ctypes.data, dist.ctypes.data, C.byref(done), None) == rbq.RBQ_EINVAL
+    assert L.rbq_wait(None, 0, ids.ctypes.data, dist.ctypes.data, 0, None) == rbq.RBQ_EINVAL
+    st = rbq.ServerStats()
+    assert L.rbq_server_get_stats(None, C.byref(st)) == rbq.RBQ_EINVAL
+    assert L.rbq_server_destroy(None) == rbq.RBQ_EINVAL
+    io = rbq.ReplayIO()
+    assert L.rbq_server_replay(None, C.byref(io)) == rbq.RBQ_EINVAL
+    assert L.rbq_replay_plain(None, C.byref(io)) == rbq.RBQ_EINVAL
+    a = np.ones(2, np.int32)
+    assert L.rbq_search_mixed(None, q.ctypes.data, 1, a.ctypes.data, a.ctypes.data, a.ctypes.data,
+                              1, ids.ctypes.data, dist.ctypes.data, None) == rbq.RBQ_EINVAL
+    assert "index is NULL" in L.rbq_last_error().decode()
