@@ -408,5 +408,7 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
 }  // namespace rbq
 
 rbq_index::~rbq_index() {
+  pool.reset();
+  for (auto& pf : pinned_free) (void)hipHostFree(pf.first);
   if (hostX) (void)hipHostFree(hostX);
 }

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "host_rerank.hpp"
 #include "kernels.hpp"
 #include "rbq.h"
 
@@ -107,6 +108,12 @@ struct rbq_index {
   rbq_timings last{};
   std::vector<rbq::TimingRec> pending;
   rbq::DevBuf tcounter;  // device sums: [0] scanned vectors, [1] record bytes read
+
+  // host re-rank (vectors_on_host): worker threads and pinned staging, made on
+  // first use and kept with the index
+  std::mutex host_mu;
+  std::unique_ptr<rbq::ThreadPool> pool;
+  std::vector<std::pair<void*, size_t>> pinned_free;
 
   ~rbq_index();
 };

@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "index.hpp"
+#include "host_rerank.hpp"
 
 namespace rbq {
 
@@ -226,14 +227,23 @@ size_t search_workspace_bytes(const rbq_index* idx, int64_t nq, int nprobe, int 
   return dry.off + 256;
 }
 
-void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
-            float* dist, hipStream_t s, const SearchIO& io) {
+namespace {
+
+// Host re-rank hand-off of one (sub-)batch: the candidate rows and the
+// queries staged in pinned host memory, ready once `ready` has passed.
+struct HostJob {
+  uint64_t* cand = nullptr;  // nq x R keys (written by the search)
+  float* qh = nullptr;       // nq x d queries (written by the search when it has them on the device)
+  hipEvent_t ready = nullptr;
+};
+
+void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
+                 float* dist, hipStream_t s, const SearchIO& io, HostJob* job) {
   if (nq == 0) return;
   RBQ_HIP(hipSetDevice(idx->device));
   const int d = idx->d, ld = idx->ld, nlist = idx->nlist, W = idx->W, bqs = idx->bqs;
   const rbq_debug_io* dbg = io.dbg;
   const bool mixed = io.q_nprobe != nullptr;
-  RBQ_CHECK(!idx->vectors_on_host, "host-resident raw vectors: re-rank on host is not available in this build");
   int64_t scanned_pairs = nq * (int64_t)nprobe;
   if (mixed) {
     RBQ_CHECK(io.q_k && io.q_R, "mixed batch needs nprobe, k and rerank_n per query");
@@ -483,11 +493,22 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
       launch_row_topk(s, so, (int)nq);
     }
     mark(4);
-    // Phase 5: exact re-rank of the top-R on the GPU
     int64_t* ids_out = ids_dev ? ids : b.ids;
     float* dist_out = dist_dev ? dist : b.dist;
-    launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
-                  ids_out, dist_out, d_k);
+    if (job) {
+      // Phase 5 on host cores: hand the candidates (and the queries, if they
+      // are only on the device) over in pinned memory
+      RBQ_HIP(hipMemcpy2DAsync(job->cand, R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
+                               R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
+      if (qdev)
+        RBQ_HIP(hipMemcpy2DAsync(job->qh, d * sizeof(float), qd, (need_qcopy ? ld : d) * sizeof(float),
+                                 d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
+      RBQ_HIP(hipEventRecord(job->ready, s));
+    } else {
+      // Phase 5: exact re-rank of the top-R on the GPU
+      launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
+                    ids_out, dist_out, d_k);
+    }
     mark(5);
 
     // host-side outputs
@@ -519,10 +540,10 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
         RBQ_HIP(hipMemcpy2DAsync(hm.data(), R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
                                  R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
       }
-      if (dbg->ids)
+      if (dbg->ids && !job)
         RBQ_HIP(hipMemcpyAsync(dbg->ids, ids_out, (size_t)nq * k * sizeof(int64_t),
                                hipMemcpyDeviceToHost, s));
-      if (dbg->sqdist)
+      if (dbg->sqdist && !job)
         RBQ_HIP(hipMemcpyAsync(dbg->sqdist, dist_out, (size_t)nq * k * sizeof(float), hipMemcpyDeviceToHost, s));
     }
     if (ws) ws_release(idx, std::move(ws), s);
@@ -539,6 +560,153 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
         if (dbg->cand_est) dbg->cand_est[t] = v == KEY_NONE ? INFINITY : f32_ord((uint32_t)(v >> 32));
       }
     }
+  }
+}
+
+// Pinned host staging for the host re-rank, cached by the index.
+struct Pinned {
+  rbq_index* idx;
+  void* p = nullptr;
+  size_t cap = 0;
+  Pinned(rbq_index* ix, size_t bytes) : idx(ix) {
+    {
+      std::lock_guard<std::mutex> g(idx->host_mu);
+      size_t best = (size_t)-1;
+      for (size_t i = 0; i < idx->pinned_free.size(); ++i)
+        if (idx->pinned_free[i].second >= bytes &&
+            (best == (size_t)-1 || idx->pinned_free[i].second < idx->pinned_free[best].second))
+          best = i;
+      if (best != (size_t)-1) {
+        p = idx->pinned_free[best].first;
+        cap = idx->pinned_free[best].second;
+        idx->pinned_free.erase(idx->pinned_free.begin() + best);
+        return;
+      }
+    }
+    RBQ_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    cap = bytes;
+  }
+  ~Pinned() {
+    std::lock_guard<std::mutex> g(idx->host_mu);
+    idx->pinned_free.emplace_back(p, cap);
+  }
+};
+
+ThreadPool& host_pool(rbq_index* idx) {
+  std::lock_guard<std::mutex> g(idx->host_mu);
+  if (!idx->pool) {
+    int t = idx->host_threads;
+    if (t <= 0) t = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+    idx->pool.reset(new ThreadPool(t));
+  }
+  return *idx->pool;
+}
+
+// Search with the re-rank on host cores (raw vectors in pinned host memory).
+// The batch is cut into sub-batches: while the host threads re-rank one, the
+// GPU already searches the next (the overlap of Sec. 3.3.4).
+void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
+                        int64_t* ids, float* dist, hipStream_t s, const SearchIO& io) {
+  const int d = idx->d;
+  const bool qdev = is_device_ptr(q);
+  const bool ids_dev = ids && is_device_ptr(ids), dist_dev = dist && is_device_ptr(dist);
+  const rbq_debug_io* dbg = io.dbg;
+  const int parts = dbg ? 1 : (nq >= 2048 ? 4 : (nq >= 256 ? 2 : 1));
+  const int64_t sb = ceil_div(nq, (int64_t)parts);
+  const bool stage_out = !ids || !dist || ids_dev || dist_dev;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t o_cand = carve((size_t)nq * R * sizeof(uint64_t));
+  const size_t o_q = qdev ? carve((size_t)nq * d * sizeof(float)) : 0;
+  const size_t o_ids = stage_out ? carve((size_t)nq * k * sizeof(int64_t)) : 0;
+  const size_t o_dist = stage_out ? carve((size_t)nq * k * sizeof(float)) : 0;
+  Pinned pin(idx, std::max<size_t>(off, 256));
+  char* base = static_cast<char*>(pin.p);
+  uint64_t* hc = reinterpret_cast<uint64_t*>(base + o_cand);
+  float* hq = qdev ? reinterpret_cast<float*>(base + o_q) : const_cast<float*>(q);
+  int64_t* hids = stage_out ? reinterpret_cast<int64_t*>(base + o_ids) : ids;
+  float* hdist = stage_out ? reinterpret_cast<float*>(base + o_dist) : dist;
+
+  ThreadPool& pool = host_pool(idx);
+  Latch latch;
+  std::mutex emu;
+  std::string err;
+  rbq_status est = RBQ_OK;
+  std::vector<hipEvent_t> events;
+  auto wait_all = [&]() {
+    latch.wait();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
+  };
+  try {
+    for (int64_t q0 = 0; q0 < nq; q0 += sb) {
+      const int64_t q1 = std::min(nq, q0 + sb);
+      HostJob job;
+      job.cand = hc + q0 * R;
+      job.qh = hq + q0 * d;
+      RBQ_HIP(hipEventCreateWithFlags(&job.ready, hipEventDisableTiming));
+      events.push_back(job.ready);
+      SearchIO sub = io;
+      if (io.q_nprobe) {
+        sub.q_nprobe = io.q_nprobe + q0;
+        sub.q_k = io.q_k + q0;
+        sub.q_R = io.q_R + q0;
+      }
+      const float* qsrc = q + q0 * d;
+      search_part(idx, qsrc, q1 - q0, nprobe, k, R, nullptr, nullptr, s, sub, &job);
+      const int tasks = std::max(1, std::min<int>(pool.size(), (int)ceil_div(q1 - q0, (int64_t)8)));
+      const int64_t per = ceil_div(q1 - q0, (int64_t)tasks);
+      for (int64_t r0 = q0; r0 < q1; r0 += per) {
+        const int64_t r1 = std::min(q1, r0 + per);
+        latch.add(1);
+        const hipEvent_t ready = job.ready;
+        pool.submit([=, &latch, &emu, &err, &est]() {
+          try {
+            RBQ_HIP(hipEventSynchronize(ready));
+            host_rerank_rows(idx->hostX, idx->n, d, hq, hc, R, io.q_k, k, r0, r1, hids, hdist);
+          } catch (const Error& e) {
+            std::lock_guard<std::mutex> g(emu);
+            est = e.status;
+            err = e.what();
+          } catch (const std::exception& e) {
+            std::lock_guard<std::mutex> g(emu);
+            est = RBQ_EDEVICE;
+            err = e.what();
+          }
+          latch.done();
+        });
+      }
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    wait_all();
+    throw;
+  }
+  wait_all();
+  if (est != RBQ_OK) throw Error(est, err);
+  if (ids && ids != hids)
+    RBQ_HIP(hipMemcpyAsync(ids, hids, (size_t)nq * k * sizeof(int64_t), hipMemcpyDefault, s));
+  if (dist && dist != hdist)
+    RBQ_HIP(hipMemcpyAsync(dist, hdist, (size_t)nq * k * sizeof(float), hipMemcpyDefault, s));
+  if (dbg && dbg->ids) std::memcpy(dbg->ids, hids, (size_t)nq * k * sizeof(int64_t));
+  if (dbg && dbg->sqdist) std::memcpy(dbg->sqdist, hdist, (size_t)nq * k * sizeof(float));
+  RBQ_HIP(hipStreamSynchronize(s));  // the staging is reused once the copies are done
+}
+
+}  // namespace
+
+void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
+            float* dist, hipStream_t s, const SearchIO& io) {
+  if (nq == 0) return;
+  if (idx->vectors_on_host) {
+    RBQ_HIP(hipSetDevice(idx->device));
+    search_host_rerank(idx, q, nq, nprobe, k, R, ids, dist, s, io);
+  } else {
+    search_part(idx, q, nq, nprobe, k, R, ids, dist, s, io, nullptr);
   }
 }
 

@@ -204,7 +204,6 @@ void lane_main(rbq_server* S, int li) {
 rbq_server* server_create(rbq_index* idx, const rbq_server_params& p0) {
   rbq_server_params p = p0;
   if (p.max_nprobe == 0) p.max_nprobe = std::min(idx->nlist, 256);
-  RBQ_CHECK(!idx->vectors_on_host, "serving needs the raw vectors in device memory");
   RBQ_CHECK(p.lanes >= 1 && p.lanes <= 8, "lanes must be in [1, 8]");
   RBQ_CHECK(p.max_batch >= 1 && p.max_batch <= 65536, "max_batch must be in [1, 65536]");
   RBQ_CHECK(p.queue_cap >= 1 && p.queue_cap <= (1 << 22), "queue_cap must be in [1, 2^22]");
