@@ -238,6 +238,10 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=128)
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rotation", choices=("fp32", "bf16"), default="fp32",
+                    help="query rotation precision (bf16: BF16 inputs, FP32 accumulation)")
+    ap.add_argument("--vectors-on-host", action="store_true",
+                    help="keep the raw vectors in pinned host memory and re-rank on host cores")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
                     help="Poisson arrival rates (queries/s) of the serving comparison; '' skips it")
     ap.add_argument("--serve-seconds", type=float, default=0.5,
@@ -270,10 +274,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t = time.perf_counter()
-    idx = Index.build(X, w.nlist, bq=w.bq, seed=w.seed)
+    idx = Index.build(X, w.nlist, bq=w.bq, seed=w.seed, vectors_on_host=args.vectors_on_host)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t
     info = idx.info()
+    idx.set_option("rotation", 1 if args.rotation == "bf16" else 0)
     log(f"[build] {build_s:.1f}s, max list {info['max_list_len']}, codes {info['code_bytes'] / 1e6:.1f} MB")
 
     Qb = [torch.from_numpy(Qall[i * w.nq:(i + 1) * w.nq]).to(dev) for i in range(nb)]
@@ -431,6 +436,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,
                    "batch": w.nq, "k": w.k, "rerank_n": R, "bq": w.bq,
+                   "rotation": args.rotation,
+                   "rerank_on": "host" if args.vectors_on_host else "gpu",
                    "parallelism": "none (1 GPU)"},
         "recall_at_10": rec[(nprobe, R)],
         "recall_by_point": {f"nprobe={p},rerank={r}": v for (p, r), v in rec.items()},

@@ -288,18 +288,22 @@ rbq_status rbq_server_replay(rbq_server* srv, const rbq_replay_io* io);
  * the serving loop is compared with). */
 rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
 
-/* Tuning options of an index (apply to later searches on any thread).
- *   RBQ_OPT_SCAN        0: choose per chunk of probe ranks (default),
+/* Tuning options of an index (apply to later searches on any thread). None
+ * changes a search's results except RBQ_OPT_ROTATION.
+ *   RBQ_OPT_SCAN        0: choose per search (default): the list-major scan
+ *                          when d <= 256 and the batch's (query, probed list)
+ *                          pairs number >= RBQ_OPT_GROUP_MIN * nlist,
  *                       1: query-major popcount scan only,
- *                       2: list-major int8-MFMA scan wherever allowed
- *                          (every chunk after the first; d <= 256)
- *   RBQ_OPT_GROUP_MIN   with RBQ_OPT_SCAN 0, a chunk uses the list-major scan
- *                       when nq * (probe ranks in the chunk) >= value * nlist
- *                       (default 4: a list is probed by >= 4 queries on average)
+ *                       2: list-major int8-MFMA scan whenever d <= 256
+ *   RBQ_OPT_GROUP_MIN   the threshold above (default 4: each list is probed
+ *                       by >= 4 queries of the batch on average)
  *   RBQ_OPT_POOL_CAP    cap on the per-query pool of the list-major scan
  *                       (0 = the workspace bound; small values exercise the
- *                       overflow path, which stays exact) */
-enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3 };
+ *                       overflow path, which stays exact)
+ *   RBQ_OPT_ROTATION    query rotation P^T q: 0 FP32 (default), 1 BF16 inputs
+ *                       with FP32 accumulation (q and P rounded to bfloat16,
+ *                       nearest-even; changes the estimates slightly) */
+enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3, RBQ_OPT_ROTATION = 4 };
 rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
 
 /* Persist / restore an index (versioned binary with per-section checksums). */

@@ -467,6 +467,10 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value) {
       if (value < 0) return invalid("RBQ_OPT_POOL_CAP must be >= 0");
       idx->opt_pool_cap.store(value);
       return RBQ_OK;
+    case RBQ_OPT_ROTATION:
+      if (value < 0 || value > 1) return invalid("RBQ_OPT_ROTATION must be 0 or 1");
+      idx->opt_rotation.store((int)value);
+      return RBQ_OK;
     default:
       return invalid("unknown option");
   }

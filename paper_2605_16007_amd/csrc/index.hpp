@@ -94,6 +94,7 @@ struct rbq_index {
   std::atomic<int> opt_scan{0};
   std::atomic<int> opt_group_min{4};
   std::atomic<int64_t> opt_pool_cap{0};
+  std::atomic<int> opt_rotation{0};  // 0 FP32, 1 BF16 inputs (FP32 accumulation)
   int num_cus = 256;
 
   // per-call scratch

@@ -156,6 +156,67 @@ void launch_gemm_tn(hipStream_t s, int mode, const float* A, int lda, const floa
   RBQ_HIP(hipGetLastError());
 }
 
+// Same product with BF16 inputs and FP32 accumulation
+// (v_mfma_f32_16x16x16_bf16): each lane rounds its four A and four B values of
+// a 16-deep K step to bfloat16 (nearest, ties to even) as it feeds the MFMA.
+// Products of bfloat16 values are exact in FP32, so the result differs from the
+// FP32 product only by the input rounding.
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // finite inputs: round the low 16 bits away, ties to even
+  return (short)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_tn_bf16(const float* __restrict__ A, int lda,
+                                                      const float* __restrict__ B, int ldb,
+                                                      float* __restrict__ C, int ldc, int M, int N,
+                                                      int K) {
+  __shared__ float As[64][17];
+  __shared__ float Bs[64][17];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int r16 = lane & 15, kq = 4 * (lane >> 4);
+  v4f acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    gemm_tile_load(A, lda, B, ldb, M, N, K, m0, n0, k0, As, Bs);
+    v4s a0, a1, b0, b1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      a0[t] = bf16_rne(As[wm + r16][kq + t]);
+      a1[t] = bf16_rne(As[wm + 16 + r16][kq + t]);
+      b0[t] = bf16_rne(Bs[wn + r16][kq + t]);
+      b1[t] = bf16_rne(Bs[wn + 16 + r16][kq + t]);
+    }
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + ti * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn + tj * 16 + (lane & 15);
+        if (row < M && col < N) C[(size_t)row * ldc + col] = acc[ti][tj][r];
+      }
+}
+
+void launch_gemm_tn_bf16(hipStream_t s, const float* A, int lda, const float* B, int ldb, float* C,
+                         int ldc, int M, int N, int K) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL(k_gemm_tn_bf16, grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K);
+  RBQ_HIP(hipGetLastError());
+}
+
 // Nearest centroid per row: each workgroup owns 64 rows of A and walks every
 // 64-column tile of B, keeping the running minimum of key64(score, column).
 __global__ __launch_bounds__(256) void k_assign_argmin(const float* __restrict__ A, int lda,

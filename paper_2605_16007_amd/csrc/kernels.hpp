@@ -33,6 +33,11 @@ struct PairsView {
 void launch_gemm_tn(hipStream_t s, int mode, const float* A, int lda, const float* B, int ldb,
                     float* C, int ldc, int M, int N, int K, const float* bnorm);
 
+// C[m][n] = sum_k bf16(A[m][k]) bf16(B[n][k]), FP32 accumulation (inputs
+// rounded to bfloat16, nearest-even). Same operand rules as launch_gemm_tn.
+void launch_gemm_tn_bf16(hipStream_t s, const float* A, int lda, const float* B, int ldb, float* C,
+                         int ldc, int M, int N, int K);
+
 // out[m] = min_n key64(bnorm[n] - 2 <A_m, B_n>, n): nearest row of B per row of A.
 void launch_assign_argmin(hipStream_t s, const float* A, int lda, const float* B, int ldb,
                           const float* bnorm, int M, int N, int K, uint64_t* out);

@@ -341,7 +341,10 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     if (mixed) launch_mask_probes(s, b.probes, (int)nq, nprobe, d_np);
     mark(1);
     // query rotation q' = P^T q (row form q P) on MFMA
-    launch_gemm_tn(s, 0, qd, ld, idx->Pt.as<float>(), ld, b.qrot, ld, (int)nq, d, ld, nullptr);
+    if (idx->opt_rotation.load() == 1)
+      launch_gemm_tn_bf16(s, qd, ld, idx->Pt.as<float>(), ld, b.qrot, ld, (int)nq, d, ld);
+    else
+      launch_gemm_tn(s, 0, qd, ld, idx->Pt.as<float>(), ld, b.qrot, ld, (int)nq, d, ld, nullptr);
     mark(2);
     // residual quantisation per (query, probe)
     if (inj_qu) {

@@ -26,7 +26,7 @@ SYMBOLS = [
     "rbq_server_params_init", "rbq_server_create", "rbq_submit", "rbq_poll", "rbq_wait",
     "rbq_server_get_stats", "rbq_server_destroy", "rbq_server_replay", "rbq_replay_plain",
 ]
-OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3}
+OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4}
 
 
 class BuildParams(C.Structure):
