@@ -242,6 +242,7 @@ def main():
                     help="query rotation precision (bf16: BF16 inputs, FP32 accumulation)")
     ap.add_argument("--vectors-on-host", action="store_true",
                     help="keep the raw vectors in pinned host memory and re-rank on host cores")
+    ap.add_argument("--no-autotune", action="store_true", help="time the built-in launch rule")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
                     help="Poisson arrival rates (queries/s) of the serving comparison; '' skips it")
     ap.add_argument("--serve-seconds", type=float, default=0.5,
@@ -343,6 +344,13 @@ def main():
     else:
         nprobe, R = max(rec, key=lambda pt: rec[pt])
         log(f"[choose] no point reached recall 0.95; timing the best one {(nprobe, R)}")
+    # the autotuner picks the launch choices of each timed shape (results are
+    # unchanged by construction and checked by the library)
+    tuned = {}
+    if not args.no_autotune:
+        for pt in ([(p, w.rerank_n) for p in w.nprobe] if not args.nprobe else []) + [(nprobe, R)]:
+            tuned[f"nprobe={pt[0]},rerank={pt[1]}"] = idx.autotune(Qb[0], pt[0], w.k, pt[1])
+            log(f"[autotune] {pt}: {tuned[f'nprobe={pt[0]},rerank={pt[1]}']}")
     listed_qps = {f"{p}": quick_qps(p, w.rerank_n) for p in w.nprobe} if not args.nprobe else {}
 
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
@@ -374,7 +382,7 @@ def main():
 
     # the two scan forms at the chosen point
     variants = {}
-    for name, mode in (("popcount_query_major", 1), ("mfma_list_major", 0)):
+    for name, mode in (("popcount_query_major", 1), ("mfma_list_major", 2)):
         idx.set_option("scan", mode)
         variants[name] = quick_qps(nprobe, R, steps=10)
     idx.set_option("scan", 0)
@@ -444,6 +452,7 @@ def main():
         "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
         "qps_at_listed_nprobe": listed_qps,
         "qps_by_scan_form": variants,
+        "autotune": tuned,
         "p50_ms": p50,
         "p99_ms": p99,
         "stage_ms": {s: tm[f"{s}_ms"] / ns for s in

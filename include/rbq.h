@@ -306,6 +306,38 @@ rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
 enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3, RBQ_OPT_ROTATION = 4 };
 rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
 
+/*
+ * Autotuner (the launch schedule of Sec. 3.3.1 adapted per batch shape).
+ * Some launch choices of a search leave its results unchanged: the scan form
+ * (query-major popcount or list-major int8 MFMA), the queries grouped per
+ * list-major work item (G), the persistent workgroups per compute unit, and
+ * the size of the first chunk of probe ranks. rbq_autotune times every
+ * candidate on the given queries (host or device, nq x d; representative of
+ * later batches), checks that each returns the same results, and stores the
+ * fastest for the bucket of (nq, nprobe, rerank_n) rounded up to powers of
+ * two. Later searches of any shape in a tuned bucket use it (an explicit
+ * RBQ_OPT_SCAN still fixes the scan form). Blocks the calling thread.
+ * The table can be saved to / loaded from a text cache; its entries are keyed
+ * by device architecture, d, B_q, nlist, n and the list-size histogram, and
+ * only matching entries load.
+ */
+typedef struct {
+  int32_t scan;          /* 1 query-major popcount, 2 list-major int8 MFMA */
+  int32_t group_size;    /* queries per list-major item */
+  int32_t wg_per_cu;     /* persistent list-major workgroups per compute unit */
+  int32_t first_factor;  /* first list-major chunk: ~first_factor * rerank_n candidates per query */
+  float ms;              /* time per search with the chosen launch choices */
+  float ms_default;      /* time per search with the built-in rule */
+  int32_t trials;        /* candidate configurations timed */
+  int32_t reserved[3];
+} rbq_tune_result;
+
+rbq_status rbq_autotune(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+                        int32_t rerank_n, rbq_tune_result* out);
+rbq_status rbq_tune_save(rbq_index* idx, const char* path);
+rbq_status rbq_tune_load(rbq_index* idx, const char* path, int32_t* loaded);
+rbq_status rbq_tune_clear(rbq_index* idx);
+
 /* Persist / restore an index (versioned binary with per-section checksums). */
 rbq_status rbq_save(const rbq_index* idx, const char* path);
 rbq_status rbq_load(const char* path, rbq_index** out);

@@ -487,6 +487,38 @@ rbq_status rbq_load(const char* path, rbq_index** out) {
   return guarded([&] { *out = rbq::load_index(path); });
 }
 
+rbq_status rbq_autotune(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+                        int32_t rerank_n, rbq_tune_result* out) {
+  return guarded([&] {
+    check_search_args(idx, q, nq, nprobe, k, rerank_n);
+    RBQ_CHECK(nq >= 1, "nq must be >= 1");
+    rbq::autotune(idx, q, nq, nprobe, k, rerank_n, out);
+  });
+}
+
+rbq_status rbq_tune_save(rbq_index* idx, const char* path) {
+  return guarded([&] {
+    RBQ_CHECK(idx != nullptr && path != nullptr, "an argument is NULL");
+    rbq::tune_save(idx, path);
+  });
+}
+
+rbq_status rbq_tune_load(rbq_index* idx, const char* path, int32_t* loaded) {
+  return guarded([&] {
+    RBQ_CHECK(idx != nullptr && path != nullptr, "an argument is NULL");
+    const int n = rbq::tune_load(idx, path);
+    if (loaded) *loaded = n;
+  });
+}
+
+rbq_status rbq_tune_clear(rbq_index* idx) {
+  return guarded([&] {
+    RBQ_CHECK(idx != nullptr, "index is NULL");
+    std::lock_guard<std::mutex> g(idx->tune_mu);
+    idx->tune.clear();
+  });
+}
+
 rbq_status rbq_server_params_init(rbq_server_params* p) {
   if (!p) return invalid("params is NULL");
   rbq::server_params_default(p);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <map>
 #include <atomic>
 #include <cstdint>
 #include <memory>
@@ -22,6 +23,15 @@ struct TimingRec {
   hipEvent_t e[6] = {};           // start, probe, rotate, quant, scan+merge, rerank
   std::vector<hipEvent_t> scan;   // (start, end) around every scan launch
   int64_t group = 0, popc = 0;    // scan launches of each form
+};
+
+// Launch choices of a search that leave its results unchanged (the autotuner
+// measures them per batch shape). scan: 1 query-major, 2 list-major; G:
+// queries per list-major item; wg_per_cu: persistent list-major workgroups
+// per CU; first_factor: the first list-major chunk holds about
+// first_factor * R candidates per query.
+struct TuneCfg {
+  int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2;
 };
 
 // A device scratch area reused across calls. `done` is recorded on the stream
@@ -95,6 +105,9 @@ struct rbq_index {
   std::atomic<int> opt_group_min{4};
   std::atomic<int64_t> opt_pool_cap{0};
   std::atomic<int> opt_rotation{0};  // 0 FP32, 1 BF16 inputs (FP32 accumulation)
+  // autotuned launch choices per batch-shape bucket (rbq_autotune)
+  std::mutex tune_mu;
+  std::map<uint64_t, rbq::TuneCfg> tune;
   int num_cus = 256;
 
   // per-call scratch
@@ -138,6 +151,7 @@ struct SearchIO {
   const int32_t* q_k = nullptr;
   const int32_t* q_R = nullptr;
   int64_t pool_budget = 0;  // bytes for the candidate rows (0: 512 MB)
+  const TuneCfg* force = nullptr;  // launch choices to use (autotuner trials)
   // caller-owned device scratch (else the index's pool); not reused by the
   // caller before the search's stream has passed this call
   char* ws_base = nullptr;
@@ -149,6 +163,15 @@ size_t search_workspace_bytes(const rbq_index* idx, int64_t nq, int nprobe, int 
                               int64_t scanned_pairs, int64_t pool_budget);
 void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
             float* dist, hipStream_t s, const SearchIO& io);
+
+// Autotuner (tune.cpp): bucket key of a batch shape, the table lookup used by
+// every search, trials, and the text cache.
+uint64_t tune_key(int64_t nq, int nprobe, int R);
+bool tune_lookup(rbq_index* idx, int64_t nq, int nprobe, int R, TuneCfg* out);
+void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
+              rbq_tune_result* out);
+void tune_save(rbq_index* idx, const char* path);
+int tune_load(rbq_index* idx, const char* path);
 
 void export_item(const rbq_index* idx, int what, void* dst, size_t bytes);
 void save_index(const rbq_index* idx, const char* path);

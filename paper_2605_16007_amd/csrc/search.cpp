@@ -102,6 +102,7 @@ struct Plan {
   int64_t cand_ld = 0, pool_cap = 0;
   bool need_qcopy = true, ids_dev = false, dist_dev = false;
   bool inj_probes = false, inj_qu = false, dumps = false, mixed = false, any_group = false;
+  int G = 64, wg_per_cu = 8;
   const rbq_debug_io* dbg = nullptr;
   std::vector<Chunk> chunks, qm_chunks;
 };
@@ -126,7 +127,7 @@ constexpr int64_t kDefaultPoolBudget = (int64_t)512 << 20;
 // is searched again, from scratch, by the query-major scan (exact; checked
 // once per search).
 Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64_t scanned_pairs,
-               int64_t pool_budget, const rbq_debug_io* dbg) {
+               int64_t pool_budget, const rbq_debug_io* dbg, const TuneCfg* force) {
   Plan P;
   P.nq = nq;
   P.nprobe = nprobe;
@@ -144,7 +145,20 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   P.first = (int)std::min<int64_t>(P.pch, std::max<int64_t>(1, (2048 + nq - 1) / nq));
   if (dbg && dbg->probe_chunk > 0) P.pch = P.first = std::min(P.pch, (int)dbg->probe_chunk);
   P.cand_ld = (int64_t)R * (1 + P.pch);
-  const int scan_mode = idx->opt_scan.load();
+  // launch choices: forced (autotuner trial), else tuned for this batch shape,
+  // else the built-in rule; an explicit RBQ_OPT_SCAN wins over a tuned form
+  TuneCfg cfg;
+  bool tuned = false;
+  if (force) {
+    cfg = *force;
+    tuned = true;
+  } else {
+    tuned = tune_lookup(const_cast<rbq_index*>(idx), nq, nprobe, R, &cfg);
+  }
+  P.G = cfg.G;
+  P.wg_per_cu = cfg.wg_per_cu;
+  int scan_mode = idx->opt_scan.load();
+  if (force || (scan_mode == 0 && tuned)) scan_mode = cfg.scan;
   const int group_min = idx->opt_group_min.load();
   P.pool_cap = (int64_t)R * P.pch;
   if (idx->opt_pool_cap.load() > 0) P.pool_cap = std::min<int64_t>(P.pool_cap, idx->opt_pool_cap.load());
@@ -161,7 +175,7 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
     const int64_t maxl = std::max<int64_t>(1, idx->max_list_len);
     const int64_t avgl = std::max<int64_t>(1, idx->n / idx->nlist);
     int pn = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nprobe, P.pool_cap / maxl,
-                                                          ceil_div(2 * (int64_t)R, avgl)}));
+                                                          ceil_div((int64_t)cfg.first_factor * R, avgl)}));
     if (dbg && dbg->probe_chunk > 0) pn = std::min(pn, (int)dbg->probe_chunk);
     for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, p0)) {
       pn = std::min(pn, nprobe - p0);
@@ -190,7 +204,7 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
     b.pair_off = c.take<int32_t>(nlist + 1);
     b.item_off = c.take<int32_t>(nlist + 1);
     b.slots = c.take<int32_t>(pairs);
-    b.items = c.take<int4>(pairs / 64 + nlist + 1);
+    b.items = c.take<int4>(pairs / P.G + nlist + 1);
     b.overflow = c.take<uint32_t>(nq);
     b.counter = c.take<uint32_t>(2);
   }
@@ -219,7 +233,7 @@ namespace rbq {
 
 size_t search_workspace_bytes(const rbq_index* idx, int64_t nq, int nprobe, int k, int R,
                               int64_t scanned_pairs, int64_t pool_budget) {
-  Plan P = make_plan(idx, nq, nprobe, k, R, scanned_pairs, pool_budget, nullptr);
+  Plan P = make_plan(idx, nq, nprobe, k, R, scanned_pairs, pool_budget, nullptr, nullptr);
   P.mixed = true;
   Carver dry(nullptr);
   Bufs b;
@@ -255,7 +269,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       scanned_pairs += io.q_nprobe[i];
     }
   }
-  Plan P = make_plan(idx, nq, nprobe, k, R, scanned_pairs, io.pool_budget, dbg);
+  Plan P = make_plan(idx, nq, nprobe, k, R, scanned_pairs, io.pool_budget, dbg, io.force);
   P.mixed = mixed;
   const bool qdev = is_device_ptr(q);
   P.need_qcopy = !qdev || ld != d || (reinterpret_cast<uintptr_t>(q) & 15);
@@ -390,7 +404,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     ga.nprobe = nprobe;
     ga.R = R;
     ga.nlist = nlist;
-    ga.G = 64;
+    ga.G = P.G;
     ga.slots = b.slots;
     ga.pair_off = b.pair_off;
     ga.item_off = b.item_off;
@@ -456,7 +470,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
           tr.scan.push_back(e1);
           RBQ_HIP(hipEventRecord(e0, s));
         }
-        launch_scan_group(s, ga, 8 * idx->num_cus);
+        launch_scan_group(s, ga, P.wg_per_cu * idx->num_cus);
         if (timed) {
           RBQ_HIP(hipEventRecord(e1, s));
           tr.group += 1;

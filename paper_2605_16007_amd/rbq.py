@@ -25,6 +25,7 @@ SYMBOLS = [
     "rbq_load", "rbq_last_error", "rbq_version", "rbq_set_option", "rbq_search_mixed",
     "rbq_server_params_init", "rbq_server_create", "rbq_submit", "rbq_poll", "rbq_wait",
     "rbq_server_get_stats", "rbq_server_destroy", "rbq_server_replay", "rbq_replay_plain",
+    "rbq_autotune", "rbq_tune_save", "rbq_tune_load", "rbq_tune_clear",
 ]
 OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4}
 
@@ -75,6 +76,12 @@ class ReplayIO(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "q", "nprobe", "k", "rerank_n", "arrival_s", "ids", "sqdist", "latency_s")] + [
         ("n", C.c_int64), ("k_stride", C.c_int32), ("reserved", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("scan", C.c_int32), ("group_size", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("first_factor", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
+                ("trials", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class RbqError(RuntimeError):
@@ -128,6 +135,10 @@ def lib():
         L.rbq_server_destroy.argtypes = [vp]
         L.rbq_server_replay.argtypes = [vp, C.POINTER(ReplayIO)]
         L.rbq_replay_plain.argtypes = [vp, C.POINTER(ReplayIO)]
+        L.rbq_autotune.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(TuneResult)]
+        L.rbq_tune_save.argtypes = [vp, C.c_char_p]
+        L.rbq_tune_load.argtypes = [vp, C.c_char_p, C.POINTER(i32)]
+        L.rbq_tune_clear.argtypes = [vp]
         for name in SYMBOLS:
             if name not in ("rbq_build_params_init", "rbq_last_error", "rbq_version"):
                 getattr(L, name).restype = C.c_int
@@ -337,6 +348,27 @@ class Index:
         _check(lib().rbq_search_debug(self._h, q.ctypes.data, nq, int(nprobe), int(k),
                                       int(rerank_n), C.byref(io)))
         return out
+
+    def autotune(self, q, nprobe, k, rerank_n) -> dict:
+        """Time the result-preserving launch choices on these queries and keep
+        the fastest for this batch shape (rbq_autotune)."""
+        if not _is_torch(q):
+            q = np.ascontiguousarray(q, np.float32)
+        r = TuneResult()
+        _check(lib().rbq_autotune(self._h, _ptr(q), q.shape[0], int(nprobe), int(k), int(rerank_n),
+                                  C.byref(r)))
+        return {f: getattr(r, f) for f, _ in TuneResult._fields_ if f != "reserved"}
+
+    def tune_save(self, path):
+        _check(lib().rbq_tune_save(self._h, os.fsencode(path)))
+
+    def tune_load(self, path) -> int:
+        n = C.c_int32()
+        _check(lib().rbq_tune_load(self._h, os.fsencode(path), C.byref(n)))
+        return n.value
+
+    def tune_clear(self):
+        _check(lib().rbq_tune_clear(self._h))
 
     def set_option(self, name: str, value: int):
         """Tuning knobs: scan (0 auto, 1 query-major popcount, 2 list-major

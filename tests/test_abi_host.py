@@ -105,6 +105,18 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(rbq.ServerParams) == 6 * 4 + 8 + 8 * 4
     assert C.sizeof(rbq.ServerStats) == 8 * 8
     assert C.sizeof(rbq.ReplayIO) == 8 * 8 + 8 + 4 + 4
+    assert C.sizeof(rbq.TuneResult) == 4 * 4 + 2 * 4 + 4 + 3 * 4
+
+
+def test_tuning_null_arguments():
+    L = rbq.lib()
+    q = np.zeros((2, 8), np.float32)
+    r = rbq.TuneResult()
+    assert L.rbq_autotune(None, q.ctypes.data, 2, 1, 1, 1, C.byref(r)) == rbq.RBQ_EINVAL
+    assert L.rbq_tune_save(None, b"/tmp/x") == rbq.RBQ_EINVAL
+    n = C.c_int32()
+    assert L.rbq_tune_load(None, b"/tmp/x", C.byref(n)) == rbq.RBQ_EINVAL
+    assert L.rbq_tune_clear(None) == rbq.RBQ_EINVAL
 
 
 def test_server_params_defaults():
