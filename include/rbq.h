@@ -187,7 +187,10 @@ typedef struct {
   int64_t read_bytes;        /* code and factor bytes the scan kernels' schedule reads
                                 (list-major items read a list once per item) */
   int64_t group_launches;    /* list-major scan launches summed */
-  int64_t popc_launches;     /* query-major scan launches summed */
+  int64_t popc_launches;     /* query-major scan launches (popcount or fused) summed */
+  float group_scan_ms;       /* the list-major scan launches alone */
+  int64_t group_vectors;     /* scanned_vectors of the list-major launches */
+  int64_t group_read_bytes;  /* read_bytes of the list-major launches */
 } rbq_timings;
 
 rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled);
@@ -290,13 +293,15 @@ rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
 
 /* Tuning options of an index (apply to later searches on any thread). None
  * changes a search's results except RBQ_OPT_ROTATION.
- *   RBQ_OPT_SCAN        0: choose per search (default): the list-major scan
- *                          when d <= 256 and the batch's (query, probed list)
- *                          pairs number >= RBQ_OPT_GROUP_MIN * nlist,
+ *   RBQ_OPT_SCAN        0: choose per chunk of probe ranks (default; or as
+ *                          autotuned): with d <= 256, the list-major scan for
+ *                          chunks whose (query, probed list) pairs number
+ *                          >= RBQ_OPT_GROUP_MIN * nlist, the query-major scan
+ *                          for the others,
  *                       1: query-major popcount scan only,
- *                       2: list-major int8-MFMA scan whenever d <= 256
+ *                       2: list-major int8-MFMA scan for every chunk (d <= 256)
  *   RBQ_OPT_GROUP_MIN   the threshold above (default 4: each list is probed
- *                       by >= 4 queries of the batch on average)
+ *                       by >= 4 queries of the chunk on average)
  *   RBQ_OPT_POOL_CAP    cap on the per-query pool of the list-major scan
  *                       (0 = the workspace bound; small values exercise the
  *                       overflow path, which stays exact)
@@ -322,14 +327,17 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
  * only matching entries load.
  */
 typedef struct {
-  int32_t scan;          /* 1 query-major popcount, 2 list-major int8 MFMA */
+  int32_t scan;          /* 1 query-major popcount only; 2 list-major int8 MFMA for the
+                            chunks of probe ranks selected by chunk_group_min */
   int32_t group_size;    /* queries per list-major item */
   int32_t wg_per_cu;     /* persistent list-major workgroups per compute unit */
-  int32_t first_factor;  /* first list-major chunk: ~first_factor * rerank_n candidates per query */
+  int32_t first_factor;  /* first chunk: ~first_factor * rerank_n candidates per query */
   float ms;              /* time per search with the chosen launch choices */
   float ms_default;      /* time per search with the built-in rule */
   int32_t trials;        /* candidate configurations timed */
-  int32_t reserved[3];
+  int32_t chunk_group_min; /* a chunk is list-major when its (query, probe) pairs
+                              number >= this * nlist (0: every chunk) */
+  int32_t reserved[2];
 } rbq_tune_result;
 
 rbq_status rbq_autotune(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,

@@ -21,11 +21,14 @@ SOURCES = ["kernels.hip", "kernels_group.hip", "build.cpp", "search.cpp", "serve
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
-    # IEEE order of operations everywhere: the estimator epilogue and the
-    # query quantiser must round exactly as written
+    # IEEE order of operations everywhere: the estimator epilogue (whose fused
+    # multiply-adds are written out explicitly) and the query quantiser must
+    # round exactly as written
     "-ffp-contract=off",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in VGPRs (no accumulator-register copies in the scan epilogue)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

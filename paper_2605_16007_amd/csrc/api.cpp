@@ -404,8 +404,8 @@ rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled) {
     idx->pending.clear();
     idx->last = rbq_timings{};
     if (enabled) {
-      if (!idx->tcounter.p) idx->tcounter.alloc(2 * sizeof(unsigned long long));
-      RBQ_HIP(hipMemset(idx->tcounter.p, 0, 2 * sizeof(unsigned long long)));
+      if (!idx->tcounter.p) idx->tcounter.alloc(4 * sizeof(unsigned long long));
+      RBQ_HIP(hipMemset(idx->tcounter.p, 0, 4 * sizeof(unsigned long long)));
     }
     idx->timing.store(enabled ? 1 : 0);
   });
@@ -418,14 +418,16 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
     std::lock_guard<std::mutex> g(idx->timing_mu);
     for (auto& a : idx->pending) {
       RBQ_HIP(hipEventSynchronize(a.e[5]));
-      float ms[5], tot = 0.f, scan = 0.f;
+      float ms[5], tot = 0.f, scan = 0.f, gscan = 0.f;
       for (int i = 0; i < 5; ++i) RBQ_HIP(hipEventElapsedTime(&ms[i], a.e[i], a.e[i + 1]));
       RBQ_HIP(hipEventElapsedTime(&tot, a.e[0], a.e[5]));
       for (size_t c = 0; c + 1 < a.scan.size(); c += 2) {
         float t = 0.f;
         RBQ_HIP(hipEventElapsedTime(&t, a.scan[c], a.scan[c + 1]));
         scan += t;
+        if (a.scan_lm[c / 2]) gscan += t;
       }
+      idx->last.group_scan_ms += gscan;
       idx->last.probe_ms += ms[0];
       idx->last.rotate_ms += ms[1];
       idx->last.quant_ms += ms[2];
@@ -441,12 +443,14 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
     }
     idx->pending.clear();
     if (idx->tcounter.p) {
-      unsigned long long c[2] = {0, 0};
+      unsigned long long c[4] = {0, 0, 0, 0};
       RBQ_HIP(hipDeviceSynchronize());
       RBQ_HIP(hipMemcpy(c, idx->tcounter.p, sizeof(c), hipMemcpyDeviceToHost));
       idx->last.scanned_vectors = (int64_t)c[0];
       idx->last.scan_bytes = (int64_t)c[0] * (idx->W * 4 + 8);
       idx->last.read_bytes = (int64_t)c[1];
+      idx->last.group_vectors = (int64_t)c[2];
+      idx->last.group_read_bytes = (int64_t)c[3];
     }
     *t = idx->last;
   });

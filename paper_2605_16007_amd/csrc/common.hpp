@@ -50,6 +50,23 @@ __host__ __device__ inline uint64_t key64(float v, uint32_t tie) {
 }
 constexpr uint64_t KEY_NONE = ~0ull;
 
+// d_hat^2 of Eq. approx-dist from the exact integer inner product
+// ip = sum_d b01_d qu_d (Eq. rabitq-ip-estimator with the B_q-bit query):
+//   d_hat^2 = ||r||^2 + n_x^2 + f_x E,  f_x = -2 n_x / (sqrt(D) alpha_x),
+//   E = v_l (2 pop - D) + Delta (2 ip - sum qu),
+// regrouped as fma(f_x Delta, 2 ip - sum qu, fma(v_l, vx, n_x^2)) + ||r||^2
+// with the per-vector vx = f_x (2 pop - D). Every scan evaluates exactly this
+// expression, so their estimates agree bit for bit.
+__device__ __forceinline__ float rbq_vx(float fmul, int pop, int D) {
+  return fmul * (float)(2 * pop - D);
+}
+// (neg_sumqu = -sum qu, so that 2 ip - sum qu is one shift-add)
+__device__ __forceinline__ float rbq_estimate(float rn2, float vl, float delta, int neg_sumqu, int ip,
+                                              float fadd, float fmul, float vx) {
+  const float g = (float)((ip << 1) + neg_sumqu);
+  return __builtin_fmaf(fmul * delta, g, __builtin_fmaf(vl, vx, fadd)) + rn2;
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 

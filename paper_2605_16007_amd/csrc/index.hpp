@@ -22,16 +22,19 @@ namespace rbq {
 struct TimingRec {
   hipEvent_t e[6] = {};           // start, probe, rotate, quant, scan+merge, rerank
   std::vector<hipEvent_t> scan;   // (start, end) around every scan launch
+  std::vector<char> scan_lm;      // per launch: list-major form
   int64_t group = 0, popc = 0;    // scan launches of each form
 };
 
 // Launch choices of a search that leave its results unchanged (the autotuner
-// measures them per batch shape). scan: 1 query-major, 2 list-major; G:
-// queries per list-major item; wg_per_cu: persistent list-major workgroups
-// per CU; first_factor: the first list-major chunk holds about
-// first_factor * R candidates per query.
+// measures them per batch shape). scan: 1 query-major everywhere, 2 the
+// list-major MFMA scan for chunks of probe ranks with >= gm * nlist (query,
+// probe) pairs (gm = 0: all chunks) and query-major for the others; G: queries
+// per list-major item; wg_per_cu: persistent list-major workgroups per CU;
+// first_factor: the first chunk holds about first_factor * R candidates per
+// query.
 struct TuneCfg {
-  int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2;
+  int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2, gm = 4;
 };
 
 // A device scratch area reused across calls. `done` is recorded on the stream
@@ -121,7 +124,8 @@ struct rbq_index {
   std::mutex timing_mu;
   rbq_timings last{};
   std::vector<rbq::TimingRec> pending;
-  rbq::DevBuf tcounter;  // device sums: [0] scanned vectors, [1] record bytes read
+  rbq::DevBuf tcounter;  // device sums: scanned vectors, record bytes read; the same two
+                         // for the list-major launches alone
 
   // host re-rank (vectors_on_host): worker threads and pinned staging, made on
   // first use and kept with the index

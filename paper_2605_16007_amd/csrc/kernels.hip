@@ -6,6 +6,7 @@
 // (Phase 4) and exact re-rank (Phase 5). Build path (Sec. 3.1.1): k-means
 // assignment GEMM with fused argmin and the RaBitQ encoder (Phase 3).
 #include <algorithm>
+#include <mutex>
 #include <cfloat>
 #include <cmath>
 
@@ -274,21 +275,46 @@ void launch_assign_argmin(hipStream_t s, const float* A, int lda, const float* B
 
 // ---------------------------------------------------------------------------
 // Row top-k: exact selection of the k smallest 64-bit keys of each row by an
-// MSB-first radix select (8-bit digits, early exit once the boundary bucket is
-// taken whole), compaction, and an LDS bitonic sort of the k survivors.
+// MSB-first radix select, compaction, and (sorted mode) an LDS bitonic sort of
+// the k survivors. The row is staged in LDS when it fits (up to ~150 KB). The
+// digits start at the highest bit in which the row's smallest and largest keys
+// differ (bits above it are common to every key and would only pile every
+// histogram atomic onto one bin); each pass takes up to 8 bits and the select
+// stops as soon as the boundary bucket is taken whole. Compaction appends with
+// one LDS atomic per wave (ballot + lane prefix).
 // ---------------------------------------------------------------------------
 
-template <bool FROM_SCORE>
-__global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
+// Inclusive prefix sum of hist[0..256) for a workgroup of NT threads
+// (threads >= 256 contribute 0). wsum: 4 words of LDS.
+template <int NT>
+__device__ uint32_t hist_incl_scan(uint32_t v, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off);
+    if (lane >= off) v += t;
+  }
+  if (lane == 63 && wave < 4) wsum[wave] = v;
+  __syncthreads();
+  uint32_t add = 0;
+  for (int w = 0; w < wave && w < 4; ++w) add += wsum[w];
+  __syncthreads();
+  return v + add;
+}
+
+template <bool FROM_SCORE, int NT>
+__global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
+  constexpr int NW = NT / 64;       // waves
+  constexpr int NH = NT >= 512 ? 4 : 1;  // histogram copies (waves share copy w % NH)
   extern __shared__ uint64_t smem[];
-  __shared__ uint32_t hist[256];
+  __shared__ uint32_t hist[NH][256];
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t s_digit, s_rem, s_bucket, s_cnt;
-  const int tid = threadIdx.x;
+  __shared__ uint64_t s_lo[NW], s_hi[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row = blockIdx.x;
   const int k = a.rowk ? a.rowk[row] : a.k, KP = a.KP;
   int ncols = a.ncols;
-  if (a.rowcnt) {  // pool mode: the row holds k running keys then rowcnt[row] new ones
+  if (a.rowcnt) {  // pool mode: the row holds a.k running keys then rowcnt[row] new ones
     const uint32_t extra = min(a.rowcnt[row], (uint32_t)a.max_extra);
     if (extra == 0) return;
     ncols = a.k + (int)extra;
@@ -301,61 +327,128 @@ __global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
     return a.keys[row * a.ld + c];
   };
   auto get = [&](int c) -> uint64_t { return cached ? cache[c] : src(c); };
-  if (cached)
-    for (int c = tid; c < ncols; c += 256) cache[c] = src(c);
-  __syncthreads();
 
   const bool take_all = ncols <= k;
   uint64_t prefix = 0, pmask = 0;
   uint32_t rem = (uint32_t)k;
-  if (!take_all) {
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      hist[tid] = 0;
-      __syncthreads();
-      for (int c = tid; c < ncols; c += 256) {
-        const uint64_t key = get(c);
-        if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+  {
+    // stage the row (eight loads in flight per thread); smallest and largest key
+    uint64_t lo = ~0ull, hi = 0;
+    for (int c0 = 0; c0 < ncols; c0 += 8 * NT) {
+      uint64_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u * NT + tid;
+        v[u] = c < ncols ? src(c) : 0ull;
       }
-      __syncthreads();
-      const uint32_t h = hist[tid];
-      const uint32_t incl = block_incl_scan_256(h, wsum);
-      const uint32_t excl = incl - h;
-      if (excl < rem && rem <= incl) {
-        s_digit = (uint32_t)tid;
-        s_rem = rem - excl;
-        s_bucket = h;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u * NT + tid;
+        if (c < ncols) {
+          if (cached) cache[c] = v[u];
+          lo = v[u] < lo ? v[u] : lo;
+          hi = v[u] > hi ? v[u] : hi;
+        }
       }
-      __syncthreads();
-      prefix |= (uint64_t)s_digit << shift;
-      pmask |= 0xFFull << shift;
-      rem = s_rem;
-      const uint32_t bucket = s_bucket;
-      __syncthreads();
-      if (bucket == rem) break;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+      lo = l2 < lo ? l2 : lo;
+      hi = h2 > hi ? h2 : hi;
+    }
+    if (lane == 0) {
+      s_lo[wave] = lo;
+      s_hi[wave] = hi;
+    }
+    __syncthreads();
+    lo = s_lo[0];
+    hi = s_hi[0];
+    for (int w = 1; w < NW; ++w) {
+      lo = s_lo[w] < lo ? s_lo[w] : lo;
+      hi = s_hi[w] > hi ? s_hi[w] : hi;
+    }
+    const uint64_t diff = lo ^ hi;
+    const int top = diff ? 63 - __clzll((long long)diff) : -1;  // highest bit in which keys differ
+    if (top < 63) {  // bits above `top` are the same in every key
+      pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
+      prefix = lo & pmask;
+    }
+    if (!take_all) {
+      for (int hb = top; hb >= 0;) {
+        const int lb = hb >= 7 ? hb - 7 : 0;
+        const uint64_t dmask = ((2ull << (hb - lb)) - 1ull);
+        for (int t = tid; t < NH * 256; t += NT) (&hist[0][0])[t] = 0;
+        __syncthreads();
+        uint32_t* hw = hist[wave % NH];
+        for (int c = tid; c < ncols; c += NT) {
+          const uint64_t key = get(c);
+          if ((key & pmask) == prefix) atomicAdd(&hw[(key >> lb) & dmask], 1u);
+        }
+        __syncthreads();
+        uint32_t h = 0;
+        if (tid < 256)
+          for (int t = 0; t < NH; ++t) h += hist[t][tid];
+        const uint32_t incl = hist_incl_scan<NT>(h, wsum);
+        const uint32_t excl = incl - h;
+        if (tid < 256 && excl < rem && rem <= incl) {
+          s_digit = (uint32_t)tid;
+          s_rem = rem - excl;
+          s_bucket = h;
+        }
+        __syncthreads();
+        prefix |= (uint64_t)s_digit << lb;
+        pmask |= dmask << lb;
+        rem = s_rem;
+        const uint32_t bucket = s_bucket;
+        __syncthreads();
+        if (bucket == rem) break;
+        hb = lb - 1;
+      }
     }
   }
   if (tid == 0) s_cnt = 0;
   __syncthreads();
+  // compaction: keys below the prefix, then boundary-bucket keys up to k in all
+  const int rounds = (ncols + NT - 1) / NT;
   if (take_all) {
-    for (int c = tid; c < ncols; c += 256) sel[atomicAdd(&s_cnt, 1u)] = get(c);
+    for (int r = 0; r < rounds; ++r) {
+      const int c = r * NT + tid;
+      const bool t = c < ncols;
+      const uint64_t m = __ballot(t);
+      uint32_t base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+      base = __shfl(base, 0);
+      if (t) sel[base + lane_prefix(m)] = get(c);
+    }
   } else {
-    for (int c = tid; c < ncols; c += 256) {
-      const uint64_t key = get(c);
-      if (key < prefix) sel[atomicAdd(&s_cnt, 1u)] = key;
+    const uint64_t hi_key = prefix | ~pmask;
+    for (int r = 0; r < rounds; ++r) {
+      const int c = r * NT + tid;
+      const uint64_t key = c < ncols ? get(c) : KEY_NONE;
+      const bool t = c < ncols && key < prefix;
+      const uint64_t m = __ballot(t);
+      uint32_t base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+      base = __shfl(base, 0);
+      if (t) sel[base + lane_prefix(m)] = key;
     }
     __syncthreads();
-    const uint64_t hi = prefix | ~pmask;
-    for (int c = tid; c < ncols; c += 256) {
-      const uint64_t key = get(c);
-      if (key >= prefix && key <= hi) {
-        const uint32_t p = atomicAdd(&s_cnt, 1u);
-        if (p < (uint32_t)k) sel[p] = key;
-      }
+    for (int r = 0; r < rounds; ++r) {
+      const int c = r * NT + tid;
+      const uint64_t key = c < ncols ? get(c) : KEY_NONE;
+      const bool t = c < ncols && key >= prefix && key <= hi_key;
+      const uint64_t m = __ballot(t);
+      uint32_t base = 0;
+      if (lane == 0 && m) base = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+      base = __shfl(base, 0);
+      const uint32_t p = base + lane_prefix(m);
+      if (t && p < (uint32_t)k) sel[p] = key;
     }
   }
   __syncthreads();
   const int cnt = min((int)s_cnt, k);
-  for (int i = cnt + tid; i < KP; i += 256) sel[i] = KEY_NONE;
+  const int fill_to = a.sorted ? KP : k;
+  for (int i = cnt + tid; i < fill_to; i += NT) sel[i] = KEY_NONE;
   __syncthreads();
   uint64_t kth;  // the k-th smallest key (KEY_NONE if fewer than k)
   if (a.sorted) {
@@ -363,18 +456,17 @@ __global__ __launch_bounds__(256) void k_row_topk(TopkArgs a) {
     kth = sel[k - 1];
   } else {  // the selected keys in any order; their maximum is the k-th
     uint64_t mx = 0;
-    for (int i = tid; i < k; i += 256) mx = sel[i] > mx ? sel[i] : mx;
+    for (int i = tid; i < k; i += NT) mx = sel[i] > mx ? sel[i] : mx;
     for (int off = 32; off > 0; off >>= 1) {
       const uint64_t o = __shfl_xor(mx, off);
       mx = o > mx ? o : mx;
     }
-    __shared__ uint64_t s_mx[4];
-    if ((tid & 63) == 0) s_mx[tid >> 6] = mx;
+    if (lane == 0) s_hi[wave] = mx;
     __syncthreads();
-    kth = s_mx[0];
-    for (int w = 1; w < 4; ++w) kth = s_mx[w] > kth ? s_mx[w] : kth;
+    kth = s_hi[0];
+    for (int w = 1; w < NW; ++w) kth = s_hi[w] > kth ? s_hi[w] : kth;
   }
-  for (int i = tid; i < k; i += 256) {
+  for (int i = tid; i < k; i += NT) {
     const uint64_t v = sel[i];
     if (a.out_keys) a.out_keys[row * a.ldo + i] = v;
     if (a.out_low) a.out_low[row * k + i] = v == KEY_NONE ? -1 : (int32_t)(uint32_t)v;
@@ -392,20 +484,34 @@ static int pow2_at_least(int n) {
   return p;
 }
 
+constexpr size_t kTopkLdsMax = 150u << 10;  // dynamic LDS of one selection workgroup
+
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   if (rows <= 0) return;
   RBQ_CHECK(a.k >= 1 && a.k <= MAX_SEL, "selection size out of range");
   a.KP = pow2_at_least(a.k);
   if (a.ldo <= 0) a.ldo = a.k;
   const int maxcols = a.rowcnt ? a.k + a.max_extra : a.ncols;
-  // stage a row in LDS when it fits next to the sort buffer (48 KB in all)
-  const int room = (int)((48 << 10) / sizeof(uint64_t)) - a.KP;
+  // selection buffer: KP keys (sorted mode) or k keys; the row is staged in
+  // LDS next to it when it fits
+  const int selcap = a.sorted ? a.KP : a.k;
+  const int room = (int)(kTopkLdsMax / sizeof(uint64_t)) - selcap;
   a.cache_cap = std::max(0, std::min(maxcols, room));
-  const size_t lds = (size_t)(a.cache_cap + a.KP) * sizeof(uint64_t);
+  const size_t lds = (size_t)(a.cache_cap + selcap) * sizeof(uint64_t);
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    for (const void* f : {reinterpret_cast<const void*>(k_row_topk<true, 256>),
+                          reinterpret_cast<const void*>(k_row_topk<false, 256>),
+                          reinterpret_cast<const void*>(k_row_topk<false, 1024>)})
+      RBQ_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTopkLdsMax));
+  });
+  // pool merges (long rows, one workgroup per CU for the LDS) run 16 waves
   if (a.score)
-    hipLaunchKernelGGL(k_row_topk<true>, dim3(rows), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_row_topk<true, 256>), dim3(rows), dim3(256), lds, s, a);
+  else if (a.rowcnt)
+    hipLaunchKernelGGL((k_row_topk<false, 1024>), dim3(rows), dim3(1024), lds, s, a);
   else
-    hipLaunchKernelGGL(k_row_topk<false>, dim3(rows), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_row_topk<false, 256>), dim3(rows), dim3(256), lds, s, a);
   RBQ_HIP(hipGetLastError());
 }
 
@@ -573,8 +679,7 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
       for (int t = 0; t < BQ; ++t) ip += acc[t] << t;
       const float fadd = __uint_as_float(blk[W * 64 + lane]);
       const float fmul = __uint_as_float(blk[(W + 1) * 64 + lane]);
-      const float E = vl * (float)(2 * pop - D) + delta * (float)(2 * ip - sumqu);
-      const float est = rn2 + fadd + fmul * E;
+      const float est = rbq_estimate(rn2, vl, delta, -sumqu, ip, fadd, fmul, rbq_vx(fmul, pop, D));
       const int v = (m << 6) + lane;
       if (v < len) {
         key = key64(est, (uint32_t)((mb0 << 6) + v));
@@ -600,11 +705,13 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
   }
   __syncthreads();
   const int n = s_n;
-  int P = 2;
-  while (P < n) P <<= 1;
-  for (int t = n + tid; t < P; t += 256) sel[t] = KEY_NONE;
-  __syncthreads();
-  bitonic_sort_lds(sel, P);
+  if (n > R) {  // keep the best R (an item with at most R survivors keeps them all, unsorted)
+    int P = 2;
+    while (P < n) P <<= 1;
+    for (int t = n + tid; t < P; t += 256) sel[t] = KEY_NONE;
+    __syncthreads();
+    bitonic_sort_lds(sel, P);
+  }
   // append this item's survivors (at most R) to the query's pool; the pool
   // holds R * (probe ranks in this launch) keys, so it cannot overflow
   const int nout = n < R ? n : R;
@@ -617,7 +724,7 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
     const int id = a.L.pos2id[(uint32_t)sv];
     dst[r] = (sv & 0xFFFFFFFF00000000ull) | (uint32_t)id;
   }
-  if (a.qthr && tid == 0 && n >= R) atomicMin(&a.qthr[i], (uint32_t)(sel[R - 1] >> 32));
+  if (a.qthr && tid == 0 && n > R) atomicMin(&a.qthr[i], (uint32_t)(sel[R - 1] >> 32));
 }
 
 template <int WT, int BQT>
@@ -643,6 +750,321 @@ void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
     scan_dispatch<30, 4>(s, a, cap, dump);
   else
     scan_dispatch<0, 0>(s, a, cap, dump);
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Fused query-major scan + selection for chunks whose lists are shared by few
+// queries: one workgroup (16 waves) per query loads the query's running top-R
+// into LDS, scans the chunk's probed lists (popcount inner products, the same
+// estimator expression as the other scans), appends every estimate at or
+// below the query's threshold to an LDS buffer, and whenever the buffer could
+// overflow keeps only its best R (radix select in LDS) and lowers the
+// threshold to their R-th estimate. At the end the best R become the query's
+// running top-R and its threshold. Nothing goes through the global pool.
+// ---------------------------------------------------------------------------
+
+template <int NT>
+struct SelShared {
+  uint32_t hist[NT >= 512 ? 4 : 1][256];
+  uint32_t wsum[4];
+  uint32_t digit, rem, bucket, cnt;
+  uint64_t lo[NT / 64], hi[NT / 64];
+};
+
+// The k smallest of keys[0..n) (LDS) into sel[0..min(n, k)), in any order, by
+// all NT threads (ends with a barrier). Returns the k-th smallest key, or
+// KEY_NONE when n < k. MSB-first radix select as in k_row_topk.
+template <int NT>
+__device__ uint64_t select_k_lds(const uint64_t* keys, int n, int k, uint64_t* sel, SelShared<NT>& sh) {
+  constexpr int NW = NT / 64;
+  constexpr int NH = NT >= 512 ? 4 : 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool take_all = n <= k;
+  uint64_t prefix = 0, pmask = 0;
+  uint32_t rem = (uint32_t)k;
+  uint64_t lo = ~0ull, hi = 0;
+  for (int c = tid; c < n; c += NT) {
+    const uint64_t v = keys[c];
+    lo = v < lo ? v : lo;
+    hi = v > hi ? v : hi;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (lane == 0) {
+    sh.lo[wave] = lo;
+    sh.hi[wave] = hi;
+  }
+  __syncthreads();
+  lo = sh.lo[0];
+  hi = sh.hi[0];
+  for (int w = 1; w < NW; ++w) {
+    lo = sh.lo[w] < lo ? sh.lo[w] : lo;
+    hi = sh.hi[w] > hi ? sh.hi[w] : hi;
+  }
+  const uint64_t diff = lo ^ hi;
+  const int top = diff ? 63 - __clzll((long long)diff) : -1;
+  if (top < 63) {
+    pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
+    prefix = lo & pmask;
+  }
+  if (!take_all) {
+    for (int hb = top; hb >= 0;) {
+      const int lb = hb >= 7 ? hb - 7 : 0;
+      const uint64_t dmask = ((2ull << (hb - lb)) - 1ull);
+      for (int t = tid; t < NH * 256; t += NT) (&sh.hist[0][0])[t] = 0;
+      __syncthreads();
+      uint32_t* hw = sh.hist[wave % NH];
+      for (int c = tid; c < n; c += NT) {
+        const uint64_t key = keys[c];
+        if ((key & pmask) == prefix) atomicAdd(&hw[(key >> lb) & dmask], 1u);
+      }
+      __syncthreads();
+      uint32_t h = 0;
+      if (tid < 256)
+        for (int t = 0; t < NH; ++t) h += sh.hist[t][tid];
+      const uint32_t incl = hist_incl_scan<NT>(h, sh.wsum);
+      const uint32_t excl = incl - h;
+      if (tid < 256 && excl < rem && rem <= incl) {
+        sh.digit = (uint32_t)tid;
+        sh.rem = rem - excl;
+        sh.bucket = h;
+      }
+      __syncthreads();
+      prefix |= (uint64_t)sh.digit << lb;
+      pmask |= dmask << lb;
+      rem = sh.rem;
+      const uint32_t bucket = sh.bucket;
+      __syncthreads();
+      if (bucket == rem) break;
+      hb = lb - 1;
+    }
+  }
+  if (tid == 0) sh.cnt = 0;
+  __syncthreads();
+  const int rounds = (n + NT - 1) / NT;
+  const uint64_t hi_key = prefix | ~pmask;
+  for (int pass = 0; pass < (take_all ? 1 : 2); ++pass) {
+    for (int r = 0; r < rounds; ++r) {
+      const int c = r * NT + tid;
+      const uint64_t key = c < n ? keys[c] : KEY_NONE;
+      const bool t = c < n && (take_all || (pass == 0 ? key < prefix : (key >= prefix && key <= hi_key)));
+      const uint64_t m = __ballot(t);
+      uint32_t base = 0;
+      if (lane == 0 && m) base = atomicAdd(&sh.cnt, (uint32_t)__popcll(m));
+      base = __shfl(base, 0);
+      const uint32_t p = base + lane_prefix(m);
+      if (t && p < (uint32_t)k) sel[p] = key;
+    }
+    __syncthreads();
+  }
+  if (n < k) return KEY_NONE;
+  // the k-th smallest is the largest selected key
+  uint64_t mx = 0;
+  for (int i = tid; i < k; i += NT) mx = sel[i] > mx ? sel[i] : mx;
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if (lane == 0) sh.hi[wave] = mx;
+  __syncthreads();
+  uint64_t kth = sh.hi[0];
+  for (int w = 1; w < NW; ++w) kth = sh.hi[w] > kth ? sh.hi[w] : kth;
+  __syncthreads();
+  return kth;
+}
+
+template <int WT, int BQT>
+__global__ __launch_bounds__(1024) void k_scan_fused(FusedArgs a) {
+  constexpr int NT = 1024, NW = NT / 64;
+  extern __shared__ uint64_t smem[];
+  __shared__ SelShared<NT> sh;
+  __shared__ int32_t s_pre[257];
+  __shared__ uint32_t s_n, s_thr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = blockIdx.x;
+  if (a.qmask && a.qmask[i] == 0u) return;  // uniform over the workgroup
+  const int W = WT > 0 ? WT : a.L.W;
+  const int BQ = BQT > 0 ? BQT : a.Q.bqs;
+  const int bqs = a.Q.bqs;
+  const int D = a.L.d;
+  const int Rq = a.rowk ? a.rowk[i] : a.R;
+  uint64_t* buf = smem;
+  uint64_t* sel = smem + a.cap;
+  uint64_t* row = a.out + (int64_t)i * a.out_ld;
+  const size_t rec = (size_t)(W + 2) * 64;
+  if (tid == 0) {
+    s_n = 0;
+    s_thr = a.qthr[i];
+  }
+  __syncthreads();
+  // the running top-R
+  for (int r0 = 0; r0 < a.R; r0 += NT) {
+    const int r = r0 + tid;
+    const uint64_t key = r < a.R ? row[r] : KEY_NONE;
+    const bool t = key != KEY_NONE;
+    const uint64_t m = __ballot(t);
+    uint32_t base = 0;
+    if (lane == 0 && m) base = atomicAdd(&s_n, (uint32_t)__popcll(m));
+    base = __shfl(base, 0);
+    if (t) buf[base + lane_prefix(m)] = key;
+  }
+  __syncthreads();
+  for (int s0 = 0; s0 < a.pn; s0 += 256) {
+    const int sn = min(256, a.pn - s0);
+    int cntmb = 0;
+    if (tid < sn) {
+      const int j = a.probes[(int64_t)i * a.nprobe + a.p0 + s0 + tid];
+      cntmb = j >= 0 ? (a.L.list_len[j] + 63) >> 6 : 0;
+    }
+    const uint32_t incl = hist_incl_scan<NT>((uint32_t)cntmb, sh.wsum);
+    if (tid < sn) s_pre[tid + 1] = (int32_t)incl;
+    if (tid == 0) s_pre[0] = 0;
+    __syncthreads();
+    const int total = s_pre[sn];
+    // this wave's micro-block of each round: its list data are loaded into
+    // registers one round ahead
+    constexpr int WR = WT > 0 ? WT : 32;
+    constexpr int PR = (WT > 0 && BQT > 0) ? WT * BQT : 1;  // bit-plane words kept in registers
+    uint32_t cw[WR], pl[PR];
+    float fa = 0.f, fm = 0.f;
+    float4 c_sc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int c_len = 0, c_pos0 = 0, c_mb = 0, c_id = 0;
+    int64_t c_pair = 0;
+    auto locate = [&](int idx, int64_t& pair, int& len, int& pos0, int& mb) {
+      int lo = 0, hi = sn;  // s_pre[lo] <= idx < s_pre[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= idx)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      mb = idx - s_pre[lo];
+      pair = (int64_t)i * a.nprobe + a.p0 + s0 + lo;
+      const int j = a.probes[pair];
+      len = a.L.list_len[j];
+      pos0 = a.L.list_mb[j] << 6;
+    };
+    auto load = [&](int64_t pair, int len, int pos0, int mb) {
+      const uint32_t* blk = a.L.blocks + (size_t)((pos0 >> 6) + mb) * rec;
+#pragma unroll
+      for (int w = 0; w < WR; ++w)
+        if (w < W) cw[w] = blk[w * 64 + lane];
+      fa = __uint_as_float(blk[W * 64 + lane]);
+      fm = __uint_as_float(blk[(W + 1) * 64 + lane]);
+      const int v = (mb << 6) + lane;
+      c_id = v < len ? a.L.pos2id[pos0 + v] : 0;
+      c_sc = a.Q.scal[pair];
+      if (PR > 1) {
+        const uint32_t* planes = a.Q.planes + pair * W * bqs;
+#pragma unroll
+        for (int w = 0; w < (WT > 0 ? WT : 1); ++w)
+#pragma unroll
+          for (int t = 0; t < (BQT > 0 ? BQT : 1); ++t) pl[(w * (BQT > 0 ? BQT : 1) + t) % PR] = planes[w * bqs + t];
+      }
+    };
+    if (wave < total) {
+      locate(wave, c_pair, c_len, c_pos0, c_mb);
+      load(c_pair, c_len, c_pos0, c_mb);
+    }
+    for (int b0 = 0; b0 < total; b0 += NW) {
+      const int idx = b0 + wave;
+      if (idx < total) {
+        uint32_t cur[WR], cpl[PR];
+#pragma unroll
+        for (int w = 0; w < WR; ++w)
+          if (w < W) cur[w] = cw[w];
+#pragma unroll
+        for (int t = 0; t < PR; ++t) cpl[t] = pl[t];
+        const float fadd = fa, fmul = fm;
+        const float4 sc = c_sc;
+        const int len = c_len, pos0 = c_pos0, mb = c_mb, id = c_id;
+        const int64_t pair = c_pair;
+        if (idx + NW < total) {  // prefetch the next round's micro-block
+          locate(idx + NW, c_pair, c_len, c_pos0, c_mb);
+          load(c_pair, c_len, c_pos0, c_mb);
+        }
+        const uint32_t* planes = a.Q.planes + pair * W * bqs;
+        int acc[BQT > 0 ? BQT : 8];
+        for (int t = 0; t < BQ; ++t) acc[t] = 0;
+        int pop = 0;
+#pragma unroll
+        for (int w = 0; w < WR; ++w) {
+          if (w < W) {
+            const uint32_t c = cur[w];
+            pop += __popc(c);
+#pragma unroll
+            for (int t = 0; t < (BQT > 0 ? BQT : 8); ++t)
+              if (t < BQ)
+                acc[t] += __popc(c & (PR > 1 ? cpl[(w * (BQT > 0 ? BQT : 1) + t) % PR] : planes[w * bqs + t]));
+          }
+        }
+        int ip = 0;
+        for (int t = 0; t < BQ; ++t) ip += acc[t] << t;
+        const float est = rbq_estimate(sc.x, sc.y, sc.z, -(int)sc.w, ip, fadd, fmul, rbq_vx(fmul, pop, D));
+        const int v = (mb << 6) + lane;
+        const bool pass = v < len && ord_f32(est) <= s_thr;
+        const uint64_t m = __ballot(pass);
+        if (m) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(m));
+          base = __shfl(base, 0);
+          if (pass) buf[base + lane_prefix(m)] = key64(est, (uint32_t)id);
+        }
+      }
+      __syncthreads();
+      if (s_n > (uint32_t)(a.cap - NT)) {  // keep the best Rq before the next round could overflow
+        const int n = (int)s_n;
+        const uint64_t kth = select_k_lds<NT>(buf, n, Rq, sel, sh);
+        for (int c = tid; c < Rq; c += NT) buf[c] = sel[c];
+        __syncthreads();
+        if (tid == 0) {
+          s_n = (uint32_t)Rq;
+          const uint32_t t = (uint32_t)(kth >> 32);
+          if (t < s_thr) s_thr = t;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+  }
+  const int n = (int)s_n;
+  const uint64_t kth = select_k_lds<NT>(buf, n, Rq, sel, sh);
+  const int keep = min(n, Rq);
+  for (int r = tid; r < Rq; r += NT) row[r] = r < keep ? sel[r] : KEY_NONE;
+  if (tid == 0 && kth != KEY_NONE) atomicMin(&a.qthr[i], (uint32_t)(kth >> 32));
+}
+
+template <int WT, int BQT>
+static void fused_dispatch(hipStream_t s, const FusedArgs& a, size_t lds) {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    RBQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scan_fused<WT, BQT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTopkLdsMax));
+  });
+  hipLaunchKernelGGL((k_scan_fused<WT, BQT>), dim3(a.nq), dim3(1024), lds, s, a);
+}
+
+void launch_scan_fused(hipStream_t s, FusedArgs a) {
+  if (a.nq <= 0 || a.pn <= 0) return;
+  const int slots = (int)(kTopkLdsMax / sizeof(uint64_t));
+  a.cap = slots - a.R;
+  RBQ_CHECK(a.cap >= a.R + 2 * 1024, "fused scan: rerank_n too large for its LDS buffer");
+  RBQ_CHECK(a.L.W <= 32, "fused scan supports d <= 1024");
+  const size_t lds = (size_t)(a.cap + a.R) * sizeof(uint64_t);
+  const int bq4 = a.Q.bqs == 4;
+  if (bq4 && a.L.W == 4)
+    fused_dispatch<4, 4>(s, a, lds);
+  else if (bq4 && a.L.W == 3)
+    fused_dispatch<3, 4>(s, a, lds);
+  else if (bq4 && a.L.W == 2)
+    fused_dispatch<2, 4>(s, a, lds);
+  else
+    fused_dispatch<0, 0>(s, a, lds);
   RBQ_HIP(hipGetLastError());
 }
 

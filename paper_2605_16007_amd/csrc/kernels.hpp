@@ -93,6 +93,25 @@ struct ScanArgs {
 };
 void launch_scan_popc(hipStream_t s, const ScanArgs& a);
 
+// Fused query-major scan + per-query selection: one workgroup per query
+// scans probe ranks [p0, p0 + pn) and leaves the query's best R (rowk[i] for a
+// mixed batch) in out row i's first R slots (unsorted, KEY_NONE padding) with
+// the threshold lowered to their R-th estimate. No pool is used.
+struct FusedArgs {
+  ListsView L;
+  PairsView Q;
+  const int32_t* probes;   // [nq][nprobe]; -1 = not probed
+  int nq, nprobe, R;
+  int p0, pn;
+  uint64_t* out;           // candidate rows: R running keys first
+  int64_t out_ld;
+  uint32_t* qthr;
+  const int32_t* rowk;     // per-query R (or null)
+  const uint32_t* qmask;   // only queries with qmask[i] != 0 (or null: all)
+  int cap = 0;             // set by the launcher
+};
+void launch_scan_fused(hipStream_t s, FusedArgs a);
+
 // List-major grouped scan on int8 MFMA (kernels_group.hip).
 struct GroupArgs {
   ListsView L;

@@ -124,9 +124,10 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   __shared__ float sThr[GMAX];                // threshold on d_hat^2 per query slot
   __shared__ int32_t sQ[GMAX];                // query id per slot
   __shared__ uint32_t sCode[4][2 * KS][64];  // per wave: the micro-block's code words
-  __shared__ __align__(16) float sPop[4][64], sAdd[4][64], sMul[4][64];
-  __shared__ uint64_t sStage[4][STAGE];        // per wave: survivors (est, position)
-  __shared__ uint8_t sStageQ[4][STAGE];        // their query slot
+  __shared__ __align__(16) float sVx[4][64], sAdd[4][64], sMul[4][64];
+  // per wave: survivors as (float bits of d_hat^2 << 32) | (query slot << 26 |
+  // position in the list)
+  __shared__ uint64_t sStage[4][STAGE];
   __shared__ uint32_t sFcnt[4][GMAX], sFbase[4][GMAX];  // per wave: flush counts and bases
   __shared__ int32_t sItem;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -139,11 +140,12 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   // counted per query slot in LDS, each slot reserves its range with one
   // global atomic, and every entry is written at its slot's base plus its
   // rank (ids looked up lane-parallel).
+  int list_pos0 = 0;  // first position of the item's list
   auto flush = [&](int nst) {
     if (nst == 0) return;
     sFcnt[wave][lane] = 0u;
     __builtin_amdgcn_wave_barrier();
-    for (int e = lane; e < nst; e += 64) atomicAdd(&sFcnt[wave][sStageQ[wave][e]], 1u);
+    for (int e = lane; e < nst; e += 64) atomicAdd(&sFcnt[wave][(uint32_t)sStage[wave][e] >> 26], 1u);
     __builtin_amdgcn_wave_barrier();
     const uint32_t c = sFcnt[wave][lane];
     sFbase[wave][lane] = c ? atomicAdd(&a.pcnt[sQ[lane]], c) : 0u;
@@ -151,10 +153,12 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     __builtin_amdgcn_wave_barrier();
     for (int e = lane; e < nst; e += 64) {
       const uint64_t kp = sStage[wave][e];
-      const int q = sStageQ[wave][e];
+      const uint32_t lo = (uint32_t)kp;
+      const int q = (int)(lo >> 26);
       const int qi = sQ[q];
       const uint32_t slot = sFbase[wave][q] + atomicAdd(&sFcnt[wave][q], 1u);
-      const uint64_t key = (kp & 0xFFFFFFFF00000000ull) | (uint32_t)a.L.pos2id[(uint32_t)kp];
+      const int id = a.L.pos2id[list_pos0 + (int)(lo & 0x3FFFFFFu)];
+      const uint64_t key = ((uint64_t)ord_f32(__uint_as_float((uint32_t)(kp >> 32))) << 32) | (uint32_t)id;
       if (slot < (uint32_t)a.cap) {
         a.pool[(int64_t)qi * a.pool_ld + a.R + slot] = key;
       } else {
@@ -210,11 +214,12 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
       qrn2[n] = sc.x;
       qvl[n] = sc.y;
       qdelta[n] = sc.z;
-      qsum[n] = (int)sc.w;
+      qsum[n] = -(int)sc.w;  // negated: the estimate adds it
       qthr[n] = q < count ? sThr[q] : NAN;
     }
     const int len = a.L.list_len[j], mb0 = a.L.list_mb[j];
     const int nmb = (len + 63) >> 6;
+    list_pos0 = mb0 << 6;
     const size_t rec = (size_t)(W + 2) * 64;
     // lane = vector of the micro-block; the next micro-block's words and
     // factors are loaded into registers while the current one is computed
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
           sCode[wave][w][lane] = cw[w];
           pop += __popc(cw[w]);
         }
-        sPop[wave][lane] = (float)(2 * pop - D);
+        sVx[wave][lane] = rbq_vx(fm, pop, D);
         const bool valid = (mb << 6) + lane < len;
         sAdd[wave][lane] = valid ? fa : NAN;
         sMul[wave][lane] = fm;
@@ -255,11 +260,13 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
         }
         // the four vectors of this lane's result rows: 16 m + 4 lg + r
         const float4 fadd4 = *reinterpret_cast<const float4*>(&sAdd[wave][16 * m + 4 * lg]);
-        const float4 pop4 = *reinterpret_cast<const float4*>(&sPop[wave][16 * m + 4 * lg]);
+        const float4 vx4 = *reinterpret_cast<const float4*>(&sVx[wave][16 * m + 4 * lg]);
         const float4 fmul4 = *reinterpret_cast<const float4*>(&sMul[wave][16 * m + 4 * lg]);
         const float fadd[4] = {fadd4.x, fadd4.y, fadd4.z, fadd4.w};
-        const float popt[4] = {pop4.x, pop4.y, pop4.z, pop4.w};
+        const float vxr[4] = {vx4.x, vx4.y, vx4.z, vx4.w};
         const float fmul[4] = {fmul4.x, fmul4.y, fmul4.z, fmul4.w};
+        // position in the list of this lane's first result row
+        const uint32_t rel0 = (uint32_t)((mb << 6) + 16 * m + 4 * lg);
 #pragma unroll
         for (int n = 0; n < GMAX / 16; ++n) {
           if (n >= nt) break;
@@ -272,20 +279,18 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
           bool anyp = false;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float E = qvl[n] * popt[r] + qdelta[n] * (float)(2 * acc[r] - qsum[n]);
-            est[r] = qrn2[n] + fadd[r] + fmul[r] * E;
+            est[r] = rbq_estimate(qrn2[n], qvl[n], qdelta[n], qsum[n], acc[r], fadd[r], fmul[r], vxr[r]);
             pass[r] = est[r] <= qthr[n];  // NaN (padding lanes, empty slots) never passes
             anyp |= pass[r];
           }
-          if (__ballot(anyp)) {  // rare: stage the survivors of this tile
-            const int q = 16 * n + (lane & 15);
+          if (__ballot(anyp)) {  // stage the survivors of this tile
+            const uint32_t tag = rel0 | ((uint32_t)(16 * n + (lane & 15)) << 26);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const uint64_t mask = __ballot(pass[r]);
               if (pass[r]) {
                 const int e = stage_n + (int)lane_prefix(mask);
-                sStage[wave][e] = key64(est[r], (uint32_t)((mb0 + mb) * 64 + 16 * m + 4 * lg + r));
-                sStageQ[wave][e] = (uint8_t)q;
+                sStage[wave][e] = ((uint64_t)__float_as_uint(est[r]) << 32) | (tag + (uint32_t)r);
               }
               stage_n += (int)__popcll(mask);
             }

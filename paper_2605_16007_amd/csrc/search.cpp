@@ -92,6 +92,8 @@ struct Bufs {
 
 struct Chunk {
   int p0, pn;
+  bool lm = false;     // list-major MFMA scan (else query-major popcount)
+  bool fused = false;  // query-major, scan and selection in one launch
 };
 
 // What a search call does and needs, fixed before any launch.
@@ -108,24 +110,28 @@ struct Plan {
 };
 
 constexpr int64_t kDefaultPoolBudget = (int64_t)512 << 20;
+// batches at least this large scan their query-major chunks with the fused
+// one-workgroup-per-query kernel (enough workgroups to fill the GPU)
+constexpr int64_t kFusedMinQueries = 128;
 
-// Probe ranks are scanned in chunks: each scan item appends at most R
-// survivors to its query's pool (row layout: R running keys, then the pool),
-// and a merge after each chunk folds the pool into the running top-R and
-// lowers the query's threshold to its exact R-th estimate, so later chunks
-// keep only candidates that can still enter the top-R (the IVF-aware pruning
-// of Sec. 3.3.3). Query-major chunks double from `first` (enough items to fill
-// the GPU) up to `pch`, the most probe ranks whose worst-case pool (R keys per
-// item) fits the pool budget.
+// Probe ranks are scanned in chunks: scan items append survivors to their
+// query's pool (row layout: R running keys, then the pool), and a merge after
+// each chunk folds the pool into the running top-R and lowers the query's
+// threshold to its exact R-th estimate, so later chunks keep only candidates
+// that can still enter the top-R (the IVF-aware pruning of Sec. 3.3.3).
 //
-// The list-major MFMA scan is used for the whole search when d <= 256 and the
-// batch probes each list several times on average (pairs >= group_min *
-// nlist), or always with RBQ_OPT_SCAN = 2. Its chunks double the prefix
-// already scanned, so with the threshold at the exact R-th estimate of that
-// prefix a pool expects about R survivors per chunk; the first chunk is sized
-// so that even all of its candidates fit. A query whose pool overflows anyway
-// is searched again, from scratch, by the query-major scan (exact; checked
-// once per search).
+// With d <= 256 the chunks double the prefix already scanned (the first holds
+// about first_factor * R candidates per query), so with the threshold at the
+// exact R-th estimate of that prefix a pool expects about R survivors per
+// chunk. Each chunk picks its scan: the list-major MFMA scan once each probed
+// list is shared by >= gm queries of the chunk on average (it reads a list
+// once per group of queries), the query-major popcount scan before (each of
+// its items keeps at most R survivors, so those chunks are cut to fit the
+// pool). A query whose pool overflows in a list-major chunk is searched again,
+// from scratch, by the query-major scan (exact; checked once per search).
+// Otherwise (query-major only) chunks double from `first` (enough items to
+// fill the GPU) up to `pch`, the most probe ranks whose worst case (R keys per
+// item) fits the pool budget.
 Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64_t scanned_pairs,
                int64_t pool_budget, const rbq_debug_io* dbg, const TuneCfg* force) {
   Plan P;
@@ -157,21 +163,34 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   }
   P.G = cfg.G;
   P.wg_per_cu = cfg.wg_per_cu;
-  int scan_mode = idx->opt_scan.load();
-  if (force || (scan_mode == 0 && tuned)) scan_mode = cfg.scan;
-  const int group_min = idx->opt_group_min.load();
+  // scan form per chunk of probe ranks: query-major (1) everywhere, or the
+  // list-major MFMA scan for every chunk whose (query, probe) pairs number at
+  // least gm * nlist (a list is probed by >= gm queries of the chunk on
+  // average; gm = 0: every chunk)
+  const int opt = idx->opt_scan.load();
+  int scan_mode = opt, gm = idx->opt_group_min.load();
+  if (force || (opt == 0 && tuned)) {
+    scan_mode = cfg.scan;
+    gm = cfg.gm;
+  } else if (opt == 2) {
+    gm = 0;
+  } else if (opt == 0) {
+    scan_mode = 2;
+  }
   P.pool_cap = (int64_t)R * P.pch;
   if (idx->opt_pool_cap.load() > 0) P.pool_cap = std::min<int64_t>(P.pool_cap, idx->opt_pool_cap.load());
-  // (per-vector dumps of the debug entry point come from the query-major scan)
-  P.any_group = scan_mode != 1 && !P.dumps && group_k_steps(idx->d) <= 4 &&
-                (scan_mode == 2 || scanned_pairs >= (int64_t)group_min * idx->nlist);
   for (int p0 = 0, pn = P.first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, P.pch)) {
     pn = std::min(pn, nprobe - p0);
-    P.qm_chunks.push_back({p0, pn});
+    P.qm_chunks.push_back({p0, pn, false, false});
   }
-  if (P.any_group) {
-    // first chunk: about 2R candidates per query on average, and never more
-    // than the pool holds even for the longest lists
+  // (per-vector dumps of the debug entry point come from the query-major scan;
+  // list-major survivors carry their position in the list in 26 bits)
+  const bool lm_ok = scan_mode == 2 && !P.dumps && group_k_steps(idx->d) <= 4 &&
+                     idx->max_list_len < (int64_t(1) << 26);
+  if (lm_ok) {
+    // chunks double the scanned prefix; the first holds about first_factor * R
+    // candidates per query on average, and never more than the pool holds
+    // even for the longest lists
     const int64_t maxl = std::max<int64_t>(1, idx->max_list_len);
     const int64_t avgl = std::max<int64_t>(1, idx->n / idx->nlist);
     int pn = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nprobe, P.pool_cap / maxl,
@@ -179,7 +198,17 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
     if (dbg && dbg->probe_chunk > 0) pn = std::min(pn, (int)dbg->probe_chunk);
     for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, p0)) {
       pn = std::min(pn, nprobe - p0);
-      P.chunks.push_back({p0, pn});
+      const int64_t chunk_pairs = scanned_pairs * pn / std::max(1, nprobe);
+      const bool lm = chunk_pairs >= (int64_t)gm * idx->nlist;
+      if (lm) {
+        P.chunks.push_back({p0, pn, true, false});
+        P.any_group = true;
+      } else if (nq >= kFusedMinQueries && idx->W <= 32) {  // one workgroup per query: scan and select in one launch
+        P.chunks.push_back({p0, pn, false, true});
+      } else {  // a query-major chunk appends up to R keys per item: split to fit the pool
+        for (int q0 = p0; q0 < p0 + pn; q0 += P.pch)
+          P.chunks.push_back({q0, std::min(P.pch, p0 + pn - q0), false, false});
+      }
     }
   } else {
     P.chunks = P.qm_chunks;
@@ -427,73 +456,115 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     ma.qthr = b.qthr;
     ma.rowk = d_R;
     ma.sorted = false;
-    auto scan_qm_chunks = [&]() {
-      for (const auto& ch : qm_chunks) {
-        sa.p0 = ch.p0;
-        sa.pn = ch.pn;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed) {
-          e0 = newev();
-          e1 = newev();
-          tr.scan.push_back(e0);
-          tr.scan.push_back(e1);
-          RBQ_HIP(hipEventRecord(e0, s));
-        }
-        launch_scan_popc(s, sa);
-        if (timed) {
-          RBQ_HIP(hipEventRecord(e1, s));
-          tr.popc += 1;
-          if (!sa.qmask) {  // (the redo of overflowed queries is not counted)
-            hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
-                               idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 1,
-                               idx->tcounter.as<unsigned long long>());
-            RBQ_HIP(hipGetLastError());
-          }
-        }
-        ma.max_extra = R * ch.pn;
-        launch_row_topk(s, ma, (int)nq);
+    auto scan_popc_chunk = [&](const Chunk& ch) {
+      sa.p0 = ch.p0;
+      sa.pn = ch.pn;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        e0 = newev();
+        e1 = newev();
+        tr.scan.push_back(e0);
+        tr.scan.push_back(e1);
+        RBQ_HIP(hipEventRecord(e0, s));
       }
-    };
-    if (!any_group) {
-      scan_qm_chunks();
-    } else {
-      launch_fill_u32(s, b.counter + 1, 0u, 1);
-      for (const auto& ch : chunks) {
-        launch_group_map(s, b.probes, (int)nq, nprobe, ch.p0, ch.pn, nlist, ga.G, b.gcnt,
-                         b.pair_off, b.item_off, b.gfill, b.slots, b.items);
-        launch_fill_u32(s, b.counter, 0u, 1);
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (timed) {
-          e0 = newev();
-          e1 = newev();
-          tr.scan.push_back(e0);
-          tr.scan.push_back(e1);
-          RBQ_HIP(hipEventRecord(e0, s));
-        }
-        launch_scan_group(s, ga, P.wg_per_cu * idx->num_cus);
-        if (timed) {
-          RBQ_HIP(hipEventRecord(e1, s));
-          tr.group += 1;
+      launch_scan_popc(s, sa);
+      if (timed) {
+        RBQ_HIP(hipEventRecord(e1, s));
+        tr.scan_lm.push_back(0);
+        tr.popc += 1;
+        if (!sa.qmask) {  // (the redo of overflowed queries is not counted)
           hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
-                             idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 0,
+                             idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 1,
                              idx->tcounter.as<unsigned long long>());
-          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s, b.gcnt,
-                             idx->list_len.as<int32_t>(), nlist, ga.G, rec_bytes,
-                             idx->tcounter.as<unsigned long long>() + 1);
           RBQ_HIP(hipGetLastError());
         }
-        ma.max_extra = (int)pool_cap;
-        launch_row_topk(s, ma, (int)nq);
       }
-      // one check per search: queries whose pool overflowed are searched
-      // again by the query-major scan
+      ma.max_extra = R * ch.pn;
+      launch_row_topk(s, ma, (int)nq);
+    };
+    auto scan_group_chunk = [&](const Chunk& ch) {
+      launch_group_map(s, b.probes, (int)nq, nprobe, ch.p0, ch.pn, nlist, ga.G, b.gcnt, b.pair_off,
+                       b.item_off, b.gfill, b.slots, b.items);
+      launch_fill_u32(s, b.counter, 0u, 1);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        e0 = newev();
+        e1 = newev();
+        tr.scan.push_back(e0);
+        tr.scan.push_back(e1);
+        RBQ_HIP(hipEventRecord(e0, s));
+      }
+      launch_scan_group(s, ga, P.wg_per_cu * idx->num_cus);
+      if (timed) {
+        RBQ_HIP(hipEventRecord(e1, s));
+        tr.scan_lm.push_back(1);
+        tr.group += 1;
+        unsigned long long* tc = idx->tcounter.as<unsigned long long>();
+        for (int part = 0; part < 2; ++part) {  // all scans, and list-major alone
+          hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
+                             idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 0,
+                             tc + 2 * part);
+          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s, b.gcnt,
+                             idx->list_len.as<int32_t>(), nlist, ga.G, rec_bytes, tc + 2 * part + 1);
+        }
+        RBQ_HIP(hipGetLastError());
+      }
+      ma.max_extra = (int)pool_cap;
+      launch_row_topk(s, ma, (int)nq);
+    };
+    if (any_group) launch_fill_u32(s, b.counter + 1, 0u, 1);
+    FusedArgs fa;
+    fa.L = sa.L;
+    fa.Q = sa.Q;
+    fa.probes = b.probes;
+    fa.nq = (int)nq;
+    fa.nprobe = nprobe;
+    fa.R = R;
+    fa.out = b.cand;
+    fa.out_ld = cand_ld;
+    fa.qthr = b.qthr;
+    fa.rowk = d_R;
+    fa.qmask = nullptr;
+    auto scan_fused_chunk = [&](const Chunk& ch) {
+      fa.p0 = ch.p0;
+      fa.pn = ch.pn;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (timed) {
+        e0 = newev();
+        e1 = newev();
+        tr.scan.push_back(e0);
+        tr.scan.push_back(e1);
+        RBQ_HIP(hipEventRecord(e0, s));
+      }
+      launch_scan_fused(s, fa);  // scan and selection in one launch: no merge
+      if (timed) {
+        RBQ_HIP(hipEventRecord(e1, s));
+        tr.scan_lm.push_back(0);
+        tr.popc += 1;
+        hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
+                           idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 1,
+                           idx->tcounter.as<unsigned long long>());
+        RBQ_HIP(hipGetLastError());
+      }
+    };
+    for (const auto& ch : chunks) {
+      if (ch.lm)
+        scan_group_chunk(ch);
+      else if (ch.fused)
+        scan_fused_chunk(ch);
+      else
+        scan_popc_chunk(ch);
+    }
+    if (any_group) {
+      // one check per search: queries whose pool overflowed in a list-major
+      // chunk are searched again, from scratch, by the query-major scan
       uint32_t any = 0;
       RBQ_HIP(hipMemcpyAsync(&any, b.counter + 1, sizeof(any), hipMemcpyDeviceToHost, s));
       RBQ_HIP(hipStreamSynchronize(s));
       if (any) {
         launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
         sa.qmask = b.overflow;
-        scan_qm_chunks();
+        for (const auto& ch : qm_chunks) scan_popc_chunk(ch);
         sa.qmask = nullptr;
       }
     }

@@ -57,7 +57,8 @@ class Timings(C.Structure):
                 ("rerank_ms", C.c_float), ("total_ms", C.c_float),
                 ("scanned_vectors", C.c_int64), ("scan_bytes", C.c_int64),
                 ("read_bytes", C.c_int64), ("group_launches", C.c_int64),
-                ("popc_launches", C.c_int64)]
+                ("popc_launches", C.c_int64), ("group_scan_ms", C.c_float),
+                ("group_vectors", C.c_int64), ("group_read_bytes", C.c_int64)]
 
 
 class ServerParams(C.Structure):
@@ -81,7 +82,8 @@ class ReplayIO(C.Structure):
 class TuneResult(C.Structure):
     _fields_ = [("scan", C.c_int32), ("group_size", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("first_factor", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
-                ("trials", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("trials", C.c_int32), ("chunk_group_min", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class RbqError(RuntimeError):

@@ -1,6 +1,7 @@
 """Parity at full size, in the launch configuration the benchmark times:
 10M x 128 skewed integer vectors, nlist 4096, one batch of 1024 queries,
-nprobe 512, rerank_n 3840, k 10, B_q 4 (list-major int8-MFMA scan).
+nprobe 512, rerank_n 3840, k 10, B_q 4 (query-major popcount scan for the
+leading small chunks of probe ranks, list-major int8-MFMA scan for the rest).
 
 The oracle cannot build a 10M-vector index in a test's time, so the index is
 made from oracle parts: centroids from two Lloyd steps (FP64) started at 4096
@@ -104,7 +105,7 @@ def injected_batch(full, oracle_pairs):
                            want={"cand_ids", "cand_est", "ids", "sqdist"})
     t = lib.timings()
     lib.set_timing(False)
-    assert t["group_launches"] > 0 and t["popc_launches"] == 0  # the list-major scan ran
+    assert t["group_launches"] > 0  # the list-major scan ran (for the large chunks)
     return out
 
 

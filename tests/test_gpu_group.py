@@ -101,3 +101,33 @@ def test_group_candidates_match_oracle(gcase):
         g = out["cand_ids"][qi]
         for i, e in zip(g[g >= 0].tolist(), out["cand_est"][qi].tolist()):
             assert abs(e - val[i]) <= tol[i]
+
+
+def test_fused_and_list_major_chunks_agree():
+    """A batch large enough (>= 128 queries) with lists shared by few queries in
+    the first chunks: those chunks take the fused one-workgroup-per-query scan,
+    the later ones the list-major scan. Results equal the query-major scan's,
+    also for a mixed batch (per-query nprobe / k / rerank_n)."""
+    _say("[group] schedule with fused query-major chunks: n=40000 d=128 nlist=256 nq=300")
+    X, Q, idx = make_case(40_000, 128, 256, 300, seed=140)
+    lib = lib_index(X, idx)
+    try:
+        lib.set_timing(True)
+        b = _run(lib, Q, 64, 10, 200, scan=0)
+        t = lib.timings()
+        lib.set_timing(False)
+        assert t["popc_launches"] > 0 and t["group_launches"] > 0, t
+        a = _run(lib, Q, 64, 10, 200, scan=1)
+        for key in WANT:
+            np.testing.assert_array_equal(b[key], a[key], err_msg=key)
+        rng = np.random.default_rng(9)
+        npb = rng.integers(1, 65, len(Q)).astype(np.int32)
+        k = rng.choice([1, 10, 25], len(Q)).astype(np.int32)
+        R = np.maximum(k, rng.choice([30, 200, 300], len(Q))).astype(np.int32)
+        m_ids, m_d = lib.search_mixed(Q, npb, k, R)
+        for i in range(0, len(Q), 5):
+            x, y = lib.search(Q[i:i + 1], int(npb[i]), int(k[i]), int(R[i]))
+            np.testing.assert_array_equal(m_ids[i, :k[i]], x[0])
+            np.testing.assert_array_equal(m_d[i, :k[i]], y[0])
+    finally:
+        lib.close()
