@@ -142,11 +142,12 @@ class CpuBaseline:
 
 # ----------------------------------------------------------------- ground truth
 
-def exact_knn_gpu(Xt, Qt, X_host, Q_host, k, shortlist=64, chunk=1 << 20):
+def exact_knn_gpu(Xt, Qt, X_host, Q_host, k, shortlist=64, chunk=0):
     """Exact kNN for recall: FP32 GEMM shortlist on the GPU with plain torch
     ops, then FP64 re-ranking of the shortlist on the host."""
     import torch
     nq = Qt.shape[0]
+    chunk = chunk or max(1 << 14, min(1 << 20, (1 << 28) // max(1, nq)))  # <= 1 GiB of distances
     qn = (Qt * Qt).sum(1, keepdim=True)
     best_v = torch.full((nq, 0), float("inf"), device=Qt.device)
     best_i = torch.zeros((nq, 0), dtype=torch.int64, device=Qt.device)
@@ -243,6 +244,8 @@ def main():
     ap.add_argument("--vectors-on-host", action="store_true",
                     help="keep the raw vectors in pinned host memory and re-rank on host cores")
     ap.add_argument("--no-autotune", action="store_true", help="time the built-in launch rule")
+    ap.add_argument("--scan", choices=("auto", "popcount", "mfma"), default="auto",
+                    help="force the scan form of the timed loop (auto: tuned per chunk)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
                     help="Poisson arrival rates (queries/s) of the serving comparison; '' skips it")
     ap.add_argument("--serve-seconds", type=float, default=0.5,
@@ -323,11 +326,16 @@ def main():
             f"(probe recall {prec[pt[0]]:.4f})")
     ok = [pt for pt in points if rec[pt] >= 0.95]
     if not ok and not args.nprobe:
+        # longer re-rank lists at every probe count whose probed lists hold
+        # >= 95% of the true neighbours (listed counts first, then wider ones)
         top = min(w.nlist, 4096)
         wider = [p for p in (256, 512, 1024, 2048) if max(w.nprobe) < p <= top]
-        for npb in wider:
-            prec[npb] = probe_recall(npb)
-            for R in sorted({min(3840, f * w.rerank_n) for f in (1, 2, 5, 10, 20, 40)}):
+        for npb in list(w.nprobe) + wider:
+            if npb not in prec:
+                prec[npb] = probe_recall(npb)
+            if prec[npb] < 0.95:
+                continue
+            for R in sorted({min(3840, f * w.rerank_n) for f in (2, 5, 10, 20, 40)}):
                 pt = (npb, R)
                 rec[pt] = eval_point(*pt)
                 log(f"[recall] nprobe {npb} rerank {R}: recall@{w.k} = {rec[pt]:.4f} "
@@ -353,6 +361,7 @@ def main():
             log(f"[autotune] {pt}: {tuned[f'nprobe={pt[0]},rerank={pt[1]}']}")
     listed_qps = {f"{p}": quick_qps(p, w.rerank_n) for p in w.nprobe} if not args.nprobe else {}
 
+    idx.set_option("scan", {"auto": 0, "popcount": 1, "mfma": 2}[args.scan])
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
     dd = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
     for s in range(args.warmup):
@@ -443,6 +452,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i8 MFMA / u32 popcount + fp32",
+        "scan_form": args.scan,
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,
                    "batch": w.nq, "k": w.k, "rerank_n": R, "bq": w.bq,

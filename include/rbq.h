@@ -314,9 +314,9 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
 /*
  * Autotuner (the launch schedule of Sec. 3.3.1 adapted per batch shape).
  * Some launch choices of a search leave its results unchanged: the scan form
- * (query-major popcount or list-major int8 MFMA), the queries grouped per
- * list-major work item (G), the persistent workgroups per compute unit, and
- * the size of the first chunk of probe ranks. rbq_autotune times every
+ * of each chunk of probe ranks (query-major popcount or list-major int8
+ * MFMA), the queries grouped per list-major work item (G), the persistent
+ * workgroups per compute unit, and the sizes of the chunks. rbq_autotune times every
  * candidate on the given queries (host or device, nq x d; representative of
  * later batches), checks that each returns the same results, and stores the
  * fastest for the bucket of (nq, nprobe, rerank_n) rounded up to powers of
@@ -337,7 +337,9 @@ typedef struct {
   int32_t trials;        /* candidate configurations timed */
   int32_t chunk_group_min; /* a chunk is list-major when its (query, probe) pairs
                               number >= this * nlist (0: every chunk) */
-  int32_t reserved[2];
+  int32_t growth;        /* each chunk after the first is (growth - 1) x the probe
+                            ranks already scanned */
+  int32_t reserved;
 } rbq_tune_result;
 
 rbq_status rbq_autotune(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,

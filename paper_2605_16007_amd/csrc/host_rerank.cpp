@@ -64,10 +64,21 @@ void host_rerank_rows(const float* X, int64_t n, int d, const float* q, const ui
                       float* dist) {
   std::vector<std::pair<double, int64_t>> c;
   c.reserve(R);
+  // the rows are random in host memory: request the rows of the candidates
+  // kAhead positions ahead while the current one is summed
+  constexpr int kAhead = 12;
+  const size_t row_bytes = (size_t)d * sizeof(float);
+  auto prefetch_row = [&](uint64_t key) {
+    if (key == KEY_NONE || (int64_t)(uint32_t)key >= n) return;
+    const char* x = reinterpret_cast<const char*>(X + (int64_t)(uint32_t)key * d);
+    for (size_t b = 0; b < row_bytes; b += 64) __builtin_prefetch(x + b, 0, 0);
+  };
   for (int64_t i = q0; i < q1; ++i) {
     const float* qi = q + i * d;
     c.clear();
+    for (int r = 0; r < std::min(R, kAhead); ++r) prefetch_row(cand[i * R + r]);
     for (int r = 0; r < R; ++r) {
+      if (r + kAhead < R) prefetch_row(cand[i * R + r + kAhead]);
       const uint64_t key = cand[i * R + r];
       if (key == KEY_NONE) continue;
       const int64_t id = (int64_t)(uint32_t)key;

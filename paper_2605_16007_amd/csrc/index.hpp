@@ -32,9 +32,9 @@ struct TimingRec {
 // probe) pairs (gm = 0: all chunks) and query-major for the others; G: queries
 // per list-major item; wg_per_cu: persistent list-major workgroups per CU;
 // first_factor: the first chunk holds about first_factor * R candidates per
-// query.
+// query; growth: each later chunk is (growth - 1) times the prefix scanned.
 struct TuneCfg {
-  int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2, gm = 4;
+  int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2, gm = 4, growth = 2;
 };
 
 // A device scratch area reused across calls. `done` is recorded on the stream

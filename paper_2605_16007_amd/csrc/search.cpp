@@ -120,10 +120,10 @@ constexpr int64_t kFusedMinQueries = 128;
 // threshold to its exact R-th estimate, so later chunks keep only candidates
 // that can still enter the top-R (the IVF-aware pruning of Sec. 3.3.3).
 //
-// With d <= 256 the chunks double the prefix already scanned (the first holds
-// about first_factor * R candidates per query), so with the threshold at the
-// exact R-th estimate of that prefix a pool expects about R survivors per
-// chunk. Each chunk picks its scan: the list-major MFMA scan once each probed
+// With d <= 256 each chunk is (growth - 1) times the prefix already scanned
+// (growth 2: doubling; the first holds about first_factor * R candidates per
+// query), so with the threshold at the exact R-th estimate of that prefix a
+// pool expects about (growth - 1) R survivors per chunk. Each chunk picks its scan: the list-major MFMA scan once each probed
 // list is shared by >= gm queries of the chunk on average (it reads a list
 // once per group of queries), the query-major popcount scan before (each of
 // its items keeps at most R survivors, so those chunks are cut to fit the
@@ -196,15 +196,21 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
     int pn = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nprobe, P.pool_cap / maxl,
                                                           ceil_div((int64_t)cfg.first_factor * R, avgl)}));
     if (dbg && dbg->probe_chunk > 0) pn = std::min(pn, (int)dbg->probe_chunk);
-    for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, p0)) {
+    for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, (cfg.growth - 1) * p0)) {
       pn = std::min(pn, nprobe - p0);
       const int64_t chunk_pairs = scanned_pairs * pn / std::max(1, nprobe);
       const bool lm = chunk_pairs >= (int64_t)gm * idx->nlist;
       if (lm) {
         P.chunks.push_back({p0, pn, true, false});
         P.any_group = true;
-      } else if (nq >= kFusedMinQueries && idx->W <= 32) {  // one workgroup per query: scan and select in one launch
-        P.chunks.push_back({p0, pn, false, true});
+      } else if (nq >= kFusedMinQueries && idx->W <= 32) {
+        // one workgroup per query scans and selects in one launch; it lowers
+        // its threshold whenever its buffer fills, so consecutive chunks of
+        // this kind become one launch
+        if (!P.chunks.empty() && P.chunks.back().fused)
+          P.chunks.back().pn += pn;
+        else
+          P.chunks.push_back({p0, pn, false, true});
       } else {  // a query-major chunk appends up to R keys per item: split to fit the pool
         for (int q0 = p0; q0 < p0 + pn; q0 += P.pch)
           P.chunks.push_back({q0, std::min(P.pch, p0 + pn - q0), false, false});
