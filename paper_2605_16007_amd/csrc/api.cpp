@@ -168,10 +168,15 @@ void save_index(const rbq_index* idx, const char* path) {
   std::vector<float> nx(idx->nmb * MB), al(idx->nmb * MB), X((size_t)idx->n * idx->d);
   RBQ_HIP(hipMemcpy(nx.data(), idx->nx.p, nx.size() * 4, hipMemcpyDeviceToHost));
   RBQ_HIP(hipMemcpy(al.data(), idx->alpha.p, al.size() * 4, hipMemcpyDeviceToHost));
-  if (idx->vectors_on_host)
+  if (idx->vectors_on_host) {
     std::memcpy(X.data(), idx->hostX, X.size() * 4);
-  else
+  } else if (idx->X8.p) {  // byte form: the values are the integers themselves
+    std::vector<uint8_t> x8((size_t)idx->n * idx->d);
+    RBQ_HIP(hipMemcpy2D(x8.data(), idx->d, idx->X8.p, idx->ld, idx->d, idx->n, hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < X.size(); ++e) X[e] = (float)x8[e];
+  } else {
     RBQ_HIP(hipMemcpy2D(X.data(), idx->d * 4, idx->X.p, idx->ld * 4, idx->d * 4, idx->n, hipMemcpyDeviceToHost));
+  }
   put_section(f, 1, idx->hC.data(), idx->hC.size() * 4);
   put_section(f, 2, idx->hP.data(), idx->hP.size() * 4);
   put_section(f, 3, idx->h_assign.data(), idx->h_assign.size() * 4);
@@ -263,6 +268,7 @@ rbq_index* load_index(const char* path) {
     RBQ_HIP(hipMemcpy2D(idx->X.p, ld * 4, X.data(), d * 4, d * 4, h.n, hipMemcpyHostToDevice));
   }
   RBQ_HIP(hipDeviceSynchronize());
+  compact_raw_vectors(idx.get(), nullptr);
   return idx.release();
 }
 
@@ -319,7 +325,7 @@ rbq_status rbq_get_info(const rbq_index* idx, rbq_index_info* info) {
   info->vectors_on_host = idx->vectors_on_host;
   info->max_list_len = idx->max_list_len;
   info->code_bytes = (int64_t)idx->blocks.bytes;
-  info->device_bytes = (int64_t)(idx->X.bytes + idx->C.bytes + idx->Crot.bytes + idx->cnorm.bytes +
+  info->device_bytes = (int64_t)(idx->X.bytes + idx->X8.bytes + idx->C.bytes + idx->Crot.bytes + idx->cnorm.bytes +
                                  idx->Pt.bytes + idx->blocks.bytes + idx->list_mb.bytes +
                                  idx->list_len.bytes + idx->pos2id.bytes + idx->nx.bytes +
                                  idx->alpha.bytes);

@@ -402,7 +402,24 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
                                d * sizeof(float), n, hipMemcpyDeviceToHost, s));
   }
   RBQ_HIP(hipStreamSynchronize(s));
+  compact_raw_vectors(idx.get(), s);
   return idx.release();
+}
+
+void compact_raw_vectors(rbq_index* idx, hipStream_t s) {
+  if (idx->vectors_on_host || !idx->X.p) return;
+  DevBuf bad;
+  bad.alloc(sizeof(unsigned));
+  RBQ_HIP(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
+  launch_count_not_u8(s, idx->X.as<float>(), idx->n, idx->d, idx->ld, bad.as<unsigned>());
+  unsigned hb = 0;
+  RBQ_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  RBQ_HIP(hipStreamSynchronize(s));
+  if (hb != 0) return;
+  idx->X8.alloc((size_t)idx->n * idx->ld);
+  launch_to_u8(s, idx->X.as<float>(), (int64_t)idx->n * idx->ld, idx->X8.as<uint8_t>());
+  RBQ_HIP(hipStreamSynchronize(s));
+  idx->X.reset();
 }
 
 }  // namespace rbq

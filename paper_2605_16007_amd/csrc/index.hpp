@@ -87,7 +87,8 @@ struct rbq_index {
   int64_t max_list_len = 0;
 
   // device arrays
-  rbq::DevBuf X;       // n x ld raw vectors in id order (vectors_on_host == 0)
+  rbq::DevBuf X;       // n x ld raw vectors in id order (vectors_on_host == 0, FP32 form)
+  rbq::DevBuf X8;      // the same as n x ld bytes when every value is an integer in [0, 255]
   rbq::DevBuf C;       // nlist x ld centroids
   rbq::DevBuf Crot;    // nlist x ld rotated centroids P^T c
   rbq::DevBuf cnorm;   // nlist, ||c||^2
@@ -145,6 +146,8 @@ bool is_device_ptr(const void* p);
 void upload_rows(float* dst, int ld, const float* src, int d, int64_t n, hipStream_t s);
 
 rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params& p);
+// Keeps idx->X as bytes (idx->X8) when every raw value is an integer in [0, 255].
+void compact_raw_vectors(rbq_index* idx, hipStream_t s);
 
 struct SearchIO {
   const rbq_debug_io* dbg = nullptr;  // stage injection / outputs (host pointers)

@@ -1134,8 +1134,20 @@ __device__ void lds_select_sorted(const uint64_t* keys, int n, int k, int KP, ui
   bitonic_sort_lds(sel, KP);
 }
 
+// Four consecutive elements of a raw-vector row as floats (FP32 rows, or
+// byte rows holding integers 0..255 exactly).
+__device__ inline float4 row4(const float* __restrict__ X, size_t e) {
+  return *reinterpret_cast<const float4*>(X + e);
+}
+__device__ inline float4 row4(const uint8_t* __restrict__ X, size_t e) {
+  const uint32_t w = *reinterpret_cast<const uint32_t*>(X + e);
+  return make_float4((float)(w & 0xFFu), (float)((w >> 8) & 0xFFu), (float)((w >> 16) & 0xFFu),
+                     (float)(w >> 24));
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int ldq,
-                                                const float* __restrict__ X, int64_t n, int ldx, int d,
+                                                const T* __restrict__ X, int64_t n, int ldx, int d,
                                                 const uint64_t* __restrict__ cand, int64_t ldc,
                                                 int R, int k, int KP, int64_t* __restrict__ ids,
                                                 float* __restrict__ dist,
@@ -1163,9 +1175,9 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
     const bool ok = key != KEY_NONE && (int64_t)(uint32_t)key < n;  // ids outside [0, n) are never read
     float acc = 0.f;
     if (ok) {
-      const float4* x = reinterpret_cast<const float4*>(X + (size_t)(uint32_t)key * ldx);
+      const size_t row = (size_t)(uint32_t)key * ldx;
       for (int f = sl; f < nf4; f += 16) {
-        const float4 xv = x[f], qv = qs[f];
+        const float4 xv = row4(X, row + 4 * (size_t)f), qv = qs[f];
         const float a0 = qv.x - xv.x, a1 = qv.y - xv.y, a2 = qv.z - xv.z, a3 = qv.w - xv.w;
         acc += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
       }
@@ -1190,9 +1202,10 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   }
 }
 
-void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64_t n, int ldx,
-                   int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
-                   float* dist, const int32_t* rowk) {
+template <typename T>
+static void rerank_impl(hipStream_t s, const float* q, int ldq, const T* X, int64_t n, int ldx,
+                        int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
+                        float* dist, const int32_t* rowk) {
   if (nq <= 0) return;
   RBQ_CHECK(ldx % 4 == 0 && ldq % 4 == 0, "rows must be padded to 4 floats");
   int KP = pow2_at_least(k);
@@ -1202,8 +1215,51 @@ void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64
     lds = (size_t)(-KP) * sizeof(uint64_t) + (size_t)ldx * sizeof(float);
   }
   RBQ_CHECK(lds <= (size_t)(64 << 10), "re-rank needs too much LDS for this d and rerank_n");
-  hipLaunchKernelGGL(k_rerank, dim3(nq), dim3(256), lds, s, q, ldq, X, n, ldx, d, cand, ldc, R, k,
+  hipLaunchKernelGGL(k_rerank<T>, dim3(nq), dim3(256), lds, s, q, ldq, X, n, ldx, d, cand, ldc, R, k,
                      KP, ids, dist, rowk);
+  RBQ_HIP(hipGetLastError());
+}
+
+void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64_t n, int ldx,
+                   int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
+                   float* dist, const int32_t* rowk) {
+  rerank_impl(s, q, ldq, X, n, ldx, d, cand, ldc, nq, R, k, ids, dist, rowk);
+}
+
+void launch_rerank_u8(hipStream_t s, const float* q, int ldq, const uint8_t* X, int64_t n, int ldx,
+                      int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
+                      float* dist, const int32_t* rowk) {
+  rerank_impl(s, q, ldq, X, n, ldx, d, cand, ldc, nq, R, k, ids, dist, rowk);
+}
+
+// Raw vectors that are all integers in [0, 255] (e.g. SIFT-style descriptors
+// stored as FP32) can be held as bytes without changing any value.
+__global__ void k_count_not_u8(const float* X, int64_t rows, int d, int ld, unsigned* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = rows * d;
+  unsigned bad = 0;
+  for (int64_t e = t; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / d;
+    const float v = X[r * ld + (e - r * d)];
+    bad += !(v >= 0.f && v <= 255.f && v == rintf(v));
+  }
+  if (bad) atomicAdd(out, bad);
+}
+
+__global__ void k_to_u8(const float* X, int64_t total, uint8_t* out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (uint8_t)X[e];
+}
+
+void launch_count_not_u8(hipStream_t s, const float* X, int64_t rows, int d, int ld, unsigned* out) {
+  hipLaunchKernelGGL(k_count_not_u8, dim3(1024), dim3(256), 0, s, X, rows, d, ld, out);
+  RBQ_HIP(hipGetLastError());
+}
+
+void launch_to_u8(hipStream_t s, const float* X, int64_t total, uint8_t* out) {
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_to_u8, dim3(2048), dim3(256), 0, s, X, total, out);
   RBQ_HIP(hipGetLastError());
 }
 

@@ -146,6 +146,16 @@ void launch_rerank(hipStream_t s, const float* q, int ldq, const float* X, int64
                    int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
                    float* dist, const int32_t* rowk = nullptr);
 
+// The same with byte rows (raw vectors that are integers 0..255, held exactly):
+// the per-lane order of the sums is the FP32 kernel's, so results are equal.
+void launch_rerank_u8(hipStream_t s, const float* q, int ldq, const uint8_t* X, int64_t n, int ldx,
+                      int d, const uint64_t* cand, int64_t ldc, int nq, int R, int k, int64_t* ids,
+                      float* dist, const int32_t* rowk = nullptr);
+// Counts the elements of X (rows x d, stride ld) that are not integers in
+// [0, 255]; converts `total` floats to bytes.
+void launch_count_not_u8(hipStream_t s, const float* X, int64_t rows, int d, int ld, unsigned* out);
+void launch_to_u8(hipStream_t s, const float* X, int64_t total, uint8_t* out);
+
 // probes[i][p] = -1 for p >= qnp[i] (a query that probes fewer lists than the
 // batch's widest one); scans and maps skip such pairs.
 void launch_mask_probes(hipStream_t s, int32_t* probes, int nq, int nprobe, const int32_t* qnp);

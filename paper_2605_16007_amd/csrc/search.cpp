@@ -600,8 +600,12 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       RBQ_HIP(hipEventRecord(job->ready, s));
     } else {
       // Phase 5: exact re-rank of the top-R on the GPU
-      launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
-                    ids_out, dist_out, d_k);
+      if (idx->X8.p)
+        launch_rerank_u8(s, qd, ld, idx->X8.as<uint8_t>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
+                         ids_out, dist_out, d_k);
+      else
+        launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
+                      ids_out, dist_out, d_k);
     }
     mark(5);
 
