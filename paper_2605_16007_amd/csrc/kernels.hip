@@ -321,7 +321,12 @@ __global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
   }
   const bool cached = ncols <= a.cache_cap;
   uint64_t* cache = smem;
-  uint64_t* sel = smem + a.cache_cap;
+  // selection buffer: after the cache (sorted mode); for unsorted output a
+  // cached row is compacted straight into the output row (all of its reads
+  // come from the cache), and an uncached row uses the cache space instead
+  const bool direct = !a.sorted && cached && a.out_keys && !a.out_low && !a.out_val;
+  uint64_t* sel = a.sorted ? smem + a.cache_cap : smem;
+  uint64_t* dst = direct ? a.out_keys + row * a.ldo : sel;
   auto src = [&](int c) -> uint64_t {
     if (FROM_SCORE) return key64(a.score[row * a.ld + c], (uint32_t)c);
     return a.keys[row * a.ld + c];
@@ -410,6 +415,7 @@ __global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
   __syncthreads();
   // compaction: keys below the prefix, then boundary-bucket keys up to k in all
   const int rounds = (ncols + NT - 1) / NT;
+  uint64_t mx = 0;  // the largest key this thread wrote
   if (take_all) {
     for (int r = 0; r < rounds; ++r) {
       const int c = r * NT + tid;
@@ -418,7 +424,11 @@ __global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
       uint32_t base = 0;
       if (lane == 0 && m) base = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
       base = __shfl(base, 0);
-      if (t) sel[base + lane_prefix(m)] = get(c);
+      if (t) {
+        const uint64_t key = get(c);
+        dst[base + lane_prefix(m)] = key;
+        mx = key > mx ? key : mx;
+      }
     }
   } else {
     const uint64_t hi_key = prefix | ~pmask;
@@ -430,7 +440,10 @@ __global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
       uint32_t base = 0;
       if (lane == 0 && m) base = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
       base = __shfl(base, 0);
-      if (t) sel[base + lane_prefix(m)] = key;
+      if (t) {
+        dst[base + lane_prefix(m)] = key;
+        mx = key > mx ? key : mx;
+      }
     }
     __syncthreads();
     for (int r = 0; r < rounds; ++r) {
@@ -442,21 +455,22 @@ __global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
       if (lane == 0 && m) base = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
       base = __shfl(base, 0);
       const uint32_t p = base + lane_prefix(m);
-      if (t && p < (uint32_t)k) sel[p] = key;
+      if (t && p < (uint32_t)k) {
+        dst[p] = key;
+        mx = key > mx ? key : mx;
+      }
     }
   }
   __syncthreads();
   const int cnt = min((int)s_cnt, k);
   const int fill_to = a.sorted ? KP : k;
-  for (int i = cnt + tid; i < fill_to; i += NT) sel[i] = KEY_NONE;
+  for (int i = cnt + tid; i < fill_to; i += NT) dst[i] = KEY_NONE;
   __syncthreads();
   uint64_t kth;  // the k-th smallest key (KEY_NONE if fewer than k)
   if (a.sorted) {
     bitonic_sort_lds(sel, KP);
     kth = sel[k - 1];
   } else {  // the selected keys in any order; their maximum is the k-th
-    uint64_t mx = 0;
-    for (int i = tid; i < k; i += NT) mx = sel[i] > mx ? sel[i] : mx;
     for (int off = 32; off > 0; off >>= 1) {
       const uint64_t o = __shfl_xor(mx, off);
       mx = o > mx ? o : mx;
@@ -465,8 +479,9 @@ __global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
     __syncthreads();
     kth = s_hi[0];
     for (int w = 1; w < NW; ++w) kth = s_hi[w] > kth ? s_hi[w] : kth;
+    if (cnt < k) kth = KEY_NONE;  // fewer than k keys
   }
-  for (int i = tid; i < k; i += NT) {
+  for (int i = tid; i < k && !direct; i += NT) {
     const uint64_t v = sel[i];
     if (a.out_keys) a.out_keys[row * a.ldo + i] = v;
     if (a.out_low) a.out_low[row * k + i] = v == KEY_NONE ? -1 : (int32_t)(uint32_t)v;
@@ -492,12 +507,20 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   a.KP = pow2_at_least(a.k);
   if (a.ldo <= 0) a.ldo = a.k;
   const int maxcols = a.rowcnt ? a.k + a.max_extra : a.ncols;
-  // selection buffer: KP keys (sorted mode) or k keys; the row is staged in
-  // LDS next to it when it fits
-  const int selcap = a.sorted ? a.KP : a.k;
-  const int room = (int)(kTopkLdsMax / sizeof(uint64_t)) - selcap;
-  a.cache_cap = std::max(0, std::min(maxcols, room));
-  const size_t lds = (size_t)(a.cache_cap + selcap) * sizeof(uint64_t);
+  // sorted mode: the row cache, then a KP-key selection buffer; unsorted
+  // mode: the cache alone (a cached row is compacted into its output row, an
+  // uncached one into the cache space, which then holds at least k keys)
+  const int slots = (int)(kTopkLdsMax / sizeof(uint64_t));
+  int lds_keys;
+  if (a.sorted) {
+    a.cache_cap = std::max(0, std::min(maxcols, slots - a.KP));
+    lds_keys = a.cache_cap + a.KP;
+  } else {
+    RBQ_CHECK(a.out_keys && !a.out_low && !a.out_val, "unsorted selection writes keys only");
+    a.cache_cap = std::min(maxcols, slots);
+    lds_keys = std::max(a.cache_cap, a.k);
+  }
+  const size_t lds = (size_t)lds_keys * sizeof(uint64_t);
   static std::once_flag attr_once;
   std::call_once(attr_once, [] {
     for (const void* f : {reinterpret_cast<const void*>(k_row_topk<true, 256>),
@@ -516,45 +539,72 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
 }
 
 // ---------------------------------------------------------------------------
-// Query quantisation: one wave per (query, probe) pair. r = P^T q - P^T c_j,
-// v_l = min r, Delta = (max r - v_l)/(2^bq - 1), qu = floor((r - v_l)/Delta
-// + 1/2) clamped; bit-planes by wave ballots (64 dims per ballot = 2 words).
+// Query quantisation: 16 lanes per (query, probe) pair, four pairs per wave;
+// lane g of a pair holds 8 consecutive dimensions of every 128-dimension step.
+// r = P^T q - P^T c_j, v_l = min r, Delta = (max r - v_l)/(2^bq - 1),
+// qu = floor((r - v_l)/Delta + 1/2) clamped; ||r||^2 and sum qu. The qu bytes
+// are stored 8 per lane, and bit-plane word w (dimensions 32w..32w+31) is
+// assembled from the bytes of the four lanes that hold those dimensions.
 // ---------------------------------------------------------------------------
+
+__device__ inline void load8(const float* p, int d0, int d, float (&v)[8]) {
+  if (d0 + 8 <= d) {  // rows are 16-byte aligned and d0 is a multiple of 8
+    const float4 a = *reinterpret_cast<const float4*>(p + d0);
+    const float4 b = *reinterpret_cast<const float4*>(p + d0 + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = d0 + u < d ? p[d0 + u] : 0.f;
+  }
+}
 
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, int ldq,
                                                const float* __restrict__ crot, int ldc,
-                                               const int32_t* __restrict__ probes, int nq, int nprobe,
-                                               int d, int W, int bq, int bqs,
+                                               const int32_t* __restrict__ probes, int64_t npairs,
+                                               int nprobe, int d, int W, int bq, int bqs,
                                                uint32_t* __restrict__ planes,
                                                uint8_t* __restrict__ qu_out, float4* __restrict__ scal,
                                                const uint8_t* __restrict__ inj_qu,
                                                const float* __restrict__ inj_scal) {
-  const int lane = threadIdx.x & 63;
-  const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (pair >= (int64_t)nq * nprobe) return;  // uniform per wave
-  const int64_t i = pair / nprobe;
-  const int j = max(probes[pair], 0);  // probes are always valid list ids; never index below 0
+  const int g = threadIdx.x & 15;
+  const int64_t pair = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const bool active = pair < npairs;  // (the 16 lanes of a pair agree)
+  const int64_t pr = active ? pair : 0;
+  const int64_t i = pr / nprobe;
+  const int j = max(probes[pr], 0);  // -1 (not probed): computed on list 0 and never used
   const float* qr = qrot + i * ldq;
   const float* cr = crot + (int64_t)j * ldc;
-  const int nch = (W * 32 + 63) / 64;
+  const int Wq = W * 32;
+  const int steps = (Wq + 127) / 128;
   float rmin = INFINITY, rmax = -INFINITY, ss = 0.f;
-  for (int t = 0; t < nch; ++t) {
-    const int dd = t * 64 + lane;
-    if (dd < d) {
-      const float r = qr[dd] - cr[dd];
-      rmin = fminf(rmin, r);
-      rmax = fmaxf(rmax, r);
-      ss += r * r;
+  float r0[8];  // the first step's residuals (all of them when d <= 128)
+  for (int st = 0; st < steps; ++st) {
+    const int d0 = st * 128 + 8 * g;
+    float a[8], c[8];
+    load8(qr, d0, d, a);
+    load8(cr, d0, d, c);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float r = a[u] - c[u];
+      if (st == 0) r0[u] = r;
+      if (d0 + u < d) {
+        rmin = fminf(rmin, r);
+        rmax = fmaxf(rmax, r);
+        ss += r * r;
+      }
     }
   }
-  rmin = wave_min(rmin);
-  rmax = wave_max(rmax);
-  ss = wave_sum(ss);
+  for (int off = 8; off > 0; off >>= 1) {  // within the pair's 16 lanes
+    rmin = fminf(rmin, __shfl_xor(rmin, off));
+    rmax = fmaxf(rmax, __shfl_xor(rmax, off));
+    ss += __shfl_xor(ss, off);
+  }
   float vl, delta, rn2;
   if (inj_scal) {
-    rn2 = inj_scal[pair * 3 + 0];
-    vl = inj_scal[pair * 3 + 1];
-    delta = inj_scal[pair * 3 + 2];
+    rn2 = inj_scal[pr * 3 + 0];
+    vl = inj_scal[pr * 3 + 1];
+    delta = inj_scal[pr * 3 + 2];
   } else {
     rn2 = ss;
     vl = rmin;
@@ -563,35 +613,64 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
   const float inv = delta > 0.f ? 1.0f / delta : 0.f;
   const uint32_t top = (1u << bq) - 1u;
   int sq = 0;
-  for (int t = 0; t < nch; ++t) {
-    const int dd = t * 64 + lane;
-    uint32_t q = 0;
-    if (dd < d) {
-      if (inj_qu) {
-        q = inj_qu[pair * d + dd];
-      } else {
-        const float r = qr[dd] - cr[dd];
-        const float y = (r - vl) * inv;
-        const float f = floorf(y + 0.5f);
-        q = f <= 0.f ? 0u : (f >= (float)top ? top : (uint32_t)f);
-      }
+  for (int st = 0; st < steps; ++st) {
+    const int d0 = st * 128 + 8 * g;
+    float r[8];
+    if (st == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = r0[u];
+    } else {
+      float a[8], c[8];
+      load8(qr, d0, d, a);
+      load8(cr, d0, d, c);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = a[u] - c[u];
     }
-    sq += (int)q;
-    if (qu_out && dd < W * 32) qu_out[pair * (W * 32) + dd] = (uint8_t)q;
-    for (int b = 0; b < bq; ++b) {
-      const uint64_t m = __ballot((q >> b) & 1u);
-      if (lane == 0) {
-        const int w0 = 2 * t;
-        planes[(pair * W + w0) * bqs + b] = (uint32_t)m;
-        if (w0 + 1 < W) planes[(pair * W + w0 + 1) * bqs + b] = (uint32_t)(m >> 32);
+    uint32_t lo = 0, hi = 0, pb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int dd = d0 + u;
+      uint32_t q = 0;
+      if (dd < d) {
+        if (inj_qu) {
+          q = inj_qu[pr * d + dd];
+        } else {
+          const float y = (r[u] - vl) * inv;
+          const float f = floorf(y + 0.5f);
+          q = f <= 0.f ? 0u : (f >= (float)top ? top : (uint32_t)f);
+        }
       }
+      sq += (int)q;
+      if (u < 4)
+        lo |= q << (8 * u);
+      else
+        hi |= q << (8 * (u - 4));
+#pragma unroll
+      for (int b = 0; b < 8; ++b) pb[b] |= ((q >> b) & 1u) << u;
+    }
+    // plane word w (dimensions 32w..32w+31) from the bytes of lanes 4k..4k+3
+    // of the pair (k = g / 4): lane 4k + t stores planes t and t + 4
+    const int t = g & 3;
+    uint32_t wd[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      uint32_t v = pb[b] << (8 * t);
+      v |= __shfl_xor(v, 1);
+      v |= __shfl_xor(v, 2);
+      wd[b] = v;
+    }
+    if (active && d0 < Wq) {
+      if (qu_out) *reinterpret_cast<uint2*>(qu_out + pr * Wq + d0) = make_uint2(lo, hi);
+      const int w = d0 >> 5;
+      uint32_t* pw = planes + (pr * W + w) * bqs;
+      const uint32_t v0 = t == 0 ? wd[0] : t == 1 ? wd[1] : t == 2 ? wd[2] : wd[3];
+      const uint32_t v1 = t == 0 ? wd[4] : t == 1 ? wd[5] : t == 2 ? wd[6] : wd[7];
+      if (t < bqs) pw[t] = t < bq ? v0 : 0u;
+      if (t + 4 < bqs) pw[t + 4] = t + 4 < bq ? v1 : 0u;
     }
   }
-  if (lane == 0)
-    for (int w = 0; w < W; ++w)
-      for (int b = bq; b < bqs; ++b) planes[(pair * W + w) * bqs + b] = 0u;
-  sq = wave_sum_i(sq);
-  if (lane == 0) scal[pair] = make_float4(rn2, vl, delta, (float)sq);
+  for (int off = 8; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+  if (active && g == 0) scal[pr] = make_float4(rn2, vl, delta, (float)sq);
 }
 
 void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, int ldc,
@@ -600,8 +679,9 @@ void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, 
                   const float* inj_scal) {
   const int64_t pairs = (int64_t)nq * nprobe;
   if (pairs <= 0) return;
-  hipLaunchKernelGGL(k_quant, dim3((unsigned)((pairs + 3) / 4)), dim3(256), 0, s, qrot, ldq, crot,
-                     ldc, probes, nq, nprobe, d, W, bq, bqs, planes, qu, scal, inj_qu, inj_scal);
+  RBQ_CHECK(bq >= 1 && bq <= 8 && bqs <= 8, "query bits out of range");
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)((pairs + 15) / 16)), dim3(256), 0, s, qrot, ldq, crot,
+                     ldc, probes, pairs, nprobe, d, W, bq, bqs, planes, qu, scal, inj_qu, inj_scal);
   RBQ_HIP(hipGetLastError());
 }
 
