@@ -33,27 +33,31 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # a sum for E, (||r||^2 + n_x^2), the factor product and its sum, the threshold
 # compare
 EPILOGUE_OPS = 9
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_scan_group_sift10m_pmc.md")
-GROUP_SRC = os.path.join(ROOT, "paper_2605_16007_amd", "csrc", "kernels_group.hip")
+# PMC summaries (HBM bytes per launch of a scan kernel at one operating point)
+PMC_SUMMARIES = {
+    "k_scan_group": (os.path.join(ROOT, "profiles", "k_scan_group_sift10m_pmc.md"),
+                     os.path.join(ROOT, "paper_2605_16007_amd", "csrc", "kernels_group.hip")),
+    "k_scan_popc": (os.path.join(ROOT, "profiles", "k_scan_popc_unit96_50m.md"),
+                    os.path.join(ROOT, "paper_2605_16007_amd", "csrc", "kernels.hip")),
+}
 
 
-def pmc_traffic(workload, nprobe, rerank):
-    """HBM bytes per k_scan_group launch from the committed PMC summary, if the
+def pmc_traffic(kernel, point):
+    """HBM bytes per launch of `kernel` from its committed PMC summary, if the
     kernel source has not changed since the counters were taken and they were
-    taken at this workload and operating point."""
+    taken at this operating point (e.g. "sift10m nprobe=512 rerank=3840")."""
     import hashlib
     import re
+    summary, src = PMC_SUMMARIES[kernel]
     try:
-        text = open(PMC_SUMMARY).read()
-        sha = hashlib.sha256(open(GROUP_SRC, "rb").read()).hexdigest()
+        text = open(summary).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
     m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    o = re.search(r"operating_point:\s*(\S+)\s+nprobe=(\d+)\s+rerank=(\d+)", text)
-    if not m or not t or not o or m.group(1) != sha:
-        return None
-    if (o.group(1), int(o.group(2)), int(o.group(3))) != (workload, nprobe, rerank):
+    o = re.search(r"operating_point:\s*(.+)", text)
+    if not m or not t or not o or m.group(1) != sha or o.group(1).strip() != point:
         return None
     return float(t.group(1))
 
@@ -83,10 +87,10 @@ class CpuBaseline:
     """The oracle as it stands, on the host cores, over a bounded sample.
 
     Sample: the first ``nqueries`` queries of the batch, searched by the oracle
-    on an oracle-built index over the first 1M database rows with nlist scaled
-    so that lists hold as many vectors as in the full workload (N / nlist);
-    each query therefore probes and scans the same number of vectors as on the
-    full index. Index construction is not timed. The worker processes are
+    on an oracle-built index over the first 2.5M database rows with nlist
+    scaled so that lists hold as many vectors as in the full workload
+    (N / nlist); each query therefore probes and scans the same number of
+    vectors as on the full index (up to nprobe = that nlist). Index construction is not timed. The worker processes are
     forked here, before the GPU is used, and run the sample later at the
     operating point the GPU run settles on.
     """
@@ -96,7 +100,7 @@ class CpuBaseline:
         import oracle as O
         from synth import database
         self.w, self.nqueries, self.cores = w, nqueries, cores
-        self.n_sub = min(w.n, 1_000_000)
+        self.n_sub = min(w.n, 2_500_000)
         self.nlist_sub = max(1, int(round(w.nlist * self.n_sub / w.n)))
         t = time.perf_counter()
         Xs = database(w, 0, self.n_sub)
@@ -244,6 +248,10 @@ def main():
     ap.add_argument("--vectors-on-host", action="store_true",
                     help="keep the raw vectors in pinned host memory and re-rank on host cores")
     ap.add_argument("--no-autotune", action="store_true", help="time the built-in launch rule")
+    ap.add_argument("--tune-cache", default="",
+                    help="autotune cache file: loaded if it exists (no tuning runs), else written")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the timing of both scan forms at the chosen point")
     ap.add_argument("--scan", choices=("auto", "popcount", "mfma"), default="auto",
                     help="force the scan form of the timed loop (auto: tuned per chunk)")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
@@ -355,10 +363,17 @@ def main():
     # the autotuner picks the launch choices of each timed shape (results are
     # unchanged by construction and checked by the library)
     tuned = {}
-    if not args.no_autotune:
+    loaded = 0
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        loaded = idx.tune_load(args.tune_cache)
+        log(f"[autotune] {loaded} tuned shapes loaded from {args.tune_cache}")
+        tuned = {"loaded_from_cache": loaded}
+    if not args.no_autotune and not loaded:
         for pt in ([(p, w.rerank_n) for p in w.nprobe] if not args.nprobe else []) + [(nprobe, R)]:
             tuned[f"nprobe={pt[0]},rerank={pt[1]}"] = idx.autotune(Qb[0], pt[0], w.k, pt[1])
             log(f"[autotune] {pt}: {tuned[f'nprobe={pt[0]},rerank={pt[1]}']}")
+        if args.tune_cache:
+            idx.tune_save(args.tune_cache)
     listed_qps = {f"{p}": quick_qps(p, w.rerank_n) for p in w.nprobe} if not args.nprobe else {}
 
     idx.set_option("scan", {"auto": 0, "popcount": 1, "mfma": 2}[args.scan])
@@ -391,11 +406,12 @@ def main():
 
     # the two scan forms at the chosen point
     variants = {}
-    for name, mode in (("popcount_query_major", 1), ("mfma_list_major", 2)):
-        idx.set_option("scan", mode)
-        variants[name] = quick_qps(nprobe, R, steps=10)
-    idx.set_option("scan", 0)
-    log("[variants] " + ", ".join(f"{k_}: {v:.0f} q/s" for k_, v in variants.items()))
+    if not args.no_variants:
+        for name, mode in (("popcount_query_major", 1), ("mfma_list_major", 2)):
+            idx.set_option("scan", mode)
+            variants[name] = quick_qps(nprobe, R, steps=10)
+        idx.set_option("scan", 0)
+        log("[variants] " + ", ".join(f"{k_}: {v:.0f} q/s" for k_, v in variants.items()))
 
     serving = serve_compare(idx, w, args) if args.serve_rates else None
 
@@ -404,6 +420,7 @@ def main():
         cpu_pool.close()
 
     ns = max(1, tm["searches"])
+    wname = w.name if not args.n else f"{w.name}/n={w.n}"  # the workload as the PMC summaries name it
     scan_s = tm["scan_ms"] / ns * 1e-3
     if tm["group_launches"] > 0:
         # list-major int8-MFMA scan (the dominant kernel): bound by the VALU epilogue
@@ -411,7 +428,7 @@ def main():
         gscan_s = tm["group_scan_ms"] / ns * 1e-3
         gvec = tm["group_vectors"] / ns
         achieved = gvec * EPILOGUE_OPS / gscan_s / 1e12
-        traffic = pmc_traffic(w.name, nprobe, R)
+        traffic = pmc_traffic("k_scan_group", f"{wname} nprobe={nprobe} rerank={R}")
         roofline = {"kernel": "k_scan_group", "bound": "alu", "achieved": achieved,
                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                     "traffic": traffic,
@@ -427,7 +444,9 @@ def main():
         achieved = tm["read_bytes"] / ns / scan_s / 1e9
         roofline = {"kernel": "k_scan_popc", "bound": "hbm", "achieved": achieved,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": None, "launches_per_step": launches,
+                    "traffic": pmc_traffic("k_scan_popc",
+                                           f"{wname} nprobe={nprobe} rerank={R} scan={args.scan}"),
+                    "launches_per_step": launches,
                     "avg_launch_ms": scan_s * 1e3 / launches,
                     "bytes_per_launch": tm["read_bytes"] / ns / launches}
     if args.calibrate_copy_gib > 0:

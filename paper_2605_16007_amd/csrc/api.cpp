@@ -441,7 +441,7 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
       idx->last.merge_ms += ms[3] - scan;
       idx->last.rerank_ms += ms[4];
       idx->last.total_ms += tot;
-      idx->last.searches += 1;
+      idx->last.searches += a.first_part ? 1 : 0;  // sub-batches of one search add up
       idx->last.group_launches += a.group;
       idx->last.popc_launches += a.popc;
       for (auto e : a.e) (void)hipEventDestroy(e);

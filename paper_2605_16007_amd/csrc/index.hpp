@@ -24,6 +24,7 @@ struct TimingRec {
   std::vector<hipEvent_t> scan;   // (start, end) around every scan launch
   std::vector<char> scan_lm;      // per launch: list-major form
   int64_t group = 0, popc = 0;    // scan launches of each form
+  bool first_part = true;         // the first (or only) part of one search
 };
 
 // Launch choices of a search that leave its results unchanged (the autotuner
@@ -159,6 +160,7 @@ struct SearchIO {
   const int32_t* q_R = nullptr;
   int64_t pool_budget = 0;  // bytes for the candidate rows (0: 512 MB)
   const TuneCfg* force = nullptr;  // launch choices to use (autotuner trials)
+  bool continues_search = false;   // a later sub-batch of a search already counted
   // caller-owned device scratch (else the index's pool); not reused by the
   // caller before the search's stream has passed this call
   char* ws_base = nullptr;

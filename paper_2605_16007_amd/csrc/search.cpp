@@ -646,6 +646,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     }
     if (ws) ws_release(idx, std::move(ws), s);
     if (timed) {
+      tr.first_part = !io.continues_search;
       std::lock_guard<std::mutex> g(idx->timing_mu);
       idx->pending.push_back(std::move(tr));
     }
@@ -749,6 +750,7 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
       RBQ_HIP(hipEventCreateWithFlags(&job.ready, hipEventDisableTiming));
       events.push_back(job.ready);
       SearchIO sub = io;
+      sub.continues_search = q0 > 0;
       if (io.q_nprobe) {
         sub.q_nprobe = io.q_nprobe + q0;
         sub.q_k = io.q_k + q0;
