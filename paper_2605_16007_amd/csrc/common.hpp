@@ -60,11 +60,15 @@ constexpr uint64_t KEY_NONE = ~0ull;
 __device__ __forceinline__ float rbq_vx(float fmul, int pop, int D) {
   return fmul * (float)(2 * pop - D);
 }
+// from g = 2 ip - sum qu, an exact integer
+__device__ __forceinline__ float rbq_estimate_g(float rn2, float vl, float delta, int g, float fadd,
+                                                float fmul, float vx) {
+  return __builtin_fmaf(fmul * delta, (float)g, __builtin_fmaf(vl, vx, fadd)) + rn2;
+}
 // (neg_sumqu = -sum qu, so that 2 ip - sum qu is one shift-add)
 __device__ __forceinline__ float rbq_estimate(float rn2, float vl, float delta, int neg_sumqu, int ip,
                                               float fadd, float fmul, float vx) {
-  const float g = (float)((ip << 1) + neg_sumqu);
-  return __builtin_fmaf(fmul * delta, g, __builtin_fmaf(vl, vx, fadd)) + rn2;
+  return rbq_estimate_g(rn2, vl, delta, (ip << 1) + neg_sumqu, fadd, fmul, vx);
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -1062,7 +1062,7 @@ __global__ __launch_bounds__(1024) void k_scan_fused(FusedArgs a) {
         for (int t = 0; t < PR; ++t) cpl[t] = pl[t];
         const float fadd = fa, fmul = fm;
         const float4 sc = c_sc;
-        const int len = c_len, pos0 = c_pos0, mb = c_mb, id = c_id;
+        const int len = c_len, mb = c_mb, id = c_id;
         const int64_t pair = c_pair;
         if (idx + NW < total) {  // prefetch the next round's micro-block
           locate(idx + NW, c_pair, c_len, c_pos0, c_mb);
@@ -1247,23 +1247,42 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   const int nf4 = ldx >> 2;
   for (int t = tid; t < nf4; t += 256)
     qs[t] = (t * 4 < d) ? reinterpret_cast<const float4*>(q + i * ldq)[t] : make_float4(0, 0, 0, 0);
+  for (int c = tid; c < R; c += 256) ck[c] = cand[i * ldc + c];  // the keys, coalesced
   __syncthreads();
-  // 16 candidates per workgroup round: wave w, slot s takes candidate 16 r + 4 w + s
-  for (int c0 = 0; c0 < R; c0 += 16) {
-    const int c = c0 + 4 * wave + sub;
-    uint64_t key = c < R ? cand[i * ldc + c] : KEY_NONE;
-    const bool ok = key != KEY_NONE && (int64_t)(uint32_t)key < n;  // ids outside [0, n) are never read
-    float acc = 0.f;
-    if (ok) {
-      const size_t row = (size_t)(uint32_t)key * ldx;
-      for (int f = sl; f < nf4; f += 16) {
-        const float4 xv = row4(X, row + 4 * (size_t)f), qv = qs[f];
-        const float a0 = qv.x - xv.x, a1 = qv.y - xv.y, a2 = qv.z - xv.z, a3 = qv.w - xv.w;
-        acc += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+  // 16 lanes per candidate, RU candidates per slot in flight: in round r, wave
+  // w, slot s takes candidates 16 (RU r + u) + 4 w + s; each slot rewrites only
+  // its own keys
+  constexpr int RU = 4;
+  for (int c0 = 0; c0 < R; c0 += 16 * RU) {
+    uint64_t key[RU];
+    size_t row[RU];
+    bool ok[RU];
+    float acc[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int c = c0 + 16 * u + 4 * wave + sub;
+      key[u] = c < R ? ck[c] : KEY_NONE;
+      ok[u] = key[u] != KEY_NONE && (int64_t)(uint32_t)key[u] < n;  // ids outside [0, n) are never read
+      row[u] = ok[u] ? (size_t)(uint32_t)key[u] * ldx : 0;
+      acc[u] = 0.f;
+    }
+    for (int f = sl; f < nf4; f += 16) {
+      const float4 qv = qs[f];
+      float4 xv[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) xv[u] = ok[u] ? row4(X, row[u] + 4 * (size_t)f) : qv;
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const float a0 = qv.x - xv[u].x, a1 = qv.y - xv[u].y, a2 = qv.z - xv[u].z, a3 = qv.w - xv[u].w;
+        acc[u] += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
       }
     }
-    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (sl == 0 && c < R) ck[c] = ok ? key64(acc, (uint32_t)key) : KEY_NONE;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      for (int off = 8; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
+      const int c = c0 + 16 * u + 4 * wave + sub;
+      if (sl == 0 && c < R) ck[c] = ok[u] ? key64(acc[u], (uint32_t)key[u]) : KEY_NONE;
+    }
   }
   __syncthreads();
   if (KP > 0) {
@@ -1527,6 +1546,32 @@ void launch_fill_rows_u64(hipStream_t s, uint64_t* p, int64_t ld, int64_t rows, 
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_rows_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, ld, rows,
                      cols, v);
+  RBQ_HIP(hipGetLastError());
+}
+
+// A search's per-query state in one launch: candidate rows empty, thresholds
+// open, pool fills and overflow flags zero, and the extra words cleared.
+__global__ void k_search_init(SearchInit a) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cells = (int64_t)a.nq * a.R;
+  for (int64_t t = t0; t < cells; t += step) {
+    const int64_t r = t / a.R;
+    a.cand[r * a.cand_ld + (t - r * a.R)] = KEY_NONE;
+  }
+  for (int64_t t = t0; t < a.nq; t += step) {
+    a.qthr[t] = 0xFFFFFFFFu;
+    a.pcnt[t] = 0u;
+    if (a.overflow) a.overflow[t] = 0u;
+  }
+  for (int64_t t = t0; t < a.n0; t += step) a.z0[t] = 0u;
+  for (int64_t t = t0; t < a.n1; t += step) a.z1[t] = 0u;
+}
+void launch_search_init(hipStream_t s, const SearchInit& a) {
+  const int64_t n = std::max<int64_t>({(int64_t)a.nq * a.R, a.nq, a.n0, a.n1});
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(k_search_init, dim3((unsigned)blocks), dim3(256), 0, s, a);
   RBQ_HIP(hipGetLastError());
 }
 

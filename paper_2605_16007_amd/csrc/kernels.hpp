@@ -118,9 +118,10 @@ struct GroupArgs {
   const uint8_t* qu;       // [pairs][W*32] quantised residuals
   const float4* scal;      // [pairs] (||r||^2, v_l, Delta, sum qu)
   int nq, nprobe, R, nlist, G;
+  int bq;                  // query bits B_q
   const int32_t* slots;    // chunk pairs grouped by list
   const int32_t* pair_off; // [nlist+1]
-  const int32_t* item_off; // [nlist+1] items per list: ceil(pairs / G)
+  const int32_t* item_off; // the chunk's [nlist+1] item offsets (first item .. end)
   const int4* items;       // per item: (list, first slot, pairs)
   uint32_t* item_counter;  // work-queue cursor, zero before the launch
   const uint32_t* qthr;    // per-query threshold (ordered float of d_hat^2)
@@ -132,7 +133,17 @@ struct GroupArgs {
   uint32_t* any_overflow;  // set with any overflow flag
 };
 int group_k_steps(int d);
-void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, int p0, int pn,
+// The list-major chunks of a search: probe ranks [bound[0], bound[nb]), chunk
+// c = [bound[c], bound[c+1]).
+constexpr int kMaxGroupChunks = 16;
+struct GroupChunks {
+  int nb = 0;
+  int bound[kMaxGroupChunks + 1] = {};
+};
+// Pairs of every list-major chunk grouped by (chunk, list): cnt, pair_off,
+// item_off and fill hold nb * nlist bins (+1 for the offsets); cnt must be
+// zero on entry.
+void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
                       int nlist, int G, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
                       int32_t* fill, int32_t* slots, int4* items);
 void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups);
@@ -170,6 +181,22 @@ void launch_encode(hipStream_t s, const float* X, int ldx, const float* C, int l
 // also nrm[r] = ||A_r||^2 (FP64 -> FP32) if nrm is set.
 void launch_rotate_rows_f64(hipStream_t s, const float* A, int lda, const float* Pt, int ldp,
                             int rows, int d, float* out, int ldo, float* nrm);
+
+// Per-search state: cand rows [nq][R] (stride cand_ld) = KEY_NONE, qthr =
+// ~0, pcnt = 0, overflow = 0 (if set), z0[0..n0) = z1[0..n1) = 0.
+struct SearchInit {
+  uint64_t* cand = nullptr;
+  int64_t cand_ld = 0;
+  int nq = 0, R = 0;
+  uint32_t* qthr = nullptr;
+  uint32_t* pcnt = nullptr;
+  uint32_t* overflow = nullptr;
+  uint32_t* z0 = nullptr;
+  int64_t n0 = 0;
+  uint32_t* z1 = nullptr;
+  int64_t n1 = 0;
+};
+void launch_search_init(hipStream_t s, const SearchInit& a);
 
 void launch_fill_u32(hipStream_t s, uint32_t* p, uint32_t v, int64_t n);
 void launch_fill_u64(hipStream_t s, uint64_t* p, uint64_t v, int64_t n);

@@ -28,80 +28,92 @@ constexpr int GMAX = 64;   // queries per item (four 16-query MFMA tiles)
 constexpr int KSMAX = 4;   // 64-dimension MFMA steps (D <= 256)
 constexpr int STAGE = 512; // survivors staged per wave before a flush
 
-// ---- inverted map of the chunk's pairs: list -> pairs probing it ----------
+// ---- inverted map of the list-major chunks' pairs: list -> pairs ----------
+// Built once per search for all list-major chunks (a suffix of the probe
+// ranks): bin c * nlist + j holds the pairs of chunk c that probe list j.
 
-__global__ void k_grp_hist(const int32_t* __restrict__ probes, int nq, int nprobe, int p0, int pn,
-                           int32_t* __restrict__ cnt) {
+__device__ inline int group_chunk_of(const GroupChunks& gc, int p) {
+  int c = 0;
+  while (c + 1 < gc.nb && p >= gc.bound[c + 1]) ++c;
+  return c;
+}
+
+__global__ void k_grp_hist(const int32_t* __restrict__ probes, int nq, int nprobe, GroupChunks gc,
+                           int nlist, int32_t* __restrict__ cnt) {
+  const int span = nprobe - gc.bound[0];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nq * pn) return;
-  const int64_t i = t / pn;
-  const int p = p0 + (int)(t - i * pn);
+  if (t >= (int64_t)nq * span) return;
+  const int64_t i = t / span;
+  const int p = gc.bound[0] + (int)(t - i * span);
   const int j = probes[i * nprobe + p];
-  if (j >= 0) atomicAdd(&cnt[j], 1);  // (-1: the query probes fewer lists)
+  if (j >= 0) atomicAdd(&cnt[group_chunk_of(gc, p) * nlist + j], 1);  // (-1: fewer probes)
 }
 
-// Exclusive prefix sums over lists of the pair counts and of the item counts
-// ceil(cnt / G); one workgroup; also clears the scatter cursors.
-__global__ __launch_bounds__(256) void k_grp_offsets(const int32_t* __restrict__ cnt, int nlist,
-                                                     int G, int32_t* __restrict__ pair_off,
-                                                     int32_t* __restrict__ item_off,
-                                                     int32_t* __restrict__ fill) {
-  __shared__ int32_t sp[256], si[256];
-  const int tid = threadIdx.x;
-  const int per = (nlist + 255) / 256;
-  const int j0 = tid * per, j1 = min(nlist, j0 + per);
+// Exclusive prefix sums over the bins of the pair counts and of the item
+// counts ceil(cnt / G), the item descriptors (list, first slot, pairs), and
+// cleared scatter cursors; one workgroup of 1024 threads, each over a
+// contiguous range of bins.
+__global__ __launch_bounds__(1024) void k_grp_offsets(const int32_t* __restrict__ cnt, int bins, int nlist,
+                                                      int G, int32_t* __restrict__ pair_off,
+                                                      int32_t* __restrict__ item_off,
+                                                      int32_t* __restrict__ fill, int4* __restrict__ items) {
+  __shared__ int32_t wp[16], wi[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (bins + 1023) / 1024;
+  const int b0 = min(bins, tid * per), b1 = min(bins, b0 + per);
   int32_t ps = 0, is = 0;
-  for (int j = j0; j < j1; ++j) {
-    ps += cnt[j];
-    is += (cnt[j] + G - 1) / G;
+  for (int b = b0; b < b1; ++b) {
+    const int32_t c = cnt[b];
+    ps += c;
+    is += (c + G - 1) / G;
   }
-  sp[tid] = ps;
-  si[tid] = is;
-  __syncthreads();
-  if (tid == 0) {
-    int32_t a = 0, b = 0;
-    for (int t = 0; t < 256; ++t) {
-      const int32_t x = sp[t], y = si[t];
-      sp[t] = a;
-      si[t] = b;
-      a += x;
-      b += y;
+  int32_t xp = ps, xi = is;  // inclusive scans within the wave
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t tp = __shfl_up(xp, off), ti = __shfl_up(xi, off);
+    if (lane >= off) {
+      xp += tp;
+      xi += ti;
     }
-    pair_off[nlist] = a;
-    item_off[nlist] = b;
+  }
+  if (lane == 63) {
+    wp[wave] = xp;
+    wi[wave] = xi;
   }
   __syncthreads();
-  int32_t a = sp[tid], b = si[tid];
-  for (int j = j0; j < j1; ++j) {
-    pair_off[j] = a;
-    item_off[j] = b;
-    a += cnt[j];
-    b += (cnt[j] + G - 1) / G;
-    fill[j] = 0;
+  int32_t a = xp - ps, bi = xi - is;  // exclusive, then plus the earlier waves
+  for (int w = 0; w < wave; ++w) {
+    a += wp[w];
+    bi += wi[w];
+  }
+  if (tid == 1023) {
+    pair_off[bins] = a + ps;
+    item_off[bins] = bi + is;
+  }
+  for (int b = b0; b < b1; ++b) {
+    const int32_t c = cnt[b];
+    pair_off[b] = a;
+    item_off[b] = bi;
+    fill[b] = 0;
+    const int j = b % nlist;
+    for (int g = 0; g * G < c; ++g) items[bi + g] = make_int4(j, a + g * G, min(G, c - g * G), 0);
+    a += c;
+    bi += (c + G - 1) / G;
   }
 }
 
-// One descriptor per item: (list, first slot of its pairs, number of pairs).
-__global__ void k_grp_items(const int32_t* __restrict__ cnt, const int32_t* __restrict__ pair_off,
-                            const int32_t* __restrict__ item_off, int nlist, int G,
-                            int4* __restrict__ items) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nlist) return;
-  const int c = cnt[j];
-  for (int g = 0; g * G < c; ++g)
-    items[item_off[j] + g] = make_int4(j, pair_off[j] + g * G, min(G, c - g * G), 0);
-}
-
-__global__ void k_grp_scatter(const int32_t* __restrict__ probes, int nq, int nprobe, int p0, int pn,
-                              const int32_t* __restrict__ pair_off, int32_t* __restrict__ fill,
+__global__ void k_grp_scatter(const int32_t* __restrict__ probes, int nq, int nprobe, GroupChunks gc,
+                              int nlist, const int32_t* __restrict__ pair_off, int32_t* __restrict__ fill,
                               int32_t* __restrict__ slots) {
+  const int span = nprobe - gc.bound[0];
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nq * pn) return;
-  const int64_t i = t / pn;
-  const int p = p0 + (int)(t - i * pn);
+  if (t >= (int64_t)nq * span) return;
+  const int64_t i = t / span;
+  const int p = gc.bound[0] + (int)(t - i * span);
   const int64_t pair = i * nprobe + p;
   const int j = probes[pair];
-  if (j >= 0) slots[pair_off[j] + atomicAdd(&fill[j], 1)] = (int32_t)pair;
+  if (j < 0) return;
+  const int b = group_chunk_of(gc, p) * nlist + j;
+  slots[pair_off[b] + atomicAdd(&fill[b], 1)] = (int32_t)pair;
 }
 
 __device__ inline uint32_t lane_prefix(uint64_t mask) {
@@ -117,14 +129,25 @@ __device__ inline v4i unpack16(uint32_t bits) {
   return r;
 }
 
-template <int KS>
+// The MFMA multiplies signed bytes. QB (query bytes) says how qu becomes the
+// B operand:
+//   QB_DOUBLE (B_q <= 6): B = 2 qu <= 126, the MFMA returns 2 ip, and
+//     g = 2 ip - sum qu is one add;
+//   QB_PLAIN (B_q = 7): B = qu <= 127, g = (ip << 1) - sum qu;
+//   QB_OFFSET (B_q = 8): B = qu - 128 and the accumulator starts at 128 pop
+//     (pop = the vector's popcount), so the MFMA still returns ip.
+// GT: 16-query tiles per item (G <= 16 GT); each lane keeps its B operands
+// for the whole item in registers.
+enum { QB_DOUBLE = 0, QB_PLAIN = 1, QB_OFFSET = 2 };
+template <int KS, int QB, int GT>
 __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
-  __shared__ v4i sB[GMAX / 16][KS][64];      // B operands: [query tile][k step][lane]
+  __shared__ v4i sB[GT][KS][64];             // B operands: [query tile][k step][lane]
   __shared__ float4 sSc[GMAX];                // (||r||^2, v_l, Delta, sum qu) per query slot
   __shared__ float sThr[GMAX];                // threshold on d_hat^2 per query slot
   __shared__ int32_t sQ[GMAX];                // query id per slot
   __shared__ uint32_t sCode[4][2 * KS][64];  // per wave: the micro-block's code words
   __shared__ __align__(16) float sVx[4][64], sAdd[4][64], sMul[4][64];
+  __shared__ __align__(16) int32_t sPop[QB == QB_OFFSET ? 4 : 1][64];  // 128 pop per vector
   // per wave: survivors as (float bits of d_hat^2 << 32) | (query slot << 26 |
   // position in the list)
   __shared__ uint64_t sStage[4][STAGE];
@@ -168,13 +191,13 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     }
     __builtin_amdgcn_wave_barrier();
   };
-  const int total = a.item_off[nlist];
+  const int first_item = a.item_off[0], end_item = a.item_off[nlist];
   for (;;) {
-    if (tid == 0) sItem = (int32_t)atomicAdd(a.item_counter, 1u);
+    if (tid == 0) sItem = first_item + (int32_t)atomicAdd(a.item_counter, 1u);
     __syncthreads();
     const int item = sItem;
     __syncthreads();  // sItem is rewritten at the next item
-    if (item >= total) break;
+    if (item >= end_item) break;
     const int4 it = a.items[item];
     const int j = it.x, first = it.y, count = it.z;
     const int nt = (count + 15) >> 4;
@@ -191,7 +214,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
         sQ[tid] = -1;
       }
     }
-    for (int e = tid; e < (GMAX / 16) * KS * 64; e += 256) {
+    for (int e = tid; e < GT * KS * 64; e += 256) {
       const int n = e / (KS * 64), t = (e / 64) % KS, l = e & 63;
       const int q = 16 * n + (l & 15);
       const int off = 64 * t + 16 * (l >> 4);
@@ -199,23 +222,29 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
       if (q < count && off < Wq) {
         const int pair = a.slots[first + q];
         v = *reinterpret_cast<const v4i*>(a.qu + (int64_t)pair * Wq + off);
+        if (QB == QB_DOUBLE) v <<= 1;  // bytes <= 63: no carry into the next byte
+        if (QB == QB_OFFSET) v ^= (int)0x80808080u;  // qu - 128 as a signed byte
       }
       sB[n][t][l] = v;
     }
     __syncthreads();
-    // this lane's query (column lane & 15 of each 16-query tile): scalars in
-    // registers for the whole item; an empty slot gets a NaN threshold
-    float qrn2[GMAX / 16], qvl[GMAX / 16], qdelta[GMAX / 16], qthr[GMAX / 16];
-    int qsum[GMAX / 16];
+    // this lane's query (column lane & 15 of each 16-query tile): its B
+    // operands and scalars in registers for the whole item; an empty slot
+    // gets a NaN threshold
+    v4i Bq[GT][KS];
+    float qrn2[GT], qvl[GT], qdelta[GT], qthr[GT];
+    int qneg[GT];
 #pragma unroll
-    for (int n = 0; n < GMAX / 16; ++n) {
+    for (int n = 0; n < GT; ++n) {
       const int q = 16 * n + (lane & 15);
       const float4 sc = sSc[q];
       qrn2[n] = sc.x;
       qvl[n] = sc.y;
       qdelta[n] = sc.z;
-      qsum[n] = -(int)sc.w;  // negated: the estimate adds it
+      qneg[n] = -(int)sc.w;
       qthr[n] = q < count ? sThr[q] : NAN;
+#pragma unroll
+      for (int t = 0; t < KS; ++t) Bq[n][t] = sB[n][t][lane];
     }
     const int len = a.L.list_len[j], mb0 = a.L.list_mb[j];
     const int nmb = (len + 63) >> 6;
@@ -242,6 +271,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
           pop += __popc(cw[w]);
         }
         sVx[wave][lane] = rbq_vx(fm, pop, D);
+        if (QB == QB_OFFSET) sPop[wave][lane] = pop << 7;
         const bool valid = (mb << 6) + lane < len;
         sAdd[wave][lane] = valid ? fa : NAN;
         sMul[wave][lane] = fm;
@@ -258,6 +288,19 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
           const uint32_t word = sCode[wave][2 * t + (lg >> 1)][vrow];
           A[t] = unpack16((word >> (16 * (lg & 1))) & 0xFFFFu);
         }
+        // every query tile's products first, then the epilogues
+        v4i c0 = {0, 0, 0, 0};
+        if (QB == QB_OFFSET) c0 = *reinterpret_cast<const v4i*>(&sPop[QB == QB_OFFSET ? wave : 0][16 * m + 4 * lg]);
+        v4i acc[GT];
+#pragma unroll
+        for (int n = 0; n < GT; ++n) {
+          if (n < nt) {
+            v4i c = c0;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) c = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t], Bq[n][t], c, 0, 0, 0);
+            acc[n] = c;
+          }
+        }
         // the four vectors of this lane's result rows: 16 m + 4 lg + r
         const float4 fadd4 = *reinterpret_cast<const float4*>(&sAdd[wave][16 * m + 4 * lg]);
         const float4 vx4 = *reinterpret_cast<const float4*>(&sVx[wave][16 * m + 4 * lg]);
@@ -268,26 +311,23 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
         // position in the list of this lane's first result row
         const uint32_t rel0 = (uint32_t)((mb << 6) + 16 * m + 4 * lg);
 #pragma unroll
-        for (int n = 0; n < GMAX / 16; ++n) {
+        for (int n = 0; n < GT; ++n) {
           if (n >= nt) break;
-          v4i acc = {0, 0, 0, 0};
-#pragma unroll
-          for (int t = 0; t < KS; ++t)
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t], sB[n][t][lane], acc, 0, 0, 0);
           float est[4];
           bool pass[4];
           bool anyp = false;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            est[r] = rbq_estimate(qrn2[n], qvl[n], qdelta[n], qsum[n], acc[r], fadd[r], fmul[r], vxr[r]);
+            const int g = (QB == QB_DOUBLE ? acc[n][r] : acc[n][r] << 1) + qneg[n];
+            est[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
             pass[r] = est[r] <= qthr[n];  // NaN (padding lanes, empty slots) never passes
             anyp |= pass[r];
           }
-          if (__ballot(anyp)) {  // stage the survivors of this tile
+          if (__builtin_amdgcn_ballot_w64(anyp)) {  // stage the survivors of this tile
             const uint32_t tag = rel0 | ((uint32_t)(16 * n + (lane & 15)) << 26);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const uint64_t mask = __ballot(pass[r]);
+              const uint64_t mask = __builtin_amdgcn_ballot_w64(pass[r]);
               if (pass[r]) {
                 const int e = stage_n + (int)lane_prefix(mask);
                 sStage[wave][e] = ((uint64_t)__float_as_uint(est[r]) << 32) | (tag + (uint32_t)r);
@@ -311,21 +351,22 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   }
 }
 
-void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, int p0, int pn,
+void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
                       int nlist, int G, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
                       int32_t* fill, int32_t* slots, int4* items) {
-  const int64_t pairs = (int64_t)nq * pn;
-  RBQ_HIP(hipMemsetAsync(cnt, 0, nlist * sizeof(int32_t), s));
+  RBQ_CHECK(gc.nb >= 1 && gc.nb <= kMaxGroupChunks && gc.bound[gc.nb] == nprobe,
+            "list-major chunk bounds");
+  const int64_t pairs = (int64_t)nq * (nprobe - gc.bound[0]);
+  if (pairs <= 0) return;
+  // (cnt was cleared by the search's state initialisation)
   hipLaunchKernelGGL(k_grp_hist, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, probes, nq,
-                     nprobe, p0, pn, cnt);
+                     nprobe, gc, nlist, cnt);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_offsets, dim3(1), dim3(256), 0, s, cnt, nlist, G, pair_off, item_off, fill);
-  RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_items, dim3((nlist + 255) / 256), dim3(256), 0, s, cnt, pair_off, item_off,
-                     nlist, G, items);
+  hipLaunchKernelGGL(k_grp_offsets, dim3(1), dim3(1024), 0, s, cnt, gc.nb * nlist, nlist, G, pair_off,
+                     item_off, fill, items);
   RBQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_grp_scatter, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, probes,
-                     nq, nprobe, p0, pn, pair_off, fill, slots);
+                     nq, nprobe, gc, nlist, pair_off, fill, slots);
   RBQ_HIP(hipGetLastError());
 }
 
@@ -335,12 +376,30 @@ void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups) {
   RBQ_CHECK(a.G >= 1 && a.G <= GMAX, "group size out of range");
   const int ks = group_k_steps(a.L.d);
   RBQ_CHECK(ks <= KSMAX, "grouped scan supports d <= 256");
-  switch (ks) {
-    case 1: hipLaunchKernelGGL(k_scan_group<1>, dim3(workgroups), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_scan_group<2>, dim3(workgroups), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_scan_group<3>, dim3(workgroups), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_scan_group<4>, dim3(workgroups), dim3(256), 0, s, a); break;
+  RBQ_CHECK(a.bq >= 1 && a.bq <= 8, "query bits out of range");
+  const int qb = a.bq <= 6 ? QB_DOUBLE : a.bq == 7 ? QB_PLAIN : QB_OFFSET;
+  const bool two = a.G <= 32;
+#define RBQ_GROUP_LAUNCH_QB(K, QBV)                                                           \
+  if (two)                                                                                  \
+    hipLaunchKernelGGL((k_scan_group<K, QBV, 2>), dim3(workgroups), dim3(256), 0, s, a);    \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_scan_group<K, QBV, 4>), dim3(workgroups), dim3(256), 0, s, a)
+#define RBQ_GROUP_LAUNCH(K)                 \
+  if (qb == QB_DOUBLE) {                    \
+    RBQ_GROUP_LAUNCH_QB(K, QB_DOUBLE);      \
+  } else if (qb == QB_PLAIN) {              \
+    RBQ_GROUP_LAUNCH_QB(K, QB_PLAIN);       \
+  } else {                                  \
+    RBQ_GROUP_LAUNCH_QB(K, QB_OFFSET);      \
   }
+  switch (ks) {
+    case 1: RBQ_GROUP_LAUNCH(1); break;
+    case 2: RBQ_GROUP_LAUNCH(2); break;
+    case 3: RBQ_GROUP_LAUNCH(3); break;
+    default: RBQ_GROUP_LAUNCH(4); break;
+  }
+#undef RBQ_GROUP_LAUNCH
+#undef RBQ_GROUP_LAUNCH_QB
   RBQ_HIP(hipGetLastError());
 }
 

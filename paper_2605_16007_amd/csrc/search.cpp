@@ -104,6 +104,7 @@ struct Plan {
   int64_t cand_ld = 0, pool_cap = 0;
   bool need_qcopy = true, ids_dev = false, dist_dev = false;
   bool inj_probes = false, inj_qu = false, dumps = false, mixed = false, any_group = false;
+  GroupChunks gc;  // the list-major chunks (a suffix of the probe ranks)
   int G = 64, wg_per_cu = 8;
   const rbq_debug_io* dbg = nullptr;
   std::vector<Chunk> chunks, qm_chunks;
@@ -150,7 +151,7 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
       1, std::min<int64_t>(nprobe, budget / std::max<int64_t>(1, nq * R * 8) - 1));
   P.first = (int)std::min<int64_t>(P.pch, std::max<int64_t>(1, (2048 + nq - 1) / nq));
   if (dbg && dbg->probe_chunk > 0) P.pch = P.first = std::min(P.pch, (int)dbg->probe_chunk);
-  P.cand_ld = (int64_t)R * (1 + P.pch);
+
   // launch choices: forced (autotuner trial), else tuned for this batch shape,
   // else the built-in rule; an explicit RBQ_OPT_SCAN wins over a tuned form
   TuneCfg cfg;
@@ -177,7 +178,12 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   } else if (opt == 0) {
     scan_mode = 2;
   }
+  // a pool holds a query-major chunk's R keys per probe, and at least the
+  // longest list (a first list-major chunk, taken before any threshold, then
+  // fits) when the budget allows
   P.pool_cap = (int64_t)R * P.pch;
+  if (P.maxlen > P.pool_cap && nq * (R + P.maxlen) * 8 <= budget) P.pool_cap = P.maxlen;
+  P.cand_ld = R + P.pool_cap;
   if (idx->opt_pool_cap.load() > 0) P.pool_cap = std::min<int64_t>(P.pool_cap, idx->opt_pool_cap.load());
   for (int p0 = 0, pn = P.first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, P.pch)) {
     pn = std::min(pn, nprobe - p0);
@@ -199,7 +205,8 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
     for (int p0 = 0; p0 < nprobe; p0 += pn, pn = std::max(pn, (cfg.growth - 1) * p0)) {
       pn = std::min(pn, nprobe - p0);
       const int64_t chunk_pairs = scanned_pairs * pn / std::max(1, nprobe);
-      const bool lm = chunk_pairs >= (int64_t)gm * idx->nlist;
+      // (once list-major, always: the chunk cut at nprobe may be the smaller)
+      const bool lm = chunk_pairs >= (int64_t)gm * idx->nlist || (!P.chunks.empty() && P.chunks.back().lm);
       if (lm) {
         P.chunks.push_back({p0, pn, true, false});
         P.any_group = true;
@@ -219,6 +226,23 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   } else {
     P.chunks = P.qm_chunks;
   }
+  if (P.any_group) {
+    // list-major chunks grow with the scanned prefix, so they form a suffix of
+    // the ranks; past kMaxGroupChunks of them the last one takes the rest
+    size_t f = 0;
+    while (!P.chunks[f].lm) ++f;
+    if (P.chunks.size() - f > (size_t)kMaxGroupChunks) {
+      Chunk& last = P.chunks[f + kMaxGroupChunks - 1];
+      last.pn = nprobe - last.p0;
+      P.chunks.resize(f + kMaxGroupChunks);
+    }
+    P.gc.nb = 0;
+    for (size_t c = f; c < P.chunks.size(); ++c) {
+      RBQ_CHECK(P.chunks[c].lm, "list-major chunks must be a suffix of the probe ranks");
+      P.gc.bound[P.gc.nb++] = P.chunks[c].p0;
+    }
+    P.gc.bound[P.gc.nb] = nprobe;
+  }
   return P;
 }
 
@@ -234,14 +258,15 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   b.planes = c.take<uint32_t>((size_t)pairs * W * idx->bqs);
   if ((dbg && dbg->qu) || P.any_group) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
   if (P.any_group) {
-    b.gcnt = c.take<int32_t>(nlist);
-    b.gfill = c.take<int32_t>(nlist);
-    b.pair_off = c.take<int32_t>(nlist + 1);
-    b.item_off = c.take<int32_t>(nlist + 1);
+    const int64_t bins = (int64_t)P.gc.nb * nlist;
+    b.gcnt = c.take<int32_t>(bins);
+    b.gfill = c.take<int32_t>(bins);
+    b.pair_off = c.take<int32_t>(bins + 1);
+    b.item_off = c.take<int32_t>(bins + 1);
     b.slots = c.take<int32_t>(pairs);
-    b.items = c.take<int4>(pairs / P.G + nlist + 1);
+    b.items = c.take<int4>(pairs / P.G + bins + 1);
     b.overflow = c.take<uint32_t>(nq);
-    b.counter = c.take<uint32_t>(2);
+    b.counter = c.take<uint32_t>(1 + kMaxGroupChunks);  // overflow flag, item cursors
   }
   b.scal = c.take<float4>(pairs);
   if (P.inj_qu) {
@@ -284,6 +309,42 @@ struct HostJob {
   uint64_t* cand = nullptr;  // nq x R keys (written by the search)
   float* qh = nullptr;       // nq x d queries (written by the search when it has them on the device)
   hipEvent_t ready = nullptr;
+};
+
+// Pinned host memory from the index's free list (returned on destruction).
+struct Pinned {
+  rbq_index* idx;
+  void* p = nullptr;
+  size_t cap = 0;
+  Pinned(rbq_index* ix, size_t bytes) : idx(ix) {
+    {
+      std::lock_guard<std::mutex> g(idx->host_mu);
+      size_t best = (size_t)-1;
+      for (size_t i = 0; i < idx->pinned_free.size(); ++i)
+        if (idx->pinned_free[i].second >= bytes &&
+            (best == (size_t)-1 || idx->pinned_free[i].second < idx->pinned_free[best].second))
+          best = i;
+      if (best != (size_t)-1) {
+        p = idx->pinned_free[best].first;
+        cap = idx->pinned_free[best].second;
+        idx->pinned_free.erase(idx->pinned_free.begin() + best);
+        return;
+      }
+    }
+    RBQ_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    cap = bytes;
+  }
+  ~Pinned() {
+    std::lock_guard<std::mutex> g(idx->host_mu);
+    idx->pinned_free.emplace_back(p, cap);
+  }
+};
+
+// An event that lives for one scope.
+struct ScopedEvent {
+  hipEvent_t e = nullptr;
+  ScopedEvent() { RBQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+  ~ScopedEvent() { (void)hipEventDestroy(e); }
 };
 
 void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
@@ -402,7 +463,6 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       RBQ_HIP(hipMemcpyAsync(b.inj_scal, dbg->inject_scalars, (size_t)pairs * 3 * sizeof(float),
                              hipMemcpyHostToDevice, s));
     }
-    launch_fill_u32(s, b.qthr, 0xFFFFFFFFu, nq);
     if (dumps) {
       RBQ_HIP(hipMemsetAsync(b.dump_ip, 0, (size_t)pairs * maxlen * sizeof(int32_t), s));
       RBQ_HIP(hipMemsetAsync(b.dump_est, 0, (size_t)pairs * maxlen * sizeof(float), s));
@@ -426,9 +486,29 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     sa.dump_ip = b.dump_ip;
     sa.dump_est = b.dump_est;
     sa.maxlen = maxlen;
-    launch_fill_rows_u64(s, b.cand, cand_ld, nq, R, KEY_NONE);  // running top-R starts empty
-    launch_fill_u32(s, b.pcnt, 0u, nq);
-    if (any_group) launch_fill_u32(s, b.overflow, 0u, nq);
+    {
+      // running top-R rows empty, thresholds open, pools empty; the list-major
+      // bins and cursors cleared
+      SearchInit si;
+      si.cand = b.cand;
+      si.cand_ld = cand_ld;
+      si.nq = (int)nq;
+      si.R = R;
+      si.qthr = b.qthr;
+      si.pcnt = b.pcnt;
+      if (any_group) {
+        si.overflow = b.overflow;
+        si.z0 = b.counter;
+        si.n0 = 1 + kMaxGroupChunks;
+        si.z1 = reinterpret_cast<uint32_t*>(b.gcnt);
+        si.n1 = (int64_t)P.gc.nb * nlist;
+      }
+      launch_search_init(s, si);
+    }
+    // the (chunk, list) -> pairs map of every list-major chunk
+    if (any_group)
+      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, b.gcnt, b.pair_off, b.item_off,
+                       b.gfill, b.slots, b.items);
     sa.pcnt = b.pcnt;
     sa.qmask = nullptr;
     GroupArgs ga;
@@ -440,12 +520,12 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     ga.R = R;
     ga.nlist = nlist;
     ga.G = P.G;
+    ga.bq = idx->bq;
     ga.slots = b.slots;
     ga.pair_off = b.pair_off;
     ga.item_off = b.item_off;
     ga.items = b.items;
-    ga.item_counter = b.counter;
-    ga.any_overflow = b.counter + 1;
+    ga.any_overflow = b.counter;
     ga.qthr = b.qthr;
     ga.pool = b.cand;
     ga.pool_ld = cand_ld;
@@ -488,10 +568,12 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       ma.max_extra = R * ch.pn;
       launch_row_topk(s, ma, (int)nq);
     };
+    int lm_chunk = 0;  // index of the next list-major chunk
     auto scan_group_chunk = [&](const Chunk& ch) {
-      launch_group_map(s, b.probes, (int)nq, nprobe, ch.p0, ch.pn, nlist, ga.G, b.gcnt, b.pair_off,
-                       b.item_off, b.gfill, b.slots, b.items);
-      launch_fill_u32(s, b.counter, 0u, 1);
+      const int c = lm_chunk++;
+      RBQ_CHECK(c < P.gc.nb && P.gc.bound[c] == ch.p0, "list-major chunk order");
+      ga.item_off = b.item_off + (int64_t)c * nlist;
+      ga.item_counter = b.counter + 1 + c;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {
         e0 = newev();
@@ -510,7 +592,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
           hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
                              idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 0,
                              tc + 2 * part);
-          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s, b.gcnt,
+          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s, b.gcnt + (int64_t)c * nlist,
                              idx->list_len.as<int32_t>(), nlist, ga.G, rec_bytes, tc + 2 * part + 1);
         }
         RBQ_HIP(hipGetLastError());
@@ -518,7 +600,6 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       ma.max_extra = (int)pool_cap;
       launch_row_topk(s, ma, (int)nq);
     };
-    if (any_group) launch_fill_u32(s, b.counter + 1, 0u, 1);
     FusedArgs fa;
     fa.L = sa.L;
     fa.Q = sa.Q;
@@ -561,51 +642,71 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       else
         scan_popc_chunk(ch);
     }
-    if (any_group) {
-      // one check per search: queries whose pool overflowed in a list-major
-      // chunk are searched again, from scratch, by the query-major scan
-      uint32_t any = 0;
-      RBQ_HIP(hipMemcpyAsync(&any, b.counter + 1, sizeof(any), hipMemcpyDeviceToHost, s));
-      RBQ_HIP(hipStreamSynchronize(s));
-      if (any) {
-        launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
-        sa.qmask = b.overflow;
-        for (const auto& ch : qm_chunks) scan_popc_chunk(ch);
-        sa.qmask = nullptr;
-      }
-    }
-    const uint64_t* top = b.cand;
-    if (dbg && (dbg->cand_ids || dbg->cand_est)) {  // the debug output lists candidates ascending
-      TopkArgs so;
-      so.keys = b.cand;
-      so.ld = cand_ld;
-      so.ncols = R;
-      so.k = R;
-      so.out_keys = b.cand;
-      so.ldo = cand_ld;
-      so.rowk = d_R;
-      launch_row_topk(s, so, (int)nq);
-    }
-    mark(4);
     int64_t* ids_out = ids_dev ? ids : b.ids;
     float* dist_out = dist_dev ? dist : b.dist;
-    if (job) {
-      // Phase 5 on host cores: hand the candidates (and the queries, if they
-      // are only on the device) over in pinned memory
-      RBQ_HIP(hipMemcpy2DAsync(job->cand, R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
-                               R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
-      if (qdev)
-        RBQ_HIP(hipMemcpy2DAsync(job->qh, d * sizeof(float), qd, (need_qcopy ? ld : d) * sizeof(float),
-                                 d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
-      RBQ_HIP(hipEventRecord(job->ready, s));
-    } else {
-      // Phase 5: exact re-rank of the top-R on the GPU
+    const uint64_t* top = b.cand;
+    auto rerank_on_gpu = [&]() {  // Phase 5: exact re-rank of the top-R on the GPU
       if (idx->X8.p)
         launch_rerank_u8(s, qd, ld, idx->X8.as<uint8_t>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
                          ids_out, dist_out, d_k);
       else
         launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
                       ids_out, dist_out, d_k);
+    };
+    // queries whose pool overflowed in a list-major chunk are searched again,
+    // from scratch, by the query-major scan; the host reads one flag per search
+    auto redo_overflowed = [&]() {
+      launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
+      sa.qmask = b.overflow;
+      for (const auto& ch : qm_chunks) scan_popc_chunk(ch);
+      sa.qmask = nullptr;
+    };
+    if (any_group && !job && !dbg) {
+      // the re-rank is queued before the flag is read (an overflow is rare),
+      // so the GPU never waits for the host here; after an overflow the
+      // redone queries are re-ranked again
+      Pinned flag(idx, sizeof(uint32_t));
+      ScopedEvent flag_ev;
+      RBQ_HIP(hipMemcpyAsync(flag.p, b.counter, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      RBQ_HIP(hipEventRecord(flag_ev.e, s));
+      mark(4);
+      rerank_on_gpu();
+      RBQ_HIP(hipEventSynchronize(flag_ev.e));
+      if (*static_cast<const uint32_t*>(flag.p)) {
+        redo_overflowed();
+        rerank_on_gpu();
+      }
+    } else {
+      if (any_group) {
+        uint32_t any = 0;
+        RBQ_HIP(hipMemcpyAsync(&any, b.counter, sizeof(any), hipMemcpyDeviceToHost, s));
+        RBQ_HIP(hipStreamSynchronize(s));
+        if (any) redo_overflowed();
+      }
+      if (dbg && (dbg->cand_ids || dbg->cand_est)) {  // the debug output lists candidates ascending
+        TopkArgs so;
+        so.keys = b.cand;
+        so.ld = cand_ld;
+        so.ncols = R;
+        so.k = R;
+        so.out_keys = b.cand;
+        so.ldo = cand_ld;
+        so.rowk = d_R;
+        launch_row_topk(s, so, (int)nq);
+      }
+      mark(4);
+      if (job) {
+        // Phase 5 on host cores: hand the candidates (and the queries, if they
+        // are only on the device) over in pinned memory
+        RBQ_HIP(hipMemcpy2DAsync(job->cand, R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
+                                 R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
+        if (qdev)
+          RBQ_HIP(hipMemcpy2DAsync(job->qh, d * sizeof(float), qd, (need_qcopy ? ld : d) * sizeof(float),
+                                   d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
+        RBQ_HIP(hipEventRecord(job->ready, s));
+      } else {
+        rerank_on_gpu();
+      }
     }
     mark(5);
 
@@ -661,35 +762,6 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     }
   }
 }
-
-// Pinned host staging for the host re-rank, cached by the index.
-struct Pinned {
-  rbq_index* idx;
-  void* p = nullptr;
-  size_t cap = 0;
-  Pinned(rbq_index* ix, size_t bytes) : idx(ix) {
-    {
-      std::lock_guard<std::mutex> g(idx->host_mu);
-      size_t best = (size_t)-1;
-      for (size_t i = 0; i < idx->pinned_free.size(); ++i)
-        if (idx->pinned_free[i].second >= bytes &&
-            (best == (size_t)-1 || idx->pinned_free[i].second < idx->pinned_free[best].second))
-          best = i;
-      if (best != (size_t)-1) {
-        p = idx->pinned_free[best].first;
-        cap = idx->pinned_free[best].second;
-        idx->pinned_free.erase(idx->pinned_free.begin() + best);
-        return;
-      }
-    }
-    RBQ_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
-    cap = bytes;
-  }
-  ~Pinned() {
-    std::lock_guard<std::mutex> g(idx->host_mu);
-    idx->pinned_free.emplace_back(p, cap);
-  }
-};
 
 ThreadPool& host_pool(rbq_index* idx) {
   std::lock_guard<std::mutex> g(idx->host_mu);

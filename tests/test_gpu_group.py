@@ -26,6 +26,10 @@ SHAPES = [
     ("g40_bq8", 9_000, 40, 10, 90, 7, 5, 40, "mixture", 8),
     ("g13", 4_000, 13, 8, 33, 6, 5, 30, "mixture", 2),
     ("g256", 6_000, 256, 8, 40, 5, 10, 80, "gamma_int", 4),
+    # the three ways qu enters the signed-byte MFMA: doubled (B_q <= 6),
+    # plain (B_q = 7), offset by -128 (B_q = 8, above)
+    ("g72_bq6", 8_000, 72, 10, 80, 6, 5, 40, "mixture", 6),
+    ("g64_bq7", 8_000, 64, 10, 80, 6, 5, 40, "mixture", 7),
 ]
 
 
@@ -44,12 +48,22 @@ def gcase(request):
     return dict(name=name, X=X, Q=Q, idx=idx, lib=lib, nprobe=nprobe, k=k, R=R, d=d)
 
 
-def _run(lib, Q, nprobe, k, R, scan, pool_cap=0, **kw):
+def _run(lib, Q, nprobe, k, R, scan, pool_cap=0, lm_only=False, **kw):
+    """lm_only: the list-major scan produced every result itself (scan 2 with
+    no pool overflow, so no query was redone by the query-major scan)."""
     lib.set_option("scan", scan)
     lib.set_option("pool_cap", pool_cap)
+    if lm_only:
+        lib.set_timing(True)
     try:
-        return lib.search_debug(Q, nprobe, k, R, want=WANT, **kw)
+        out = lib.search_debug(Q, nprobe, k, R, want=WANT, **kw)
+        if lm_only:
+            t = lib.timings()
+            assert t["group_launches"] > 0 and t["popc_launches"] == 0, t
+        return out
     finally:
+        if lm_only:
+            lib.set_timing(False)
         lib.set_option("scan", 0)
         lib.set_option("pool_cap", 0)
 
@@ -57,7 +71,7 @@ def _run(lib, Q, nprobe, k, R, scan, pool_cap=0, **kw):
 def test_group_equals_query_major(gcase):
     lib, Q = gcase["lib"], gcase["Q"]
     a = _run(lib, Q, gcase["nprobe"], gcase["k"], gcase["R"], scan=1)
-    b = _run(lib, Q, gcase["nprobe"], gcase["k"], gcase["R"], scan=2)
+    b = _run(lib, Q, gcase["nprobe"], gcase["k"], gcase["R"], scan=2, lm_only=True)
     for key in WANT:
         np.testing.assert_array_equal(b[key], a[key], err_msg=key)
 
@@ -84,7 +98,8 @@ def test_group_candidates_match_oracle(gcase):
         for p in range(nprobe):
             qu[qi, p] = st["qu"][qi][p]
             sc[qi, p] = (st["rnorm2"][qi][p], st["vl"][qi][p], st["delta"][qi][p])
-    out = _run(lib, Q, nprobe, k, R, scan=2, inject_probes=probes, inject_qu=qu, inject_scalars=sc)
+    out = _run(lib, Q, nprobe, k, R, scan=2, lm_only=True, inject_probes=probes, inject_qu=qu,
+               inject_scalars=sc)
     for qi in range(nq):
         val, tol = {}, {}
         for p, pl in enumerate(st["per_list"][qi]):
