@@ -493,6 +493,196 @@ __global__ __launch_bounds__(NT) void k_row_topk(TopkArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Pool merge: the same selection for a query's candidate row in pool mode
+// (k running keys, then rowcnt[row] new ones; the k smallest are written, in
+// any order, to the row's first k slots). The row is held in registers, KPT
+// keys per thread, in pieces of NT * KPT keys (one piece for rows up to that
+// size, read once; larger rows are re-read per pass, and the first piece,
+// which holds the output slots, is always read before any write). Histogram
+// counts are fire-and-forget LDS atomics; the output positions come from one
+// workgroup scan per piece (keys below the boundary digit, then boundary keys
+// up to k). Small LDS and registers: two workgroups per CU.
+// ---------------------------------------------------------------------------
+
+// Exclusive scan of v over a workgroup of NT threads; *total = the sum.
+// wsum: NT/64 words of LDS.
+template <int NT>
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(x, off);
+    if (lane >= off) x += t;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t t = wsum[w];
+    before += w < wave ? t : 0u;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+template <int NT, int KPT>
+__global__ __launch_bounds__(NT) void k_pool_merge(TopkArgs a) {
+  constexpr int NW = NT / 64;
+  constexpr int NH = 4;  // histogram copies (wave w uses copy w % NH)
+  constexpr int PIECE = NT * KPT;
+  __shared__ uint32_t hist[NH][256];
+  __shared__ uint32_t wsum[NW > 4 ? NW : 4];
+  __shared__ uint32_t s_digit, s_rem, s_bucket;
+  __shared__ uint64_t s_lo[NW], s_hi[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row = blockIdx.x;
+  const uint32_t extra = min(a.rowcnt[row], (uint32_t)a.max_extra);
+  if (extra == 0) return;
+  const int k = a.rowk ? a.rowk[row] : a.k;
+  const int ncols = a.k + (int)extra;
+  const uint64_t* src = a.keys + row * a.ld;
+  uint64_t* dst = a.out_keys + row * a.ldo;
+  const bool one = ncols <= PIECE;
+  uint64_t v[KPT];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+      const int c = p0 + u * NT + tid;
+      v[u] = c < ncols ? src[c] : KEY_NONE;
+    }
+  };
+  // (slots past ncols read as KEY_NONE and are never counted or written:
+  // every count below is over c < ncols)
+  auto valid = [&](int p0, int u) { return p0 + u * NT + tid < ncols; };
+
+  // smallest and largest key
+  uint64_t lo = ~0ull, hi = 0;
+  for (int p0 = 0; p0 < ncols; p0 += PIECE) {
+    load(p0);
+#pragma unroll
+    for (int u = 0; u < KPT; ++u)
+      if (valid(p0, u)) {
+        lo = v[u] < lo ? v[u] : lo;
+        hi = v[u] > hi ? v[u] : hi;
+      }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (lane == 0) {
+    s_lo[wave] = lo;
+    s_hi[wave] = hi;
+  }
+  __syncthreads();
+  lo = s_lo[0];
+  hi = s_hi[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    lo = s_lo[w] < lo ? s_lo[w] : lo;
+    hi = s_hi[w] > hi ? s_hi[w] : hi;
+  }
+  // MSB-first radix select from the highest bit in which the keys differ
+  uint64_t prefix = 0, pmask = 0;
+  uint32_t rem = (uint32_t)k;
+  const uint64_t diff = lo ^ hi;
+  const int top = diff ? 63 - __clzll((long long)diff) : -1;
+  if (top < 63) {
+    pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
+    prefix = lo & pmask;
+  }
+  for (int hb = top; hb >= 0;) {
+    const int lb = hb >= 7 ? hb - 7 : 0;
+    const uint64_t dmask = (2ull << (hb - lb)) - 1ull;
+    for (int t = tid; t < NH * 256; t += NT) (&hist[0][0])[t] = 0u;
+    __syncthreads();
+    uint32_t* hw = hist[wave % NH];
+    for (int p0 = 0; p0 < ncols; p0 += PIECE) {
+      if (!one) load(p0);
+#pragma unroll
+      for (int u = 0; u < KPT; ++u)
+        if (valid(p0, u) && (v[u] & pmask) == prefix) atomicAdd(&hw[(v[u] >> lb) & dmask], 1u);
+    }
+    __syncthreads();
+    uint32_t h = 0;
+    if (tid < 256)
+#pragma unroll
+      for (int t = 0; t < NH; ++t) h += hist[t][tid];
+    const uint32_t incl = hist_incl_scan<NT>(h, wsum);
+    const uint32_t excl = incl - h;
+    if (tid < 256 && excl < rem && rem <= incl) {
+      s_digit = (uint32_t)tid;
+      s_rem = rem - excl;
+      s_bucket = h;
+    }
+    __syncthreads();
+    prefix |= (uint64_t)s_digit << lb;
+    pmask |= dmask << lb;
+    rem = s_rem;
+    const uint32_t bucket = s_bucket;
+    __syncthreads();
+    if (bucket == rem) break;
+    hb = lb - 1;
+  }
+  // compaction: keys below the boundary bucket fill [0, k - rem); boundary
+  // keys fill [k - rem, k) in arrival order until rem are taken
+  const uint64_t hi_key = prefix | ~pmask;
+  const uint32_t nlt = (uint32_t)k - rem;
+  uint32_t base_lt = 0, base_eq = 0;
+  uint64_t mx = 0;
+  if (!one) load(0);  // the first piece holds every output slot: read before any write
+  __syncthreads();
+  for (int p0 = 0; p0 < ncols; p0 += PIECE) {
+    if (!one && p0 > 0) load(p0);
+    uint32_t clt = 0, ceq = 0;
+#pragma unroll
+    for (int u = 0; u < KPT; ++u)
+      if (valid(p0, u)) {
+        clt += v[u] < prefix ? 1u : 0u;
+        ceq += (v[u] >= prefix && v[u] <= hi_key) ? 1u : 0u;
+      }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<NT>((clt << 16) | ceq, wsum, &tot);
+    uint32_t plt = base_lt + (ex >> 16), peq = base_eq + (ex & 0xFFFFu);
+#pragma unroll
+    for (int u = 0; u < KPT; ++u)
+      if (valid(p0, u)) {
+        if (v[u] < prefix) {
+          dst[plt++] = v[u];
+          mx = v[u] > mx ? v[u] : mx;
+        } else if (v[u] <= hi_key) {
+          if (peq < rem) {
+            dst[nlt + peq] = v[u];
+            mx = v[u] > mx ? v[u] : mx;
+          }
+          ++peq;
+        }
+      }
+    base_lt += tot >> 16;
+    base_eq += tot & 0xFFFFu;
+  }
+  // the k-th smallest key is the largest one written
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if (lane == 0) s_hi[wave] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t kth = s_hi[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) kth = s_hi[w] > kth ? s_hi[w] : kth;
+    a.rowcnt[row] = 0;
+    if (a.qthr && kth != KEY_NONE) atomicMin(&a.qthr[row], (uint32_t)(kth >> 32));
+  }
+}
+
 static int pow2_at_least(int n) {
   int p = 2;
   while (p < n) p <<= 1;
@@ -528,7 +718,13 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
                           reinterpret_cast<const void*>(k_row_topk<false, 1024>)})
       RBQ_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTopkLdsMax));
   });
-  // pool merges (long rows, one workgroup per CU for the LDS) run 16 waves
+  // pool merges: the register-resident kernel
+  if (a.rowcnt && !a.sorted) {
+    RBQ_CHECK(a.k <= 512 * 32, "pool merge: running keys exceed one piece");
+    hipLaunchKernelGGL((k_pool_merge<512, 32>), dim3(rows), dim3(512), 0, s, a);
+    RBQ_HIP(hipGetLastError());
+    return;
+  }
   if (a.score)
     hipLaunchKernelGGL((k_row_topk<true, 256>), dim3(rows), dim3(256), lds, s, a);
   else if (a.rowcnt)
