@@ -1448,7 +1448,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   // 16 lanes per candidate, RU candidates per slot in flight: in round r, wave
   // w, slot s takes candidates 16 (RU r + u) + 4 w + s; each slot rewrites only
   // its own keys
-  constexpr int RU = 4;
+  constexpr int RU = 8;
   for (int c0 = 0; c0 < R; c0 += 16 * RU) {
     uint64_t key[RU];
     size_t row[RU];

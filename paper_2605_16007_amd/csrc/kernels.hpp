@@ -140,9 +140,10 @@ struct GroupChunks {
   int nb = 0;
   int bound[kMaxGroupChunks + 1] = {};
 };
-// Pairs of every list-major chunk grouped by (chunk, list): cnt, pair_off,
-// item_off and fill hold nb * nlist bins (+1 for the offsets); cnt must be
-// zero on entry.
+// Pairs of every list-major chunk grouped by (chunk, list): pair_off and
+// item_off hold nb * nlist + 1 offsets; the counters cnt and fill hold one
+// word per bin every kGroupBinPad words (cnt zero on entry).
+constexpr int kGroupBinPad = 16;
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
                       int nlist, int G, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
                       int32_t* fill, int32_t* slots, int4* items);

@@ -30,7 +30,9 @@ constexpr int STAGE = 512; // survivors staged per wave before a flush
 
 // ---- inverted map of the list-major chunks' pairs: list -> pairs ----------
 // Built once per search for all list-major chunks (a suffix of the probe
-// ranks): bin c * nlist + j holds the pairs of chunk c that probe list j.
+// ranks): bin c * nlist + j holds the pairs of chunk c that probe list j. The
+// per-bin counters sit kGroupBinPad words apart (one cache line each), so that
+// the atomics of a popular list do not serialise the lists that share its line.
 
 __device__ inline int group_chunk_of(const GroupChunks& gc, int p) {
   int c = 0;
@@ -46,58 +48,70 @@ __global__ void k_grp_hist(const int32_t* __restrict__ probes, int nq, int nprob
   const int64_t i = t / span;
   const int p = gc.bound[0] + (int)(t - i * span);
   const int j = probes[i * nprobe + p];
-  if (j >= 0) atomicAdd(&cnt[group_chunk_of(gc, p) * nlist + j], 1);  // (-1: fewer probes)
+  if (j >= 0) atomicAdd(&cnt[(int64_t)(group_chunk_of(gc, p) * nlist + j) * kGroupBinPad], 1);
 }
 
 // Exclusive prefix sums over the bins of the pair counts and of the item
 // counts ceil(cnt / G), the item descriptors (list, first slot, pairs), and
-// cleared scatter cursors; one workgroup of 1024 threads, each over a
-// contiguous range of bins.
+// cleared scatter cursors; one workgroup of 1024 threads, 1024 bins per round
+// (eight rounds' counts loaded at once).
 __global__ __launch_bounds__(1024) void k_grp_offsets(const int32_t* __restrict__ cnt, int bins, int nlist,
                                                       int G, int32_t* __restrict__ pair_off,
                                                       int32_t* __restrict__ item_off,
                                                       int32_t* __restrict__ fill, int4* __restrict__ items) {
   __shared__ int32_t wp[16], wi[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int per = (bins + 1023) / 1024;
-  const int b0 = min(bins, tid * per), b1 = min(bins, b0 + per);
-  int32_t ps = 0, is = 0;
-  for (int b = b0; b < b1; ++b) {
-    const int32_t c = cnt[b];
-    ps += c;
-    is += (c + G - 1) / G;
-  }
-  int32_t xp = ps, xi = is;  // inclusive scans within the wave
-  for (int off = 1; off < 64; off <<= 1) {
-    const int32_t tp = __shfl_up(xp, off), ti = __shfl_up(xi, off);
-    if (lane >= off) {
-      xp += tp;
-      xi += ti;
+  const int rounds = (bins + 1023) / 1024;
+  int32_t carry_p = 0, carry_i = 0;
+  for (int r0 = 0; r0 < rounds; r0 += 8) {
+    int32_t cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = (r0 + u) * 1024 + tid;
+      cv[u] = b < bins ? cnt[(int64_t)b * kGroupBinPad] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (r0 + u >= rounds) break;
+      const int b = (r0 + u) * 1024 + tid;
+      const int32_t c = cv[u], ni = (c + G - 1) / G;
+      int32_t xp = c, xi = ni;  // inclusive scans within the wave
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t tp = __shfl_up(xp, off), ti = __shfl_up(xi, off);
+        if (lane >= off) {
+          xp += tp;
+          xi += ti;
+        }
+      }
+      if (lane == 63) {
+        wp[wave] = xp;
+        wi[wave] = xi;
+      }
+      __syncthreads();
+      int32_t a = carry_p + xp - c, bi = carry_i + xi - ni;
+#pragma unroll
+      for (int w = 0; w < 16; ++w) {
+        const int32_t tp = wp[w], ti = wi[w];
+        if (w < wave) {
+          a += tp;
+          bi += ti;
+        }
+        carry_p += tp;
+        carry_i += ti;
+      }
+      __syncthreads();
+      if (b < bins) {
+        pair_off[b] = a;
+        item_off[b] = bi;
+        fill[(int64_t)b * kGroupBinPad] = 0;
+        const int j = b % nlist;
+        for (int g = 0; g < ni; ++g) items[bi + g] = make_int4(j, a + g * G, min(G, c - g * G), 0);
+      }
     }
   }
-  if (lane == 63) {
-    wp[wave] = xp;
-    wi[wave] = xi;
-  }
-  __syncthreads();
-  int32_t a = xp - ps, bi = xi - is;  // exclusive, then plus the earlier waves
-  for (int w = 0; w < wave; ++w) {
-    a += wp[w];
-    bi += wi[w];
-  }
-  if (tid == 1023) {
-    pair_off[bins] = a + ps;
-    item_off[bins] = bi + is;
-  }
-  for (int b = b0; b < b1; ++b) {
-    const int32_t c = cnt[b];
-    pair_off[b] = a;
-    item_off[b] = bi;
-    fill[b] = 0;
-    const int j = b % nlist;
-    for (int g = 0; g * G < c; ++g) items[bi + g] = make_int4(j, a + g * G, min(G, c - g * G), 0);
-    a += c;
-    bi += (c + G - 1) / G;
+  if (tid == 0) {
+    pair_off[bins] = carry_p;
+    item_off[bins] = carry_i;
   }
 }
 
@@ -113,7 +127,7 @@ __global__ void k_grp_scatter(const int32_t* __restrict__ probes, int nq, int np
   const int j = probes[pair];
   if (j < 0) return;
   const int b = group_chunk_of(gc, p) * nlist + j;
-  slots[pair_off[b] + atomicAdd(&fill[b], 1)] = (int32_t)pair;
+  slots[pair_off[b] + atomicAdd(&fill[(int64_t)b * kGroupBinPad], 1)] = (int32_t)pair;
 }
 
 __device__ inline uint32_t lane_prefix(uint64_t mask) {
@@ -153,6 +167,9 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   __shared__ uint64_t sStage[4][STAGE];
   __shared__ uint32_t sFcnt[4][GMAX], sFbase[4][GMAX];  // per wave: flush counts and bases
   __shared__ int32_t sItem;
+  // 8 code bits -> 8 bytes of 0/1 (byte b = bit b): the unpacking of the A
+  // operand is two table reads per 16 bits
+  __shared__ uint2 sLut[256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int W = a.L.W;
   const int D = a.L.d;
@@ -192,6 +209,11 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     __builtin_amdgcn_wave_barrier();
   };
   const int first_item = a.item_off[0], end_item = a.item_off[nlist];
+  if (tid < 256) {
+    const v4i u = unpack16((uint32_t)tid);
+    sLut[tid] = make_uint2((uint32_t)u[0], (uint32_t)u[1]);
+  }
+  // (the first item's barriers order these writes before any read)
   for (;;) {
     if (tid == 0) sItem = first_item + (int32_t)atomicAdd(a.item_counter, 1u);
     __syncthreads();
@@ -286,7 +308,9 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 #pragma unroll
         for (int t = 0; t < KS; ++t) {
           const uint32_t word = sCode[wave][2 * t + (lg >> 1)][vrow];
-          A[t] = unpack16((word >> (16 * (lg & 1))) & 0xFFFFu);
+          const uint2 lo8 = sLut[(word >> (16 * (lg & 1))) & 0xFFu];
+          const uint2 hi8 = sLut[(word >> (16 * (lg & 1) + 8)) & 0xFFu];
+          A[t] = v4i{(int)lo8.x, (int)lo8.y, (int)hi8.x, (int)hi8.y};
         }
         // every query tile's products first, then the epilogues
         v4i c0 = {0, 0, 0, 0};
@@ -314,25 +338,26 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
         for (int n = 0; n < GT; ++n) {
           if (n >= nt) break;
           float est[4];
-          bool pass[4];
-          bool anyp = false;
+          uint64_t pm[4];  // the lanes that pass, per result row
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int g = (QB == QB_DOUBLE ? acc[n][r] : acc[n][r] << 1) + qneg[n];
             est[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
-            pass[r] = est[r] <= qthr[n];  // NaN (padding lanes, empty slots) never passes
-            anyp |= pass[r];
+            // NaN (padding lanes, empty slots) never passes
+            pm[r] = __builtin_amdgcn_ballot_w64(est[r] <= qthr[n]);
           }
-          if (__builtin_amdgcn_ballot_w64(anyp)) {  // stage the survivors of this tile
+          if (pm[0] | pm[1] | pm[2] | pm[3]) {  // stage the survivors of this tile
             const uint32_t tag = rel0 | ((uint32_t)(16 * n + (lane & 15)) << 26);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              const uint64_t mask = __builtin_amdgcn_ballot_w64(pass[r]);
-              if (pass[r]) {
-                const int e = stage_n + (int)lane_prefix(mask);
-                sStage[wave][e] = ((uint64_t)__float_as_uint(est[r]) << 32) | (tag + (uint32_t)r);
+              if (pm[r]) {
+                if (est[r] <= qthr[n]) {  // (the compare behind pm[r])
+                  const uint32_t e = __builtin_amdgcn_mbcnt_hi(
+                      (uint32_t)(pm[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm[r], (uint32_t)stage_n));
+                  sStage[wave][e] = ((uint64_t)__float_as_uint(est[r]) << 32) | (tag + (uint32_t)r);
+                }
+                stage_n += (int)__popcll(pm[r]);
               }
-              stage_n += (int)__popcll(mask);
             }
             if (stage_n > STAGE - 256) {
               __builtin_amdgcn_wave_barrier();

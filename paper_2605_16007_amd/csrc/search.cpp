@@ -44,13 +44,15 @@ __global__ void k_count_scanned(const int32_t* probes, const int32_t* list_len, 
   }
 }
 
-// acc += padded record bytes of every list-major item (items x list bytes)
+// acc += padded record bytes of every list-major item (items x list bytes);
+// cnt holds one count per list every kGroupBinPad words
 __global__ void k_count_group_bytes(const int32_t* cnt, const int32_t* list_len, int nlist, int G,
                                     int rec_bytes, unsigned long long* acc) {
   __shared__ unsigned long long part[256];
   unsigned long long b = 0;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < nlist; j += gridDim.x * 256)
-    b += (unsigned long long)((cnt[j] + G - 1) / G) * ((list_len[j] + 63) / 64) * 64 * rec_bytes;
+    b += (unsigned long long)((cnt[(int64_t)j * kGroupBinPad] + G - 1) / G) * ((list_len[j] + 63) / 64) *
+         64 * rec_bytes;
   part[threadIdx.x] = b;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -259,8 +261,8 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   if ((dbg && dbg->qu) || P.any_group) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
   if (P.any_group) {
     const int64_t bins = (int64_t)P.gc.nb * nlist;
-    b.gcnt = c.take<int32_t>(bins);
-    b.gfill = c.take<int32_t>(bins);
+    b.gcnt = c.take<int32_t>(bins * kGroupBinPad);
+    b.gfill = c.take<int32_t>(bins * kGroupBinPad);
     b.pair_off = c.take<int32_t>(bins + 1);
     b.item_off = c.take<int32_t>(bins + 1);
     b.slots = c.take<int32_t>(pairs);
@@ -501,7 +503,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         si.z0 = b.counter;
         si.n0 = 1 + kMaxGroupChunks;
         si.z1 = reinterpret_cast<uint32_t*>(b.gcnt);
-        si.n1 = (int64_t)P.gc.nb * nlist;
+        si.n1 = (int64_t)P.gc.nb * nlist * kGroupBinPad;
       }
       launch_search_init(s, si);
     }
@@ -592,7 +594,8 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
           hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
                              idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 0,
                              tc + 2 * part);
-          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s, b.gcnt + (int64_t)c * nlist,
+          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s,
+                             b.gcnt + (int64_t)c * nlist * kGroupBinPad,
                              idx->list_len.as<int32_t>(), nlist, ga.G, rec_bytes, tc + 2 * part + 1);
         }
         RBQ_HIP(hipGetLastError());
