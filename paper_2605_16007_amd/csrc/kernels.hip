@@ -1415,10 +1415,31 @@ __device__ void lds_select_sorted(const uint64_t* keys, int n, int k, int KP, ui
 __device__ inline float4 row4(const float* __restrict__ X, size_t e) {
   return *reinterpret_cast<const float4*>(X + e);
 }
-__device__ inline float4 row4(const uint8_t* __restrict__ X, size_t e) {
-  const uint32_t w = *reinterpret_cast<const uint32_t*>(X + e);
+__device__ inline float4 bytes4(uint32_t w) {
   return make_float4((float)(w & 0xFFu), (float)((w >> 8) & 0xFFu), (float)((w >> 16) & 0xFFu),
                      (float)(w >> 24));
+}
+__device__ inline float4 row4(const uint8_t* __restrict__ X, size_t e) {
+  return bytes4(*reinterpret_cast<const uint32_t*>(X + e));
+}
+// Sixteen consecutive elements (four groups of four) starting at element e,
+// of which the first `ng` groups are read (the rest are zero). Byte rows whose
+// starts are 16-byte aligned take one 16-byte load.
+__device__ inline void row16(const float* __restrict__ X, size_t e, int ng, bool, float4 (&x)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] = j < ng ? row4(X, e + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+__device__ inline void row16(const uint8_t* __restrict__ X, size_t e, int ng, bool a16, float4 (&x)[4]) {
+  if (a16 && ng >= 4) {
+    const uint4 w = *reinterpret_cast<const uint4*>(X + e);
+    x[0] = bytes4(w.x);
+    x[1] = bytes4(w.y);
+    x[2] = bytes4(w.z);
+    x[3] = bytes4(w.w);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = j < ng ? row4(X, e + 4 * j) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
 }
 
 template <typename T>
@@ -1437,7 +1458,6 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t s_misc[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int sub = lane >> 4, sl = lane & 15;  // candidate slot in the wave, lane in the slot
   const int64_t i = blockIdx.x;
   const int kr = rowk ? rowk[i] : k;  // this row's k (<= k)
   const int nf4 = ldx >> 2;
@@ -1445,39 +1465,55 @@ __global__ __launch_bounds__(256) void k_rerank(const float* __restrict__ q, int
     qs[t] = (t * 4 < d) ? reinterpret_cast<const float4*>(q + i * ldq)[t] : make_float4(0, 0, 0, 0);
   for (int c = tid; c < R; c += 256) ck[c] = cand[i * ldc + c];  // the keys, coalesced
   __syncthreads();
-  // 16 lanes per candidate, RU candidates per slot in flight: in round r, wave
-  // w, slot s takes candidates 16 (RU r + u) + 4 w + s; each slot rewrites only
-  // its own keys
-  constexpr int RU = 8;
-  for (int c0 = 0; c0 < R; c0 += 16 * RU) {
+  // 8 lanes per candidate (a lane takes 16 consecutive elements of every 128),
+  // RU candidates per slot in flight: in round r, wave w, slot s takes
+  // candidates 32 (RU r + u) + 8 w + s; each slot rewrites only its own keys.
+  // Byte and FP32 rows are summed in the same order.
+  constexpr int RU = 4;
+  const int sub8 = lane >> 3, sl8 = lane & 7;
+  const bool a16 = (ldx * sizeof(T)) % 16 == 0;
+  for (int c0 = 0; c0 < R; c0 += 32 * RU) {
     uint64_t key[RU];
     size_t row[RU];
     bool ok[RU];
     float acc[RU];
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
-      const int c = c0 + 16 * u + 4 * wave + sub;
+      const int c = c0 + 32 * u + 8 * wave + sub8;
       key[u] = c < R ? ck[c] : KEY_NONE;
       ok[u] = key[u] != KEY_NONE && (int64_t)(uint32_t)key[u] < n;  // ids outside [0, n) are never read
       row[u] = ok[u] ? (size_t)(uint32_t)key[u] * ldx : 0;
       acc[u] = 0.f;
     }
-    for (int f = sl; f < nf4; f += 16) {
-      const float4 qv = qs[f];
-      float4 xv[RU];
+    for (int f0 = 4 * sl8; f0 < nf4; f0 += 32) {
+      const int ng = min(4, nf4 - f0);
+      float4 qv[4];
 #pragma unroll
-      for (int u = 0; u < RU; ++u) xv[u] = ok[u] ? row4(X, row[u] + 4 * (size_t)f) : qv;
+      for (int j = 0; j < 4; ++j) qv[j] = j < ng ? qs[f0 + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 xv[RU][4];
 #pragma unroll
       for (int u = 0; u < RU; ++u) {
-        const float a0 = qv.x - xv[u].x, a1 = qv.y - xv[u].y, a2 = qv.z - xv[u].z, a3 = qv.w - xv[u].w;
-        acc[u] += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+        if (ok[u]) {
+          row16(X, row[u] + 4 * (size_t)f0, ng, a16, xv[u]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) xv[u][j] = qv[j];
+        }
       }
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float a0 = qv[j].x - xv[u][j].x, a1 = qv[j].y - xv[u][j].y, a2 = qv[j].z - xv[u][j].z,
+                      a3 = qv[j].w - xv[u][j].w;
+          acc[u] += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+        }
     }
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
-      for (int off = 8; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
-      const int c = c0 + 16 * u + 4 * wave + sub;
-      if (sl == 0 && c < R) ck[c] = ok[u] ? key64(acc[u], (uint32_t)key[u]) : KEY_NONE;
+      for (int off = 4; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off);
+      const int c = c0 + 32 * u + 8 * wave + sub8;
+      if (sl8 == 0 && c < R) ck[c] = ok[u] ? key64(acc[u], (uint32_t)key[u]) : KEY_NONE;
     }
   }
   __syncthreads();

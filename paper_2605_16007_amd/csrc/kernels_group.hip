@@ -145,8 +145,8 @@ __device__ inline v4i unpack16(uint32_t bits) {
 
 // The MFMA multiplies signed bytes. QB (query bytes) says how qu becomes the
 // B operand:
-//   QB_DOUBLE (B_q <= 6): B = 2 qu <= 126, the MFMA returns 2 ip, and
-//     g = 2 ip - sum qu is one add;
+//   QB_DOUBLE (B_q <= 6): B = 2 qu <= 126 and the accumulator starts at
+//     -sum qu, so the MFMA returns g = 2 ip - sum qu itself;
 //   QB_PLAIN (B_q = 7): B = qu <= 127, g = (ip << 1) - sum qu;
 //   QB_OFFSET (B_q = 8): B = qu - 128 and the accumulator starts at 128 pop
 //     (pop = the vector's popcount), so the MFMA still returns ip.
@@ -319,7 +319,8 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 #pragma unroll
         for (int n = 0; n < GT; ++n) {
           if (n < nt) {
-            v4i c = c0;
+            // QB_DOUBLE: the accumulator starts at -sum qu, so it ends at g
+            v4i c = QB == QB_DOUBLE ? v4i{qneg[n], qneg[n], qneg[n], qneg[n]} : c0;
 #pragma unroll
             for (int t = 0; t < KS; ++t) c = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t], Bq[n][t], c, 0, 0, 0);
             acc[n] = c;
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
           uint64_t pm[4];  // the lanes that pass, per result row
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int g = (QB == QB_DOUBLE ? acc[n][r] : acc[n][r] << 1) + qneg[n];
+            const int g = QB == QB_DOUBLE ? acc[n][r] : (acc[n][r] << 1) + qneg[n];
             est[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
             // NaN (padding lanes, empty slots) never passes
             pm[r] = __builtin_amdgcn_ballot_w64(est[r] <= qthr[n]);
