@@ -1782,7 +1782,7 @@ void launch_fill_rows_u64(hipStream_t s, uint64_t* p, int64_t ld, int64_t rows, 
 }
 
 // A search's per-query state in one launch: candidate rows empty, thresholds
-// open, pool fills and overflow flags zero, and the extra words cleared.
+// open, pool fills and overflow flags zero, the extra words cleared or set.
 __global__ void k_search_init(SearchInit a) {
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1797,10 +1797,10 @@ __global__ void k_search_init(SearchInit a) {
     if (a.overflow) a.overflow[t] = 0u;
   }
   for (int64_t t = t0; t < a.n0; t += step) a.z0[t] = 0u;
-  for (int64_t t = t0; t < a.n1; t += step) a.z1[t] = 0u;
+  for (int64_t t = t0; t < a.n2; t += step) a.f2[t] = 0xFFFFFFFFu;
 }
 void launch_search_init(hipStream_t s, const SearchInit& a) {
-  const int64_t n = std::max<int64_t>({(int64_t)a.nq * a.R, a.nq, a.n0, a.n1});
+  const int64_t n = std::max<int64_t>({(int64_t)a.nq * a.R, a.nq, a.n0, a.n2});
   if (n <= 0) return;
   const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
   hipLaunchKernelGGL(k_search_init, dim3((unsigned)blocks), dim3(256), 0, s, a);

@@ -140,13 +140,12 @@ struct GroupChunks {
   int nb = 0;
   int bound[kMaxGroupChunks + 1] = {};
 };
-// Pairs of every list-major chunk grouped by (chunk, list): pair_off and
-// item_off hold nb * nlist + 1 offsets; the counters cnt and fill hold one
-// word per bin every kGroupBinPad words (cnt zero on entry).
-constexpr int kGroupBinPad = 16;
+// Pairs of every list-major chunk grouped by (chunk, list), queries ascending
+// within a bin: rank is an nlist x nq int16 table, all -1 on entry; cnt holds
+// nb * nlist counts, pair_off and item_off nb * nlist + 1 offsets.
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
-                      int nlist, int G, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
-                      int32_t* fill, int32_t* slots, int4* items);
+                      int nlist, int G, int16_t* rank, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
+                      int32_t* slots, int4* items);
 void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups);
 void launch_reset_masked(hipStream_t s, const uint32_t* mask, uint64_t* rows, int64_t ld, int R,
                          uint32_t* qthr, uint32_t* pcnt, int nq);
@@ -184,7 +183,7 @@ void launch_rotate_rows_f64(hipStream_t s, const float* A, int lda, const float*
                             int rows, int d, float* out, int ldo, float* nrm);
 
 // Per-search state: cand rows [nq][R] (stride cand_ld) = KEY_NONE, qthr =
-// ~0, pcnt = 0, overflow = 0 (if set), z0[0..n0) = z1[0..n1) = 0.
+// ~0, pcnt = 0, overflow = 0 (if set), z0[0..n0) = 0, f2[0..n2) = ~0.
 struct SearchInit {
   uint64_t* cand = nullptr;
   int64_t cand_ld = 0;
@@ -194,8 +193,8 @@ struct SearchInit {
   uint32_t* overflow = nullptr;
   uint32_t* z0 = nullptr;
   int64_t n0 = 0;
-  uint32_t* z1 = nullptr;
-  int64_t n1 = 0;
+  uint32_t* f2 = nullptr;  // f2[0..n2) = 0xFFFFFFFF
+  int64_t n2 = 0;
 };
 void launch_search_init(hipStream_t s, const SearchInit& a);
 

@@ -30,9 +30,7 @@ constexpr int STAGE = 512; // survivors staged per wave before a flush
 
 // ---- inverted map of the list-major chunks' pairs: list -> pairs ----------
 // Built once per search for all list-major chunks (a suffix of the probe
-// ranks): bin c * nlist + j holds the pairs of chunk c that probe list j. The
-// per-bin counters sit kGroupBinPad words apart (one cache line each), so that
-// the atomics of a popular list do not serialise the lists that share its line.
+// ranks): bin c * nlist + j holds the pairs of chunk c that probe list j.
 
 __device__ inline int group_chunk_of(const GroupChunks& gc, int p) {
   int c = 0;
@@ -40,25 +38,14 @@ __device__ inline int group_chunk_of(const GroupChunks& gc, int p) {
   return c;
 }
 
-__global__ void k_grp_hist(const int32_t* __restrict__ probes, int nq, int nprobe, GroupChunks gc,
-                           int nlist, int32_t* __restrict__ cnt) {
-  const int span = nprobe - gc.bound[0];
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nq * span) return;
-  const int64_t i = t / span;
-  const int p = gc.bound[0] + (int)(t - i * span);
-  const int j = probes[i * nprobe + p];
-  if (j >= 0) atomicAdd(&cnt[(int64_t)(group_chunk_of(gc, p) * nlist + j) * kGroupBinPad], 1);
-}
-
 // Exclusive prefix sums over the bins of the pair counts and of the item
-// counts ceil(cnt / G), the item descriptors (list, first slot, pairs), and
-// cleared scatter cursors; one workgroup of 1024 threads, 1024 bins per round
-// (eight rounds' counts loaded at once).
+// counts ceil(cnt / G), and the item descriptors (list, first slot, pairs);
+// one workgroup of 1024 threads, 1024 bins per round (eight rounds' counts
+// loaded at once).
 __global__ __launch_bounds__(1024) void k_grp_offsets(const int32_t* __restrict__ cnt, int bins, int nlist,
                                                       int G, int32_t* __restrict__ pair_off,
                                                       int32_t* __restrict__ item_off,
-                                                      int32_t* __restrict__ fill, int4* __restrict__ items) {
+                                                      int4* __restrict__ items) {
   __shared__ int32_t wp[16], wi[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rounds = (bins + 1023) / 1024;
@@ -68,7 +55,7 @@ __global__ __launch_bounds__(1024) void k_grp_offsets(const int32_t* __restrict_
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int b = (r0 + u) * 1024 + tid;
-      cv[u] = b < bins ? cnt[(int64_t)b * kGroupBinPad] : 0;
+      cv[u] = b < bins ? cnt[b] : 0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -103,7 +90,6 @@ __global__ __launch_bounds__(1024) void k_grp_offsets(const int32_t* __restrict_
       if (b < bins) {
         pair_off[b] = a;
         item_off[b] = bi;
-        fill[(int64_t)b * kGroupBinPad] = 0;
         const int j = b % nlist;
         for (int g = 0; g < ni; ++g) items[bi + g] = make_int4(j, a + g * G, min(G, c - g * G), 0);
       }
@@ -115,19 +101,70 @@ __global__ __launch_bounds__(1024) void k_grp_offsets(const int32_t* __restrict_
   }
 }
 
-__global__ void k_grp_scatter(const int32_t* __restrict__ probes, int nq, int nprobe, GroupChunks gc,
-                              int nlist, const int32_t* __restrict__ pair_off, int32_t* __restrict__ fill,
-                              int32_t* __restrict__ slots) {
-  const int span = nprobe - gc.bound[0];
+// rank[j * nq + i] = the probe rank p at which query i probes list j within
+// the list-major ranks (-1 otherwise; cleared by the search's state
+// initialisation); then one wave per list counts, and later fills, its bins
+// with ballots (no atomics; queries in ascending order within a bin).
+__global__ void k_grp_mark(const int32_t* __restrict__ probes, int nq, int nprobe, int r0,
+                           int16_t* __restrict__ rank) {
+  const int span = nprobe - r0;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nq * span) return;
   const int64_t i = t / span;
-  const int p = gc.bound[0] + (int)(t - i * span);
-  const int64_t pair = i * nprobe + p;
-  const int j = probes[pair];
-  if (j < 0) return;
-  const int b = group_chunk_of(gc, p) * nlist + j;
-  slots[pair_off[b] + atomicAdd(&fill[(int64_t)b * kGroupBinPad], 1)] = (int32_t)pair;
+  const int p = r0 + (int)(t - i * span);
+  const int j = probes[i * nprobe + p];
+  if (j >= 0) rank[(int64_t)j * nq + i] = (int16_t)p;
+}
+
+__global__ __launch_bounds__(256) void k_grp_count(const int16_t* __restrict__ rank, int nq, GroupChunks gc,
+                                                   int nlist, int32_t* __restrict__ cnt) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= nlist) return;
+  int32_t c[kMaxGroupChunks];
+#pragma unroll
+  for (int b = 0; b < kMaxGroupChunks; ++b) c[b] = 0;
+  const int16_t* rj = rank + (int64_t)j * nq;
+  for (int i0 = 0; i0 < nq; i0 += 64) {
+    const int i = i0 + lane;
+    const int p = i < nq ? rj[i] : -1;
+    const int ch = p >= 0 ? group_chunk_of(gc, p) : -1;
+#pragma unroll
+    for (int b = 0; b < kMaxGroupChunks; ++b)
+      if (b < gc.nb) c[b] += (int32_t)__popcll(__builtin_amdgcn_ballot_w64(ch == b));
+  }
+  if (lane < gc.nb) {
+    int32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < kMaxGroupChunks; ++b) v = b == lane ? c[b] : v;
+    cnt[lane * nlist + j] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_grp_fill(const int16_t* __restrict__ rank, int nq, int nprobe,
+                                                  GroupChunks gc, int nlist,
+                                                  const int32_t* __restrict__ pair_off,
+                                                  int32_t* __restrict__ slots) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (j >= nlist) return;
+  int32_t pos[kMaxGroupChunks];
+#pragma unroll
+  for (int b = 0; b < kMaxGroupChunks; ++b) pos[b] = b < gc.nb ? pair_off[b * nlist + j] : 0;
+  const int16_t* rj = rank + (int64_t)j * nq;
+  for (int i0 = 0; i0 < nq; i0 += 64) {
+    const int i = i0 + lane;
+    const int p = i < nq ? rj[i] : -1;
+    const int ch = p >= 0 ? group_chunk_of(gc, p) : -1;
+#pragma unroll
+    for (int b = 0; b < kMaxGroupChunks; ++b) {
+      if (b >= gc.nb) break;
+      const uint64_t m = __builtin_amdgcn_ballot_w64(ch == b);
+      if (ch == b)
+        slots[pos[b] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+            (int32_t)((int64_t)i * nprobe + p);
+      pos[b] += (int32_t)__popcll(m);
+    }
+  }
 }
 
 __device__ inline uint32_t lane_prefix(uint64_t mask) {
@@ -378,21 +415,23 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 }
 
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
-                      int nlist, int G, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
-                      int32_t* fill, int32_t* slots, int4* items) {
+                      int nlist, int G, int16_t* rank, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
+                      int32_t* slots, int4* items) {
   RBQ_CHECK(gc.nb >= 1 && gc.nb <= kMaxGroupChunks && gc.bound[gc.nb] == nprobe,
             "list-major chunk bounds");
+  RBQ_CHECK(nprobe <= 32767, "list-major map: nprobe out of range");
   const int64_t pairs = (int64_t)nq * (nprobe - gc.bound[0]);
   if (pairs <= 0) return;
-  // (cnt was cleared by the search's state initialisation)
-  hipLaunchKernelGGL(k_grp_hist, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, probes, nq,
-                     nprobe, gc, nlist, cnt);
+  const unsigned lgrid = (unsigned)((nlist + 3) / 4);
+  hipLaunchKernelGGL(k_grp_mark, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, probes, nq, nprobe,
+                     gc.bound[0], rank);
+  RBQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_grp_count, dim3(lgrid), dim3(256), 0, s, rank, nq, gc, nlist, cnt);
   RBQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_grp_offsets, dim3(1), dim3(1024), 0, s, cnt, gc.nb * nlist, nlist, G, pair_off,
-                     item_off, fill, items);
+                     item_off, items);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_scatter, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, probes,
-                     nq, nprobe, gc, nlist, pair_off, fill, slots);
+  hipLaunchKernelGGL(k_grp_fill, dim3(lgrid), dim3(256), 0, s, rank, nq, nprobe, gc, nlist, pair_off, slots);
   RBQ_HIP(hipGetLastError());
 }
 

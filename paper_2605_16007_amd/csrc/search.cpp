@@ -44,15 +44,13 @@ __global__ void k_count_scanned(const int32_t* probes, const int32_t* list_len, 
   }
 }
 
-// acc += padded record bytes of every list-major item (items x list bytes);
-// cnt holds one count per list every kGroupBinPad words
+// acc += padded record bytes of every list-major item (items x list bytes)
 __global__ void k_count_group_bytes(const int32_t* cnt, const int32_t* list_len, int nlist, int G,
                                     int rec_bytes, unsigned long long* acc) {
   __shared__ unsigned long long part[256];
   unsigned long long b = 0;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < nlist; j += gridDim.x * 256)
-    b += (unsigned long long)((cnt[(int64_t)j * kGroupBinPad] + G - 1) / G) * ((list_len[j] + 63) / 64) *
-         64 * rec_bytes;
+    b += (unsigned long long)((cnt[j] + G - 1) / G) * ((list_len[j] + 63) / 64) * 64 * rec_bytes;
   part[threadIdx.x] = b;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
@@ -77,7 +75,7 @@ struct Bufs {
   uint32_t* pcnt = nullptr;
   uint8_t* qu8 = nullptr;
   int32_t* gcnt = nullptr;
-  int32_t* gfill = nullptr;
+  int16_t* rankmat = nullptr;  // nlist x nq probe ranks (list-major map)
   int32_t* pair_off = nullptr;
   int32_t* item_off = nullptr;
   int32_t* slots = nullptr;
@@ -261,14 +259,14 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   if ((dbg && dbg->qu) || P.any_group) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
   if (P.any_group) {
     const int64_t bins = (int64_t)P.gc.nb * nlist;
-    b.gcnt = c.take<int32_t>(bins * kGroupBinPad);
-    b.gfill = c.take<int32_t>(bins * kGroupBinPad);
+    b.gcnt = c.take<int32_t>(bins);
     b.pair_off = c.take<int32_t>(bins + 1);
     b.item_off = c.take<int32_t>(bins + 1);
     b.slots = c.take<int32_t>(pairs);
     b.items = c.take<int4>(pairs / P.G + bins + 1);
     b.overflow = c.take<uint32_t>(nq);
     b.counter = c.take<uint32_t>(1 + kMaxGroupChunks);  // overflow flag, item cursors
+    b.rankmat = c.take<int16_t>(((size_t)nlist * nq + 1) & ~size_t(1));
   }
   b.scal = c.take<float4>(pairs);
   if (P.inj_qu) {
@@ -502,15 +500,15 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         si.overflow = b.overflow;
         si.z0 = b.counter;
         si.n0 = 1 + kMaxGroupChunks;
-        si.z1 = reinterpret_cast<uint32_t*>(b.gcnt);
-        si.n1 = (int64_t)P.gc.nb * nlist * kGroupBinPad;
+        si.f2 = reinterpret_cast<uint32_t*>(b.rankmat);  // every rank -1
+        si.n2 = ((int64_t)nlist * nq + 1) / 2;
       }
       launch_search_init(s, si);
     }
     // the (chunk, list) -> pairs map of every list-major chunk
     if (any_group)
-      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, b.gcnt, b.pair_off, b.item_off,
-                       b.gfill, b.slots, b.items);
+      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, b.rankmat, b.gcnt, b.pair_off,
+                       b.item_off, b.slots, b.items);
     sa.pcnt = b.pcnt;
     sa.qmask = nullptr;
     GroupArgs ga;
@@ -594,8 +592,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
           hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
                              idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 0,
                              tc + 2 * part);
-          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s,
-                             b.gcnt + (int64_t)c * nlist * kGroupBinPad,
+          hipLaunchKernelGGL(k_count_group_bytes, dim3(16), dim3(256), 0, s, b.gcnt + (int64_t)c * nlist,
                              idx->list_len.as<int32_t>(), nlist, ga.G, rec_bytes, tc + 2 * part + 1);
         }
         RBQ_HIP(hipGetLastError());
