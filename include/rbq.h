@@ -339,7 +339,9 @@ typedef struct {
                               number >= this * nlist (0: every chunk) */
   int32_t growth;        /* each chunk after the first is (growth - 1) x the probe
                             ranks already scanned */
-  int32_t reserved;
+  int32_t early_form;    /* chunks before the list-major ones, in batches of >= 128
+                            queries: 0 one workgroup per query scans and selects;
+                            1 popcount scan per (query, probe), then a merge */
 } rbq_tune_result;
 
 rbq_status rbq_autotune(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,

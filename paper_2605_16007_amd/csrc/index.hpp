@@ -36,6 +36,7 @@ struct TimingRec {
 // query; growth: each later chunk is (growth - 1) times the prefix scanned.
 struct TuneCfg {
   int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2, gm = 4, growth = 2;
+  int early = 0;  // chunks before the list-major ones: 0 fused scan+select, 1 popcount scan + merge
 };
 
 // A device scratch area reused across calls. `done` is recorded on the stream

@@ -210,7 +210,7 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
       if (lm) {
         P.chunks.push_back({p0, pn, true, false});
         P.any_group = true;
-      } else if (nq >= kFusedMinQueries && idx->W <= 32) {
+      } else if (nq >= kFusedMinQueries && idx->W <= 32 && cfg.early == 0) {
         // one workgroup per query scans and selects in one launch; it lowers
         // its threshold whenever its buffer fills, so consecutive chunks of
         // this kind become one launch

@@ -69,13 +69,18 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
   RBQ_HIP(hipSetDevice(idx->device));
   const int d = idx->d;
   std::vector<TuneCfg> cands;
-  cands.push_back(TuneCfg{1, 64, 8, 2, 4, 2});
+  cands.push_back(TuneCfg{1, 64, 8, 2, 4, 2, 0});
   if (group_k_steps(d) <= 4)
     for (int gm : {0, 4, 16, 64})
-      for (int G : {32, 64})
-        for (int wg : {4, 8})
-          for (int ff : {1, 2, 4})
-            for (int gr : {2, 3, 4}) cands.push_back(TuneCfg{2, G, wg, ff, gm, gr});
+      for (int early : {0, 1}) {
+        // (gm 0: every chunk list-major, no early chunks; gm 64: early only
+        // for the batch shapes where list-major rarely pays, fused kept)
+        if (early == 1 && (gm == 0 || gm == 64)) continue;
+        for (int G : {32, 64})
+          for (int wg : {4, 8})
+            for (int ff : {1, 2, 4})
+              for (int gr : {2, 3, 4}) cands.push_back(TuneCfg{2, G, wg, ff, gm, gr, early});
+      }
 
   hipStream_t s = nullptr;
   RBQ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -138,6 +143,7 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
       out->first_factor = best.first_factor;
       out->chunk_group_min = best.gm;
       out->growth = best.growth;
+      out->early_form = best.early;
       out->ms = best_ms;
       out->ms_default = ms_default;
       out->trials = (int32_t)cands.size();
@@ -157,7 +163,8 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
   RBQ_HIP(hipStreamDestroy(s));
 }
 
-// Cache file: one entry per line, "<signature> <key> <scan> <G> <wg> <ff> <gm> <growth>";
+// Cache file: one entry per line,
+// "<signature> <key> <scan> <G> <wg> <ff> <gm> <growth> <early>";
 // lines of other signatures are kept when this index's entries are rewritten.
 void tune_save(rbq_index* idx, const char* path) {
   const std::string sig = signature(idx);
@@ -173,13 +180,13 @@ void tune_save(rbq_index* idx, const char* path) {
   {
     std::ofstream o(tmp, std::ios::trunc);
     RBQ_CHECK(o.good(), "cannot write the autotune cache");
-    o << "# librbq autotune cache v3: signature key scan G wg_per_cu first_factor gm growth\n";
+    o << "# librbq autotune cache v4: signature key scan G wg_per_cu first_factor gm growth early\n";
     for (const auto& l : keep) o << l << "\n";
     std::lock_guard<std::mutex> g(idx->tune_mu);
     for (const auto& kv : idx->tune)
       o << sig << " " << kv.first << " " << kv.second.scan << " " << kv.second.G << " "
         << kv.second.wg_per_cu << " " << kv.second.first_factor << " " << kv.second.gm << " "
-        << kv.second.growth << "\n";
+        << kv.second.growth << " " << kv.second.early << "\n";
     RBQ_CHECK(o.good(), "writing the autotune cache failed");
   }
   RBQ_CHECK(std::rename(tmp.c_str(), path) == 0, "cannot replace the autotune cache");
@@ -198,11 +205,13 @@ int tune_load(rbq_index* idx, const char* path) {
     std::string s;
     uint64_t key = 0;
     TuneCfg c;
-    if (!(ls >> s >> key >> c.scan >> c.G >> c.wg_per_cu >> c.first_factor >> c.gm >> c.growth)) continue;
+    if (!(ls >> s >> key >> c.scan >> c.G >> c.wg_per_cu >> c.first_factor >> c.gm >> c.growth >> c.early))
+      continue;
     if (s != sig) continue;
     const bool ok = (c.scan == 1 || c.scan == 2) && c.G >= 1 && c.G <= 64 && c.wg_per_cu >= 1 &&
                     c.wg_per_cu <= 64 && c.first_factor >= 1 && c.first_factor <= 64 &&
-                    c.gm >= 0 && c.gm <= (1 << 20) && c.growth >= 2 && c.growth <= 16;
+                    c.gm >= 0 && c.gm <= (1 << 20) && c.growth >= 2 && c.growth <= 16 &&
+                    (c.early == 0 || c.early == 1);
     RBQ_CHECK(ok, "autotune cache entry out of range");
     got[key] = c;
     ++loaded;

@@ -36,7 +36,8 @@ def test_autotune_keeps_results(tcase, nprobe, R):
     before = lib.search(Q, nprobe, 10, R)
     r = lib.autotune(Q, nprobe, 10, R)
     _say(f"[tune] chose {r}")
-    assert r["scan"] in (1, 2) and r["trials"] == 145 and r["chunk_group_min"] in (0, 4, 16, 64) and r["growth"] in (2, 3, 4)
+    assert r["scan"] in (1, 2) and r["trials"] == 217 and r["chunk_group_min"] in (0, 4, 16, 64) and r["growth"] in (2, 3, 4)
+    assert r["early_form"] in (0, 1)
     assert r["group_size"] in (32, 64) and r["wg_per_cu"] in (4, 8) and r["first_factor"] in (1, 2, 4)
     assert r["ms"] > 0 and r["ms"] <= r["ms_default"] * 1.5
     after = lib.search(Q, nprobe, 10, R)
@@ -76,7 +77,7 @@ def test_tune_cache_round_trip(tcase):
         finally:
             diff.close()
         with open(path, "a") as f:
-            f.write(lines[0].rsplit(" ", 7)[0] + " 5 7 32 8 2 4 2\n")  # scan 7: out of range
+            f.write(lines[0].rsplit(" ", 8)[0] + " 5 7 32 8 2 4 2 0\n")  # scan 7: out of range
         with pytest.raises(RbqError):
             lib.tune_load(path)
     lib.tune_clear()
