@@ -1031,40 +1031,49 @@ void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
 
 // ---------------------------------------------------------------------------
 // Fused query-major scan + selection for chunks whose lists are shared by few
-// queries: one workgroup (16 waves) per query loads the query's running top-R
-// into LDS, scans the chunk's probed lists (popcount inner products, the same
-// estimator expression as the other scans), appends every estimate at or
-// below the query's threshold to an LDS buffer, and whenever the buffer could
-// overflow keeps only its best R (radix select in LDS) and lowers the
-// threshold to their R-th estimate. At the end the best R become the query's
-// running top-R and its threshold. Nothing goes through the global pool.
+// queries: one workgroup (8 waves, 64 KB of LDS: two per CU) per query loads
+// the query's running top-R into an LDS buffer, scans the chunk's probed lists
+// (popcount inner products, the same estimator expression as the other
+// scans), appends every estimate at or below the query's threshold, and
+// whenever the buffer could overflow keeps only its best R and lowers the
+// threshold to their R-th estimate. The selection holds the buffer in
+// registers (an MSB-first radix select with fire-and-forget histogram atomics,
+// positions from one workgroup scan). Each wave takes every eighth micro-block
+// of the chunk's lists with the data of its next two loaded ahead (two register
+// sets, alternate rounds). At the end the best R become the query's running
+// top-R and its threshold. Nothing goes through the global pool.
 // ---------------------------------------------------------------------------
 
+constexpr int kFusedNT = 512;                 // threads per workgroup
+constexpr int kFusedKPT = 16;                 // buffer keys per thread in a selection
+constexpr int kFusedCap = kFusedNT * kFusedKPT;  // LDS buffer keys (64 KB)
+
 template <int NT>
-struct SelShared {
-  uint32_t hist[NT >= 512 ? 4 : 1][256];
-  uint32_t wsum[4];
-  uint32_t digit, rem, bucket, cnt;
+struct SelRegShared {
+  uint32_t hist[4][256];
+  uint32_t wsum[NT / 64 > 4 ? NT / 64 : 4];
+  uint32_t digit, rem, bucket;
   uint64_t lo[NT / 64], hi[NT / 64];
 };
 
-// The k smallest of keys[0..n) (LDS) into sel[0..min(n, k)), in any order, by
-// all NT threads (ends with a barrier). Returns the k-th smallest key, or
-// KEY_NONE when n < k. MSB-first radix select as in k_row_topk.
-template <int NT>
-__device__ uint64_t select_k_lds(const uint64_t* keys, int n, int k, uint64_t* sel, SelShared<NT>& sh) {
+// The k smallest of the n keys held KPT per thread (key u of thread t is key
+// u * NT + t; keys at n and beyond are ignored) written to dst[0..k) in any
+// order; returns the k-th smallest, or KEY_NONE when n <= k (then every key is
+// written). Every thread must call it; the keys must not live in dst's range
+// of memory except in these registers (all reads are done before the first
+// write, behind a barrier). Ends with a barrier.
+template <int NT, int KPT>
+__device__ uint64_t select_regs(const uint64_t (&v)[KPT], int n, int k, uint64_t* dst, SelRegShared<NT>& sh) {
   constexpr int NW = NT / 64;
-  constexpr int NH = NT >= 512 ? 4 : 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool take_all = n <= k;
-  uint64_t prefix = 0, pmask = 0;
-  uint32_t rem = (uint32_t)k;
+  auto valid = [&](int u) { return u * NT + tid < n; };
   uint64_t lo = ~0ull, hi = 0;
-  for (int c = tid; c < n; c += NT) {
-    const uint64_t v = keys[c];
-    lo = v < lo ? v : lo;
-    hi = v > hi ? v : hi;
-  }
+#pragma unroll
+  for (int u = 0; u < KPT; ++u)
+    if (valid(u)) {
+      lo = v[u] < lo ? v[u] : lo;
+      hi = v[u] > hi ? v[u] : hi;
+    }
   for (int off = 32; off > 0; off >>= 1) {
     const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
     lo = l2 < lo ? l2 : lo;
@@ -1077,31 +1086,33 @@ __device__ uint64_t select_k_lds(const uint64_t* keys, int n, int k, uint64_t* s
   __syncthreads();
   lo = sh.lo[0];
   hi = sh.hi[0];
+#pragma unroll
   for (int w = 1; w < NW; ++w) {
     lo = sh.lo[w] < lo ? sh.lo[w] : lo;
     hi = sh.hi[w] > hi ? sh.hi[w] : hi;
   }
-  const uint64_t diff = lo ^ hi;
-  const int top = diff ? 63 - __clzll((long long)diff) : -1;
-  if (top < 63) {
-    pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
-    prefix = lo & pmask;
-  }
+  const bool take_all = n <= k;
+  uint64_t prefix = 0, pmask = 0;
+  uint32_t rem = (uint32_t)(take_all ? n : k);
   if (!take_all) {
+    const uint64_t diff = lo ^ hi;
+    const int top = diff ? 63 - __clzll((long long)diff) : -1;
+    if (top < 63) {
+      pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
+      prefix = lo & pmask;
+    }
     for (int hb = top; hb >= 0;) {
       const int lb = hb >= 7 ? hb - 7 : 0;
-      const uint64_t dmask = ((2ull << (hb - lb)) - 1ull);
-      for (int t = tid; t < NH * 256; t += NT) (&sh.hist[0][0])[t] = 0;
+      const uint64_t dmask = (2ull << (hb - lb)) - 1ull;
+      for (int t = tid; t < 4 * 256; t += NT) (&sh.hist[0][0])[t] = 0u;
       __syncthreads();
-      uint32_t* hw = sh.hist[wave % NH];
-      for (int c = tid; c < n; c += NT) {
-        const uint64_t key = keys[c];
-        if ((key & pmask) == prefix) atomicAdd(&hw[(key >> lb) & dmask], 1u);
-      }
+      uint32_t* hw = sh.hist[wave & 3];
+#pragma unroll
+      for (int u = 0; u < KPT; ++u)
+        if (valid(u) && (v[u] & pmask) == prefix) atomicAdd(&hw[(v[u] >> lb) & dmask], 1u);
       __syncthreads();
       uint32_t h = 0;
-      if (tid < 256)
-        for (int t = 0; t < NH; ++t) h += sh.hist[t][tid];
+      if (tid < 256) h = sh.hist[0][tid] + sh.hist[1][tid] + sh.hist[2][tid] + sh.hist[3][tid];
       const uint32_t incl = hist_incl_scan<NT>(h, sh.wsum);
       const uint32_t excl = incl - h;
       if (tid < 256 && excl < rem && rem <= incl) {
@@ -1119,28 +1130,36 @@ __device__ uint64_t select_k_lds(const uint64_t* keys, int n, int k, uint64_t* s
       hb = lb - 1;
     }
   }
-  if (tid == 0) sh.cnt = 0;
-  __syncthreads();
-  const int rounds = (n + NT - 1) / NT;
-  const uint64_t hi_key = prefix | ~pmask;
-  for (int pass = 0; pass < (take_all ? 1 : 2); ++pass) {
-    for (int r = 0; r < rounds; ++r) {
-      const int c = r * NT + tid;
-      const uint64_t key = c < n ? keys[c] : KEY_NONE;
-      const bool t = c < n && (take_all || (pass == 0 ? key < prefix : (key >= prefix && key <= hi_key)));
-      const uint64_t m = __ballot(t);
-      uint32_t base = 0;
-      if (lane == 0 && m) base = atomicAdd(&sh.cnt, (uint32_t)__popcll(m));
-      base = __shfl(base, 0);
-      const uint32_t p = base + lane_prefix(m);
-      if (t && p < (uint32_t)k) sel[p] = key;
+  // keys below the boundary bucket fill [0, k - rem), boundary keys fill
+  // [k - rem, k) until rem are taken (take_all: every key)
+  const uint64_t hi_key = take_all ? ~0ull : (prefix | ~pmask);
+  const uint64_t lt_key = take_all ? 0ull : prefix;
+  const uint32_t nlt = take_all ? 0u : (uint32_t)k - rem;
+  uint32_t clt = 0, ceq = 0;
+#pragma unroll
+  for (int u = 0; u < KPT; ++u)
+    if (valid(u)) {
+      clt += v[u] < lt_key ? 1u : 0u;
+      ceq += (v[u] >= lt_key && v[u] <= hi_key) ? 1u : 0u;
     }
-    __syncthreads();
-  }
-  if (n < k) return KEY_NONE;
-  // the k-th smallest is the largest selected key
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan<NT>((clt << 16) | ceq, sh.wsum, &tot);
+  uint32_t plt = ex >> 16, peq = ex & 0xFFFFu;
   uint64_t mx = 0;
-  for (int i = tid; i < k; i += NT) mx = sel[i] > mx ? sel[i] : mx;
+#pragma unroll
+  for (int u = 0; u < KPT; ++u)
+    if (valid(u)) {
+      if (v[u] < lt_key) {
+        dst[plt++] = v[u];
+        mx = v[u] > mx ? v[u] : mx;
+      } else if (v[u] <= hi_key) {
+        if (peq < rem) {
+          dst[nlt + peq] = v[u];
+          mx = v[u] > mx ? v[u] : mx;
+        }
+        ++peq;
+      }
+    }
   for (int off = 32; off > 0; off >>= 1) {
     const uint64_t o = __shfl_xor(mx, off);
     mx = o > mx ? o : mx;
@@ -1148,19 +1167,39 @@ __device__ uint64_t select_k_lds(const uint64_t* keys, int n, int k, uint64_t* s
   if (lane == 0) sh.hi[wave] = mx;
   __syncthreads();
   uint64_t kth = sh.hi[0];
+#pragma unroll
   for (int w = 1; w < NW; ++w) kth = sh.hi[w] > kth ? sh.hi[w] : kth;
   __syncthreads();
-  return kth;
+  return take_all ? KEY_NONE : kth;
 }
 
+// One micro-block's data for the fused scan, loaded ahead: per lane its
+// vector's code words, factors and id; per wave (uniform, scalar loads) the
+// pair's bit-planes and scalars and the block's place in its list.
+template <int WR, int PR>
+struct FusedSlot {
+  uint32_t cw[WR];
+  float fa, fm;
+  int id;
+  uint32_t pl[PR];
+  float4 sc;
+  int len, mb;
+  int64_t pair;
+};
+
+__device__ inline int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <int WT, int BQT>
-__global__ __launch_bounds__(1024) void k_scan_fused(FusedArgs a) {
-  constexpr int NT = 1024, NW = NT / 64;
-  extern __shared__ uint64_t smem[];
-  __shared__ SelShared<NT> sh;
+__global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
+  constexpr int NT = kFusedNT, NW = NT / 64, KPT = kFusedKPT;
+  constexpr int WR = WT > 0 ? WT : 32;
+  constexpr int PR = (WT > 0 && BQT > 0) ? WT * BQT : 1;  // bit-plane words kept ahead
+  extern __shared__ uint64_t buf[];  // a.cap keys
+  __shared__ SelRegShared<NT> sh;
   __shared__ int32_t s_pre[257];
   __shared__ uint32_t s_n, s_thr;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = uniform_i32(tid >> 6);
   const int i = blockIdx.x;
   if (a.qmask && a.qmask[i] == 0u) return;  // uniform over the workgroup
   const int W = WT > 0 ? WT : a.L.W;
@@ -1168,8 +1207,6 @@ __global__ __launch_bounds__(1024) void k_scan_fused(FusedArgs a) {
   const int bqs = a.Q.bqs;
   const int D = a.L.d;
   const int Rq = a.rowk ? a.rowk[i] : a.R;
-  uint64_t* buf = smem;
-  uint64_t* sel = smem + a.cap;
   uint64_t* row = a.out + (int64_t)i * a.out_ld;
   const size_t rec = (size_t)(W + 2) * 64;
   if (tid == 0) {
@@ -1189,6 +1226,26 @@ __global__ __launch_bounds__(1024) void k_scan_fused(FusedArgs a) {
     if (t) buf[base + lane_prefix(m)] = key;
   }
   __syncthreads();
+  // keep the best Rq of the buffer and lower the threshold (whole workgroup)
+  auto shrink = [&]() __attribute__((always_inline)) {
+    const int n = (int)s_n;
+    uint64_t v[KPT];
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+      const int c = u * NT + tid;
+      v[u] = c < n ? buf[c] : KEY_NONE;
+    }
+    __syncthreads();  // every key read before any is overwritten
+    const uint64_t kth = select_regs<NT, KPT>(v, n, Rq, buf, sh);
+    if (tid == 0) {
+      s_n = (uint32_t)min(n, Rq);
+      if (kth != KEY_NONE) {
+        const uint32_t t = (uint32_t)(kth >> 32);
+        if (t < s_thr) s_thr = t;
+      }
+    }
+    __syncthreads();
+  };
   for (int s0 = 0; s0 < a.pn; s0 += 256) {
     const int sn = min(256, a.pn - s0);
     int cntmb = 0;
@@ -1200,138 +1257,120 @@ __global__ __launch_bounds__(1024) void k_scan_fused(FusedArgs a) {
     if (tid < sn) s_pre[tid + 1] = (int32_t)incl;
     if (tid == 0) s_pre[0] = 0;
     __syncthreads();
-    const int total = s_pre[sn];
-    // this wave's micro-block of each round: its list data are loaded into
-    // registers one round ahead
-    constexpr int WR = WT > 0 ? WT : 32;
-    constexpr int PR = (WT > 0 && BQT > 0) ? WT * BQT : 1;  // bit-plane words kept in registers
-    uint32_t cw[WR], pl[PR];
-    float fa = 0.f, fm = 0.f;
-    float4 c_sc = make_float4(0.f, 0.f, 0.f, 0.f);
-    int c_len = 0, c_pos0 = 0, c_mb = 0, c_id = 0;
-    int64_t c_pair = 0;
-    auto locate = [&](int idx, int64_t& pair, int& len, int& pos0, int& mb) {
+    const int total = uniform_i32(s_pre[sn]);
+    auto load = [&](int idx, FusedSlot<WR, PR>& f) __attribute__((always_inline)) {  // idx: wave-uniform
       int lo = 0, hi = sn;  // s_pre[lo] <= idx < s_pre[hi]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (s_pre[mid] <= idx)
+        if (uniform_i32(s_pre[mid]) <= idx)
           lo = mid;
         else
           hi = mid;
       }
-      mb = idx - s_pre[lo];
-      pair = (int64_t)i * a.nprobe + a.p0 + s0 + lo;
-      const int j = a.probes[pair];
-      len = a.L.list_len[j];
-      pos0 = a.L.list_mb[j] << 6;
-    };
-    auto load = [&](int64_t pair, int len, int pos0, int mb) {
-      const uint32_t* blk = a.L.blocks + (size_t)((pos0 >> 6) + mb) * rec;
+      f.mb = idx - uniform_i32(s_pre[lo]);
+      f.pair = (int64_t)i * a.nprobe + a.p0 + s0 + lo;
+      const int j = uniform_i32(a.probes[f.pair]);
+      f.len = uniform_i32(a.L.list_len[j]);
+      const int pos0 = uniform_i32(a.L.list_mb[j]) << 6;
+      const uint32_t* blk = a.L.blocks + (size_t)((pos0 >> 6) + f.mb) * rec;
 #pragma unroll
       for (int w = 0; w < WR; ++w)
-        if (w < W) cw[w] = blk[w * 64 + lane];
-      fa = __uint_as_float(blk[W * 64 + lane]);
-      fm = __uint_as_float(blk[(W + 1) * 64 + lane]);
-      const int v = (mb << 6) + lane;
-      c_id = v < len ? a.L.pos2id[pos0 + v] : 0;
-      c_sc = a.Q.scal[pair];
+        if (w < W) f.cw[w] = blk[w * 64 + lane];
+      f.fa = __uint_as_float(blk[W * 64 + lane]);
+      f.fm = __uint_as_float(blk[(W + 1) * 64 + lane]);
+      const int v = (f.mb << 6) + lane;
+      f.id = v < f.len ? a.L.pos2id[pos0 + v] : 0;
+      f.sc = a.Q.scal[f.pair];
       if (PR > 1) {
-        const uint32_t* planes = a.Q.planes + pair * W * bqs;
+        const uint32_t* planes = a.Q.planes + f.pair * W * bqs;
 #pragma unroll
         for (int w = 0; w < (WT > 0 ? WT : 1); ++w)
 #pragma unroll
-          for (int t = 0; t < (BQT > 0 ? BQT : 1); ++t) pl[(w * (BQT > 0 ? BQT : 1) + t) % PR] = planes[w * bqs + t];
+          for (int t = 0; t < (BQT > 0 ? BQT : 1); ++t) f.pl[(w * (BQT > 0 ? BQT : 1) + t) % PR] = planes[w * bqs + t];
       }
     };
-    if (wave < total) {
-      locate(wave, c_pair, c_len, c_pos0, c_mb);
-      load(c_pair, c_len, c_pos0, c_mb);
-    }
-    for (int b0 = 0; b0 < total; b0 += NW) {
-      const int idx = b0 + wave;
+    // estimates of one micro-block; survivors appended to the buffer
+    auto scan = [&](const FusedSlot<WR, PR>& f) __attribute__((always_inline)) {
+      const uint32_t* planes = a.Q.planes + f.pair * W * bqs;
+      int acc[BQT > 0 ? BQT : 8];
+#pragma unroll
+      for (int t = 0; t < (BQT > 0 ? BQT : 8); ++t) acc[t] = 0;
+      int pop = 0;
+#pragma unroll
+      for (int w = 0; w < WR; ++w) {
+        if (w < W) {
+          const uint32_t c = f.cw[w];
+          pop += __popc(c);
+#pragma unroll
+          for (int t = 0; t < (BQT > 0 ? BQT : 8); ++t)
+            if (t < BQ)
+              acc[t] += __popc(c & (PR > 1 ? f.pl[(w * (BQT > 0 ? BQT : 1) + t) % PR] : planes[w * bqs + t]));
+        }
+      }
+      int ip = 0;
+#pragma unroll
+      for (int t = 0; t < (BQT > 0 ? BQT : 8); ++t)
+        if (t < BQ) ip += acc[t] << t;
+      const float est =
+          rbq_estimate(f.sc.x, f.sc.y, f.sc.z, -(int)f.sc.w, ip, f.fa, f.fm, rbq_vx(f.fm, pop, D));
+      const int v = (f.mb << 6) + lane;
+      const bool pass = v < f.len && ord_f32(est) <= s_thr;
+      const uint64_t m = __ballot(pass);
+      if (m) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(m));
+        base = __shfl(base, 0);
+        if (pass) buf[base + lane_prefix(m)] = key64(est, (uint32_t)f.id);
+      }
+    };
+    // round r: wave w takes micro-block r * NW + w, from register set r % 2,
+    // which is then refilled with the micro-block two rounds on
+    FusedSlot<WR, PR> A, B;
+    auto round = [&](int idx, FusedSlot<WR, PR>& f) __attribute__((always_inline)) {
       if (idx < total) {
-        uint32_t cur[WR], cpl[PR];
-#pragma unroll
-        for (int w = 0; w < WR; ++w)
-          if (w < W) cur[w] = cw[w];
-#pragma unroll
-        for (int t = 0; t < PR; ++t) cpl[t] = pl[t];
-        const float fadd = fa, fmul = fm;
-        const float4 sc = c_sc;
-        const int len = c_len, mb = c_mb, id = c_id;
-        const int64_t pair = c_pair;
-        if (idx + NW < total) {  // prefetch the next round's micro-block
-          locate(idx + NW, c_pair, c_len, c_pos0, c_mb);
-          load(c_pair, c_len, c_pos0, c_mb);
-        }
-        const uint32_t* planes = a.Q.planes + pair * W * bqs;
-        int acc[BQT > 0 ? BQT : 8];
-        for (int t = 0; t < BQ; ++t) acc[t] = 0;
-        int pop = 0;
-#pragma unroll
-        for (int w = 0; w < WR; ++w) {
-          if (w < W) {
-            const uint32_t c = cur[w];
-            pop += __popc(c);
-#pragma unroll
-            for (int t = 0; t < (BQT > 0 ? BQT : 8); ++t)
-              if (t < BQ)
-                acc[t] += __popc(c & (PR > 1 ? cpl[(w * (BQT > 0 ? BQT : 1) + t) % PR] : planes[w * bqs + t]));
-          }
-        }
-        int ip = 0;
-        for (int t = 0; t < BQ; ++t) ip += acc[t] << t;
-        const float est = rbq_estimate(sc.x, sc.y, sc.z, -(int)sc.w, ip, fadd, fmul, rbq_vx(fmul, pop, D));
-        const int v = (mb << 6) + lane;
-        const bool pass = v < len && ord_f32(est) <= s_thr;
-        const uint64_t m = __ballot(pass);
-        if (m) {
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(m));
-          base = __shfl(base, 0);
-          if (pass) buf[base + lane_prefix(m)] = key64(est, (uint32_t)id);
-        }
+        scan(f);
+        if (idx + 2 * NW < total) load(idx + 2 * NW, f);
       }
       __syncthreads();
-      if (s_n > (uint32_t)(a.cap - NT)) {  // keep the best Rq before the next round could overflow
-        const int n = (int)s_n;
-        const uint64_t kth = select_k_lds<NT>(buf, n, Rq, sel, sh);
-        for (int c = tid; c < Rq; c += NT) buf[c] = sel[c];
-        __syncthreads();
-        if (tid == 0) {
-          s_n = (uint32_t)Rq;
-          const uint32_t t = (uint32_t)(kth >> 32);
-          if (t < s_thr) s_thr = t;
-        }
-        __syncthreads();
-      }
+      // every thread takes the same decision: the fill is read before any wave
+      // of the next round can append
+      const uint32_t fill = s_n;
+      __syncthreads();
+      if (fill > (uint32_t)(a.cap - NT)) shrink();  // the next round could overflow
+    };
+    if (wave < total) load(wave, A);
+    if (NW + wave < total) load(NW + wave, B);
+    for (int b0 = 0; b0 < total; b0 += 2 * NW) {
+      round(b0 + wave, A);
+      round(b0 + NW + wave, B);
     }
     __syncthreads();
   }
-  const int n = (int)s_n;
-  const uint64_t kth = select_k_lds<NT>(buf, n, Rq, sel, sh);
-  const int keep = min(n, Rq);
-  for (int r = tid; r < Rq; r += NT) row[r] = r < keep ? sel[r] : KEY_NONE;
-  if (tid == 0 && kth != KEY_NONE) atomicMin(&a.qthr[i], (uint32_t)(kth >> 32));
+  if ((int)s_n > Rq) shrink();
+  const int keep = min((int)s_n, Rq);
+  for (int r = tid; r < Rq; r += NT) row[r] = r < keep ? buf[r] : KEY_NONE;
+  // s_thr is the R-th estimate of the last selection (the kept keys' R-th when
+  // the buffer ended above Rq), else the threshold the query came with: an
+  // upper bound on its R-th estimate either way
+  if (tid == 0) atomicMin(&a.qthr[i], s_thr);
 }
 
 template <int WT, int BQT>
 static void fused_dispatch(hipStream_t s, const FusedArgs& a, size_t lds) {
-  static std::once_flag once;
-  std::call_once(once, [] {
+  static std::once_flag once;  // (static and dynamic LDS together exceed 64 KB)
+  std::call_once(once, [lds] {
     RBQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_scan_fused<WT, BQT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTopkLdsMax));
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   });
-  hipLaunchKernelGGL((k_scan_fused<WT, BQT>), dim3(a.nq), dim3(1024), lds, s, a);
+  hipLaunchKernelGGL((k_scan_fused<WT, BQT>), dim3(a.nq), dim3(kFusedNT), lds, s, a);
 }
 
 void launch_scan_fused(hipStream_t s, FusedArgs a) {
   if (a.nq <= 0 || a.pn <= 0) return;
-  const int slots = (int)(kTopkLdsMax / sizeof(uint64_t));
-  a.cap = slots - a.R;
-  RBQ_CHECK(a.cap >= a.R + 2 * 1024, "fused scan: rerank_n too large for its LDS buffer");
+  a.cap = kFusedCap;
+  RBQ_CHECK(a.R + kFusedNT <= a.cap - kFusedNT, "fused scan: rerank_n too large for its LDS buffer");
   RBQ_CHECK(a.L.W <= 32, "fused scan supports d <= 1024");
-  const size_t lds = (size_t)(a.cap + a.R) * sizeof(uint64_t);
+  const size_t lds = (size_t)a.cap * sizeof(uint64_t);
   const int bq4 = a.Q.bqs == 4;
   if (bq4 && a.L.W == 4)
     fused_dispatch<4, 4>(s, a, lds);

@@ -123,8 +123,14 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
     for (const TuneCfg& c : cands) {
       const float ms = time_cfg(&c, got_ids, got_d);
       // every choice computes the same exact selection
-      if (got_ids != ref_ids || std::memcmp(got_d.data(), ref_d.data(), got_d.size() * 4) != 0)
-        fail(RBQ_EDEVICE, "autotune: launch choices returned different results");
+      if (got_ids != ref_ids || std::memcmp(got_d.data(), ref_d.data(), got_d.size() * 4) != 0) {
+        char msg[192];
+        std::snprintf(msg, sizeof(msg),
+                      "autotune: launch choices returned different results (scan %d G %d wg_per_cu %d "
+                      "first_factor %d gm %d growth %d early %d)",
+                      c.scan, c.G, c.wg_per_cu, c.first_factor, c.gm, c.growth, c.early);
+        fail(RBQ_EDEVICE, msg);
+      }
       if (!have || ms < best_ms) {
         best = c;
         best_ms = ms;

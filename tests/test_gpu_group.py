@@ -118,6 +118,27 @@ def test_group_candidates_match_oracle(gcase):
             assert abs(e - val[i]) <= tol[i]
 
 
+def test_fused_buffer_shrinks_mid_chunk():
+    """Lists of ~10k vectors: the first fused chunk holds more candidates than
+    the fused kernel's LDS buffer, so it keeps only the best R and lowers the
+    threshold several times while it scans. Results equal the query-major
+    scan's."""
+    _say("[group] fused chunk larger than its buffer: n=640000 d=32 nlist=64 nq=160")
+    X, Q, idx = make_case(640_000, 32, 64, 160, seed=141)
+    lib = lib_index(X, idx)
+    try:
+        lib.set_timing(True)
+        b = _run(lib, Q, 16, 10, 200, scan=0)
+        t = lib.timings()
+        lib.set_timing(False)
+        assert t["popc_launches"] > 0, t  # the fused chunk ran
+        a = _run(lib, Q, 16, 10, 200, scan=1)
+        for key in WANT:
+            np.testing.assert_array_equal(b[key], a[key], err_msg=key)
+    finally:
+        lib.close()
+
+
 def test_fused_and_list_major_chunks_agree():
     """A batch large enough (>= 128 queries) with lists shared by few queries in
     the first chunks: those chunks take the fused one-workgroup-per-query scan,
