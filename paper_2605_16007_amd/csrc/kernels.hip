@@ -691,6 +691,11 @@ static int pow2_at_least(int n) {
 
 constexpr size_t kTopkLdsMax = 150u << 10;  // dynamic LDS of one selection workgroup
 
+// Sorted top-k of float scores with the row in registers (rows of up to
+// kScoreTopkCols scores); defined with the register-resident selection.
+constexpr int kScoreTopkCols = 256 * 16;
+static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows);
+
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   if (rows <= 0) return;
   RBQ_CHECK(a.k >= 1 && a.k <= MAX_SEL, "selection size out of range");
@@ -723,6 +728,10 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
     RBQ_CHECK(a.k <= 512 * 32, "pool merge: running keys exceed one piece");
     hipLaunchKernelGGL((k_pool_merge<512, 32>), dim3(rows), dim3(512), 0, s, a);
     RBQ_HIP(hipGetLastError());
+    return;
+  }
+  if (a.score && a.sorted && a.ncols <= kScoreTopkCols && !a.rowcnt) {
+    launch_score_topk(s, a, rows);
     return;
   }
   if (a.score)
@@ -1171,6 +1180,41 @@ __device__ uint64_t select_regs(const uint64_t (&v)[KPT], int n, int k, uint64_t
   for (int w = 1; w < NW; ++w) kth = sh.hi[w] > kth ? sh.hi[w] : kth;
   __syncthreads();
   return take_all ? KEY_NONE : kth;
+}
+
+// Sorted top-k of a row of float scores (key = ordered score << 32 | column):
+// the row in registers (16 per thread), the k smallest selected, then an LDS
+// bitonic sort of those k.
+template <int NT, int KPT>
+__global__ __launch_bounds__(NT) void k_score_topk(TopkArgs a) {
+  extern __shared__ uint64_t sel[];  // KP keys
+  __shared__ SelRegShared<NT> sh;
+  const int tid = threadIdx.x;
+  const int64_t row = blockIdx.x;
+  const int k = a.rowk ? a.rowk[row] : a.k;
+  const int n = a.ncols;
+  uint64_t v[KPT];
+#pragma unroll
+  for (int u = 0; u < KPT; ++u) {
+    const int c = u * NT + tid;
+    v[u] = c < n ? key64(a.score[row * a.ld + c], (uint32_t)c) : KEY_NONE;
+  }
+  (void)select_regs<NT, KPT>(v, n, k, sel, sh);
+  for (int t = min(n, k) + tid; t < a.KP; t += NT) sel[t] = KEY_NONE;
+  __syncthreads();
+  bitonic_sort_lds(sel, a.KP);
+  for (int t = tid; t < k; t += NT) {
+    const uint64_t x = sel[t];
+    if (a.out_keys) a.out_keys[row * a.ldo + t] = x;
+    if (a.out_low) a.out_low[row * k + t] = x == KEY_NONE ? -1 : (int32_t)(uint32_t)x;
+    if (a.out_val) a.out_val[row * k + t] = x == KEY_NONE ? INFINITY : f32_ord((uint32_t)(x >> 32));
+  }
+}
+
+static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows) {
+  RBQ_CHECK(a.ncols <= kScoreTopkCols && a.KP >= a.k, "score top-k: row too long");
+  hipLaunchKernelGGL((k_score_topk<256, 16>), dim3(rows), dim3(256), (size_t)a.KP * sizeof(uint64_t), s, a);
+  RBQ_HIP(hipGetLastError());
 }
 
 // One micro-block's data for the fused scan, loaded ahead: per lane its

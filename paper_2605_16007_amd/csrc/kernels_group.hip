@@ -38,73 +38,15 @@ __device__ inline int group_chunk_of(const GroupChunks& gc, int p) {
   return c;
 }
 
-// Exclusive prefix sums over the bins of the pair counts and of the item
-// counts ceil(cnt / G), and the item descriptors (list, first slot, pairs);
-// one workgroup of 1024 threads, 1024 bins per round (eight rounds' counts
-// loaded at once).
-__global__ __launch_bounds__(1024) void k_grp_offsets(const int32_t* __restrict__ cnt, int bins, int nlist,
-                                                      int G, int32_t* __restrict__ pair_off,
-                                                      int32_t* __restrict__ item_off,
-                                                      int4* __restrict__ items) {
-  __shared__ int32_t wp[16], wi[16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rounds = (bins + 1023) / 1024;
-  int32_t carry_p = 0, carry_i = 0;
-  for (int r0 = 0; r0 < rounds; r0 += 8) {
-    int32_t cv[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int b = (r0 + u) * 1024 + tid;
-      cv[u] = b < bins ? cnt[b] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (r0 + u >= rounds) break;
-      const int b = (r0 + u) * 1024 + tid;
-      const int32_t c = cv[u], ni = (c + G - 1) / G;
-      int32_t xp = c, xi = ni;  // inclusive scans within the wave
-      for (int off = 1; off < 64; off <<= 1) {
-        const int32_t tp = __shfl_up(xp, off), ti = __shfl_up(xi, off);
-        if (lane >= off) {
-          xp += tp;
-          xi += ti;
-        }
-      }
-      if (lane == 63) {
-        wp[wave] = xp;
-        wi[wave] = xi;
-      }
-      __syncthreads();
-      int32_t a = carry_p + xp - c, bi = carry_i + xi - ni;
-#pragma unroll
-      for (int w = 0; w < 16; ++w) {
-        const int32_t tp = wp[w], ti = wi[w];
-        if (w < wave) {
-          a += tp;
-          bi += ti;
-        }
-        carry_p += tp;
-        carry_i += ti;
-      }
-      __syncthreads();
-      if (b < bins) {
-        pair_off[b] = a;
-        item_off[b] = bi;
-        const int j = b % nlist;
-        for (int g = 0; g < ni; ++g) items[bi + g] = make_int4(j, a + g * G, min(G, c - g * G), 0);
-      }
-    }
-  }
-  if (tid == 0) {
-    pair_off[bins] = carry_p;
-    item_off[bins] = carry_i;
-  }
-}
-
 // rank[j * nq + i] = the probe rank p at which query i probes list j within
 // the list-major ranks (-1 otherwise; cleared by the search's state
-// initialisation); then one wave per list counts, and later fills, its bins
-// with ballots (no atomics; queries in ascending order within a bin).
+// initialisation). Then, without atomics, queries ascending within a bin:
+//   count: one wave per list counts its pairs per chunk (a lane takes 16
+//          consecutive queries of every 1024); each workgroup of 16 lists
+//          adds up its pairs and items (ceil(count / G)) per chunk;
+//   scan:  one workgroup turns the workgroup sums (chunk-major) into bases,
+//          and the item range of every chunk;
+//   fill:  one wave per list places its pairs and writes its items.
 __global__ void k_grp_mark(const int32_t* __restrict__ probes, int nq, int nprobe, int r0,
                            int16_t* __restrict__ rank) {
   const int span = nprobe - r0;
@@ -116,53 +58,165 @@ __global__ void k_grp_mark(const int32_t* __restrict__ probes, int nq, int nprob
   if (j >= 0) rank[(int64_t)j * nq + i] = (int16_t)p;
 }
 
-__global__ __launch_bounds__(256) void k_grp_count(const int16_t* __restrict__ rank, int nq, GroupChunks gc,
-                                                   int nlist, int32_t* __restrict__ cnt) {
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (j >= nlist) return;
+constexpr int kMapLists = 16;  // lists (waves) per map workgroup
+
+// per lane: how many of its queries [i0, i0 + 16) fall in each chunk
+__device__ inline void map_lane_counts(const int16_t* rj, int i0, int nq, const GroupChunks& gc,
+                                       int32_t (&c)[kMaxGroupChunks]) {
+  int16_t p[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) p[e] = i0 + e < nq ? rj[i0 + e] : (int16_t)-1;
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    if (p[e] >= 0) {
+      const int ch = group_chunk_of(gc, p[e]);
+#pragma unroll
+      for (int b = 0; b < kMaxGroupChunks; ++b) c[b] += b == ch ? 1 : 0;
+    }
+}
+
+__device__ inline int32_t wave_sum(int32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ inline int32_t wave_excl(int32_t v) {
+  const int lane = threadIdx.x & 63;
+  int32_t x = v;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t t = __shfl_up(x, off);
+    if (lane >= off) x += t;
+  }
+  return x - v;
+}
+
+__global__ __launch_bounds__(1024) void k_grp_count(const int16_t* __restrict__ rank, int nq, GroupChunks gc,
+                                                    int nlist, int G, int nwg, int32_t* __restrict__ cnt,
+                                                    int32_t* __restrict__ wpart) {
+  __shared__ int32_t sc[kMaxGroupChunks][kMapLists];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wg = blockIdx.x;
+  const int j = wg * kMapLists + wave;
   int32_t c[kMaxGroupChunks];
 #pragma unroll
   for (int b = 0; b < kMaxGroupChunks; ++b) c[b] = 0;
-  const int16_t* rj = rank + (int64_t)j * nq;
-  for (int i0 = 0; i0 < nq; i0 += 64) {
-    const int i = i0 + lane;
-    const int p = i < nq ? rj[i] : -1;
-    const int ch = p >= 0 ? group_chunk_of(gc, p) : -1;
-#pragma unroll
-    for (int b = 0; b < kMaxGroupChunks; ++b)
-      if (b < gc.nb) c[b] += (int32_t)__popcll(__builtin_amdgcn_ballot_w64(ch == b));
+  if (j < nlist) {
+    const int16_t* rj = rank + (int64_t)j * nq;
+    for (int i0 = 16 * lane; i0 < nq; i0 += 1024) map_lane_counts(rj, i0, nq, gc, c);
   }
-  if (lane < gc.nb) {
-    int32_t v = 0;
 #pragma unroll
-    for (int b = 0; b < kMaxGroupChunks; ++b) v = b == lane ? c[b] : v;
-    cnt[lane * nlist + j] = v;
+  for (int b = 0; b < kMaxGroupChunks; ++b) {
+    if (b >= gc.nb) break;
+    const int32_t tot = wave_sum(c[b]);
+    if (lane == 0) {
+      sc[b][wave] = tot;
+      if (j < nlist) cnt[b * nlist + j] = tot;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < gc.nb) {
+    const int b = threadIdx.x;
+    int32_t pairs = 0, items = 0;
+    for (int w = 0; w < kMapLists; ++w) {
+      pairs += sc[b][w];
+      items += (sc[b][w] + G - 1) / G;
+    }
+    wpart[b * nwg + wg] = pairs;
+    wpart[(gc.nb + b) * nwg + wg] = items;
   }
 }
 
-__global__ __launch_bounds__(256) void k_grp_fill(const int16_t* __restrict__ rank, int nq, int nprobe,
-                                                  GroupChunks gc, int nlist,
-                                                  const int32_t* __restrict__ pair_off,
-                                                  int32_t* __restrict__ slots) {
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+// In place: wpart[0..V) pair sums and wpart[V..2V) item sums (V = nb * nwg,
+// chunk-major) become exclusive bases; chunk_items[c] = the first item of
+// chunk c (chunk_items[nb] = all items). One workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_grp_scan(int32_t* __restrict__ wpart, int V, int nwg, int nb,
+                                                   int32_t* __restrict__ chunk_items) {
+  __shared__ int32_t wp[16], wi[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int32_t carry_p = 0, carry_i = 0;
+  for (int v0 = 0; v0 < V; v0 += 1024) {
+    const int v = v0 + tid;
+    const int32_t p = v < V ? wpart[v] : 0, it = v < V ? wpart[V + v] : 0;
+    int32_t xp = p, xi = it;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t tp = __shfl_up(xp, off), ti = __shfl_up(xi, off);
+      if (lane >= off) {
+        xp += tp;
+        xi += ti;
+      }
+    }
+    if (lane == 63) {
+      wp[wave] = xp;
+      wi[wave] = xi;
+    }
+    __syncthreads();
+    int32_t a = carry_p + xp - p, bi = carry_i + xi - it;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const int32_t tp = wp[w], ti = wi[w];
+      if (w < wave) {
+        a += tp;
+        bi += ti;
+      }
+      carry_p += tp;
+      carry_i += ti;
+    }
+    __syncthreads();
+    if (v < V) {
+      wpart[v] = a;
+      wpart[V + v] = bi;
+      if (v % nwg == 0) chunk_items[v / nwg] = bi;
+    }
+  }
+  if (tid == 0) chunk_items[nb] = carry_i;
+}
+
+__global__ __launch_bounds__(1024) void k_grp_fill(const int16_t* __restrict__ rank, int nq, int nprobe,
+                                                   GroupChunks gc, int nlist, int G, int nwg,
+                                                   const int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ wpart,
+                                                   int32_t* __restrict__ slots, int4* __restrict__ items) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wg = blockIdx.x;
+  const int j = wg * kMapLists + wave;
   if (j >= nlist) return;
+  const int V = gc.nb * nwg;
+  // this list's bases per chunk: the workgroup's base plus the lists before it
   int32_t pos[kMaxGroupChunks];
 #pragma unroll
-  for (int b = 0; b < kMaxGroupChunks; ++b) pos[b] = b < gc.nb ? pair_off[b * nlist + j] : 0;
+  for (int b = 0; b < kMaxGroupChunks; ++b) {
+    if (b >= gc.nb) break;
+    const int jl = wg * kMapLists + lane;
+    const int32_t cl = lane < wave && jl < nlist ? cnt[b * nlist + jl] : 0;
+    const int32_t pb = wpart[b * nwg + wg] + wave_sum(cl);
+    const int32_t ib = wpart[V + b * nwg + wg] + wave_sum((cl + G - 1) / G);
+    const int32_t cn = cnt[b * nlist + j];
+    for (int g = lane; g * G < cn; g += 64) items[ib + g] = make_int4(j, pb + g * G, min(G, cn - g * G), 0);
+    pos[b] = pb;
+  }
   const int16_t* rj = rank + (int64_t)j * nq;
-  for (int i0 = 0; i0 < nq; i0 += 64) {
-    const int i = i0 + lane;
-    const int p = i < nq ? rj[i] : -1;
-    const int ch = p >= 0 ? group_chunk_of(gc, p) : -1;
+  for (int blk = 0; blk < nq; blk += 1024) {
+    const int i0 = blk + 16 * lane;
+    int32_t c[kMaxGroupChunks];
+#pragma unroll
+    for (int b = 0; b < kMaxGroupChunks; ++b) c[b] = 0;
+    map_lane_counts(rj, i0, nq, gc, c);
+    int32_t at[kMaxGroupChunks];  // this lane's first position per chunk
 #pragma unroll
     for (int b = 0; b < kMaxGroupChunks; ++b) {
       if (b >= gc.nb) break;
-      const uint64_t m = __builtin_amdgcn_ballot_w64(ch == b);
-      if (ch == b)
-        slots[pos[b] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
-            (int32_t)((int64_t)i * nprobe + p);
-      pos[b] += (int32_t)__popcll(m);
+      at[b] = pos[b] + wave_excl(c[b]);
+      pos[b] += wave_sum(c[b]);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int i = i0 + e;
+      const int p = i < nq ? rj[i] : -1;
+      if (p >= 0) {
+        const int ch = group_chunk_of(gc, p);
+        int32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < kMaxGroupChunks; ++b)
+          if (b == ch) o = at[b]++;
+        slots[o] = (int32_t)((int64_t)i * nprobe + p);
+      }
     }
   }
 }
@@ -245,7 +299,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     }
     __builtin_amdgcn_wave_barrier();
   };
-  const int first_item = a.item_off[0], end_item = a.item_off[nlist];
+  const int first_item = a.item_off[0], end_item = a.item_off[1];
   if (tid < 256) {
     const v4i u = unpack16((uint32_t)tid);
     sLut[tid] = make_uint2((uint32_t)u[0], (uint32_t)u[1]);
@@ -415,25 +469,27 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 }
 
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
-                      int nlist, int G, int16_t* rank, int32_t* cnt, int32_t* pair_off, int32_t* item_off,
+                      int nlist, int G, int16_t* rank, int32_t* cnt, int32_t* wpart, int32_t* chunk_items,
                       int32_t* slots, int4* items) {
   RBQ_CHECK(gc.nb >= 1 && gc.nb <= kMaxGroupChunks && gc.bound[gc.nb] == nprobe,
             "list-major chunk bounds");
   RBQ_CHECK(nprobe <= 32767, "list-major map: nprobe out of range");
   const int64_t pairs = (int64_t)nq * (nprobe - gc.bound[0]);
   if (pairs <= 0) return;
-  const unsigned lgrid = (unsigned)((nlist + 3) / 4);
+  const int nwg = group_map_workgroups(nlist);
   hipLaunchKernelGGL(k_grp_mark, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, probes, nq, nprobe,
                      gc.bound[0], rank);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_count, dim3(lgrid), dim3(256), 0, s, rank, nq, gc, nlist, cnt);
+  hipLaunchKernelGGL(k_grp_count, dim3(nwg), dim3(1024), 0, s, rank, nq, gc, nlist, G, nwg, cnt, wpart);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_offsets, dim3(1), dim3(1024), 0, s, cnt, gc.nb * nlist, nlist, G, pair_off,
-                     item_off, items);
+  hipLaunchKernelGGL(k_grp_scan, dim3(1), dim3(1024), 0, s, wpart, gc.nb * nwg, nwg, gc.nb, chunk_items);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_fill, dim3(lgrid), dim3(256), 0, s, rank, nq, nprobe, gc, nlist, pair_off, slots);
+  hipLaunchKernelGGL(k_grp_fill, dim3(nwg), dim3(1024), 0, s, rank, nq, nprobe, gc, nlist, G, nwg, cnt, wpart,
+                     slots, items);
   RBQ_HIP(hipGetLastError());
 }
+
+int group_map_workgroups(int nlist) { return (nlist + kMapLists - 1) / kMapLists; }
 
 int group_k_steps(int d) { return (d + 63) / 64; }
 

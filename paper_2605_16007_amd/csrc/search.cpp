@@ -76,8 +76,8 @@ struct Bufs {
   uint8_t* qu8 = nullptr;
   int32_t* gcnt = nullptr;
   int16_t* rankmat = nullptr;  // nlist x nq probe ranks (list-major map)
-  int32_t* pair_off = nullptr;
-  int32_t* item_off = nullptr;
+  int32_t* wpart = nullptr;        // list-major map: workgroup sums, then bases
+  int32_t* chunk_items = nullptr;  // list-major map: item range of every chunk
   int32_t* slots = nullptr;
   int4* items = nullptr;
   uint32_t* overflow = nullptr;
@@ -260,8 +260,8 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   if (P.any_group) {
     const int64_t bins = (int64_t)P.gc.nb * nlist;
     b.gcnt = c.take<int32_t>(bins);
-    b.pair_off = c.take<int32_t>(bins + 1);
-    b.item_off = c.take<int32_t>(bins + 1);
+    b.wpart = c.take<int32_t>((size_t)2 * P.gc.nb * group_map_workgroups(nlist));
+    b.chunk_items = c.take<int32_t>(kMaxGroupChunks + 1);
     b.slots = c.take<int32_t>(pairs);
     b.items = c.take<int4>(pairs / P.G + bins + 1);
     b.overflow = c.take<uint32_t>(nq);
@@ -507,8 +507,8 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     }
     // the (chunk, list) -> pairs map of every list-major chunk
     if (any_group)
-      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, b.rankmat, b.gcnt, b.pair_off,
-                       b.item_off, b.slots, b.items);
+      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, b.rankmat, b.gcnt, b.wpart,
+                       b.chunk_items, b.slots, b.items);
     sa.pcnt = b.pcnt;
     sa.qmask = nullptr;
     GroupArgs ga;
@@ -522,8 +522,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     ga.G = P.G;
     ga.bq = idx->bq;
     ga.slots = b.slots;
-    ga.pair_off = b.pair_off;
-    ga.item_off = b.item_off;
+    ga.item_off = b.chunk_items;
     ga.items = b.items;
     ga.any_overflow = b.counter;
     ga.qthr = b.qthr;
@@ -572,7 +571,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     auto scan_group_chunk = [&](const Chunk& ch) {
       const int c = lm_chunk++;
       RBQ_CHECK(c < P.gc.nb && P.gc.bound[c] == ch.p0, "list-major chunk order");
-      ga.item_off = b.item_off + (int64_t)c * nlist;
+      ga.item_off = b.chunk_items + c;
       ga.item_counter = b.counter + 1 + c;
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (timed) {

@@ -79,7 +79,7 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
         for (int G : {32, 64})
           for (int wg : {4, 8})
             for (int ff : {1, 2, 4})
-              for (int gr : {2, 3, 4}) cands.push_back(TuneCfg{2, G, wg, ff, gm, gr, early});
+              for (int gr : {2, 3, 4, 6, 8}) cands.push_back(TuneCfg{2, G, wg, ff, gm, gr, early});
       }
 
   hipStream_t s = nullptr;

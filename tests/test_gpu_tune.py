@@ -36,7 +36,8 @@ def test_autotune_keeps_results(tcase, nprobe, R):
     before = lib.search(Q, nprobe, 10, R)
     r = lib.autotune(Q, nprobe, 10, R)
     _say(f"[tune] chose {r}")
-    assert r["scan"] in (1, 2) and r["trials"] == 217 and r["chunk_group_min"] in (0, 4, 16, 64) and r["growth"] in (2, 3, 4)
+    assert r["scan"] in (1, 2) and r["trials"] == 361 and r["chunk_group_min"] in (0, 4, 16, 64)
+    assert r["growth"] in (2, 3, 4, 6, 8)
     assert r["early_form"] in (0, 1)
     assert r["group_size"] in (32, 64) and r["wg_per_cu"] in (4, 8) and r["first_factor"] in (1, 2, 4)
     assert r["ms"] > 0 and r["ms"] <= r["ms_default"] * 1.5
