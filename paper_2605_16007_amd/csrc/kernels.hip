@@ -831,7 +831,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
 #pragma unroll
       for (int u = 0; u < 8; ++u) r[u] = a[u] - c[u];
     }
-    uint32_t lo = 0, hi = 0, pb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int dd = d0 + u;
@@ -850,16 +850,22 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
         lo |= q << (8 * u);
       else
         hi |= q << (8 * (u - 4));
-#pragma unroll
-      for (int b = 0; b < 8; ++b) pb[b] |= ((q >> b) & 1u) << u;
     }
     // plane word w (dimensions 32w..32w+31) from the bytes of lanes 4k..4k+3
-    // of the pair (k = g / 4): lane 4k + t stores planes t and t + 4
+    // of the pair (k = g / 4): lane 4k + t stores planes t and t + 4. Bit b
+    // of each of four bytes is gathered by one multiply: the bits sit at 0,
+    // 8, 16, 24 and x 0x10204080 moves them to 28..31 with no carries.
     const int t = g & 3;
     uint32_t wd[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      uint32_t v = pb[b] << (8 * t);
+      if (b >= bqs) {
+        wd[b] = 0u;
+        continue;
+      }
+      const uint32_t pl = (((lo >> b) & 0x01010101u) * 0x10204080u) >> 28;
+      const uint32_t ph = (((hi >> b) & 0x01010101u) * 0x10204080u) >> 28;
+      uint32_t v = (pl | (ph << 4)) << (8 * t);
       v |= __shfl_xor(v, 1);
       v |= __shfl_xor(v, 2);
       wd[b] = v;
