@@ -340,13 +340,6 @@ struct Pinned {
   }
 };
 
-// An event that lives for one scope.
-struct ScopedEvent {
-  hipEvent_t e = nullptr;
-  ScopedEvent() { RBQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
-  ~ScopedEvent() { (void)hipEventDestroy(e); }
-};
-
 void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
                  float* dist, hipStream_t s, const SearchIO& io, HostJob* job) {
   if (nq == 0) return;
@@ -652,60 +645,63 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
                       ids_out, dist_out, d_k);
     };
-    // queries whose pool overflowed in a list-major chunk are searched again,
-    // from scratch, by the query-major scan; the host reads one flag per search
-    auto redo_overflowed = [&]() {
+    // Queries whose pool overflowed in a list-major chunk are searched again,
+    // from scratch and exactly. On the device (d <= 1024): their rows and
+    // thresholds are reset and the fused scan, masked to them, covers every
+    // probe rank; its workgroups of other queries return at once, so nothing
+    // waits for the host. Otherwise the host reads one flag and, if it is
+    // set, the query-major scan redoes them.
+    if (any_group) {
       launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
-      sa.qmask = b.overflow;
-      for (const auto& ch : qm_chunks) scan_popc_chunk(ch);
-      sa.qmask = nullptr;
-    };
-    if (any_group && !job && !dbg) {
-      // the re-rank is queued before the flag is read (an overflow is rare),
-      // so the GPU never waits for the host here; after an overflow the
-      // redone queries are re-ranked again
-      Pinned flag(idx, sizeof(uint32_t));
-      ScopedEvent flag_ev;
-      RBQ_HIP(hipMemcpyAsync(flag.p, b.counter, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      RBQ_HIP(hipEventRecord(flag_ev.e, s));
-      mark(4);
-      rerank_on_gpu();
-      RBQ_HIP(hipEventSynchronize(flag_ev.e));
-      if (*static_cast<const uint32_t*>(flag.p)) {
-        redo_overflowed();
-        rerank_on_gpu();
-      }
-    } else {
-      if (any_group) {
+      if (idx->W <= 32) {
+        FusedArgs ra = fa;
+        ra.p0 = 0;
+        ra.pn = nprobe;
+        ra.qmask = b.overflow;
+        launch_scan_fused(s, ra);
+      } else {
         uint32_t any = 0;
         RBQ_HIP(hipMemcpyAsync(&any, b.counter, sizeof(any), hipMemcpyDeviceToHost, s));
         RBQ_HIP(hipStreamSynchronize(s));
-        if (any) redo_overflowed();
+        if (any) {
+          sa.qmask = b.overflow;
+          for (const auto& ch : qm_chunks) scan_popc_chunk(ch);
+          sa.qmask = nullptr;
+        }
       }
-      if (dbg && (dbg->cand_ids || dbg->cand_est)) {  // the debug output lists candidates ascending
-        TopkArgs so;
-        so.keys = b.cand;
-        so.ld = cand_ld;
-        so.ncols = R;
-        so.k = R;
-        so.out_keys = b.cand;
-        so.ldo = cand_ld;
-        so.rowk = d_R;
-        launch_row_topk(s, so, (int)nq);
-      }
-      mark(4);
-      if (job) {
-        // Phase 5 on host cores: hand the candidates (and the queries, if they
-        // are only on the device) over in pinned memory
-        RBQ_HIP(hipMemcpy2DAsync(job->cand, R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
-                                 R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
-        if (qdev)
-          RBQ_HIP(hipMemcpy2DAsync(job->qh, d * sizeof(float), qd, (need_qcopy ? ld : d) * sizeof(float),
-                                   d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
-        RBQ_HIP(hipEventRecord(job->ready, s));
-      } else {
-        rerank_on_gpu();
-      }
+    }
+    int64_t* ids_out = ids_dev ? ids : b.ids;
+    float* dist_out = dist_dev ? dist : b.dist;
+    const uint64_t* top = b.cand;
+    if (dbg && (dbg->cand_ids || dbg->cand_est)) {  // the debug output lists candidates ascending
+      TopkArgs so;
+      so.keys = b.cand;
+      so.ld = cand_ld;
+      so.ncols = R;
+      so.k = R;
+      so.out_keys = b.cand;
+      so.ldo = cand_ld;
+      so.rowk = d_R;
+      launch_row_topk(s, so, (int)nq);
+    }
+    mark(4);
+    if (job) {
+      // Phase 5 on host cores: hand the candidates (and the queries, if they
+      // are only on the device) over in pinned memory
+      RBQ_HIP(hipMemcpy2DAsync(job->cand, R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
+                               R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
+      if (qdev)
+        RBQ_HIP(hipMemcpy2DAsync(job->qh, d * sizeof(float), qd, (need_qcopy ? ld : d) * sizeof(float),
+                                 d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
+      RBQ_HIP(hipEventRecord(job->ready, s));
+    } else {
+      // Phase 5: exact re-rank of the top-R on the GPU
+      if (idx->X8.p)
+        launch_rerank_u8(s, qd, ld, idx->X8.as<uint8_t>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
+                         ids_out, dist_out, d_k);
+      else
+        launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
+                      ids_out, dist_out, d_k);
     }
     mark(5);
 
