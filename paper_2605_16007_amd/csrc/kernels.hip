@@ -1062,7 +1062,6 @@ void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
 constexpr int kFusedNT = 512;                 // threads per workgroup
 constexpr int kFusedKPT = 16;                 // buffer keys per thread in a selection
 constexpr int kFusedCap = kFusedNT * kFusedKPT;  // LDS buffer keys (64 KB)
-constexpr int kFusedCheck = 4;                // rounds between fill checks (even)
 
 template <int NT>
 struct SelRegShared {
@@ -1375,28 +1374,25 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
       }
     };
     // round r: wave w takes micro-block r * NW + w, from register set r % 2,
-    // which is then refilled with the micro-block two rounds on. The waves
-    // meet every kFusedCheck rounds (a round appends at most NT keys): the
-    // fill is read by every thread before any wave of the next rounds can
-    // append, so all take the same decision.
+    // which is then refilled with the micro-block two rounds on
     FusedSlot<WR, PR> A, B;
     auto round = [&](int idx, FusedSlot<WR, PR>& f) __attribute__((always_inline)) {
       if (idx < total) {
         scan(f);
         if (idx + 2 * NW < total) load(idx + 2 * NW, f);
       }
+      __syncthreads();
+      // every thread takes the same decision: the fill is read before any wave
+      // of the next round can append
+      const uint32_t fill = s_n;
+      __syncthreads();
+      if (fill > (uint32_t)(a.cap - NT)) shrink();  // the next round could overflow
     };
     if (wave < total) load(wave, A);
     if (NW + wave < total) load(NW + wave, B);
     for (int b0 = 0; b0 < total; b0 += 2 * NW) {
       round(b0 + wave, A);
       round(b0 + NW + wave, B);
-      if ((b0 / (2 * NW)) % (kFusedCheck / 2) == kFusedCheck / 2 - 1 || b0 + 2 * NW >= total) {
-        __syncthreads();
-        const uint32_t fill = s_n;
-        __syncthreads();
-        if (fill > (uint32_t)(a.cap - kFusedCheck * NT)) shrink();  // the next rounds could overflow
-      }
     }
     __syncthreads();
   }
@@ -1422,8 +1418,7 @@ static void fused_dispatch(hipStream_t s, const FusedArgs& a, size_t lds) {
 void launch_scan_fused(hipStream_t s, FusedArgs a) {
   if (a.nq <= 0 || a.pn <= 0) return;
   a.cap = kFusedCap;
-  RBQ_CHECK(a.R + kFusedNT <= a.cap - kFusedCheck * kFusedNT,
-            "fused scan: rerank_n too large for its LDS buffer");
+  RBQ_CHECK(a.R + kFusedNT <= a.cap - kFusedNT, "fused scan: rerank_n too large for its LDS buffer");
   RBQ_CHECK(a.L.W <= 32, "fused scan supports d <= 1024");
   const size_t lds = (size_t)a.cap * sizeof(uint64_t);
   const int bq4 = a.Q.bqs == 4;

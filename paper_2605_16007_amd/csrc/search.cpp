@@ -634,17 +634,6 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       else
         scan_popc_chunk(ch);
     }
-    int64_t* ids_out = ids_dev ? ids : b.ids;
-    float* dist_out = dist_dev ? dist : b.dist;
-    const uint64_t* top = b.cand;
-    auto rerank_on_gpu = [&]() {  // Phase 5: exact re-rank of the top-R on the GPU
-      if (idx->X8.p)
-        launch_rerank_u8(s, qd, ld, idx->X8.as<uint8_t>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
-                         ids_out, dist_out, d_k);
-      else
-        launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
-                      ids_out, dist_out, d_k);
-    };
     // Queries whose pool overflowed in a list-major chunk are searched again,
     // from scratch and exactly. On the device (d <= 1024): their rows and
     // thresholds are reset and the fused scan, masked to them, covers every
