@@ -1247,7 +1247,9 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
   extern __shared__ uint64_t buf[];  // a.cap keys
   __shared__ SelRegShared<NT> sh;
   __shared__ int32_t s_pre[257];
+  __shared__ int32_t s_lpos[256], s_llen[256];  // the group's lists: first position, length
   __shared__ uint32_t s_n, s_thr;
+  __shared__ uint32_t s_cnt[3];  // appends of round r counted in s_cnt[r % 3]
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = uniform_i32(tid >> 6);
   const int i = blockIdx.x;
@@ -1262,6 +1264,7 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
   if (tid == 0) {
     s_n = 0;
     s_thr = a.qthr[i];
+    s_cnt[0] = s_cnt[1] = s_cnt[2] = 0u;
   }
   __syncthreads();
   // the running top-R
@@ -1276,9 +1279,12 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
     if (t) buf[base + lane_prefix(m)] = key;
   }
   __syncthreads();
+  // buffer fill (the same value in every thread) and round number
+  int fill = (int)s_n;
+  int rr = 0;
   // keep the best Rq of the buffer and lower the threshold (whole workgroup)
   auto shrink = [&]() __attribute__((always_inline)) {
-    const int n = (int)s_n;
+    const int n = fill;
     uint64_t v[KPT];
 #pragma unroll
     for (int u = 0; u < KPT; ++u) {
@@ -1287,8 +1293,8 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
     }
     __syncthreads();  // every key read before any is overwritten
     const uint64_t kth = select_regs<NT, KPT>(v, n, Rq, buf, sh);
+    fill = min(n, Rq);
     if (tid == 0) {
-      s_n = (uint32_t)min(n, Rq);
       if (kth != KEY_NONE) {
         const uint32_t t = (uint32_t)(kth >> 32);
         if (t < s_thr) s_thr = t;
@@ -1301,7 +1307,10 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
     int cntmb = 0;
     if (tid < sn) {
       const int j = a.probes[(int64_t)i * a.nprobe + a.p0 + s0 + tid];
-      cntmb = j >= 0 ? (a.L.list_len[j] + 63) >> 6 : 0;
+      const int len = j >= 0 ? a.L.list_len[j] : 0;
+      cntmb = (len + 63) >> 6;
+      s_llen[tid] = len;
+      s_lpos[tid] = j >= 0 ? a.L.list_mb[j] << 6 : 0;
     }
     const uint32_t incl = hist_incl_scan<NT>((uint32_t)cntmb, sh.wsum);
     if (tid < sn) s_pre[tid + 1] = (int32_t)incl;
@@ -1319,9 +1328,8 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
       }
       f.mb = idx - uniform_i32(s_pre[lo]);
       f.pair = (int64_t)i * a.nprobe + a.p0 + s0 + lo;
-      const int j = uniform_i32(a.probes[f.pair]);
-      f.len = uniform_i32(a.L.list_len[j]);
-      const int pos0 = uniform_i32(a.L.list_mb[j]) << 6;
+      f.len = uniform_i32(s_llen[lo]);
+      const int pos0 = uniform_i32(s_lpos[lo]);
       const uint32_t* blk = a.L.blocks + (size_t)((pos0 >> 6) + f.mb) * rec;
 #pragma unroll
       for (int w = 0; w < WR; ++w)
@@ -1340,7 +1348,7 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
       }
     };
     // estimates of one micro-block; survivors appended to the buffer
-    auto scan = [&](const FusedSlot<WR, PR>& f) __attribute__((always_inline)) {
+    auto scan = [&](const FusedSlot<WR, PR>& f, int par) __attribute__((always_inline)) {
       const uint32_t* planes = a.Q.planes + f.pair * W * bqs;
       int acc[BQT > 0 ? BQT : 8];
 #pragma unroll
@@ -1368,25 +1376,29 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
       const uint64_t m = __ballot(pass);
       if (m) {
         uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&s_n, (uint32_t)__popcll(m));
+        if (lane == 0) base = (uint32_t)fill + atomicAdd(&s_cnt[par], (uint32_t)__popcll(m));
         base = __shfl(base, 0);
         if (pass) buf[base + lane_prefix(m)] = key64(est, (uint32_t)f.id);
       }
     };
     // round r: wave w takes micro-block r * NW + w, from register set r % 2,
-    // which is then refilled with the micro-block two rounds on
+    // which is then refilled with the micro-block two rounds on. Round r
+    // appends behind the fill through counter s_cnt[r % 3]; the counter of
+    // round r + 1 is cleared during round r (its last readers, after round
+    // r - 2's barrier, are all past round r - 1's), so one barrier per round
+    // gives every thread the same fill.
     FusedSlot<WR, PR> A, B;
     auto round = [&](int idx, FusedSlot<WR, PR>& f) __attribute__((always_inline)) {
+      const int par = rr % 3;
+      if (tid == 0) s_cnt[(rr + 1) % 3] = 0u;
       if (idx < total) {
-        scan(f);
+        scan(f, par);
         if (idx + 2 * NW < total) load(idx + 2 * NW, f);
       }
       __syncthreads();
-      // every thread takes the same decision: the fill is read before any wave
-      // of the next round can append
-      const uint32_t fill = s_n;
-      __syncthreads();
-      if (fill > (uint32_t)(a.cap - NT)) shrink();  // the next round could overflow
+      fill += (int)s_cnt[par];
+      ++rr;
+      if (fill > a.cap - NT) shrink();  // the next round could overflow
     };
     if (wave < total) load(wave, A);
     if (NW + wave < total) load(NW + wave, B);
@@ -1396,8 +1408,8 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
     }
     __syncthreads();
   }
-  if ((int)s_n > Rq) shrink();
-  const int keep = min((int)s_n, Rq);
+  if (fill > Rq) shrink();
+  const int keep = min(fill, Rq);
   for (int r = tid; r < Rq; r += NT) row[r] = r < keep ? buf[r] : KEY_NONE;
   // s_thr is the R-th estimate of the last selection (the kept keys' R-th when
   // the buffer ended above Rq), else the threshold the query came with: an
