@@ -750,6 +750,11 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
 // qu = floor((r - v_l)/Delta + 1/2) clamped; ||r||^2 and sum qu. The qu bytes
 // are stored 8 per lane, and bit-plane word w (dimensions 32w..32w+31) is
 // assembled from the bytes of the four lanes that hold those dimensions.
+// Workgroup (x, y) takes query x and probe ranks 16y..16y+15. The pair's
+// reductions run on DPP lane moves inside its 16-lane row: rotations by 8 and
+// 4, then swaps within quads by 2 and 1, which combine the same pairs in the
+// same order as an xor butterfly over 8, 4, 2, 1, so lane 0's sum of squares
+// is that butterfly's.
 // ---------------------------------------------------------------------------
 
 __device__ inline void load8(const float* p, int d0, int d, float (&v)[8]) {
@@ -764,24 +769,36 @@ __device__ inline void load8(const float* p, int d0, int d, float (&v)[8]) {
   }
 }
 
+// the value of lane CTRL(lane) of this lane's row of 16 (DPP control CTRL)
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline float dpp_f32(float v) {
+  return __uint_as_float(dpp_u32<CTRL>(__float_as_uint(v)));
+}
+constexpr int kDppRor8 = 0x128, kDppRor4 = 0x124;  // row rotations
+constexpr int kDppXor2 = 0x4E, kDppXor1 = 0xB1;    // quad permutations [2,3,0,1], [1,0,3,2]
+
+template <int STEPS, bool INJ>
 __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, int ldq,
                                                const float* __restrict__ crot, int ldc,
-                                               const int32_t* __restrict__ probes, int64_t npairs,
-                                               int nprobe, int d, int W, int bq, int bqs,
-                                               uint32_t* __restrict__ planes,
+                                               const int32_t* __restrict__ probes, int nprobe, int d,
+                                               int W, int bq, int bqs, uint32_t* __restrict__ planes,
                                                uint8_t* __restrict__ qu_out, float4* __restrict__ scal,
                                                const uint8_t* __restrict__ inj_qu,
                                                const float* __restrict__ inj_scal) {
   const int g = threadIdx.x & 15;
-  const int64_t pair = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;
-  const bool active = pair < npairs;  // (the 16 lanes of a pair agree)
-  const int64_t pr = active ? pair : 0;
-  const int64_t i = pr / nprobe;
+  const int64_t i = blockIdx.x;
+  const int p = (int)blockIdx.y * 16 + (int)(threadIdx.x >> 4);
+  const bool active = p < nprobe;  // (the 16 lanes of a pair agree)
+  const int64_t pr = i * nprobe + (active ? p : 0);
   const int j = max(probes[pr], 0);  // -1 (not probed): computed on list 0 and never used
   const float* qr = qrot + i * ldq;
   const float* cr = crot + (int64_t)j * ldc;
   const int Wq = W * 32;
-  const int steps = (Wq + 127) / 128;
+  const int steps = STEPS > 0 ? STEPS : (Wq + 127) / 128;
   float rmin = INFINITY, rmax = -INFINITY, ss = 0.f;
   float r0[8];  // the first step's residuals (all of them when d <= 128)
   for (int st = 0; st < steps; ++st) {
@@ -800,13 +817,20 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
       }
     }
   }
-  for (int off = 8; off > 0; off >>= 1) {  // within the pair's 16 lanes
-    rmin = fminf(rmin, __shfl_xor(rmin, off));
-    rmax = fmaxf(rmax, __shfl_xor(rmax, off));
-    ss += __shfl_xor(ss, off);
-  }
+  rmin = fminf(rmin, dpp_f32<kDppRor8>(rmin));
+  rmax = fmaxf(rmax, dpp_f32<kDppRor8>(rmax));
+  ss += dpp_f32<kDppRor8>(ss);
+  rmin = fminf(rmin, dpp_f32<kDppRor4>(rmin));
+  rmax = fmaxf(rmax, dpp_f32<kDppRor4>(rmax));
+  ss += dpp_f32<kDppRor4>(ss);
+  rmin = fminf(rmin, dpp_f32<kDppXor2>(rmin));
+  rmax = fmaxf(rmax, dpp_f32<kDppXor2>(rmax));
+  ss += dpp_f32<kDppXor2>(ss);
+  rmin = fminf(rmin, dpp_f32<kDppXor1>(rmin));
+  rmax = fmaxf(rmax, dpp_f32<kDppXor1>(rmax));
+  ss += dpp_f32<kDppXor1>(ss);
   float vl, delta, rn2;
-  if (inj_scal) {
+  if (INJ && inj_scal) {
     rn2 = inj_scal[pr * 3 + 0];
     vl = inj_scal[pr * 3 + 1];
     delta = inj_scal[pr * 3 + 2];
@@ -837,7 +861,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
       const int dd = d0 + u;
       uint32_t q = 0;
       if (dd < d) {
-        if (inj_qu) {
+        if (INJ && inj_qu) {
           q = inj_qu[pr * d + dd];
         } else {
           const float y = (r[u] - vl) * inv;
@@ -866,8 +890,8 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
       const uint32_t pl = (((lo >> b) & 0x01010101u) * 0x10204080u) >> 28;
       const uint32_t ph = (((hi >> b) & 0x01010101u) * 0x10204080u) >> 28;
       uint32_t v = (pl | (ph << 4)) << (8 * t);
-      v |= __shfl_xor(v, 1);
-      v |= __shfl_xor(v, 2);
+      v |= dpp_u32<kDppXor1>(v);
+      v |= dpp_u32<kDppXor2>(v);
       wd[b] = v;
     }
     if (active && d0 < Wq) {
@@ -880,7 +904,10 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
       if (t + 4 < bqs) pw[t + 4] = t + 4 < bq ? v1 : 0u;
     }
   }
-  for (int off = 8; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+  sq += (int)dpp_u32<kDppRor8>((uint32_t)sq);
+  sq += (int)dpp_u32<kDppRor4>((uint32_t)sq);
+  sq += (int)dpp_u32<kDppXor2>((uint32_t)sq);
+  sq += (int)dpp_u32<kDppXor1>((uint32_t)sq);
   if (active && g == 0) scal[pr] = make_float4(rn2, vl, delta, (float)sq);
 }
 
@@ -888,11 +915,24 @@ void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, 
                   const int32_t* probes, int nq, int nprobe, int d, int W, int bq, int bqs,
                   uint32_t* planes, uint8_t* qu, float4* scal, const uint8_t* inj_qu,
                   const float* inj_scal) {
-  const int64_t pairs = (int64_t)nq * nprobe;
-  if (pairs <= 0) return;
+  if (nq <= 0 || nprobe <= 0) return;
   RBQ_CHECK(bq >= 1 && bq <= 8 && bqs <= 8, "query bits out of range");
-  hipLaunchKernelGGL(k_quant, dim3((unsigned)((pairs + 15) / 16)), dim3(256), 0, s, qrot, ldq, crot,
-                     ldc, probes, pairs, nprobe, d, W, bq, bqs, planes, qu, scal, inj_qu, inj_scal);
+  RBQ_CHECK((nprobe + 15) / 16 <= 65535, "quantisation: nprobe out of range");
+  const dim3 grid((unsigned)nq, (unsigned)((nprobe + 15) / 16));
+  const int steps = (W * 32 + 127) / 128;
+  const bool inj = inj_qu || inj_scal;
+#define RBQ_QUANT(ST, INJV)                                                                            \
+  hipLaunchKernelGGL((k_quant<ST, INJV>), grid, dim3(256), 0, s, qrot, ldq, crot, ldc, probes, nprobe, d, \
+                     W, bq, bqs, planes, qu, scal, inj_qu, inj_scal)
+  if (inj)
+    RBQ_QUANT(0, true);
+  else if (steps == 1)
+    RBQ_QUANT(1, false);
+  else if (steps == 2)
+    RBQ_QUANT(2, false);
+  else
+    RBQ_QUANT(0, false);
+#undef RBQ_QUANT
   RBQ_HIP(hipGetLastError());
 }
 
