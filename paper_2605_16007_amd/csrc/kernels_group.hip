@@ -32,21 +32,18 @@ constexpr int STAGE = 512; // survivors staged per wave before a flush
 // Built once per search for all list-major chunks (a suffix of the probe
 // ranks): bin c * nlist + j holds the pairs of chunk c that probe list j.
 
-__device__ inline int group_chunk_of(const GroupChunks& gc, int p) {
-  int c = 0;
-  while (c + 1 < gc.nb && p >= gc.bound[c + 1]) ++c;
-  return c;
-}
-
 // rank[j * nq + i] = the probe rank p at which query i probes list j within
 // the list-major ranks (-1 otherwise; cleared by the search's state
 // initialisation). Then, without atomics, queries ascending within a bin:
-//   count: one wave per list counts its pairs per chunk (a lane takes 16
-//          consecutive queries of every 1024); each workgroup of 16 lists
-//          adds up its pairs and items (ceil(count / G)) per chunk;
+//   count: one wave per list counts its pairs per chunk (64 queries per
+//          step, one lane each, counted with one ballot per chunk); each
+//          workgroup of 16 lists adds up its pairs and items (ceil(count /
+//          G)) per chunk;
 //   scan:  one workgroup turns the workgroup sums (chunk-major) into bases,
 //          and the item range of every chunk;
-//   fill:  one wave per list places its pairs and writes its items.
+//   fill:  one wave per list places its pairs (the same steps: a pair's
+//          slot is its chunk's running base plus its rank in the ballot)
+//          and writes its items.
 __global__ void k_grp_mark(const int32_t* __restrict__ probes, int nq, int nprobe, int r0,
                            int16_t* __restrict__ rank) {
   const int span = nprobe - r0;
@@ -60,34 +57,28 @@ __global__ void k_grp_mark(const int32_t* __restrict__ probes, int nq, int nprob
 
 constexpr int kMapLists = 16;  // lists (waves) per map workgroup
 
-// per lane: how many of its queries [i0, i0 + 16) fall in each chunk
-__device__ inline void map_lane_counts(const int16_t* rj, int i0, int nq, const GroupChunks& gc,
-                                       int32_t (&c)[kMaxGroupChunks]) {
-  int16_t p[16];
+// chunk of list-major probe rank p (-1 for no pair): bounds are ascending
+__device__ inline int map_chunk(const GroupChunks& gc, int p) {
+  int ch = p >= 0 ? 0 : -1;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) p[e] = i0 + e < nq ? rj[i0 + e] : (int16_t)-1;
-#pragma unroll
-  for (int e = 0; e < 16; ++e)
-    if (p[e] >= 0) {
-      const int ch = group_chunk_of(gc, p[e]);
-#pragma unroll
-      for (int b = 0; b < kMaxGroupChunks; ++b) c[b] += b == ch ? 1 : 0;
-    }
+  for (int b = 1; b < kMaxGroupChunks; ++b) {
+    if (b >= gc.nb) break;
+    ch += p >= gc.bound[b] ? 1 : 0;
+  }
+  return ch;
 }
 
 __device__ inline int32_t wave_sum(int32_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   return v;
 }
-__device__ inline int32_t wave_excl(int32_t v) {
-  const int lane = threadIdx.x & 63;
-  int32_t x = v;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int32_t t = __shfl_up(x, off);
-    if (lane >= off) x += t;
-  }
-  return x - v;
+
+__device__ inline uint32_t lane_prefix(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
+
+constexpr int kMapUnroll = 4;  // 64-query steps whose ranks are loaded together
 
 __global__ __launch_bounds__(1024) void k_grp_count(const int16_t* __restrict__ rank, int nq, GroupChunks gc,
                                                     int nlist, int G, int nwg, int32_t* __restrict__ cnt,
@@ -95,17 +86,31 @@ __global__ __launch_bounds__(1024) void k_grp_count(const int16_t* __restrict__ 
   __shared__ int32_t sc[kMaxGroupChunks][kMapLists];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wg = blockIdx.x;
   const int j = wg * kMapLists + wave;
-  int32_t c[kMaxGroupChunks];
+  int32_t c[kMaxGroupChunks];  // wave-uniform pair counts per chunk
 #pragma unroll
   for (int b = 0; b < kMaxGroupChunks; ++b) c[b] = 0;
   if (j < nlist) {
     const int16_t* rj = rank + (int64_t)j * nq;
-    for (int i0 = 16 * lane; i0 < nq; i0 += 1024) map_lane_counts(rj, i0, nq, gc, c);
+    for (int i0 = 0; i0 < nq; i0 += 64 * kMapUnroll) {
+      int ch[kMapUnroll];
+#pragma unroll
+      for (int u = 0; u < kMapUnroll; ++u) {
+        const int i = i0 + 64 * u + lane;
+        ch[u] = map_chunk(gc, i < nq ? (int)rj[i] : -1);
+      }
+#pragma unroll
+      for (int u = 0; u < kMapUnroll; ++u)
+#pragma unroll
+        for (int b = 0; b < kMaxGroupChunks; ++b) {
+          if (b >= gc.nb) break;
+          c[b] += (int32_t)__popcll(__ballot(ch[u] == b));
+        }
+    }
   }
 #pragma unroll
   for (int b = 0; b < kMaxGroupChunks; ++b) {
     if (b >= gc.nb) break;
-    const int32_t tot = wave_sum(c[b]);
+    const int32_t tot = c[b];
     if (lane == 0) {
       sc[b][wave] = tot;
       if (j < nlist) cnt[b * nlist + j] = tot;
@@ -192,38 +197,28 @@ __global__ __launch_bounds__(1024) void k_grp_fill(const int16_t* __restrict__ r
     pos[b] = pb;
   }
   const int16_t* rj = rank + (int64_t)j * nq;
-  for (int blk = 0; blk < nq; blk += 1024) {
-    const int i0 = blk + 16 * lane;
-    int32_t c[kMaxGroupChunks];
+  for (int i0 = 0; i0 < nq; i0 += 64 * kMapUnroll) {
+    int pr[kMapUnroll];
 #pragma unroll
-    for (int b = 0; b < kMaxGroupChunks; ++b) c[b] = 0;
-    map_lane_counts(rj, i0, nq, gc, c);
-    int32_t at[kMaxGroupChunks];  // this lane's first position per chunk
-#pragma unroll
-    for (int b = 0; b < kMaxGroupChunks; ++b) {
-      if (b >= gc.nb) break;
-      at[b] = pos[b] + wave_excl(c[b]);
-      pos[b] += wave_sum(c[b]);
+    for (int u = 0; u < kMapUnroll; ++u) {
+      const int i = i0 + 64 * u + lane;
+      pr[u] = i < nq ? (int)rj[i] : -1;
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int i = i0 + e;
-      const int p = i < nq ? rj[i] : -1;
-      if (p >= 0) {
-        const int ch = group_chunk_of(gc, p);
-        int32_t o = 0;
+    for (int u = 0; u < kMapUnroll; ++u) {
+      const int i = i0 + 64 * u + lane;
+      const int ch = map_chunk(gc, pr[u]);
+      int32_t o = 0;
 #pragma unroll
-        for (int b = 0; b < kMaxGroupChunks; ++b)
-          if (b == ch) o = at[b]++;
-        slots[o] = (int32_t)((int64_t)i * nprobe + p);
+      for (int b = 0; b < kMaxGroupChunks; ++b) {
+        if (b >= gc.nb) break;
+        const uint64_t m = __ballot(ch == b);
+        if (ch == b) o = pos[b] + (int32_t)lane_prefix(m);
+        pos[b] += (int32_t)__popcll(m);
       }
+      if (ch >= 0) slots[o] = (int32_t)((int64_t)i * nprobe + pr[u]);
     }
   }
-}
-
-__device__ inline uint32_t lane_prefix(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
 // 16 code bits -> 16 bytes of 0/1 (byte b = bit b), as four dwords.
