@@ -60,10 +60,16 @@ constexpr uint64_t KEY_NONE = ~0ull;
 __device__ __forceinline__ float rbq_vx(float fmul, int pop, int D) {
   return fmul * (float)(2 * pop - D);
 }
+// from g = 2 ip - sum qu as a float that holds the integer exactly (|g| <
+// 2^24), as a float-accumulating matrix core returns it
+__device__ __forceinline__ float rbq_estimate_gf(float rn2, float vl, float delta, float g, float fadd,
+                                                 float fmul, float vx) {
+  return __builtin_fmaf(fmul * delta, g, __builtin_fmaf(vl, vx, fadd)) + rn2;
+}
 // from g = 2 ip - sum qu, an exact integer
 __device__ __forceinline__ float rbq_estimate_g(float rn2, float vl, float delta, int g, float fadd,
                                                 float fmul, float vx) {
-  return __builtin_fmaf(fmul * delta, (float)g, __builtin_fmaf(vl, vx, fadd)) + rn2;
+  return rbq_estimate_gf(rn2, vl, delta, (float)g, fadd, fmul, vx);
 }
 // (neg_sumqu = -sum qu, so that 2 ip - sum qu is one shift-add)
 __device__ __forceinline__ float rbq_estimate(float rn2, float vl, float delta, int neg_sumqu, int ip,

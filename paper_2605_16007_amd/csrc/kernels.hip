@@ -786,7 +786,8 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
                                                const float* __restrict__ crot, int ldc,
                                                const int32_t* __restrict__ probes, int nprobe, int d,
                                                int W, int bq, int bqs, uint32_t* __restrict__ planes,
-                                               uint8_t* __restrict__ qu_out, float4* __restrict__ scal,
+                                               uint8_t* __restrict__ qu_out, uint8_t* __restrict__ qu8,
+                                               int qu8_ld, float4* __restrict__ scal,
                                                const uint8_t* __restrict__ inj_qu,
                                                const float* __restrict__ inj_scal) {
   const int g = threadIdx.x & 15;
@@ -856,6 +857,7 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
       for (int u = 0; u < 8; ++u) r[u] = a[u] - c[u];
     }
     uint32_t lo = 0, hi = 0;
+    uint32_t qv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int dd = d0 + u;
@@ -864,12 +866,15 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
         if (INJ && inj_qu) {
           q = inj_qu[pr * d + dd];
         } else {
+          // f is integral and at least 0 (r >= v_l): clamping it to [0, top]
+          // and truncating gives the code
           const float y = (r[u] - vl) * inv;
           const float f = floorf(y + 0.5f);
-          q = f <= 0.f ? 0u : (f >= (float)top ? top : (uint32_t)f);
+          q = (uint32_t)__builtin_amdgcn_fmed3f(f, 0.f, (float)top);
         }
       }
       sq += (int)q;
+      qv[u] = q;
       if (u < 4)
         lo |= q << (8 * u);
       else
@@ -894,6 +899,15 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
       v |= dpp_u32<kDppXor2>(v);
       wd[b] = v;
     }
+    if (qu8 && active) {  // every lane: the row's bytes past d are zeros
+      // (the offsets of j = 1, 2, 3 are those of j = 0 plus 8, 32, 40)
+      uint8_t* row = qu8 + pr * qu8_ld + st * 128 + group_qu8_offset(g, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int v = __builtin_amdgcn_cvt_pk_fp8_f32((float)(qv[j] << 1), (float)(qv[j + 4] << 1), 0, false);
+        *reinterpret_cast<uint16_t*>(row + 32 * (j >> 1) + 8 * (j & 1)) = (uint16_t)v;
+      }
+    }
     if (active && d0 < Wq) {
       if (qu_out) *reinterpret_cast<uint2*>(qu_out + pr * Wq + d0) = make_uint2(lo, hi);
       const int w = d0 >> 5;
@@ -913,9 +927,10 @@ __global__ __launch_bounds__(256) void k_quant(const float* __restrict__ qrot, i
 
 void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, int ldc,
                   const int32_t* probes, int nq, int nprobe, int d, int W, int bq, int bqs,
-                  uint32_t* planes, uint8_t* qu, float4* scal, const uint8_t* inj_qu,
-                  const float* inj_scal) {
+                  uint32_t* planes, uint8_t* qu, uint8_t* qu8, int qu8_ld, float4* scal,
+                  const uint8_t* inj_qu, const float* inj_scal) {
   if (nq <= 0 || nprobe <= 0) return;
+  RBQ_CHECK(!qu8 || (bq <= 4 && qu8_ld == 128 * ((W * 32 + 127) / 128)), "quantisation: fp8 operand rows");
   RBQ_CHECK(bq >= 1 && bq <= 8 && bqs <= 8, "query bits out of range");
   RBQ_CHECK((nprobe + 15) / 16 <= 65535, "quantisation: nprobe out of range");
   const dim3 grid((unsigned)nq, (unsigned)((nprobe + 15) / 16));
@@ -923,7 +938,7 @@ void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, 
   const bool inj = inj_qu || inj_scal;
 #define RBQ_QUANT(ST, INJV)                                                                            \
   hipLaunchKernelGGL((k_quant<ST, INJV>), grid, dim3(256), 0, s, qrot, ldq, crot, ldc, probes, nprobe, d, \
-                     W, bq, bqs, planes, qu, scal, inj_qu, inj_scal)
+                     W, bq, bqs, planes, qu, qu8, qu8_ld, scal, inj_qu, inj_scal)
   if (inj)
     RBQ_QUANT(0, true);
   else if (steps == 1)

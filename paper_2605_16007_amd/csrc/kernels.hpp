@@ -70,10 +70,13 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows);
 
 // Residual r = qrot_i - crot_j for every (query, probe) pair, B_q-bit
 // quantisation, bit-planes and scalars; or pack injected qu / scalars.
+// qu (optional): [pairs][W*32] bytes in dimension order. qu8 (optional, B_q
+// <= 4): [pairs][qu8_ld] fp8 E4M3 bytes of 2 qu in the B-operand order of the
+// fp4 x fp8 list-major scan (qu8_ld = 128 ceil(d / 128); see group_qu8_offset).
 void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, int ldc,
                   const int32_t* probes, int nq, int nprobe, int d, int W, int bq, int bqs,
-                  uint32_t* planes, uint8_t* qu, float4* scal, const uint8_t* inj_qu,
-                  const float* inj_scal);
+                  uint32_t* planes, uint8_t* qu, uint8_t* qu8, int qu8_ld, float4* scal,
+                  const uint8_t* inj_qu, const float* inj_scal);
 
 // Code scan with fused estimator and streaming top-R per (query, probe) item.
 struct ScanArgs {
@@ -115,7 +118,8 @@ void launch_scan_fused(hipStream_t s, FusedArgs a);
 // List-major grouped scan on int8 MFMA (kernels_group.hip).
 struct GroupArgs {
   ListsView L;
-  const uint8_t* qu;       // [pairs][W*32] quantised residuals
+  const uint8_t* qu;       // per pair: qu bytes (B_q > 4) or the fp8 operand row (B_q <= 4)
+  int qu_ld;               // bytes per pair in qu
   const float4* scal;      // [pairs] (||r||^2, v_l, Delta, sum qu)
   int nq, nprobe, R, nlist, G;
   int bq;                  // query bits B_q
@@ -132,6 +136,24 @@ struct GroupArgs {
   uint32_t* any_overflow;  // set with any overflow flag
 };
 int group_k_steps(int d);
+// The fp4 x fp8 form of the list-major scan (B_q <= 4): 128-dimension steps
+// per pair, and the bytes per pair of its operand rows.
+int group_f8_steps(int d);
+inline bool group_uses_f8(int bq, int d) { return bq <= 4 && d <= 256; }
+// Byte offset, in a pair's 128-byte fp8 operand row of one step, of the two
+// bytes for dimensions 8 l + j and 8 l + j + 4 of the step (l = 0..15, j =
+// 0..3). The scan's fp4 A operand gives lane group g the bits of code word g
+// of the step with dimension 32 g + 4 i + q at element k = 32 g + 8 q + i
+// (nibble i of dword q); the matrix core reads B elements k in [16 g, 16 g +
+// 16) from bytes [32 g, 32 g + 16) of lane group g and k in [64 + 16 g, 80 +
+// 16 g) from bytes [32 g + 16, 32 g + 32), so the byte for dimension 32 g +
+// 4 i + q sits where that k is read; the two dimensions 4 apart are
+// neighbouring k and share a 16-bit word. For every l the offsets of j = 1,
+// 2, 3 exceed that of j = 0 by 8, 32 and 40.
+__host__ __device__ inline int group_qu8_offset(int l, int j) {
+  const int k = 32 * (l >> 2) + 8 * j + 2 * (l & 3);
+  return k < 64 ? 32 * (k >> 4) + (k & 15) : 32 * ((k - 64) >> 4) + 16 + ((k - 64) & 15);
+}
 // The list-major chunks of a search: probe ranks [bound[0], bound[nb]), chunk
 // c = [bound[c], bound[c+1]).
 constexpr int kMaxGroupChunks = 16;

@@ -238,14 +238,27 @@ __device__ inline v4i unpack16(uint32_t bits) {
 //     (pop = the vector's popcount), so the MFMA still returns ip.
 // GT: 16-query tiles per item (G <= 16 GT); each lane keeps its B operands
 // for the whole item in registers.
-enum { QB_DOUBLE = 0, QB_PLAIN = 1, QB_OFFSET = 2 };
+//   QB_F8 (B_q <= 4): the codes as fp4 (E2M1, 1.0 per set bit) and B = 2 qu
+//     as fp8 (E4M3; 2 qu <= 30 is exact), accumulated in fp32 from -sum qu:
+//     g comes out as an exactly integral float and no conversion is needed.
+//     Each step covers 128 dimensions (KS counts these steps); lane group g
+//     of a row expands code word g of the step by shifts and masks (bit
+//     4 i + q -> nibble i of dword q), and the quantiser writes the pair's
+//     B bytes in the matching order, so staging B is a plain 32-byte load.
+enum { QB_DOUBLE = 0, QB_PLAIN = 1, QB_OFFSET = 2, QB_F8 = 3 };
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 template <int KS, int QB, int GT>
 __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
-  __shared__ v4i sB[GT][KS][64];             // B operands: [query tile][k step][lane]
+  constexpr bool F8 = QB == QB_F8;
+  constexpr int CW = F8 ? 4 * KS : 2 * KS;  // code words per vector staged
+  using BT = typename std::conditional<F8, v8i, v4i>::type;
+  using AccT = typename std::conditional<F8, v4f, v4i>::type;
+  __shared__ BT sB[GT][KS][64];              // B operands: [query tile][k step][lane]
   __shared__ float4 sSc[GMAX];                // (||r||^2, v_l, Delta, sum qu) per query slot
   __shared__ float sThr[GMAX];                // threshold on d_hat^2 per query slot
   __shared__ int32_t sQ[GMAX];                // query id per slot
-  __shared__ uint32_t sCode[4][2 * KS][64];  // per wave: the micro-block's code words
+  __shared__ uint32_t sCode[4][CW][64];      // per wave: the micro-block's code words
   __shared__ __align__(16) float sVx[4][64], sAdd[4][64], sMul[4][64];
   __shared__ __align__(16) int32_t sPop[QB == QB_OFFSET ? 4 : 1][64];  // 128 pop per vector
   // per wave: survivors as (float bits of d_hat^2 << 32) | (query slot << 26 |
@@ -255,7 +268,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   __shared__ int32_t sItem;
   // 8 code bits -> 8 bytes of 0/1 (byte b = bit b): the unpacking of the A
   // operand is two table reads per 16 bits
-  __shared__ uint2 sLut[256];
+  __shared__ uint2 sLut[F8 ? 1 : 256];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int W = a.L.W;
   const int D = a.L.d;
@@ -295,7 +308,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     __builtin_amdgcn_wave_barrier();
   };
   const int first_item = a.item_off[0], end_item = a.item_off[1];
-  if (tid < 256) {
+  if (!F8 && tid < 256) {
     const v4i u = unpack16((uint32_t)tid);
     sLut[tid] = make_uint2((uint32_t)u[0], (uint32_t)u[1]);
   }
@@ -326,12 +339,19 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
       const int n = e / (KS * 64), t = (e / 64) % KS, l = e & 63;
       const int q = 16 * n + (l & 15);
       const int off = 64 * t + 16 * (l >> 4);
-      v4i v = {0, 0, 0, 0};
-      if (q < count && off < Wq) {
-        const int pair = a.slots[first + q];
-        v = *reinterpret_cast<const v4i*>(a.qu + (int64_t)pair * Wq + off);
-        if (QB == QB_DOUBLE) v <<= 1;  // bytes <= 63: no carry into the next byte
-        if (QB == QB_OFFSET) v ^= (int)0x80808080u;  // qu - 128 as a signed byte
+      BT v = {};
+      if constexpr (F8) {
+        if (q < count) {
+          const int pair = a.slots[first + q];
+          v = *reinterpret_cast<const v8i*>(a.qu + (int64_t)pair * a.qu_ld + 128 * t + 32 * (l >> 4));
+        }
+      } else {
+        if (q < count && off < Wq) {
+          const int pair = a.slots[first + q];
+          v = *reinterpret_cast<const v4i*>(a.qu + (int64_t)pair * a.qu_ld + off);
+          if (QB == QB_DOUBLE) v <<= 1;  // bytes <= 63: no carry into the next byte
+          if (QB == QB_OFFSET) v ^= (int)0x80808080u;  // qu - 128 as a signed byte
+        }
       }
       sB[n][t][l] = v;
     }
@@ -339,7 +359,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     // this lane's query (column lane & 15 of each 16-query tile): its B
     // operands and scalars in registers for the whole item; an empty slot
     // gets a NaN threshold
-    v4i Bq[GT][KS];
+    BT Bq[GT][KS];
     float qrn2[GT], qvl[GT], qdelta[GT], qthr[GT];
     int qneg[GT];
 #pragma unroll
@@ -360,12 +380,12 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     const size_t rec = (size_t)(W + 2) * 64;
     // lane = vector of the micro-block; the next micro-block's words and
     // factors are loaded into registers while the current one is computed
-    uint32_t cw[2 * KS];
+    uint32_t cw[CW];
     float fa = 0.f, fm = 0.f;
     auto load_mb = [&](int mbi) {
       const uint32_t* blk = a.L.blocks + (size_t)(mb0 + mbi) * rec;
 #pragma unroll
-      for (int w = 0; w < 2 * KS; ++w) cw[w] = w < W ? blk[w * 64 + lane] : 0u;
+      for (int w = 0; w < CW; ++w) cw[w] = w < W ? blk[w * 64 + lane] : 0u;
       fa = __uint_as_float(blk[W * 64 + lane]);
       fm = __uint_as_float(blk[(W + 1) * 64 + lane]);
     };
@@ -374,7 +394,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
       {
         int pop = 0;
 #pragma unroll
-        for (int w = 0; w < 2 * KS; ++w) {
+        for (int w = 0; w < CW; ++w) {
           sCode[wave][w][lane] = cw[w];
           pop += __popc(cw[w]);
         }
@@ -387,31 +407,65 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
       __builtin_amdgcn_wave_barrier();
       if (mb + 4 < nmb) load_mb(mb + 4);
       const int lg = lane >> 4;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        v4i A[KS];
+      // A operands of row block m (vectors 16 m + (lane & 15)). For small
+      // items those of block m + 1 are read from LDS before block m's
+      // epilogue, so the reads are in flight while it computes (for larger
+      // items the extra registers would cost a wave of occupancy)
+      constexpr bool pre = F8 ? KS * GT <= 2 : KS * GT <= 4;
+      auto unpack_a = [&](int m, v4i (&A)[KS]) __attribute__((always_inline)) {
         const int vrow = 16 * m + (lane & 15);
 #pragma unroll
         for (int t = 0; t < KS; ++t) {
-          const uint32_t word = sCode[wave][2 * t + (lg >> 1)][vrow];
-          const uint2 lo8 = sLut[(word >> (16 * (lg & 1))) & 0xFFu];
-          const uint2 hi8 = sLut[(word >> (16 * (lg & 1) + 8)) & 0xFFu];
-          A[t] = v4i{(int)lo8.x, (int)lo8.y, (int)hi8.x, (int)hi8.y};
+          if constexpr (F8) {
+            const uint32_t w = sCode[wave][4 * t + lg][vrow];
+            A[t] = v4i{(int)((w << 1) & 0x22222222u), (int)(w & 0x22222222u), (int)((w >> 1) & 0x22222222u),
+                       (int)((w >> 2) & 0x22222222u)};
+          } else {
+            const uint32_t word = sCode[wave][2 * t + (lg >> 1)][vrow];
+            const uint2 lo8 = sLut[(word >> (16 * (lg & 1))) & 0xFFu];
+            const uint2 hi8 = sLut[(word >> (16 * (lg & 1) + 8)) & 0xFFu];
+            A[t] = v4i{(int)lo8.x, (int)lo8.y, (int)hi8.x, (int)hi8.y};
+          }
+        }
+      };
+      v4i An[KS];
+      unpack_a(0, An);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        v4i A[KS];
+        if (pre || m == 0) {
+#pragma unroll
+          for (int t = 0; t < KS; ++t) A[t] = An[t];
+        } else {
+          unpack_a(m, A);
         }
         // every query tile's products first, then the epilogues
         v4i c0 = {0, 0, 0, 0};
         if (QB == QB_OFFSET) c0 = *reinterpret_cast<const v4i*>(&sPop[QB == QB_OFFSET ? wave : 0][16 * m + 4 * lg]);
-        v4i acc[GT];
+        AccT acc[GT];
 #pragma unroll
         for (int n = 0; n < GT; ++n) {
           if (n < nt) {
             // QB_DOUBLE: the accumulator starts at -sum qu, so it ends at g
-            v4i c = QB == QB_DOUBLE ? v4i{qneg[n], qneg[n], qneg[n], qneg[n]} : c0;
+            if constexpr (F8) {
+              const float qf = (float)qneg[n];
+              v4f c = {qf, qf, qf, qf};
 #pragma unroll
-            for (int t = 0; t < KS; ++t) c = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t], Bq[n][t], c, 0, 0, 0);
-            acc[n] = c;
+              for (int t = 0; t < KS; ++t) {
+                const v8i a8 = {A[t][0], A[t][1], A[t][2], A[t][3], 0, 0, 0, 0};
+                // A fp4 (format 4), B fp8 E4M3 (format 0), unit scales
+                c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, Bq[n][t], c, 4, 0, 0, 0, 0, 0);
+              }
+              acc[n] = c;
+            } else {
+              v4i c = QB == QB_DOUBLE ? v4i{qneg[n], qneg[n], qneg[n], qneg[n]} : c0;
+#pragma unroll
+              for (int t = 0; t < KS; ++t) c = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[t], Bq[n][t], c, 0, 0, 0);
+              acc[n] = c;
+            }
           }
         }
+        if (pre && m < 3) unpack_a(m + 1, An);
         // the four vectors of this lane's result rows: 16 m + 4 lg + r
         const float4 fadd4 = *reinterpret_cast<const float4*>(&sAdd[wave][16 * m + 4 * lg]);
         const float4 vx4 = *reinterpret_cast<const float4*>(&sVx[wave][16 * m + 4 * lg]);
@@ -428,8 +482,12 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
           uint64_t pm[4];  // the lanes that pass, per result row
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int g = QB == QB_DOUBLE ? acc[n][r] : (acc[n][r] << 1) + qneg[n];
-            est[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
+            if constexpr (F8) {
+              est[r] = rbq_estimate_gf(qrn2[n], qvl[n], qdelta[n], acc[n][r], fadd[r], fmul[r], vxr[r]);
+            } else {
+              const int g = QB == QB_DOUBLE ? acc[n][r] : (acc[n][r] << 1) + qneg[n];
+              est[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
+            }
             // NaN (padding lanes, empty slots) never passes
             pm[r] = __builtin_amdgcn_ballot_w64(est[r] <= qthr[n]);
           }
@@ -488,13 +546,30 @@ int group_map_workgroups(int nlist) { return (nlist + kMapLists - 1) / kMapLists
 
 int group_k_steps(int d) { return (d + 63) / 64; }
 
+int group_f8_steps(int d) { return (d + 127) / 128; }
+
 void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups) {
   RBQ_CHECK(a.G >= 1 && a.G <= GMAX, "group size out of range");
   const int ks = group_k_steps(a.L.d);
   RBQ_CHECK(ks <= KSMAX, "grouped scan supports d <= 256");
   RBQ_CHECK(a.bq >= 1 && a.bq <= 8, "query bits out of range");
-  const int qb = a.bq <= 6 ? QB_DOUBLE : a.bq == 7 ? QB_PLAIN : QB_OFFSET;
   const bool two = a.G <= 32;
+  if (group_uses_f8(a.bq, a.L.d)) {
+    const int ks8 = group_f8_steps(a.L.d);
+    RBQ_CHECK(a.qu_ld == 128 * ks8, "fp8 list-major scan: operand rows");
+    if (ks8 == 1 && two)
+      hipLaunchKernelGGL((k_scan_group<1, QB_F8, 2>), dim3(workgroups), dim3(256), 0, s, a);
+    else if (ks8 == 1)
+      hipLaunchKernelGGL((k_scan_group<1, QB_F8, 4>), dim3(workgroups), dim3(256), 0, s, a);
+    else if (two)
+      hipLaunchKernelGGL((k_scan_group<2, QB_F8, 2>), dim3(workgroups), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_scan_group<2, QB_F8, 4>), dim3(workgroups), dim3(256), 0, s, a);
+    RBQ_HIP(hipGetLastError());
+    return;
+  }
+  RBQ_CHECK(a.qu_ld == a.L.W * 32, "list-major scan: qu rows");
+  const int qb = a.bq <= 6 ? QB_DOUBLE : a.bq == 7 ? QB_PLAIN : QB_OFFSET;
 #define RBQ_GROUP_LAUNCH_QB(K, QBV)                                                           \
   if (two)                                                                                  \
     hipLaunchKernelGGL((k_scan_group<K, QBV, 2>), dim3(workgroups), dim3(256), 0, s, a);    \

@@ -68,12 +68,12 @@ struct Bufs {
   float* qrot = nullptr;
   uint32_t* planes = nullptr;
   uint8_t* qu = nullptr;
+  uint8_t* qu8 = nullptr;  // fp8 operand rows of the fp4 x fp8 list-major scan
   float4* scal = nullptr;
   uint8_t* inj_qu = nullptr;
   float* inj_scal = nullptr;
   uint32_t* qthr = nullptr;
   uint32_t* pcnt = nullptr;
-  uint8_t* qu8 = nullptr;
   int32_t* gcnt = nullptr;
   int16_t* rankmat = nullptr;  // nlist x nq probe ranks (list-major map)
   int32_t* wpart = nullptr;        // list-major map: workgroup sums, then bases
@@ -256,7 +256,9 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
   b.qrot = c.take<float>((size_t)nq * ld);
   b.planes = c.take<uint32_t>((size_t)pairs * W * idx->bqs);
-  if ((dbg && dbg->qu) || P.any_group) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
+  const bool f8 = P.any_group && group_uses_f8(idx->bq, d);
+  if ((dbg && dbg->qu) || (P.any_group && !f8)) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
+  if (f8) b.qu8 = c.take<uint8_t>((size_t)pairs * 128 * group_f8_steps(d));
   if (P.any_group) {
     const int64_t bins = (int64_t)P.gc.nb * nlist;
     b.gcnt = c.take<int32_t>(bins);
@@ -461,7 +463,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       RBQ_HIP(hipMemsetAsync(b.dump_est, 0, (size_t)pairs * maxlen * sizeof(float), s));
     }
     launch_quant(s, b.qrot, ld, idx->Crot.as<float>(), ld, b.probes, (int)nq, nprobe, d, W, idx->bq,
-                 bqs, b.planes, b.qu, b.scal, b.inj_qu, b.inj_scal);
+                 bqs, b.planes, b.qu, b.qu8, 128 * group_f8_steps(d), b.scal, b.inj_qu, b.inj_scal);
     mark(3);
     // Phase 3 + Phase 4: code scan with the estimator and per-item top-R,
     // then the per-query merge, one chunk of probe ranks at a time
@@ -506,7 +508,8 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     sa.qmask = nullptr;
     GroupArgs ga;
     ga.L = sa.L;
-    ga.qu = b.qu;
+    ga.qu = b.qu8 ? b.qu8 : b.qu;
+    ga.qu_ld = b.qu8 ? 128 * group_f8_steps(d) : W * 32;
     ga.scal = b.scal;
     ga.nq = (int)nq;
     ga.nprobe = nprobe;
