@@ -60,11 +60,25 @@ constexpr uint64_t KEY_NONE = ~0ull;
 __device__ __forceinline__ float rbq_vx(float fmul, int pop, int D) {
   return fmul * (float)(2 * pop - D);
 }
-// from g = 2 ip - sum qu as a float that holds the integer exactly (|g| <
-// 2^24), as a float-accumulating matrix core returns it
+// The estimate without its last term ||r||^2, from g = 2 ip - sum qu as a
+// float that holds the integer exactly (|g| < 2^24), as a float-accumulating
+// matrix core returns it; d_hat^2 = part + ||r||^2.
+__device__ __forceinline__ float rbq_estimate_part(float vl, float delta, float g, float fadd, float fmul,
+                                                   float vx) {
+  return __builtin_fmaf(fmul * delta, g, __builtin_fmaf(vl, vx, fadd));
+}
 __device__ __forceinline__ float rbq_estimate_gf(float rn2, float vl, float delta, float g, float fadd,
                                                  float fmul, float vx) {
-  return __builtin_fmaf(fmul * delta, g, __builtin_fmaf(vl, vx, fadd)) + rn2;
+  return rbq_estimate_part(vl, delta, g, fadd, fmul, vx) + rn2;
+}
+// A bound b on the part such that part + ||r||^2 <= thr (rounded to nearest)
+// implies part <= b: the sum's rounding error is at most |thr| 2^-24 below
+// thr, and the margin (|thr| + ||r||^2) 2^-20 also covers the two roundings
+// of b itself. +inf stays +inf; a NaN threshold gives a NaN bound (no part
+// passes).
+__device__ __forceinline__ float rbq_part_bound(float thr, float rn2) {
+  const float m = __builtin_fmaxf((__builtin_fabsf(thr) + __builtin_fabsf(rn2)) * 0x1p-20f, 0x1p-100f);
+  return (thr - rn2) + m;
 }
 // from g = 2 ip - sum qu, an exact integer
 __device__ __forceinline__ float rbq_estimate_g(float rn2, float vl, float delta, int g, float fadd,

@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     // operands and scalars in registers for the whole item; an empty slot
     // gets a NaN threshold
     BT Bq[GT][KS];
-    float qrn2[GT], qvl[GT], qdelta[GT], qthr[GT];
+    float qrn2[GT], qvl[GT], qdelta[GT], qthr[GT], qbound[GT];
     int qneg[GT];
 #pragma unroll
     for (int n = 0; n < GT; ++n) {
@@ -371,6 +371,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
       qdelta[n] = sc.z;
       qneg[n] = -(int)sc.w;
       qthr[n] = q < count ? sThr[q] : NAN;
+      if (F8) qbound[n] = rbq_part_bound(qthr[n], qrn2[n]);
 #pragma unroll
       for (int t = 0; t < KS; ++t) Bq[n][t] = sB[n][t][lane];
     }
@@ -478,30 +479,37 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 #pragma unroll
         for (int n = 0; n < GT; ++n) {
           if (n >= nt) break;
-          float est[4];
-          uint64_t pm[4];  // the lanes that pass, per result row
+          // QB_F8: the estimate without ||r||^2 is tested against the
+          // query's bound on it; the lanes that pass form the estimate and
+          // test it exactly
+          float part[4];
+          uint64_t pm[4];  // the lanes that may pass, per result row
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             if constexpr (F8) {
-              est[r] = rbq_estimate_gf(qrn2[n], qvl[n], qdelta[n], acc[n][r], fadd[r], fmul[r], vxr[r]);
-            } else {
+              part[r] = rbq_estimate_part(qvl[n], qdelta[n], acc[n][r], fadd[r], fmul[r], vxr[r]);
+              // NaN (padding lanes, empty slots) never passes
+              pm[r] = __builtin_amdgcn_ballot_w64(part[r] <= qbound[n]);
+            } else {  // (the signed-byte forms test the estimate itself: fewer registers)
               const int g = QB == QB_DOUBLE ? acc[n][r] : (acc[n][r] << 1) + qneg[n];
-              est[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
+              part[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
+              pm[r] = __builtin_amdgcn_ballot_w64(part[r] <= qthr[n]);
             }
-            // NaN (padding lanes, empty slots) never passes
-            pm[r] = __builtin_amdgcn_ballot_w64(est[r] <= qthr[n]);
           }
           if (pm[0] | pm[1] | pm[2] | pm[3]) {  // stage the survivors of this tile
             const uint32_t tag = rel0 | ((uint32_t)(16 * n + (lane & 15)) << 26);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               if (pm[r]) {
-                if (est[r] <= qthr[n]) {  // (the compare behind pm[r])
+                const float est = F8 ? part[r] + qrn2[n] : part[r];  // d_hat^2, as every scan forms it
+                const bool pass = est <= qthr[n];
+                const uint64_t me = __builtin_amdgcn_ballot_w64(pass);
+                if (pass) {
                   const uint32_t e = __builtin_amdgcn_mbcnt_hi(
-                      (uint32_t)(pm[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm[r], (uint32_t)stage_n));
-                  sStage[wave][e] = ((uint64_t)__float_as_uint(est[r]) << 32) | (tag + (uint32_t)r);
+                      (uint32_t)(me >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)me, (uint32_t)stage_n));
+                  sStage[wave][e] = ((uint64_t)__float_as_uint(est) << 32) | (tag + (uint32_t)r);
                 }
-                stage_n += (int)__popcll(pm[r]);
+                stage_n += (int)__popcll(me);
               }
             }
             if (stage_n > STAGE - 256) {
