@@ -34,24 +34,35 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # compare
 EPILOGUE_OPS = 9
 # PMC summaries (HBM bytes per launch of a scan kernel at one operating point)
+_CSRC = os.path.join(ROOT, "paper_2605_16007_amd", "csrc")
+# kernel -> (its PMC summary, the sources whose concatenation's sha256 the
+# summary records: the kernel's file and the two headers it includes)
 PMC_SUMMARIES = {
     "k_scan_group": (os.path.join(ROOT, "profiles", "k_scan_group_sift10m_pmc.md"),
-                     os.path.join(ROOT, "paper_2605_16007_amd", "csrc", "kernels_group.hip")),
+                     [os.path.join(_CSRC, f) for f in ("kernels_group.hip", "kernels.hpp", "common.hpp")]),
     "k_scan_popc": (os.path.join(ROOT, "profiles", "k_scan_popc_unit96_50m.md"),
-                    os.path.join(ROOT, "paper_2605_16007_amd", "csrc", "kernels.hip")),
+                    [os.path.join(_CSRC, f) for f in ("kernels.hip", "kernels.hpp", "common.hpp")]),
 }
+
+
+def source_sha(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def pmc_traffic(kernel, point):
     """HBM bytes per launch of `kernel` from its committed PMC summary, if the
     kernel source has not changed since the counters were taken and they were
     taken at this operating point (e.g. "sift10m nprobe=512 rerank=3840")."""
-    import hashlib
     import re
-    summary, src = PMC_SUMMARIES[kernel]
+    summary, srcs = PMC_SUMMARIES[kernel]
     try:
         text = open(summary).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = source_sha(srcs)
     except OSError:
         return None
     m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
