@@ -530,9 +530,15 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total)
   return before + x - v;
 }
 
+// Output rows of up to this many keys are assembled in LDS and then copied
+// out with consecutive threads on consecutive keys (the compaction's own
+// stores go to scattered positions).
+constexpr int kMergeStageKeys = 4096;
+
 template <int NT, int KPT>
 __global__ __launch_bounds__(NT) void k_pool_merge(TopkArgs a) {
   constexpr int NW = NT / 64;
+  extern __shared__ uint64_t s_out[];  // a.k keys when a.k <= kMergeStageKeys
   constexpr int NH = 4;  // histogram copies (wave w uses copy w % NH)
   constexpr int PIECE = NT * KPT;
   __shared__ uint32_t hist[NH][256];
@@ -546,7 +552,9 @@ __global__ __launch_bounds__(NT) void k_pool_merge(TopkArgs a) {
   const int k = a.rowk ? a.rowk[row] : a.k;
   const int ncols = a.k + (int)extra;
   const uint64_t* src = a.keys + row * a.ld;
-  uint64_t* dst = a.out_keys + row * a.ldo;
+  uint64_t* const out = a.out_keys + row * a.ldo;
+  const bool staged = a.k <= kMergeStageKeys;
+  uint64_t* dst = staged ? s_out : out;
   const bool one = ncols <= PIECE;
   uint64_t v[KPT];
   auto load = [&](int p0) {
@@ -674,6 +682,8 @@ __global__ __launch_bounds__(NT) void k_pool_merge(TopkArgs a) {
   }
   if (lane == 0) s_hi[wave] = mx;
   __syncthreads();
+  if (staged)
+    for (int i = tid; i < k; i += NT) out[i] = s_out[i];
   if (tid == 0) {
     uint64_t kth = s_hi[0];
 #pragma unroll
@@ -726,7 +736,8 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   // pool merges: the register-resident kernel
   if (a.rowcnt && !a.sorted) {
     RBQ_CHECK(a.k <= 512 * 32, "pool merge: running keys exceed one piece");
-    hipLaunchKernelGGL((k_pool_merge<512, 32>), dim3(rows), dim3(512), 0, s, a);
+    const size_t stage = a.k <= kMergeStageKeys ? (size_t)a.k * sizeof(uint64_t) : 0;
+    hipLaunchKernelGGL((k_pool_merge<512, 32>), dim3(rows), dim3(512), stage, s, a);
     RBQ_HIP(hipGetLastError());
     return;
   }
