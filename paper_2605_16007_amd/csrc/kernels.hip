@@ -1329,12 +1329,12 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
   const size_t rec = (size_t)(W + 2) * 64;
   if (tid == 0) {
     s_n = 0;
-    s_thr = a.qthr[i];
+    s_thr = a.reset ? 0xFFFFFFFFu : a.qthr[i];
     s_cnt[0] = s_cnt[1] = s_cnt[2] = 0u;
   }
   __syncthreads();
-  // the running top-R
-  for (int r0 = 0; r0 < a.R; r0 += NT) {
+  // the running top-R (none when starting afresh)
+  for (int r0 = 0; r0 < (a.reset ? 0 : a.R); r0 += NT) {
     const int r = r0 + tid;
     const uint64_t key = r < a.R ? row[r] : KEY_NONE;
     const bool t = key != KEY_NONE;
@@ -1480,7 +1480,12 @@ __global__ __launch_bounds__(kFusedNT) void k_scan_fused(FusedArgs a) {
   // s_thr is the R-th estimate of the last selection (the kept keys' R-th when
   // the buffer ended above Rq), else the threshold the query came with: an
   // upper bound on its R-th estimate either way
-  if (tid == 0) atomicMin(&a.qthr[i], s_thr);
+  if (tid == 0) {
+    if (a.reset)
+      a.qthr[i] = s_thr;  // (this workgroup alone handles query i)
+    else
+      atomicMin(&a.qthr[i], s_thr);
+  }
 }
 
 template <int WT, int BQT>

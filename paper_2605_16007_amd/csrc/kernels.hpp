@@ -111,11 +111,13 @@ struct FusedArgs {
   uint32_t* qthr;
   const int32_t* rowk;     // per-query R (or null)
   const uint32_t* qmask;   // only queries with qmask[i] != 0 (or null: all)
+  int reset = 0;           // 1: each query starts afresh (empty running top-R, no threshold)
   int cap = 0;             // set by the launcher
 };
 void launch_scan_fused(hipStream_t s, FusedArgs a);
 
-// List-major grouped scan on int8 MFMA (kernels_group.hip).
+// List-major grouped scan on the matrix cores: fp4 x fp8 for B_q <= 4, int8
+// otherwise (kernels_group.hip).
 struct GroupArgs {
   ListsView L;
   const uint8_t* qu;       // per pair: qu bytes (B_q > 4) or the fp8 operand row (B_q <= 4)

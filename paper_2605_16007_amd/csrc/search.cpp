@@ -638,20 +638,22 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         scan_popc_chunk(ch);
     }
     // Queries whose pool overflowed in a list-major chunk are searched again,
-    // from scratch and exactly. On the device (d <= 1024): their rows and
-    // thresholds are reset and the fused scan, masked to them, covers every
-    // probe rank; its workgroups of other queries return at once, so nothing
-    // waits for the host. Otherwise the host reads one flag and, if it is
-    // set, the query-major scan redoes them.
+    // from scratch and exactly. On the device (d <= 1024): the fused scan,
+    // masked to them, starts each afresh (empty running top-R, no threshold)
+    // and covers every probe rank; its workgroups of other queries return at
+    // once, so nothing waits for the host. Otherwise their rows are reset and
+    // the host reads one flag and, if it is set, the query-major scan redoes
+    // them.
     if (any_group) {
-      launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
       if (idx->W <= 32) {
         FusedArgs ra = fa;
         ra.p0 = 0;
         ra.pn = nprobe;
         ra.qmask = b.overflow;
+        ra.reset = 1;
         launch_scan_fused(s, ra);
       } else {
+        launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
         uint32_t any = 0;
         RBQ_HIP(hipMemcpyAsync(&any, b.counter, sizeof(any), hipMemcpyDeviceToHost, s));
         RBQ_HIP(hipStreamSynchronize(s));
