@@ -30,6 +30,10 @@ SHAPES = [
     # plain (B_q = 7), offset by -128 (B_q = 8, above)
     ("g72_bq6", 8_000, 72, 10, 80, 6, 5, 40, "mixture", 6),
     ("g64_bq7", 8_000, 64, 10, 80, 6, 5, 40, "mixture", 7),
+    # the fp4 x fp8 form (B_q <= 4) at its edges: a second 128-dimension step
+    # padded past d = 200, and the smallest query codes (2 qu <= 14, <= 2)
+    ("g200_bq3", 6_000, 200, 8, 40, 5, 10, 80, "mixture", 3),
+    ("g160_bq1", 6_000, 160, 8, 40, 5, 10, 80, "unit_mixture", 1),
 ]
 
 
