@@ -44,15 +44,15 @@ constexpr int STAGE = 512; // survivors staged per wave before a flush
 //   fill:  one wave per list places its pairs (the same steps: a pair's
 //          slot is its chunk's running base plus its rank in the ballot)
 //          and writes its items.
+// (x: 256 probe ranks per workgroup; y: queries, striding by gridDim.y)
 __global__ void k_grp_mark(const int32_t* __restrict__ probes, int nq, int nprobe, int r0,
                            int16_t* __restrict__ rank) {
-  const int span = nprobe - r0;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nq * span) return;
-  const int64_t i = t / span;
-  const int p = r0 + (int)(t - i * span);
-  const int j = probes[i * nprobe + p];
-  if (j >= 0) rank[(int64_t)j * nq + i] = (int16_t)p;
+  const int p = r0 + (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (p >= nprobe) return;
+  for (int64_t i = blockIdx.y; i < nq; i += gridDim.y) {
+    const int j = probes[i * nprobe + p];
+    if (j >= 0) rank[(int64_t)j * nq + i] = (int16_t)p;
+  }
 }
 
 constexpr int kMapLists = 16;  // lists (waves) per map workgroup
@@ -538,8 +538,9 @@ void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, 
   const int64_t pairs = (int64_t)nq * (nprobe - gc.bound[0]);
   if (pairs <= 0) return;
   const int nwg = group_map_workgroups(nlist);
-  hipLaunchKernelGGL(k_grp_mark, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, probes, nq, nprobe,
-                     gc.bound[0], rank);
+  const int span = nprobe - gc.bound[0];
+  hipLaunchKernelGGL(k_grp_mark, dim3((unsigned)((span + 255) / 256), (unsigned)std::min(nq, 65535)), dim3(256),
+                     0, s, probes, nq, nprobe, gc.bound[0], rank);
   RBQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_grp_count, dim3(nwg), dim3(1024), 0, s, rank, nq, gc, nlist, G, nwg, cnt, wpart);
   RBQ_HIP(hipGetLastError());
