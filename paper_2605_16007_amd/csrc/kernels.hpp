@@ -127,7 +127,7 @@ struct GroupArgs {
   int bq;                  // query bits B_q
   const int32_t* slots;    // chunk pairs grouped by list
   const int32_t* item_off; // the chunk's item range: [0] first item, [1] end
-  const int4* items;       // per item: (list, first slot, pairs)
+  const int4* items;       // per item: (list's first micro-block, first slot, pairs, list length)
   uint32_t* item_counter;  // work-queue cursor, zero before the launch
   const uint32_t* qthr;    // per-query threshold (ordered float of d_hat^2)
   uint64_t* pool;          // candidate rows: R running keys then the pool
@@ -166,11 +166,12 @@ struct GroupChunks {
 // Pairs of every list-major chunk grouped by (chunk, list), queries ascending
 // within a bin: rank is an nlist x nq int16 table, all -1 on entry; cnt holds
 // nb * nlist counts; wpart 2 * nb * group_map_workgroups(nlist) words of
-// scratch; chunk_items[c .. c+1] the item range of chunk c (nb + 1 words).
+// scratch; chunk_items[c .. c+1] the item range of chunk c (nb + 1 words);
+// items[i] = (the list's first micro-block, first slot, pairs, list length).
 int group_map_workgroups(int nlist);
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
-                      int nlist, int G, int16_t* rank, int32_t* cnt, int32_t* wpart, int32_t* chunk_items,
-                      int32_t* slots, int4* items);
+                      int nlist, int G, const int32_t* list_mb, const int32_t* list_len, int16_t* rank,
+                      int32_t* cnt, int32_t* wpart, int32_t* chunk_items, int32_t* slots, int4* items);
 void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups);
 void launch_reset_masked(hipStream_t s, const uint32_t* mask, uint64_t* rows, int64_t ld, int R,
                          uint32_t* qthr, uint32_t* pcnt, int nq);

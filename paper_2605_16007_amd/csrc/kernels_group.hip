@@ -176,6 +176,8 @@ __global__ __launch_bounds__(1024) void k_grp_scan(int32_t* __restrict__ wpart, 
 
 __global__ __launch_bounds__(1024) void k_grp_fill(const int16_t* __restrict__ rank, int nq, int nprobe,
                                                    GroupChunks gc, int nlist, int G, int nwg,
+                                                   const int32_t* __restrict__ list_mb,
+                                                   const int32_t* __restrict__ list_len,
                                                    const int32_t* __restrict__ cnt,
                                                    const int32_t* __restrict__ wpart,
                                                    int32_t* __restrict__ slots, int4* __restrict__ items) {
@@ -193,7 +195,8 @@ __global__ __launch_bounds__(1024) void k_grp_fill(const int16_t* __restrict__ r
     const int32_t pb = wpart[b * nwg + wg] + wave_sum(cl);
     const int32_t ib = wpart[V + b * nwg + wg] + wave_sum((cl + G - 1) / G);
     const int32_t cn = cnt[b * nlist + j];
-    for (int g = lane; g * G < cn; g += 64) items[ib + g] = make_int4(j, pb + g * G, min(G, cn - g * G), 0);
+    const int mbj = list_mb[j], lenj = list_len[j];
+    for (int g = lane; g * G < cn; g += 64) items[ib + g] = make_int4(mbj, pb + g * G, min(G, cn - g * G), lenj);
     pos[b] = pb;
   }
   const int16_t* rj = rank + (int64_t)j * nq;
@@ -320,8 +323,25 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     __syncthreads();  // sItem is rewritten at the next item
     if (item >= end_item) break;
     const int4 it = a.items[item];
-    const int j = it.x, first = it.y, count = it.z;
+    const int first = it.y, count = it.z;
     const int nt = (count + 15) >> 4;
+    const int mb0 = it.x, len = it.w;
+    const int nmb = (len + 63) >> 6;
+    list_pos0 = mb0 << 6;
+    const size_t rec = (size_t)(W + 2) * 64;
+    // lane = vector of the micro-block; the next micro-block's words and
+    // factors are loaded into registers while the current one is computed
+    // (the first ones are in flight while the item's queries are staged)
+    uint32_t cw[CW];
+    float fa = 0.f, fm = 0.f;
+    auto load_mb = [&](int mbi) {
+      const uint32_t* blk = a.L.blocks + (size_t)(mb0 + mbi) * rec;
+#pragma unroll
+      for (int w = 0; w < CW; ++w) cw[w] = w < W ? blk[w * 64 + lane] : 0u;
+      fa = __uint_as_float(blk[W * 64 + lane]);
+      fm = __uint_as_float(blk[(W + 1) * 64 + lane]);
+    };
+    if (wave < nmb) load_mb(wave);
     // stage the group's queries
     if (tid < GMAX) {
       if (tid < count) {
@@ -375,22 +395,6 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 #pragma unroll
       for (int t = 0; t < KS; ++t) Bq[n][t] = sB[n][t][lane];
     }
-    const int len = a.L.list_len[j], mb0 = a.L.list_mb[j];
-    const int nmb = (len + 63) >> 6;
-    list_pos0 = mb0 << 6;
-    const size_t rec = (size_t)(W + 2) * 64;
-    // lane = vector of the micro-block; the next micro-block's words and
-    // factors are loaded into registers while the current one is computed
-    uint32_t cw[CW];
-    float fa = 0.f, fm = 0.f;
-    auto load_mb = [&](int mbi) {
-      const uint32_t* blk = a.L.blocks + (size_t)(mb0 + mbi) * rec;
-#pragma unroll
-      for (int w = 0; w < CW; ++w) cw[w] = w < W ? blk[w * 64 + lane] : 0u;
-      fa = __uint_as_float(blk[W * 64 + lane]);
-      fm = __uint_as_float(blk[(W + 1) * 64 + lane]);
-    };
-    if (wave < nmb) load_mb(wave);
     for (int mb = wave; mb < nmb; mb += 4) {
       {
         int pop = 0;
@@ -530,8 +534,8 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 }
 
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
-                      int nlist, int G, int16_t* rank, int32_t* cnt, int32_t* wpart, int32_t* chunk_items,
-                      int32_t* slots, int4* items) {
+                      int nlist, int G, const int32_t* list_mb, const int32_t* list_len, int16_t* rank,
+                      int32_t* cnt, int32_t* wpart, int32_t* chunk_items, int32_t* slots, int4* items) {
   RBQ_CHECK(gc.nb >= 1 && gc.nb <= kMaxGroupChunks && gc.bound[gc.nb] == nprobe,
             "list-major chunk bounds");
   RBQ_CHECK(nprobe <= 32767, "list-major map: nprobe out of range");
@@ -546,8 +550,8 @@ void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, 
   RBQ_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_grp_scan, dim3(1), dim3(1024), 0, s, wpart, gc.nb * nwg, nwg, gc.nb, chunk_items);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_fill, dim3(nwg), dim3(1024), 0, s, rank, nq, nprobe, gc, nlist, G, nwg, cnt, wpart,
-                     slots, items);
+  hipLaunchKernelGGL(k_grp_fill, dim3(nwg), dim3(1024), 0, s, rank, nq, nprobe, gc, nlist, G, nwg, list_mb,
+                     list_len, cnt, wpart, slots, items);
   RBQ_HIP(hipGetLastError());
 }
 

@@ -502,7 +502,8 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     }
     // the (chunk, list) -> pairs map of every list-major chunk
     if (any_group)
-      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, b.rankmat, b.gcnt, b.wpart,
+      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, idx->list_mb.as<int32_t>(),
+                       idx->list_len.as<int32_t>(), b.rankmat, b.gcnt, b.wpart,
                        b.chunk_items, b.slots, b.items);
     sa.pcnt = b.pcnt;
     sa.qmask = nullptr;
