@@ -455,7 +455,7 @@ def main():
     wname = w.name if not args.n else f"{w.name}/n={w.n}"  # the workload as the PMC summaries name it
     scan_s = tm["scan_ms"] / ns * 1e-3
     if tm["group_launches"] > 0:
-        # list-major int8-MFMA scan (the dominant kernel): bound by the VALU epilogue
+        # list-major matrix-core scan (the dominant kernel): bound by the VALU epilogue
         launches = tm["group_launches"] / ns
         gscan_s = tm["group_scan_ms"] / ns * 1e-3
         gvec = tm["group_vectors"] / ns
@@ -502,7 +502,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8 MFMA / u32 popcount + fp32",
+        # the list-major scan's matrix-core operands (fp4 codes x fp8 2 qu for
+        # B_q <= 4, int8 above; d > 256 has none), the query-major popcounts,
+        # and the fp32 estimator
+        "dtype": ("fp4 x fp8 MFMA" if w.bq <= 4 and w.d <= 256 else "i8 MFMA" if w.d <= 256 else "no MFMA")
+                 + " / u32 popcount + fp32",
         "scan_form": args.scan,
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,

@@ -299,7 +299,7 @@ rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
  *                          >= RBQ_OPT_GROUP_MIN * nlist, the query-major scan
  *                          for the others,
  *                       1: query-major popcount scan only,
- *                       2: list-major int8-MFMA scan for every chunk (d <= 256)
+ *                       2: list-major matrix-core scan for every chunk (d <= 256)
  *   RBQ_OPT_GROUP_MIN   the threshold above (default 4: each list is probed
  *                       by >= 4 queries of the chunk on average)
  *   RBQ_OPT_POOL_CAP    cap on the per-query pool of the list-major scan
@@ -314,8 +314,8 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
 /*
  * Autotuner (the launch schedule of Sec. 3.3.1 adapted per batch shape).
  * Some launch choices of a search leave its results unchanged: the scan form
- * of each chunk of probe ranks (query-major popcount or list-major int8
- * MFMA), the queries grouped per list-major work item (G), the persistent
+ * of each chunk of probe ranks (query-major popcount or the list-major
+ * matrix-core scan), the queries grouped per list-major work item (G), the persistent
  * workgroups per compute unit, and the sizes of the chunks. rbq_autotune times every
  * candidate on the given queries (host or device, nq x d; representative of
  * later batches), checks that each returns the same results, and stores the
@@ -327,7 +327,7 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
  * only matching entries load.
  */
 typedef struct {
-  int32_t scan;          /* 1 query-major popcount only; 2 list-major int8 MFMA for the
+  int32_t scan;          /* 1 query-major popcount only; 2 list-major matrix core for the
                             chunks of probe ranks selected by chunk_group_min */
   int32_t group_size;    /* queries per list-major item */
   int32_t wg_per_cu;     /* persistent list-major workgroups per compute unit */

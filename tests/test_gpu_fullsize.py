@@ -1,7 +1,8 @@
 """Parity at full size, in the launch configuration the benchmark times:
 10M x 128 skewed integer vectors, nlist 4096, one batch of 1024 queries,
 nprobe 512, rerank_n 3840, k 10, B_q 4 (query-major popcount scan for the
-leading small chunks of probe ranks, list-major int8-MFMA scan for the rest).
+leading small chunks of probe ranks, the list-major fp4 x fp8 matrix-core scan
+for the rest).
 
 The oracle cannot build a 10M-vector index in a test's time, so the index is
 made from oracle parts: centroids from two Lloyd steps (FP64) started at 4096

@@ -1,10 +1,12 @@
-"""GPU tests of the list-major int8-MFMA scan.
+"""GPU tests of the list-major matrix-core scan (fp4 x fp8 for B_q <= 4, int8
+above).
 
 Its estimator epilogue is the same expression as the query-major popcount
 scan's and the selection is exact, so both scans must return identical
 candidates and results; with the oracle's probes, qu and scalars injected the
 candidates must also match the oracle's (same rule as test_gpu_parity P6).
-A tiny pool capacity forces the overflow path (restore + query-major redo).
+A tiny pool capacity forces the overflow path (the flagged queries are
+searched again from scratch by the fused query-major scan).
 """
 import math
 import sys
