@@ -62,7 +62,7 @@ __device__ inline int map_chunk(const GroupChunks& gc, int p) {
   int ch = p >= 0 ? 0 : -1;
 #pragma unroll
   for (int b = 1; b < kMaxGroupChunks; ++b) {
-    if (b >= gc.nb) break;
+    if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
     ch += p >= gc.bound[b] ? 1 : 0;
   }
   return ch;
@@ -102,14 +102,14 @@ __global__ __launch_bounds__(1024) void k_grp_count(const int16_t* __restrict__ 
       for (int u = 0; u < kMapUnroll; ++u)
 #pragma unroll
         for (int b = 0; b < kMaxGroupChunks; ++b) {
-          if (b >= gc.nb) break;
+          if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
           c[b] += (int32_t)__popcll(__ballot(ch[u] == b));
         }
     }
   }
 #pragma unroll
   for (int b = 0; b < kMaxGroupChunks; ++b) {
-    if (b >= gc.nb) break;
+    if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
     const int32_t tot = c[b];
     if (lane == 0) {
       sc[b][wave] = tot;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(1024) void k_grp_fill(const int16_t* __restrict__ r
   int32_t pos[kMaxGroupChunks];
 #pragma unroll
   for (int b = 0; b < kMaxGroupChunks; ++b) {
-    if (b >= gc.nb) break;
+    if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
     const int jl = wg * kMapLists + lane;
     const int32_t cl = lane < wave && jl < nlist ? cnt[b * nlist + jl] : 0;
     const int32_t pb = wpart[b * nwg + wg] + wave_sum(cl);
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(1024) void k_grp_fill(const int16_t* __restrict__ r
       int32_t o = 0;
 #pragma unroll
       for (int b = 0; b < kMaxGroupChunks; ++b) {
-        if (b >= gc.nb) break;
+        if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
         const uint64_t m = __ballot(ch == b);
         if (ch == b) o = pos[b] + (int32_t)lane_prefix(m);
         pos[b] += (int32_t)__popcll(m);
@@ -276,7 +276,6 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   const int W = a.L.W;
   const int D = a.L.d;
   const int Wq = W * 32;  // qu bytes per pair
-  const int nlist = a.nlist;
   int stage_n = 0;  // wave-uniform fill of this wave's stage
   // Moves the staged survivors to their queries' pools: the entries are
   // counted per query slot in LDS, each slot reserves its range with one
