@@ -29,7 +29,7 @@ __all__ = [
     "encode", "pack_bits", "unpack_bits", "probe", "rotate", "quantize",
     "ip_dense", "ip_bitplanes", "bitplanes", "est_terms", "estimate",
     "topk_lex", "rerank", "Index", "build", "search", "brute_force_knn",
-    "s_hat_unquantized",
+    "s_hat_unquantized", "est_terms_unquantized", "ivf_flat_search",
 ]
 
 
@@ -275,6 +275,18 @@ def s_hat_unquantized(P, codes, u_q, alpha, d):
     return (b @ z_q) / (np.sqrt(d) * np.asarray(alpha, np.float64))
 
 
+def est_terms_unquantized(codes: np.ndarray, r: np.ndarray, d: int):
+    """E = sum_d b_d r_d with the query residual r = P^T q - P^T c kept in full
+    precision: Eq. rabitq-ip-estimator without query quantisation (the form the
+    paper's accelerator path evaluates, Sec. 4.3), times sqrt(D) alpha_x
+    ||q - c||. Returns (E FP64, ip = sum_d b01_d r_d FP64, pop int64); since
+    b = 2 b01 - 1, E = 2 ip - sum_d r_d."""
+    b01 = unpack_bits(codes, d).astype(np.float64)
+    b = 2.0 * b01 - 1.0
+    r = np.asarray(r, np.float64)
+    return b @ r, b01 @ r, b01.sum(axis=1).astype(np.int64)
+
+
 def topk_lex(values: np.ndarray, ids: np.ndarray, k: int):
     """The k smallest (value, id) pairs in lexicographic order; if fewer than k
     exist, all of them followed by (+inf, -1) padding."""
@@ -368,13 +380,15 @@ def build(X, nlist=None, *, bq=4, centroids=None, P=None, assignment=None, rng=N
 
 
 def search(index: Index, X: np.ndarray, Q: np.ndarray, nprobe: int, k: int, rerank_n: int,
-           stages: bool = False, probes=None):
+           stages: bool = False, probes=None, unquantized: bool = False):
     """IVF-RaBitQ search of a batch (Sec. 3.1.2 Phases 1, 3, 4, 5).
 
     For each query: probe the nprobe nearest lists; for each probed list j,
     r = P^T q - P^T c_j, quantise r to bq bits, estimate d_hat^2 for every
     vector of the list; keep the rerank_n smallest (d_hat^2, id); re-rank them
     by exact distance and return the k best (ids int64 [nq,k], sqdist FP64).
+    With ``unquantized`` the residual r enters the estimator as it is (no
+    query quantisation: E = sum_d b_d r_d, ``est_terms_unquantized``).
     With ``stages`` also returns a dict of every intermediate result.
     ``probes`` optionally fixes the probed lists ([nq, nprobe] list ids).
     """
@@ -398,17 +412,21 @@ def search(index: Index, X: np.ndarray, Q: np.ndarray, nprobe: int, k: int, rera
         qus, vls, dls, rns, sqs, pls = [], [], [], [], [], []
         for j in pr:
             r = qrot - Cr[j]
-            qu, vl, delta, squ = quantize(r, index.bq)
             rnorm2 = float(r @ r)
             ids = index.lists[j]
-            E, ip, pop = est_terms(index.codes[ids], qu, vl, delta, d)
+            if unquantized:
+                qu, vl, delta, squ = None, 0.0, 0.0, 0
+                E, ip, pop = est_terms_unquantized(index.codes[ids], r, d)
+            else:
+                qu, vl, delta, squ = quantize(r, index.bq)
+                E, ip, pop = est_terms(index.codes[ids], qu, vl, delta, d)
             est = estimate(rnorm2, E, index.n_x[ids], index.alpha[ids], d)
             all_e.append(est)
             all_i.append(ids)
             if stages:
                 qus.append(qu); vls.append(vl); dls.append(delta)
                 rns.append(rnorm2); sqs.append(squ)
-                pls.append({"ids": ids, "ip": ip, "pop": pop, "E": E, "est": est})
+                pls.append({"ids": ids, "ip": ip, "pop": pop, "E": E, "est": est, "r": r})
         e = np.concatenate(all_e) if all_e else np.zeros(0)
         ii = np.concatenate(all_i) if all_i else np.zeros(0, np.int64)
         ce, ci = topk_lex(e, ii, rerank_n)
@@ -422,4 +440,22 @@ def search(index: Index, X: np.ndarray, Q: np.ndarray, nprobe: int, k: int, rera
             st["cand_est"].append(ce); st["per_list"].append(pls)
     if stages:
         return out_ids, out_d, st
+    return out_ids, out_d
+
+
+def ivf_flat_search(index: Index, X: np.ndarray, Q: np.ndarray, nprobe: int, k: int):
+    """IVF-Flat search (Sec. 2.1.2 query processing with full-precision
+    vectors, the comparison system of Sec. 4.2): probe the nprobe nearest
+    lists, compute the exact squared distance ||q - x||^2 (FP64) to every
+    vector in them and return the k best by (distance, id), padded with
+    (-1, +inf). Returns (ids int64 [nq, k], sqdist FP64 [nq, k])."""
+    Q = np.asarray(Q, np.float32)
+    nq = len(Q)
+    out_ids = np.full((nq, k), -1, np.int64)
+    out_d = np.full((nq, k), np.inf)
+    for qi in range(nq):
+        pr, _ = probe(Q[qi], index.centroids, nprobe)
+        ids = np.concatenate([index.lists[j] for j in pr]) if len(pr) else np.zeros(0, np.int64)
+        diff = np.asarray(X[ids], np.float64) - np.asarray(Q[qi], np.float64)[None, :]
+        out_d[qi], out_ids[qi] = topk_lex(np.sum(diff * diff, axis=1), ids, k)
     return out_ids, out_d
