@@ -60,11 +60,20 @@ typedef struct {
   const float* centroids;  /* optional host nlist*d centroids; NULL: k-means */
   const int32_t* assignment; /* optional host n list ids in [0,nlist); NULL:
                               nearest centroid */
-  int32_t vectors_on_host; /* 0: keep the raw vectors in HBM and re-rank on the
-                              GPU; 1: keep them in pinned host memory and
-                              re-rank on host cores (Sec. 3.3.4) */
+  int32_t vectors_on_host; /* where the raw vectors of the exact re-rank live
+                              (Sec. 3.3.4): 0 HBM (GPU re-rank); 1 pinned host
+                              memory (re-rank on host cores); -1 (default)
+                              automatic: HBM when, with the index built, they
+                              leave at least max(8 GiB, 1/8 of the device) of
+                              device memory free, else pinned host memory */
   int32_t host_threads;    /* host re-rank threads (0 = hardware concurrency) */
-  int32_t reserved[6];     /* must be zero */
+  int32_t borrow_vectors;  /* 1: when the vectors end on the host, the index
+                              keeps the caller's rows instead of a copy: x must
+                              then be pinned host memory (hipHostMalloc) holding
+                              n*d float32, and the caller keeps it unchanged
+                              until rbq_free_index. EINVAL with
+                              vectors_on_host = 0 or a pageable or device x */
+  int32_t reserved[5];     /* must be zero */
 } rbq_build_params;
 
 void rbq_build_params_init(rbq_build_params* p);
@@ -74,9 +83,11 @@ void rbq_build_params_init(rbq_build_params* p);
  * centroids (given or k-means on a training sample, Phases 1-2), assignment of
  * every vector to its nearest centroid (Sec. 2.1.2), random orthogonal P, and
  * the RaBitQ encoding of each vector against its centroid (Phase 3;
- * Eqs. normalized-residual, quantize, rabitq-alpha). The index copies x.
- * Errors: EINVAL for n < 1, d < 1, nlist outside [1,n], bq outside [1,8],
- * non-finite inputs, a bad assignment; ENOMEM; EDEVICE.
+ * Eqs. normalized-residual, quantize, rabitq-alpha). The index copies x
+ * (unless it borrows x, see borrow_vectors); the build itself stages all n
+ * rows in device memory. Errors: EINVAL for n < 1, d < 1, nlist outside
+ * [1,n], bq outside [1,8], non-finite inputs, a bad assignment, a bad
+ * vectors_on_host / borrow_vectors combination; ENOMEM; EDEVICE.
  */
 rbq_status rbq_build_index(const float* x, int64_t n, int32_t d, const rbq_build_params* p,
                            rbq_index** out);
@@ -85,10 +96,12 @@ rbq_status rbq_free_index(rbq_index* idx);
 
 typedef struct {
   int64_t n;
-  int32_t d, nlist, bq, vectors_on_host;
+  int32_t d, nlist, bq, vectors_on_host;  /* vectors_on_host as placed: 0 or 1 */
   int64_t max_list_len;      /* largest list */
   int64_t device_bytes;      /* device memory held by the index */
   int64_t code_bytes;        /* packed codes + factors on the device */
+  int32_t vectors_borrowed;  /* 1: the host rows are the caller's (borrow_vectors) */
+  int32_t reserved;
 } rbq_index_info;
 
 rbq_status rbq_get_info(const rbq_index* idx, rbq_index_info* info);
@@ -165,6 +178,9 @@ typedef struct {
   float* sqdist;
   int32_t probe_chunk;  /* probe ranks per scan launch (0 = automatic) */
   int32_t reserved;
+  const float* inject_qrot; /* nq*d float32 rotated queries P^T q used instead of
+                               the rotation's (the residuals of both estimators
+                               are formed from them) */
 } rbq_debug_io;
 
 rbq_status rbq_search_debug(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
@@ -191,6 +207,11 @@ typedef struct {
   float group_scan_ms;       /* the list-major scan launches alone */
   int64_t group_vectors;     /* scanned_vectors of the list-major launches */
   int64_t group_read_bytes;  /* read_bytes of the list-major launches */
+  int64_t fused_launches;    /* of popc_launches: the fused scan-and-select launches */
+  float fused_scan_ms;       /* the fused launches alone */
+  int32_t reserved;
+  int64_t fused_vectors;     /* scanned_vectors of the fused launches */
+  int64_t fused_read_bytes;  /* read_bytes of the fused launches */
 } rbq_timings;
 
 rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled);
@@ -299,7 +320,10 @@ rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
  *                          >= RBQ_OPT_GROUP_MIN * nlist, the query-major scan
  *                          for the others,
  *                       1: query-major popcount scan only,
- *                       2: list-major matrix-core scan for every chunk (d <= 256)
+ *                       2: list-major matrix-core scan for every chunk (d <= 256),
+ *                       3: one work item per query: a workgroup per query scans
+ *                          and selects over all its probes in one launch
+ *                          (batches of >= 128 queries with d <= 1024; else 1)
  *   RBQ_OPT_GROUP_MIN   the threshold above (default 4: each list is probed
  *                       by >= 4 queries of the chunk on average)
  *   RBQ_OPT_POOL_CAP    cap on the per-query pool of the list-major scan
@@ -307,8 +331,21 @@ rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
  *                       overflow path, which stays exact)
  *   RBQ_OPT_ROTATION    query rotation P^T q: 0 FP32 (default), 1 BF16 inputs
  *                       with FP32 accumulation (q and P rounded to bfloat16,
- *                       nearest-even; changes the estimates slightly) */
-enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3, RBQ_OPT_ROTATION = 4 };
+ *                       nearest-even; changes the estimates slightly)
+ *   RBQ_OPT_GROUP_SIZE  queries per list-major work item, 1..64 (0 = as
+ *                       autotuned, else 64); items of up to 32 queries take
+ *                       two 16-query matrix-core tiles, larger ones four
+ *   RBQ_OPT_ESTIMATOR   0 (default): the residual is quantised to B_q bits
+ *                       (Sec. 2.2.2); 1: unquantised, E = sum_d b_d r_d with
+ *                       r the FP32 rotated residual, as the paper's
+ *                       accelerator path computes it (Eq.
+ *                       rabitq-ip-estimator, Sec. 4.3); query-major scan with
+ *                       sign-pattern tables of 8-dimension groups (4 when
+ *                       d > 128), d <= 1024; changes the estimates. In this
+ *                       mode rbq_search_debug does not fill qu and scalars,
+ *                       and ip holds nothing */
+enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3, RBQ_OPT_ROTATION = 4,
+       RBQ_OPT_GROUP_SIZE = 5, RBQ_OPT_ESTIMATOR = 6 };
 rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
 
 /*

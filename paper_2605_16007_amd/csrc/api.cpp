@@ -282,6 +282,7 @@ void rbq_build_params_init(rbq_build_params* p) {
   p->bq = 4;
   p->kmeans_iters = 25;
   p->kmeans_restarts = 3;
+  p->vectors_on_host = -1;
 }
 
 rbq_status rbq_build_index(const float* x, int64_t n, int32_t d, const rbq_build_params* p,
@@ -295,7 +296,12 @@ rbq_status rbq_build_index(const float* x, int64_t n, int32_t d, const rbq_build
   if (p->bq < 1 || p->bq > 8) return invalid("bq must be in [1, 8]");
   if (p->kmeans_iters < 0 || p->kmeans_restarts < 0 || p->train_n < 0)
     return invalid("k-means parameters must be >= 0");
-  if (p->vectors_on_host != 0 && p->vectors_on_host != 1) return invalid("vectors_on_host must be 0 or 1");
+  if (p->vectors_on_host < -1 || p->vectors_on_host > 1) return invalid("vectors_on_host must be -1, 0 or 1");
+  if (p->borrow_vectors != 0 && p->borrow_vectors != 1) return invalid("borrow_vectors must be 0 or 1");
+  if (p->borrow_vectors) {
+    if (p->vectors_on_host == 0) return invalid("borrow_vectors needs the vectors on the host (vectors_on_host 1 or -1)");
+    if (!rbq::is_pinned_host_ptr(x)) return invalid("borrow_vectors needs x in pinned host memory");
+  }
   for (int r : p->reserved)
     if (r != 0) return invalid("reserved fields must be zero");
   if (n > (int64_t)INT32_MAX) return invalid("n must fit in 31 bits");
@@ -323,6 +329,8 @@ rbq_status rbq_get_info(const rbq_index* idx, rbq_index_info* info) {
   info->nlist = idx->nlist;
   info->bq = idx->bq;
   info->vectors_on_host = idx->vectors_on_host;
+  info->vectors_borrowed = idx->hostX && !idx->hostX_owned ? 1 : 0;
+  info->reserved = 0;
   info->max_list_len = idx->max_list_len;
   info->code_bytes = (int64_t)idx->blocks.bytes;
   info->device_bytes = (int64_t)(idx->X.bytes + idx->X8.bytes + idx->C.bytes + idx->Crot.bytes + idx->cnorm.bytes +
@@ -410,8 +418,8 @@ rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled) {
     idx->pending.clear();
     idx->last = rbq_timings{};
     if (enabled) {
-      if (!idx->tcounter.p) idx->tcounter.alloc(4 * sizeof(unsigned long long));
-      RBQ_HIP(hipMemset(idx->tcounter.p, 0, 4 * sizeof(unsigned long long)));
+      if (!idx->tcounter.p) idx->tcounter.alloc(6 * sizeof(unsigned long long));
+      RBQ_HIP(hipMemset(idx->tcounter.p, 0, 6 * sizeof(unsigned long long)));
     }
     idx->timing.store(enabled ? 1 : 0);
   });
@@ -424,16 +432,19 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
     std::lock_guard<std::mutex> g(idx->timing_mu);
     for (auto& a : idx->pending) {
       RBQ_HIP(hipEventSynchronize(a.e[5]));
-      float ms[5], tot = 0.f, scan = 0.f, gscan = 0.f;
+      float ms[5], tot = 0.f, scan = 0.f, gscan = 0.f, fscan = 0.f;
       for (int i = 0; i < 5; ++i) RBQ_HIP(hipEventElapsedTime(&ms[i], a.e[i], a.e[i + 1]));
       RBQ_HIP(hipEventElapsedTime(&tot, a.e[0], a.e[5]));
       for (size_t c = 0; c + 1 < a.scan.size(); c += 2) {
         float t = 0.f;
         RBQ_HIP(hipEventElapsedTime(&t, a.scan[c], a.scan[c + 1]));
         scan += t;
-        if (a.scan_lm[c / 2]) gscan += t;
+        if (a.scan_lm[c / 2] == 1) gscan += t;
+        if (a.scan_lm[c / 2] == 2) fscan += t;
       }
       idx->last.group_scan_ms += gscan;
+      idx->last.fused_scan_ms += fscan;
+      idx->last.fused_launches += a.fused;
       idx->last.probe_ms += ms[0];
       idx->last.rotate_ms += ms[1];
       idx->last.quant_ms += ms[2];
@@ -449,7 +460,7 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
     }
     idx->pending.clear();
     if (idx->tcounter.p) {
-      unsigned long long c[4] = {0, 0, 0, 0};
+      unsigned long long c[6] = {0, 0, 0, 0, 0, 0};
       RBQ_HIP(hipDeviceSynchronize());
       RBQ_HIP(hipMemcpy(c, idx->tcounter.p, sizeof(c), hipMemcpyDeviceToHost));
       idx->last.scanned_vectors = (int64_t)c[0];
@@ -457,6 +468,8 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
       idx->last.read_bytes = (int64_t)c[1];
       idx->last.group_vectors = (int64_t)c[2];
       idx->last.group_read_bytes = (int64_t)c[3];
+      idx->last.fused_vectors = (int64_t)c[4];
+      idx->last.fused_read_bytes = (int64_t)c[5];
     }
     *t = idx->last;
   });
@@ -466,7 +479,7 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value) {
   if (!idx) return invalid("index is NULL");
   switch (option) {
     case RBQ_OPT_SCAN:
-      if (value < 0 || value > 2) return invalid("RBQ_OPT_SCAN must be 0, 1 or 2");
+      if (value < 0 || value > 3) return invalid("RBQ_OPT_SCAN must be 0, 1, 2 or 3");
       idx->opt_scan.store((int)value);
       return RBQ_OK;
     case RBQ_OPT_GROUP_MIN:
@@ -480,6 +493,16 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value) {
     case RBQ_OPT_ROTATION:
       if (value < 0 || value > 1) return invalid("RBQ_OPT_ROTATION must be 0 or 1");
       idx->opt_rotation.store((int)value);
+      return RBQ_OK;
+    case RBQ_OPT_ESTIMATOR:
+      if (value < 0 || value > 1) return invalid("RBQ_OPT_ESTIMATOR must be 0 or 1");
+      if (value == 1 && idx->d > rbq::scan_lut_max_d())
+        return invalid("RBQ_OPT_ESTIMATOR 1 supports d <= 1024");
+      idx->opt_estimator.store((int)value);
+      return RBQ_OK;
+    case RBQ_OPT_GROUP_SIZE:
+      if (value < 0 || value > 64) return invalid("RBQ_OPT_GROUP_SIZE must be in [0, 64]");
+      idx->opt_group_size.store((int)value);
       return RBQ_OK;
     default:
       return invalid("unknown option");

@@ -41,6 +41,16 @@ bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+bool is_pinned_host_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
+
 std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes) {
   std::unique_ptr<Workspace> got;
   {
@@ -258,16 +268,16 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
   idx->bq = p.bq;
   idx->bqs = p.bq <= 4 ? 4 : 8;
   idx->W = (d + 31) / 32;
-  idx->vectors_on_host = p.vectors_on_host;
+  idx->vectors_on_host = p.vectors_on_host;  // -1 (automatic) is settled once the index is built
   idx->host_threads = p.host_threads;
   const int ld = idx->ld, nlist = p.nlist, W = idx->W;
   StreamGuard sg;
   hipStream_t s = sg.s;
   Rng rng(p.seed);
 
-  // raw vectors on the device, rows padded to ld with zeros
-  DevBuf tmpX;
-  DevBuf& Xd = idx->vectors_on_host ? tmpX : idx->X;
+  // raw vectors on the device, rows padded to ld with zeros (kept as the
+  // index's own copy when they stay in HBM)
+  DevBuf& Xd = idx->X;
   Xd.alloc((size_t)n * ld * sizeof(float));
   if (ld != d) RBQ_HIP(hipMemsetAsync(Xd.p, 0, Xd.bytes, s));
   upload_rows(Xd.as<float>(), ld, x, d, n, s);
@@ -392,16 +402,31 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
                   idx->pos2id.as<int32_t>(), dmb.as<int32_t>(), m0, std::min(nmb, m0 + step), d, W,
                   idx->blocks.as<uint32_t>(), idx->nx.as<float>(), idx->alpha.as<float>());
 
-  if (idx->vectors_on_host) {
-    RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&idx->hostX), (size_t)n * d * sizeof(float),
-                          hipHostMallocDefault));
-    if (ld == d)
-      RBQ_HIP(hipMemcpyAsync(idx->hostX, Xd.p, (size_t)n * d * sizeof(float), hipMemcpyDeviceToHost, s));
-    else
-      RBQ_HIP(hipMemcpy2DAsync(idx->hostX, d * sizeof(float), Xd.p, ld * sizeof(float),
-                               d * sizeof(float), n, hipMemcpyDeviceToHost, s));
-  }
   RBQ_HIP(hipStreamSynchronize(s));
+  if (idx->vectors_on_host < 0) {
+    // automatic placement: HBM if the raw vectors (already resident) leave
+    // enough device memory free for search workspaces, else the host
+    size_t free_b = 0, total_b = 0;
+    RBQ_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t reserve = std::max<size_t>((size_t)8 << 30, total_b / 8);
+    idx->vectors_on_host = free_b >= reserve ? 0 : 1;
+  }
+  if (idx->vectors_on_host) {
+    if (p.borrow_vectors) {
+      idx->hostX = const_cast<float*>(x);  // the caller's pinned rows
+      idx->hostX_owned = false;
+    } else {
+      RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&idx->hostX), (size_t)n * d * sizeof(float),
+                            hipHostMallocDefault));
+      if (ld == d)
+        RBQ_HIP(hipMemcpyAsync(idx->hostX, Xd.p, (size_t)n * d * sizeof(float), hipMemcpyDeviceToHost, s));
+      else
+        RBQ_HIP(hipMemcpy2DAsync(idx->hostX, d * sizeof(float), Xd.p, ld * sizeof(float),
+                                 d * sizeof(float), n, hipMemcpyDeviceToHost, s));
+      RBQ_HIP(hipStreamSynchronize(s));
+    }
+    Xd.reset();
+  }
   compact_raw_vectors(idx.get(), s);
   return idx.release();
 }
@@ -427,5 +452,5 @@ void compact_raw_vectors(rbq_index* idx, hipStream_t s) {
 rbq_index::~rbq_index() {
   pool.reset();
   for (auto& pf : pinned_free) (void)hipHostFree(pf.first);
-  if (hostX) (void)hipHostFree(hostX);
+  if (hostX && hostX_owned) (void)hipHostFree(hostX);
 }

@@ -22,8 +22,9 @@ namespace rbq {
 struct TimingRec {
   hipEvent_t e[6] = {};           // start, probe, rotate, quant, scan+merge, rerank
   std::vector<hipEvent_t> scan;   // (start, end) around every scan launch
-  std::vector<char> scan_lm;      // per launch: list-major form
-  int64_t group = 0, popc = 0;    // scan launches of each form
+  std::vector<char> scan_lm;      // per launch: 0 query-major popcount, 1 list-major, 2 fused
+  int64_t group = 0, popc = 0;    // scan launches: list-major; query-major (popcount or fused)
+  int64_t fused = 0;              // of the query-major launches, the fused ones
   bool first_part = true;         // the first (or only) part of one search
 };
 
@@ -105,12 +106,15 @@ struct rbq_index {
   std::vector<int32_t> h_assign;  // n
   std::vector<int32_t> h_list_len, h_list_mb, h_pos2id;
   float* hostX = nullptr;         // pinned n x d when vectors_on_host
+  bool hostX_owned = true;        // false: the caller's rows (borrow_vectors)
 
   // options (rbq_set_option) and device facts
   std::atomic<int> opt_scan{0};
   std::atomic<int> opt_group_min{4};
   std::atomic<int64_t> opt_pool_cap{0};
   std::atomic<int> opt_rotation{0};  // 0 FP32, 1 BF16 inputs (FP32 accumulation)
+  std::atomic<int> opt_group_size{0};  // queries per list-major item (0: tuned or built-in)
+  std::atomic<int> opt_estimator{0};   // 0 B_q-bit query, 1 unquantised FP32 residual
   // autotuned launch choices per batch-shape bucket (rbq_autotune)
   std::mutex tune_mu;
   std::map<uint64_t, rbq::TuneCfg> tune;
@@ -128,7 +132,7 @@ struct rbq_index {
   rbq_timings last{};
   std::vector<rbq::TimingRec> pending;
   rbq::DevBuf tcounter;  // device sums: scanned vectors, record bytes read; the same two
-                         // for the list-major launches alone
+                         // for the list-major launches alone, then for the fused ones
 
   // host re-rank (vectors_on_host): worker threads and pinned staging, made on
   // first use and kept with the index
@@ -145,6 +149,7 @@ std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes);
 void ws_release(rbq_index* idx, std::unique_ptr<Workspace> ws, hipStream_t s);
 
 bool is_device_ptr(const void* p);
+bool is_pinned_host_ptr(const void* p);
 void upload_rows(float* dst, int ld, const float* src, int d, int64_t n, hipStream_t s);
 
 rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params& p);
@@ -166,13 +171,23 @@ struct SearchIO {
   // caller before the search's stream has passed this call
   char* ws_base = nullptr;
   size_t ws_cap = 0;
+  bool untimed = false;  // never record stage events (no event creation)
 };
 // Workspace bytes of a mixed search of nq queries (nprobe, k, R the batch's
 // largest, scanned_pairs the sum of per-query nprobe) with that pool budget.
 size_t search_workspace_bytes(const rbq_index* idx, int64_t nq, int nprobe, int k, int R,
                               int64_t scanned_pairs, int64_t pool_budget);
+// The largest pool budget >= lo whose workspace (search_workspace_bytes) fits
+// in cap bytes; -1 if not even lo fits.
+int64_t fit_pool_budget(const rbq_index* idx, int64_t nq, int nprobe, int k, int R,
+                        int64_t scanned_pairs, size_t cap, int64_t lo);
 void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
             float* dist, hipStream_t s, const SearchIO& io);
+// Phases 1-4 only: the coarse top-R of every query (nq x R sort keys) is
+// copied into cand_host, and the queries into q_host when q is on the device
+// (both pinned host memory); returns when they are there. The re-rank's input.
+void search_candidates(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
+                       uint64_t* cand_host, float* q_host, hipStream_t s, const SearchIO& io);
 
 // Autotuner (tune.cpp): bucket key of a batch shape, the table lookup used by
 // every search, trials, and the text cache.

@@ -1111,6 +1111,155 @@ void launch_scan_popc(hipStream_t s, const ScanArgs& a) {
 }
 
 // ---------------------------------------------------------------------------
+// Query-major scan with the unquantised residual. The item's residual
+// r = P^T q - P^T c_j is formed in LDS (zero past d), its squared norm summed
+// in a fixed order, and a table lut[g][m] = sum_i s_i r_{GB g + i}, s_i = +1
+// for bit i of m set and -1 otherwise, is built for every group g of GB
+// dimensions. A vector's E = sum_d b_d r_d is then one lookup per group of its
+// code, summed in group order; the rest (threshold, LDS selection, pools) is
+// the popcount scan's.
+// ---------------------------------------------------------------------------
+constexpr int kLutMaxD = 1024;
+
+template <int GB, bool DUMP>
+__global__ __launch_bounds__(256) void k_scan_lut(ScanArgs a, int cap) {
+  extern __shared__ uint64_t sel[];
+  constexpr int NE = 1 << GB;                    // table entries per group
+  constexpr int NG = (GB == 8 ? 128 : kLutMaxD) / GB;  // groups held (16 KB of table)
+  __shared__ float lut[NG * NE];
+  __shared__ float rs[NG * GB];
+  __shared__ float red[256];
+  __shared__ int s_n;
+  __shared__ uint64_t s_thr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int W = a.L.W;
+  const int D = a.L.d;
+  const int ng = (D + GB - 1) / GB;
+  const int it = blockIdx.x;
+  const int pr = it / a.nq, i = it - pr * a.nq;
+  const int p = a.p0 + pr;
+  if (a.qmask && a.qmask[i] == 0u) return;  // uniform over the workgroup
+  const int64_t pair = (int64_t)i * a.nprobe + p;
+  const int j = a.probes[pair];
+  const int len = j >= 0 ? a.L.list_len[j] : 0, mb0 = j >= 0 ? a.L.list_mb[j] : 0;
+  const int nmb = (len + 63) >> 6;
+  const int R = a.R;
+  if (len == 0) return;  // nothing to scan (uniform)
+  // the residual and its squared norm (each thread sums a fixed stride)
+  float part = 0.f;
+  for (int d = tid; d < ng * GB; d += 256) {
+    const float r = d < D ? a.qrot[(int64_t)i * a.ldq + d] - a.crot[(int64_t)j * a.ldc + d] : 0.f;
+    rs[d] = r;
+    part = fmaf(r, r, part);
+  }
+  red[tid] = part;
+  if (tid == 0) {
+    s_n = 0;
+    s_thr = a.qthr ? ((static_cast<uint64_t>(a.qthr[i]) << 32) | 0xFFFFFFFFull) : KEY_NONE;
+  }
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  const float rn2 = red[0];
+  // the sign-pattern tables, each entry summed in dimension order
+  for (int e = tid; e < ng * NE; e += 256) {
+    const int g = e / NE, m = e - g * NE;
+    float acc = 0.f;
+#pragma unroll
+    for (int b = 0; b < GB; ++b) {
+      const float r = rs[g * GB + b];
+      acc += ((m >> b) & 1) ? r : -r;
+    }
+    lut[e] = acc;
+  }
+  __syncthreads();
+  const size_t rec = (size_t)(W + 2) * 64;
+  for (int base = 0; base < nmb; base += 4) {
+    const int m = base + wave;
+    uint64_t key = KEY_NONE;
+    if (m < nmb) {
+      const uint32_t* blk = a.L.blocks + (size_t)(mb0 + m) * rec;
+      float E = 0.f;
+      for (int w = 0; w < W; ++w) {
+        const uint32_t c = blk[w * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < 32 / GB; ++t) {
+          const int g = w * (32 / GB) + t;
+          if (g < ng) E += lut[g * NE + ((c >> (GB * t)) & (NE - 1))];
+        }
+      }
+      const float fadd = __uint_as_float(blk[W * 64 + lane]);
+      const float fmul = __uint_as_float(blk[(W + 1) * 64 + lane]);
+      const float est = fmaf(fmul, E, fadd) + rn2;
+      const int v = (m << 6) + lane;
+      if (v < len) {
+        key = key64(est, (uint32_t)((mb0 << 6) + v));
+        if (DUMP) a.dump_est[pair * a.maxlen + v] = est;
+      }
+    }
+    const uint64_t thr = s_thr;
+    const bool pass = key < thr;
+    const uint64_t mask = __ballot(pass);
+    if (mask) {
+      int off = 0;
+      if (lane == 0) off = atomicAdd(&s_n, (int)__popcll(mask));
+      off = __shfl(off, 0);
+      if (pass) sel[off + (int)lane_prefix(mask)] = key;
+    }
+    __syncthreads();
+    const int nn = s_n;
+    __syncthreads();  // every thread has read the count before the next appends
+    if (nn > cap - 256) sel_compact(sel, cap, R, &s_n, &s_thr);
+  }
+  __syncthreads();
+  const int n = s_n;
+  if (n > R) {  // keep the best R
+    int P = 2;
+    while (P < n) P <<= 1;
+    for (int t = n + tid; t < P; t += 256) sel[t] = KEY_NONE;
+    __syncthreads();
+    bitonic_sort_lds(sel, P);
+  }
+  const int nout = n < R ? n : R;
+  __shared__ int s_base;
+  if (tid == 0) s_base = nout ? (int)atomicAdd(&a.pcnt[i], (uint32_t)nout) : 0;
+  __syncthreads();
+  uint64_t* dst = a.out + (int64_t)i * a.out_ld + R + s_base;
+  for (int r = tid; r < nout; r += 256) {
+    const uint64_t sv = sel[r];
+    const int id = a.L.pos2id[(uint32_t)sv];
+    dst[r] = (sv & 0xFFFFFFFF00000000ull) | (uint32_t)id;
+  }
+  if (a.qthr && tid == 0 && n > R) atomicMin(&a.qthr[i], (uint32_t)(sel[R - 1] >> 32));
+}
+
+int scan_lut_max_d() { return kLutMaxD; }
+
+void launch_scan_lut(hipStream_t s, const ScanArgs& a) {
+  if ((int64_t)a.nq * a.pn <= 0) return;
+  RBQ_CHECK(a.L.d <= kLutMaxD, "the unquantised-query scan supports d <= 1024");
+  RBQ_CHECK(a.qrot && a.crot, "unquantised-query scan: rotated queries and centroids");
+  const int cap = pow2_at_least(a.R + 256);
+  const unsigned items = (unsigned)((int64_t)a.nq * a.pn);
+  const size_t lds = (size_t)cap * sizeof(uint64_t);
+  const bool dump = a.dump_est != nullptr;
+  if (a.L.d <= 128) {
+    if (dump)
+      hipLaunchKernelGGL((k_scan_lut<8, true>), dim3(items), dim3(256), lds, s, a, cap);
+    else
+      hipLaunchKernelGGL((k_scan_lut<8, false>), dim3(items), dim3(256), lds, s, a, cap);
+  } else {
+    if (dump)
+      hipLaunchKernelGGL((k_scan_lut<4, true>), dim3(items), dim3(256), lds, s, a, cap);
+    else
+      hipLaunchKernelGGL((k_scan_lut<4, false>), dim3(items), dim3(256), lds, s, a, cap);
+  }
+  RBQ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // Fused query-major scan + selection for chunks whose lists are shared by few
 // queries: one workgroup (8 waves, 64 KB of LDS: two per CU) per query loads
 // the query's running top-R into an LDS buffer, scans the chunk's probed lists

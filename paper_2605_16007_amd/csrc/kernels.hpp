@@ -93,8 +93,24 @@ struct ScanArgs {
   int32_t* dump_ip;        // debug: [nq][nprobe][maxlen] (or null)
   float* dump_est;
   int64_t maxlen;
+  // unquantised-query scan only: rotated queries P^T q and rotated centroids
+  // P^T c (row strides ldq, ldc); the residual r = P^T q - P^T c stays FP32
+  const float* qrot = nullptr;
+  int ldq = 0;
+  const float* crot = nullptr;
+  int ldc = 0;
 };
 void launch_scan_popc(hipStream_t s, const ScanArgs& a);
+
+// Query-major scan with the unquantised FP32 residual (Eq.
+// rabitq-ip-estimator as the paper's accelerator path evaluates it, no query
+// quantisation): per (query, probe) item, E = sum_d b_d r_d by table lookups,
+// b_d = +-1, from an LDS table of every sign pattern of each group of 8
+// dimensions (4 when d > 128; d <= 1024), then
+// d_hat^2 = ||r||^2 + n_x^2 - 2 n_x E / (sqrt(D) alpha_x). Selection, pools
+// and dumps (est only) as launch_scan_popc.
+void launch_scan_lut(hipStream_t s, const ScanArgs& a);
+int scan_lut_max_d();
 
 // Fused query-major scan + per-query selection: one workgroup per query
 // scans probe ranks [p0, p0 + pn) and leaves the query's best R (rowk[i] for a
@@ -136,6 +152,9 @@ struct GroupArgs {
   uint32_t* pcnt;          // [nq] pool fill
   uint32_t* overflow;      // [nq] set when a query's pool overflowed
   uint32_t* any_overflow;  // set with any overflow flag
+  int32_t* dump_ip = nullptr;  // debug: [pairs][maxlen] ip and d_hat^2 of every estimate (or null)
+  float* dump_est = nullptr;
+  int64_t maxlen = 0;
 };
 int group_k_steps(int d);
 // The fp4 x fp8 form of the list-major scan (B_q <= 4): 128-dimension steps

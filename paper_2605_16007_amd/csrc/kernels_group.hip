@@ -251,7 +251,10 @@ __device__ inline v4i unpack16(uint32_t bits) {
 enum { QB_DOUBLE = 0, QB_PLAIN = 1, QB_OFFSET = 2, QB_F8 = 3 };
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-template <int KS, int QB, int GT>
+// DUMP (debug entry point only): every estimate of the item is also written
+// out per (pair, position in the list) with its inner product ip, before any
+// threshold test.
+template <int KS, int QB, int GT, bool DUMP>
 __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   constexpr bool F8 = QB == QB_F8;
   constexpr int CW = F8 ? 4 * KS : 2 * KS;  // code words per vector staged
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   __shared__ float4 sSc[GMAX];                // (||r||^2, v_l, Delta, sum qu) per query slot
   __shared__ float sThr[GMAX];                // threshold on d_hat^2 per query slot
   __shared__ int32_t sQ[GMAX];                // query id per slot
+  __shared__ int32_t sPair[DUMP ? GMAX : 1];  // (query, probe) pair per slot
   __shared__ uint32_t sCode[4][CW][64];      // per wave: the micro-block's code words
   __shared__ __align__(16) float sVx[4][64], sAdd[4][64], sMul[4][64];
   __shared__ __align__(16) int32_t sPop[QB == QB_OFFSET ? 4 : 1][64];  // 128 pop per vector
@@ -347,6 +351,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
         const int pair = a.slots[first + tid];
         const int qi = pair / a.nprobe;
         sQ[tid] = qi;
+        if (DUMP) sPair[tid] = pair;
         sSc[tid] = a.scal[pair];
         const uint32_t th = a.qthr[qi];
         sThr[tid] = th == 0xFFFFFFFFu ? INFINITY : f32_ord(th);
@@ -498,6 +503,24 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
               part[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
               pm[r] = __builtin_amdgcn_ballot_w64(part[r] <= qthr[n]);
             }
+            if constexpr (DUMP) {
+              const int q = 16 * n + (lane & 15);
+              const uint32_t pos = rel0 + (uint32_t)r;
+              if (q < count && pos < (uint32_t)len) {
+                // g = 2 ip - sum qu (QB_F8, QB_DOUBLE) or ip itself
+                const int sq = -qneg[n];
+                int ip;
+                if constexpr (F8)
+                  ip = ((int)acc[n][r] + sq) >> 1;
+                else if constexpr (QB == QB_DOUBLE)
+                  ip = (acc[n][r] + sq) >> 1;
+                else
+                  ip = acc[n][r];
+                const int64_t o = (int64_t)sPair[q] * a.maxlen + pos;
+                a.dump_ip[o] = ip;
+                a.dump_est[o] = F8 ? part[r] + qrn2[n] : part[r];
+              }
+            }
           }
           if (pm[0] | pm[1] | pm[2] | pm[3]) {  // stage the survivors of this tile
             const uint32_t tag = rel0 | ((uint32_t)(16 * n + (lane & 15)) << 26);
@@ -560,23 +583,19 @@ int group_k_steps(int d) { return (d + 63) / 64; }
 
 int group_f8_steps(int d) { return (d + 127) / 128; }
 
-void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups) {
-  RBQ_CHECK(a.G >= 1 && a.G <= GMAX, "group size out of range");
-  const int ks = group_k_steps(a.L.d);
-  RBQ_CHECK(ks <= KSMAX, "grouped scan supports d <= 256");
-  RBQ_CHECK(a.bq >= 1 && a.bq <= 8, "query bits out of range");
-  const bool two = a.G <= 32;
+template <bool DUMP>
+void launch_scan_group_t(hipStream_t s, const GroupArgs& a, int workgroups, int ks, bool two) {
   if (group_uses_f8(a.bq, a.L.d)) {
     const int ks8 = group_f8_steps(a.L.d);
     RBQ_CHECK(a.qu_ld == 128 * ks8, "fp8 list-major scan: operand rows");
     if (ks8 == 1 && two)
-      hipLaunchKernelGGL((k_scan_group<1, QB_F8, 2>), dim3(workgroups), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_scan_group<1, QB_F8, 2, DUMP>), dim3(workgroups), dim3(256), 0, s, a);
     else if (ks8 == 1)
-      hipLaunchKernelGGL((k_scan_group<1, QB_F8, 4>), dim3(workgroups), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_scan_group<1, QB_F8, 4, DUMP>), dim3(workgroups), dim3(256), 0, s, a);
     else if (two)
-      hipLaunchKernelGGL((k_scan_group<2, QB_F8, 2>), dim3(workgroups), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_scan_group<2, QB_F8, 2, DUMP>), dim3(workgroups), dim3(256), 0, s, a);
     else
-      hipLaunchKernelGGL((k_scan_group<2, QB_F8, 4>), dim3(workgroups), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_scan_group<2, QB_F8, 4, DUMP>), dim3(workgroups), dim3(256), 0, s, a);
     RBQ_HIP(hipGetLastError());
     return;
   }
@@ -584,9 +603,9 @@ void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups) {
   const int qb = a.bq <= 6 ? QB_DOUBLE : a.bq == 7 ? QB_PLAIN : QB_OFFSET;
 #define RBQ_GROUP_LAUNCH_QB(K, QBV)                                                           \
   if (two)                                                                                  \
-    hipLaunchKernelGGL((k_scan_group<K, QBV, 2>), dim3(workgroups), dim3(256), 0, s, a);    \
+    hipLaunchKernelGGL((k_scan_group<K, QBV, 2, DUMP>), dim3(workgroups), dim3(256), 0, s, a);    \
   else                                                                                      \
-    hipLaunchKernelGGL((k_scan_group<K, QBV, 4>), dim3(workgroups), dim3(256), 0, s, a)
+    hipLaunchKernelGGL((k_scan_group<K, QBV, 4, DUMP>), dim3(workgroups), dim3(256), 0, s, a)
 #define RBQ_GROUP_LAUNCH(K)                 \
   if (qb == QB_DOUBLE) {                    \
     RBQ_GROUP_LAUNCH_QB(K, QB_DOUBLE);      \
@@ -605,6 +624,20 @@ void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups) {
 #undef RBQ_GROUP_LAUNCH_QB
   RBQ_HIP(hipGetLastError());
 }
+
+void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups) {
+  RBQ_CHECK(a.G >= 1 && a.G <= GMAX, "group size out of range");
+  const int ks = group_k_steps(a.L.d);
+  RBQ_CHECK(ks <= KSMAX, "grouped scan supports d <= 256");
+  RBQ_CHECK(a.bq >= 1 && a.bq <= 8, "query bits out of range");
+  const bool two = a.G <= 32;
+  if (a.dump_ip) {
+    launch_scan_group_t<true>(s, a, workgroups, ks, two);
+    return;
+  }
+  launch_scan_group_t<false>(s, a, workgroups, ks, two);
+}
+
 
 // Queries whose pool overflowed in a list-major pass are searched again from
 // scratch by the query-major scan: empty running top-R, no threshold, empty

@@ -162,7 +162,7 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   } else {
     tuned = tune_lookup(const_cast<rbq_index*>(idx), nq, nprobe, R, &cfg);
   }
-  P.G = cfg.G;
+  P.G = idx->opt_group_size.load() > 0 ? idx->opt_group_size.load() : cfg.G;
   P.wg_per_cu = cfg.wg_per_cu;
   // scan form per chunk of probe ranks: query-major (1) everywhere, or the
   // list-major MFMA scan for every chunk whose (query, probe) pairs number at
@@ -189,9 +189,8 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
     pn = std::min(pn, nprobe - p0);
     P.qm_chunks.push_back({p0, pn, false, false});
   }
-  // (per-vector dumps of the debug entry point come from the query-major scan;
-  // list-major survivors carry their position in the list in 26 bits)
-  const bool lm_ok = scan_mode == 2 && !P.dumps && group_k_steps(idx->d) <= 4 &&
+  // (list-major survivors carry their position in the list in 26 bits)
+  const bool lm_ok = scan_mode == 2 && group_k_steps(idx->d) <= 4 &&
                      idx->max_list_len < (int64_t(1) << 26);
   if (lm_ok) {
     // chunks double the scanned prefix; the first holds about first_factor * R
@@ -210,7 +209,8 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
       if (lm) {
         P.chunks.push_back({p0, pn, true, false});
         P.any_group = true;
-      } else if (nq >= kFusedMinQueries && idx->W <= 32 && cfg.early == 0) {
+      } else if (nq >= kFusedMinQueries && idx->W <= 32 && cfg.early == 0 && !P.dumps) {
+        // (per-vector dumps come from the popcount and list-major scans)
         // one workgroup per query scans and selects in one launch; it lowers
         // its threshold whenever its buffer fills, so consecutive chunks of
         // this kind become one launch
@@ -223,6 +223,10 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
           P.chunks.push_back({q0, std::min(P.pch, p0 + pn - q0), false, false});
       }
     }
+  } else if (scan_mode == 3 && nq >= kFusedMinQueries && idx->W <= 32 && !P.dumps) {
+    // one workgroup per query scans and selects over every probe rank in one
+    // launch (one work item per query)
+    P.chunks.push_back({0, nprobe, false, true});
   } else {
     P.chunks = P.qm_chunks;
   }
@@ -303,6 +307,28 @@ size_t search_workspace_bytes(const rbq_index* idx, int64_t nq, int nprobe, int 
   return dry.off + 256;
 }
 
+int64_t fit_pool_budget(const rbq_index* idx, int64_t nq, int nprobe, int k, int R,
+                        int64_t scanned_pairs, size_t cap, int64_t lo) {
+  lo = std::max<int64_t>(1, lo);
+  auto fits = [&](int64_t b) {
+    return search_workspace_bytes(idx, nq, nprobe, k, R, scanned_pairs, b) <= cap;
+  };
+  if (!fits(lo)) return -1;
+  // the workspace grows with the pool budget (larger pools, and the chunk
+  // schedule that goes with them), so the largest fitting budget is found by
+  // bisection; the result is checked, since the schedule's buffers only
+  // mostly grow with it
+  int64_t good = lo, hi = (int64_t)cap;
+  while (good < hi) {
+    const int64_t mid = good + (hi - good + 1) / 2;
+    if (fits(mid))
+      good = mid;
+    else
+      hi = mid - 1;
+  }
+  return fits(good) ? good : lo;
+}
+
 namespace {
 
 // Host re-rank hand-off of one (sub-)batch: the candidate rows and the
@@ -370,7 +396,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
   const int64_t pairs = P.pairs;
   const bool inj_probes = P.inj_probes, inj_qu = P.inj_qu, dumps = P.dumps;
   const int64_t maxlen = P.maxlen;
-  const bool timed = idx->timing.load() != 0;
+  const bool timed = !io.untimed && idx->timing.load() != 0;
   const int rec_bytes = W * 4 + 8;  // code words and two factors per vector
   const int64_t cand_ld = P.cand_ld;
   const int64_t pool_cap = P.pool_cap;
@@ -421,7 +447,8 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
 
     const float* qd = q;
     if (need_qcopy) {
-      if (ld != d) RBQ_HIP(hipMemsetAsync(b.qpad, 0, (size_t)nq * ld * sizeof(float), s));
+      // (a fill kernel: no memset node when the caller captures the stream)
+      if (ld != d) launch_fill_u32(s, reinterpret_cast<uint32_t*>(b.qpad), 0u, nq * ld);
       upload_rows(b.qpad, ld, q, d, nq, s);
       qd = b.qpad;
     }
@@ -528,6 +555,9 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     ga.cap = (int)pool_cap;
     ga.pcnt = b.pcnt;
     ga.overflow = b.overflow;
+    ga.dump_ip = b.dump_ip;
+    ga.dump_est = b.dump_est;
+    ga.maxlen = maxlen;
     TopkArgs ma;
     ma.keys = b.cand;
     ma.ld = cand_ld;
@@ -622,11 +652,14 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       launch_scan_fused(s, fa);  // scan and selection in one launch: no merge
       if (timed) {
         RBQ_HIP(hipEventRecord(e1, s));
-        tr.scan_lm.push_back(0);
+        tr.scan_lm.push_back(2);
         tr.popc += 1;
-        hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
-                           idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 1,
-                           idx->tcounter.as<unsigned long long>());
+        tr.fused += 1;
+        unsigned long long* tc = idx->tcounter.as<unsigned long long>();
+        for (int slot : {0, 4})  // all scans, and the fused ones alone
+          hipLaunchKernelGGL(k_count_scanned, dim3(64), dim3(256), 0, s, b.probes,
+                             idx->list_len.as<int32_t>(), (int)nq, nprobe, ch.p0, ch.pn, rec_bytes, 1,
+                             tc + slot);
         RBQ_HIP(hipGetLastError());
       }
     };
@@ -860,6 +893,25 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
 }
 
 }  // namespace
+
+void search_candidates(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
+                       uint64_t* cand_host, float* q_host, hipStream_t s, const SearchIO& io) {
+  if (nq == 0) return;
+  RBQ_HIP(hipSetDevice(idx->device));
+  HostJob job;
+  job.cand = cand_host;
+  job.qh = q_host;
+  RBQ_HIP(hipEventCreateWithFlags(&job.ready, hipEventDisableTiming));
+  try {
+    search_part(idx, q, nq, nprobe, k, R, nullptr, nullptr, s, io, &job);
+    RBQ_HIP(hipEventSynchronize(job.ready));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(job.ready);
+    throw;
+  }
+  RBQ_HIP(hipEventDestroy(job.ready));
+}
 
 void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
             float* dist, hipStream_t s, const SearchIO& io) {

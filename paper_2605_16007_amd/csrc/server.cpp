@@ -93,10 +93,12 @@ void run_batch(rbq_server* S, Lane& L, const std::vector<uint32_t>& batch) {
   io.q_R = L.hspec + 2 * nb;
   io.ws_base = L.ws;
   io.ws_cap = (size_t)S->p.mem_budget;
-  // the candidate rows get what the rest of the batch leaves of the workspace
-  // (a margin covers the alignment of the buffers that follow them)
-  const int64_t fixed = (int64_t)batch_need(S->idx, nb, np, k, R, pairs) - min_pool(nb, R);
-  io.pool_budget = std::max<int64_t>(min_pool(nb, R), S->p.mem_budget - fixed - 8192);
+  // the candidate rows get the largest budget whose whole workspace (sized by
+  // the plan at that budget) still fits mem_budget; admission checked that the
+  // smallest one does
+  io.pool_budget = std::max<int64_t>(
+      min_pool(nb, R),
+      fit_pool_budget(S->idx, nb, np, k, R, pairs, (size_t)S->p.mem_budget, min_pool(nb, R)));
   search(S->idx, L.dq, nb, np, k, R, L.dids, L.ddist, L.stream, io);
   RBQ_HIP(hipMemcpyAsync(L.hids, L.dids, (size_t)nb * k * sizeof(int64_t), hipMemcpyDeviceToHost,
                          L.stream));

@@ -5,6 +5,7 @@
 // shape falls in a tuned bucket uses the stored choices. The table can be saved
 // to and loaded from a text cache, whose entries are keyed by a signature of
 // the device architecture, D, B_q, nlist, n and the list-size histogram.
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -100,13 +101,42 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
       std::lock_guard<std::mutex> g(idx->tune_mu);
       idx->tune.erase(tune_key(nq, nprobe, R));
     }
+    // With the raw vectors on the host the re-rank runs on host cores and no
+    // launch choice touches it: the choices are timed on the GPU phases alone
+    // (probe to coarse top-R) and compared on the candidates they return.
+    const bool host_rr = idx->vectors_on_host != 0;
+    uint64_t* hc = nullptr;
+    float* hq = nullptr;
+    std::vector<uint64_t> ref_c, got_c;
+    if (host_rr) {
+      RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&hc), (size_t)nq * R * sizeof(uint64_t), hipHostMallocDefault));
+      RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&hq), (size_t)nq * d * sizeof(float), hipHostMallocDefault));
+      ref_c.resize((size_t)nq * R);
+      got_c.resize((size_t)nq * R);
+    }
+    struct PinnedFree {
+      void* a;
+      void* b;
+      ~PinnedFree() {
+        if (a) (void)hipHostFree(a);
+        if (b) (void)hipHostFree(b);
+      }
+    } pinned_guard{hc, hq};
     auto time_cfg = [&](const TuneCfg* cfg, std::vector<int64_t>& oi, std::vector<float>& od) {
       SearchIO io;
       io.force = cfg;
+      constexpr int reps = 3;
+      if (host_rr) {
+        std::vector<uint64_t>& oc = &oi == &ref_ids ? ref_c : got_c;
+        search_candidates(idx, dq.as<float>(), nq, nprobe, k, R, hc, hq, s, io);
+        std::memcpy(oc.data(), hc, oc.size() * sizeof(uint64_t));
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; r < reps; ++r) search_candidates(idx, dq.as<float>(), nq, nprobe, k, R, hc, hq, s, io);
+        return std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+      }
       search(idx, dq.as<float>(), nq, nprobe, k, R, ids.as<int64_t>(), dist.as<float>(), s, io);
       RBQ_HIP(hipMemcpyAsync(oi.data(), ids.p, oi.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
       RBQ_HIP(hipMemcpyAsync(od.data(), dist.p, od.size() * sizeof(float), hipMemcpyDeviceToHost, s));
-      constexpr int reps = 3;
       RBQ_HIP(hipEventRecord(e0, s));
       for (int r = 0; r < reps; ++r)
         search(idx, dq.as<float>(), nq, nprobe, k, R, ids.as<int64_t>(), dist.as<float>(), s, io);
@@ -123,7 +153,10 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
     for (const TuneCfg& c : cands) {
       const float ms = time_cfg(&c, got_ids, got_d);
       // every choice computes the same exact selection
-      if (got_ids != ref_ids || std::memcmp(got_d.data(), ref_d.data(), got_d.size() * 4) != 0) {
+      const bool differs = host_rr ? got_c != ref_c
+                                   : (got_ids != ref_ids ||
+                                      std::memcmp(got_d.data(), ref_d.data(), got_d.size() * 4) != 0);
+      if (differs) {
         char msg[192];
         std::snprintf(msg, sizeof(msg),
                       "autotune: launch choices returned different results (scan %d G %d wg_per_cu %d "

@@ -25,9 +25,9 @@ SYMBOLS = [
     "rbq_load", "rbq_last_error", "rbq_version", "rbq_set_option", "rbq_search_mixed",
     "rbq_server_params_init", "rbq_server_create", "rbq_submit", "rbq_poll", "rbq_wait",
     "rbq_server_get_stats", "rbq_server_destroy", "rbq_server_replay", "rbq_replay_plain",
-    "rbq_autotune", "rbq_tune_save", "rbq_tune_load", "rbq_tune_clear",
+    "rbq_autotune", "rbq_tune_save", "rbq_tune_load", "rbq_tune_clear"
 ]
-OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4}
+OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4, "group_size": 5, "estimator": 6}
 
 
 class BuildParams(C.Structure):
@@ -35,20 +35,22 @@ class BuildParams(C.Structure):
                 ("kmeans_iters", C.c_int32), ("kmeans_restarts", C.c_int32),
                 ("train_n", C.c_int64), ("rotation", C.c_void_p), ("centroids", C.c_void_p),
                 ("assignment", C.c_void_p), ("vectors_on_host", C.c_int32),
-                ("host_threads", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("host_threads", C.c_int32), ("borrow_vectors", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class IndexInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("nlist", C.c_int32), ("bq", C.c_int32),
                 ("vectors_on_host", C.c_int32), ("max_list_len", C.c_int64),
-                ("device_bytes", C.c_int64), ("code_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("code_bytes", C.c_int64),
+                ("vectors_borrowed", C.c_int32), ("reserved", C.c_int32)]
 
 
 class DebugIO(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "inject_probes", "inject_qu", "inject_scalars", "probes", "probe_score", "qrot", "qu",
         "scalars", "ip", "est", "cand_ids", "cand_est", "ids", "sqdist")] + [
-        ("probe_chunk", C.c_int32), ("reserved", C.c_int32)]
+        ("probe_chunk", C.c_int32), ("reserved", C.c_int32), ("inject_qrot", C.c_void_p)]
 
 
 class Timings(C.Structure):
@@ -58,7 +60,10 @@ class Timings(C.Structure):
                 ("scanned_vectors", C.c_int64), ("scan_bytes", C.c_int64),
                 ("read_bytes", C.c_int64), ("group_launches", C.c_int64),
                 ("popc_launches", C.c_int64), ("group_scan_ms", C.c_float),
-                ("group_vectors", C.c_int64), ("group_read_bytes", C.c_int64)]
+                ("group_vectors", C.c_int64), ("group_read_bytes", C.c_int64),
+                ("fused_launches", C.c_int64), ("fused_scan_ms", C.c_float),
+                ("reserved", C.c_int32), ("fused_vectors", C.c_int64),
+                ("fused_read_bytes", C.c_int64)]
 
 
 class ServerParams(C.Structure):
@@ -186,8 +191,13 @@ class Index:
     # ---------------------------------------------------------------- build
     @classmethod
     def build(cls, x, nlist, *, bq=4, seed=0, kmeans_iters=25, kmeans_restarts=3, train_n=0,
-              rotation=None, centroids=None, assignment=None, vectors_on_host=False,
-              host_threads=0):
+              rotation=None, centroids=None, assignment=None, vectors_on_host=None,
+              host_threads=0, borrow_vectors=False):
+        """Build an index over x (NumPy array or torch tensor, n x d float32).
+        vectors_on_host: False (HBM), True (pinned host memory, host re-rank) or
+        None (automatic). borrow_vectors: keep x itself (pinned host memory,
+        e.g. a torch tensor made with pin_memory=True) as the host rows; the
+        caller keeps it alive and unchanged while the index exists."""
         if _is_torch(x):
             assert str(x.dtype) == "torch.float32"
         else:
@@ -210,11 +220,15 @@ class Index:
             assignment = np.ascontiguousarray(assignment, np.int32)
             keep.append(assignment)
             p.assignment = assignment.ctypes.data
-        p.vectors_on_host = int(bool(vectors_on_host))
+        p.vectors_on_host = -1 if vectors_on_host is None else int(bool(vectors_on_host))
         p.host_threads = int(host_threads)
+        p.borrow_vectors = int(bool(borrow_vectors))
         h = C.c_void_p()
         _check(lib().rbq_build_index(_ptr(x), n, d, C.byref(p), C.byref(h)))
-        return cls(h.value)
+        ix = cls(h.value)
+        if borrow_vectors:
+            ix._borrowed = x  # the index reads these rows until it is freed
+        return ix
 
     @classmethod
     def load(cls, path):
@@ -309,7 +323,7 @@ class Index:
                      "cand_est", "ids", "sqdist")
 
     def search_debug(self, q, nprobe, k, rerank_n, *, inject_probes=None, inject_qu=None,
-                     inject_scalars=None, want=None, probe_chunk=0):
+                     inject_scalars=None, inject_qrot=None, want=None, probe_chunk=0):
         """Stage-by-stage search (host arrays). Returns a dict of the stage
         outputs named in ``want`` (default: all); see rbq_search_debug in
         include/rbq.h for the layouts."""
@@ -344,6 +358,10 @@ class Index:
             b = np.ascontiguousarray(inject_scalars, np.float32).reshape(pairs * 3)
             keep += [a, b]
             io.inject_qu, io.inject_scalars = a.ctypes.data, b.ctypes.data
+        if inject_qrot is not None:
+            a = np.ascontiguousarray(inject_qrot, np.float32).reshape(nq * d)
+            keep.append(a)
+            io.inject_qrot = a.ctypes.data
         for key, arr in out.items():
             setattr(io, key, arr.ctypes.data)
         io.probe_chunk = int(probe_chunk)
@@ -374,7 +392,9 @@ class Index:
 
     def set_option(self, name: str, value: int):
         """Tuning knobs: scan (0 auto, 1 query-major popcount, 2 list-major
-        MFMA), group_min, pool_cap; see rbq_set_option in include/rbq.h."""
+        MFMA, 3 one item per query), group_min, pool_cap, rotation,
+        group_size, estimator (0 B_q-bit query, 1 unquantised); see
+        rbq_set_option in include/rbq.h."""
         _check(lib().rbq_set_option(self._h, OPTIONS[name], int(value)))
 
     # ---------------------------------------------------------------- timing

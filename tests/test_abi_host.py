@@ -42,6 +42,7 @@ def _params(**kw):
 def test_params_defaults():
     p = _params()
     assert p.bq == 4 and p.kmeans_iters == 25 and p.kmeans_restarts == 3 and p.train_n == 0
+    assert p.vectors_on_host == -1 and p.borrow_vectors == 0
 
 
 @pytest.mark.parametrize("n,d,kw,msg", [
@@ -52,6 +53,12 @@ def test_params_defaults():
     (10, 8, {"bq": 0}, "bq"),
     (10, 8, {"bq": 9}, "bq"),
     (10, 8, {"vectors_on_host": 2}, "vectors_on_host"),
+    (10, 8, {"vectors_on_host": -2}, "vectors_on_host"),
+    (10, 8, {"borrow_vectors": 2}, "borrow_vectors"),
+    (10, 8, {"borrow_vectors": 1, "vectors_on_host": 0}, "borrow_vectors needs the vectors on the host"),
+    # a NumPy array is pageable memory: it cannot be borrowed
+    (10, 8, {"borrow_vectors": 1, "vectors_on_host": 1}, "pinned host memory"),
+    (10, 8, {"borrow_vectors": 1}, "pinned host memory"),
 ])
 def test_build_rejects_bad_arguments(n, d, kw, msg):
     L = rbq.lib()
@@ -98,10 +105,10 @@ def test_null_arguments():
 
 def test_struct_sizes_match_header_layout():
     # natural C layout of the public structs (x86-64 / LP64)
-    assert C.sizeof(rbq.BuildParams) == 4 + 4 + 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4 + 6 * 4
-    assert C.sizeof(rbq.DebugIO) == 14 * 8 + 8
-    assert C.sizeof(rbq.Timings) == 8 + 7 * 4 + 4 + 5 * 8 + 4 + 4 + 2 * 8
-    assert C.sizeof(rbq.IndexInfo) == 8 + 4 * 4 + 3 * 8
+    assert C.sizeof(rbq.BuildParams) == 4 + 4 + 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4 + 4 + 5 * 4
+    assert C.sizeof(rbq.DebugIO) == 14 * 8 + 8 + 8
+    assert C.sizeof(rbq.Timings) == 8 + 7 * 4 + 4 + 5 * 8 + 4 + 4 + 2 * 8 + 8 + 4 + 4 + 2 * 8
+    assert C.sizeof(rbq.IndexInfo) == 8 + 4 * 4 + 3 * 8 + 4 + 4
     assert C.sizeof(rbq.ServerParams) == 6 * 4 + 8 + 8 * 4
     assert C.sizeof(rbq.ServerStats) == 8 * 8
     assert C.sizeof(rbq.ReplayIO) == 8 * 8 + 8 + 4 + 4

@@ -160,12 +160,30 @@ def test_membership_sound(full, oracle_pairs):
                 assert dj - dmin[np.searchsorted(ids, v)] <= 1e-5 * dj, (j, v)
 
 
-def test_p4_p5_sampled_queries(full, oracle_pairs, sampled_oracle):
+@pytest.mark.parametrize("scan,group", [(1, 0), (2, 32), (2, 64)],
+                         ids=["popcount", "list-major-G32", "list-major-G64"])
+def test_p4_p5_sampled_queries(full, oracle_pairs, sampled_oracle, scan, group):
+    """Every estimate of the sampled queries' 512 probed lists, formed by the
+    popcount scan or by the list-major scan in the benchmark's item size (32
+    queries, two matrix-core tiles) and in the four-tile form."""
     lib, Q = full["lib"], full["Q"]
     rows = list(SAMPLED)
-    out = lib.search_debug(Q[rows], NPROBE, K, R, inject_probes=oracle_pairs["probes"][rows],
-                           inject_qu=oracle_pairs["qu"][rows], inject_scalars=oracle_pairs["sc"][rows],
-                           want={"ip", "est"})
+    lib.set_option("scan", scan)
+    lib.set_option("group_size", group)
+    lib.set_timing(True)
+    try:
+        out = lib.search_debug(Q[rows], NPROBE, K, R, inject_probes=oracle_pairs["probes"][rows],
+                               inject_qu=oracle_pairs["qu"][rows], inject_scalars=oracle_pairs["sc"][rows],
+                               want={"ip", "est"})
+        t = lib.timings()
+    finally:
+        lib.set_timing(False)
+        lib.set_option("scan", 0)
+        lib.set_option("group_size", 0)
+    if scan == 2:
+        assert t["group_launches"] > 0 and t["popc_launches"] == 0, t
+    else:
+        assert t["group_launches"] == 0, t
     worst = 0.0
     for t, i in enumerate(rows):
         for p, ol in enumerate(sampled_oracle[i]):
@@ -175,7 +193,7 @@ def test_p4_p5_sampled_queries(full, oracle_pairs, sampled_oracle):
             if m:
                 worst = max(worst, float(err.max()))
             assert np.all(err <= 1e-5), (i, p, float(err.max()))
-    _say(f"[fullsize] P4 exact, P5 worst scaled error {worst:.2e}")
+    _say(f"[fullsize] scan {scan} G {group}: P4 exact, P5 worst scaled error {worst:.2e}")
 
 
 def test_p6_p7_sampled_queries_in_batch(full, injected_batch, sampled_oracle):
@@ -191,6 +209,10 @@ def test_p6_p7_sampled_queries_in_batch(full, injected_batch, sampled_oracle):
         boundary = ref_v[-1]
         bad = set_diff_ok(out["cand_ids"][i], ref_i, lambda x: val[x], boundary, lambda x: tol[x])
         assert not bad, ("P6", i, bad[:5])
+        # every returned candidate's estimate within 1e-5 S of the oracle's
+        for x, e in zip(out["cand_ids"][i].tolist(), out["cand_est"][i].tolist()):
+            if x >= 0:
+                assert abs(e - val[x]) <= 0.5 * tol[x], ("P5 of a candidate", i, x, e, val[x])
         # P7: final top-k from the oracle's candidates
         fv, fi = O.rerank(Q[i], X, ref_i, K)
         exact = lambda x: float(np.sum((X[x].astype(np.float64) - Q[i].astype(np.float64)) ** 2))

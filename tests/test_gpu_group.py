@@ -54,7 +54,7 @@ def gcase(request):
     return dict(name=name, X=X, Q=Q, idx=idx, lib=lib, nprobe=nprobe, k=k, R=R, d=d)
 
 
-def _run(lib, Q, nprobe, k, R, scan, pool_cap=0, lm_only=False, **kw):
+def _run(lib, Q, nprobe, k, R, scan, pool_cap=0, lm_only=False, want_extra=(), **kw):
     """lm_only: the list-major scan produced every result itself (scan 2 with
     no pool overflow, so no query was redone by the query-major scan)."""
     lib.set_option("scan", scan)
@@ -62,7 +62,7 @@ def _run(lib, Q, nprobe, k, R, scan, pool_cap=0, lm_only=False, **kw):
     if lm_only:
         lib.set_timing(True)
     try:
-        out = lib.search_debug(Q, nprobe, k, R, want=WANT, **kw)
+        out = lib.search_debug(Q, nprobe, k, R, want=WANT | set(want_extra), **kw)
         if lm_only:
             t = lib.timings()
             assert t["group_launches"] > 0 and t["popc_launches"] == 0, t
@@ -92,7 +92,13 @@ def test_group_overflow_path_is_exact(gcase, cap):
 
 
 def test_group_candidates_match_oracle(gcase):
-    """Oracle probes, qu and scalars injected; list-major scan; P6 rule."""
+    """Oracle probes, qu and scalars injected; every chunk on the list-major
+    scan, which also writes out each estimate it forms. P4: its integer inner
+    products equal the oracle's for every (query, vector); P5: its d_hat^2 is
+    within 1e-5 S of the oracle's. P6: candidate sets equal up to near-ties at
+    the R-th value (an element and the boundary may each move by 1e-5 S, so
+    sets are compared with a 2e-5 S window), and every returned candidate's
+    estimate within 1e-5 S of the oracle's."""
     lib, Q, X, idx = gcase["lib"], gcase["Q"], gcase["X"], gcase["idx"]
     nprobe, k, R, d = gcase["nprobe"], gcase["k"], gcase["R"], gcase["d"]
     _, _, st = O.search(idx, X, Q, nprobe, k, R, stages=True)
@@ -106,22 +112,32 @@ def test_group_candidates_match_oracle(gcase):
             sc[qi, p] = (st["rnorm2"][qi][p], st["vl"][qi][p], st["delta"][qi][p])
     out = _run(lib, Q, nprobe, k, R, scan=2, lm_only=True, inject_probes=probes, inject_qu=qu,
                inject_scalars=sc)
+    dumps = _run(lib, Q, nprobe, k, R, scan=2, lm_only=True, inject_probes=probes, inject_qu=qu,
+                 inject_scalars=sc, want_extra={"ip", "est"})
+    worst = 0.0
     for qi in range(nq):
         val, tol = {}, {}
         for p, pl in enumerate(st["per_list"][qi]):
             S = est_scale(st["rnorm2"][qi][p], st["vl"][qi][p], st["delta"][qi][p],
                           st["sumqu"][qi][p], pl["ip"], pl["pop"], idx.n_x[pl["ids"]],
                           idx.alpha[pl["ids"]], d)
+            m = len(pl["ids"])
+            np.testing.assert_array_equal(dumps["ip"][qi, p, :m], pl["ip"], err_msg=f"P4 q{qi} p{p}")
+            err = np.abs(dumps["est"][qi, p, :m].astype(np.float64) - pl["est"]) / S
+            assert np.all(err <= 1e-5), (qi, p, float(err.max()))
+            worst = max(worst, float(err.max()) if m else 0.0)
             for i, e, s in zip(pl["ids"].tolist(), pl["est"].tolist(), S.tolist()):
-                val[i], tol[i] = e, 2e-5 * s
+                val[i], tol[i] = e, s
         ref = st["cand_ids"][qi]
         rv = ref[ref >= 0]
         boundary = val[int(rv[-1])] if len(rv) else math.inf
-        bad = set_diff_ok(out["cand_ids"][qi], ref, lambda x: val[x], boundary, lambda x: tol[x])
+        bad = set_diff_ok(out["cand_ids"][qi], ref, lambda x: val[x], boundary, lambda x: 2e-5 * tol[x])
         assert not bad, (qi, bad[:5])
         g = out["cand_ids"][qi]
         for i, e in zip(g[g >= 0].tolist(), out["cand_est"][qi].tolist()):
-            assert abs(e - val[i]) <= tol[i]
+            assert abs(e - val[i]) <= 1e-5 * tol[i]
+        np.testing.assert_array_equal(out["cand_ids"][qi], dumps["cand_ids"][qi])
+    _say(f"[group {gcase['name']}] P4 exact, P5 worst {worst:.2e} S")
 
 
 def test_fused_buffer_shrinks_mid_chunk():

@@ -114,3 +114,35 @@ def test_host_rerank_device_inputs_and_mixed(pair):
         s_ids, s_d, _ = srv.replay(Q[:500], npb, k, R, np.zeros(500))
     np.testing.assert_array_equal(s_ids, m_ids)
     np.testing.assert_array_equal(s_d, m_d)
+
+
+def test_borrowed_and_automatic_placement(pair):
+    """borrow_vectors keeps the caller's pinned rows (no copy) and returns the
+    copied host index's results; automatic placement keeps a small index's
+    vectors in HBM; pageable memory cannot be borrowed."""
+    import torch
+    from paper_2605_16007_amd.rbq import RbqError
+    X, Q, idx, dev, host = pair
+    xp = torch.empty(X.shape, dtype=torch.float32, pin_memory=True)
+    xp.numpy()[:] = X
+    kw = dict(centroids=idx.centroids, rotation=idx.P, assignment=idx.assign.astype(np.int32))
+    b = Index.build(xp, idx.nlist, vectors_on_host=True, borrow_vectors=True, host_threads=4, **kw)
+    auto = Index.build(X, idx.nlist, **kw)
+    try:
+        assert b.info()["vectors_borrowed"] == 1 and b.info()["vectors_on_host"] == 1
+        assert host.info()["vectors_borrowed"] == 0
+        assert auto.info()["vectors_on_host"] == 0
+        for nq in (1, 700, 2100):
+            x_ids, x_d = host.search(Q[:nq], 6, 10, 100)
+            y_ids, y_d = b.search(Q[:nq], 6, 10, 100)
+            np.testing.assert_array_equal(x_ids, y_ids)
+            np.testing.assert_array_equal(x_d, y_d)
+        a_ids, a_d = auto.search(Q[:300], 6, 10, 100)
+        d_ids, d_d = dev.search(Q[:300], 6, 10, 100)
+        np.testing.assert_array_equal(a_ids, d_ids)
+        np.testing.assert_array_equal(a_d, d_d)
+        with pytest.raises(RbqError, match="pinned host memory"):
+            Index.build(X, idx.nlist, vectors_on_host=True, borrow_vectors=True, **kw)
+    finally:
+        b.close()
+        auto.close()

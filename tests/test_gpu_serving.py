@@ -146,6 +146,31 @@ def test_server_memory_admission(case):
     assert st["budget_cuts"] > 0 and st["max_batch_seen"] < len(Q)
 
 
+@pytest.mark.parametrize("budget_mb", [3, 5, 8, 12, 20])
+def test_server_budget_limits_the_pool(case, budget_mb):
+    """Budgets at which the candidate pool is the limiting term, with rerank_n
+    (1000) above the average list length (469) over the first chunk factor:
+    the schedule at the pool budget a lane picks may hold list-major chunks
+    that the smallest pool's schedule has not; the lane sizes the whole
+    workspace at the budget it uses, so every batch runs and results equal the
+    alone ones."""
+    Q = case["Q"][:120]
+    rows = list(range(120))
+    npb = np.full(120, 64, np.int32)
+    k = np.full(120, 100, np.int32)
+    R = np.full(120, 1000, np.int32)
+    alone = [case["lib"].search(Q[i:i + 1], 64, 100, 1000) for i in range(0, 120, 17)]
+    with Server(case["lib"], lanes=1, max_batch=1024, max_nprobe=64, max_k=100,
+                max_rerank=1000, mem_budget=budget_mb << 20) as srv:
+        ids, dists, _ = srv.replay(Q, npb, k, R, np.zeros(120))
+        st = srv.stats()
+    _say(f"[serving] budget {budget_mb} MB: {st}")
+    assert st["completed"] == 120
+    for t, i in enumerate(range(0, 120, 17)):
+        np.testing.assert_array_equal(ids[i], alone[t][0][0])
+        np.testing.assert_array_equal(dists[i], alone[t][1][0])
+
+
 def test_server_concurrent_submitters(case):
     _say("[serving] 4 submitting threads, poll and wait")
     Q = case["Q"]
