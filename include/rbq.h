@@ -117,6 +117,24 @@ rbq_status rbq_search(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe
                       int32_t rerank_n, int64_t* ids, float* sqdist, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (work recorded under stream
+ * capture, serving loops that forbid allocation): rbq_search whose device
+ * workspace is a fixed 256 MiB array inside the library, one per GPU, held
+ * from the first call on that GPU until the process ends. The call allocates
+ * no device or pinned host memory and creates no events. q, ids and sqdist
+ * must be device pointers; the index must keep its raw vectors in HBM
+ * (vectors_on_host 0). Results equal rbq_search's. The candidate pool is
+ * sized to fit the array, so a large batch may take more chunks than with
+ * rbq_search. Errors: as rbq_search, and EINVAL for host pointers, a host
+ * re-rank index, or a batch whose smallest workspace exceeds the array (the
+ * message gives its size; split the batch). Calls that overlap on one GPU
+ * (concurrent streams or threads) share the array and race: the caller
+ * serialises them.
+ */
+rbq_status rbq_search_noalloc(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+                              int32_t rerank_n, int64_t* ids, float* sqdist, void* stream);
+
+/*
  * Mixed batch: the batch-processing search of Sec. 3.1.2 in which query i uses
  * its own nprobe[i], k[i] and rerank_n[i] (host int32 arrays of nq, each in the
  * ranges rbq_search accepts). Query i's result is the same as rbq_search of

@@ -350,6 +350,15 @@ rbq_status rbq_search(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe
   });
 }
 
+rbq_status rbq_search_noalloc(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+                              int32_t rerank_n, int64_t* ids, float* sqdist, void* stream) {
+  return guarded([&] {
+    check_search_args(idx, q, nq, nprobe, k, rerank_n);
+    RBQ_CHECK(nq == 0 || (ids != nullptr && sqdist != nullptr), "outputs are NULL");
+    rbq::search_noalloc(idx, q, nq, nprobe, k, rerank_n, ids, sqdist, static_cast<hipStream_t>(stream));
+  });
+}
+
 rbq_status rbq_search_mixed(rbq_index* idx, const float* q, int64_t nq, const int32_t* nprobe,
                             const int32_t* k, const int32_t* rerank_n, int32_t k_stride,
                             int64_t* ids, float* sqdist, void* stream) {

@@ -188,6 +188,10 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
 // (both pinned host memory); returns when they are there. The re-rank's input.
 void search_candidates(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
                        uint64_t* cand_host, float* q_host, hipStream_t s, const SearchIO& io);
+// rbq_search on the library's fixed per-GPU workspace array (noalloc.hip).
+void search_noalloc(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
+                    float* dist, hipStream_t s);
+size_t noalloc_scratch_bytes();
 
 // Autotuner (tune.cpp): bucket key of a batch shape, the table lookup used by
 // every search, trials, and the text cache.

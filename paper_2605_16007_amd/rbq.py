@@ -25,7 +25,7 @@ SYMBOLS = [
     "rbq_load", "rbq_last_error", "rbq_version", "rbq_set_option", "rbq_search_mixed",
     "rbq_server_params_init", "rbq_server_create", "rbq_submit", "rbq_poll", "rbq_wait",
     "rbq_server_get_stats", "rbq_server_destroy", "rbq_server_replay", "rbq_replay_plain",
-    "rbq_autotune", "rbq_tune_save", "rbq_tune_load", "rbq_tune_clear"
+    "rbq_autotune", "rbq_tune_save", "rbq_tune_load", "rbq_tune_clear", "rbq_search_noalloc",
 ]
 OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4, "group_size": 5, "estimator": 6}
 
@@ -121,6 +121,7 @@ def lib():
         L.rbq_free_index.argtypes = [vp]
         L.rbq_get_info.argtypes = [vp, C.POINTER(IndexInfo)]
         L.rbq_search.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp]
+        L.rbq_search_noalloc.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp]
         L.rbq_export.argtypes = [vp, i32, vp, C.c_size_t]
         L.rbq_search_debug.argtypes = [vp, vp, i64, i32, i32, i32, C.POINTER(DebugIO)]
         L.rbq_set_timing.argtypes = [vp, i32]
@@ -289,6 +290,20 @@ class Index:
         s = _stream_of(q, stream)
         _check(lib().rbq_search(self._h, _ptr(q), nq, int(nprobe), int(k), int(rerank_n),
                                 _ptr(ids), _ptr(dists), s))
+        return ids, dists
+
+    def search_noalloc(self, q, nprobe, k, rerank_n, ids=None, dists=None, stream=None):
+        """rbq_search on the library's fixed per-GPU workspace (no device
+        allocation): q, and ids / dists if given, are GPU tensors."""
+        import torch
+        nq = q.shape[0]
+        if ids is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
+        if dists is None:
+            dists = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        s = _stream_of(q, stream)
+        _check(lib().rbq_search_noalloc(self._h, _ptr(q), nq, int(nprobe), int(k), int(rerank_n),
+                                        _ptr(ids), _ptr(dists), s))
         return ids, dists
 
     def search_mixed(self, q, nprobe, k, rerank_n, stream=None):
