@@ -73,7 +73,15 @@ typedef struct {
                               n*d float32, and the caller keeps it unchanged
                               until rbq_free_index. EINVAL with
                               vectors_on_host = 0 or a pageable or device x */
-  int32_t reserved[5];     /* must be zero */
+  int32_t ivf_flat;        /* 1: also keep every list's full-precision vectors
+                              in HBM, in list order (d <= 256), for the IVF-Flat
+                              scan (RBQ_OPT_ESTIMATOR 2, the comparison system
+                              of Sec. 4.2); not saved by rbq_save */
+  int32_t kmeans_init;     /* 0: k-means++ seeding (default); 1: nlist distinct
+                              training rows drawn uniformly, the random initial
+                              centroids of Sec. 3.1.1 Phase 1 (no sequential
+                              seeding pass: for very large nlist) */
+  int32_t reserved[3];     /* must be zero */
 } rbq_build_params;
 
 void rbq_build_params_init(rbq_build_params* p);
@@ -361,9 +369,20 @@ rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
  *                       sign-pattern tables of 8-dimension groups (4 when
  *                       d > 128), d <= 1024; changes the estimates. In this
  *                       mode rbq_search_debug does not fill qu and scalars,
- *                       and ip holds nothing */
+ *                       and ip holds nothing; 2: IVF-Flat (an index built
+ *                       with ivf_flat): exact squared distances of the
+ *                       full-precision vectors of the probed lists on the FP32
+ *                       matrix cores (||q||^2 + ||x||^2 - 2<q,x>), the best
+ *                       rerank_n re-ranked exactly as usual (rerank_n = k
+ *                       gives plain IVF-Flat); list-major scan only. A query
+ *                       whose candidate pool would overflow fails the search
+ *                       (RBQ_ENOMEM) instead of returning a wrong result
+ *   RBQ_OPT_BLOCK       list-major work items cover index blocks of this many
+ *                       64-vector micro-blocks of a list (Sec. 3.3.1), so a
+ *                       long list is shared out over several workgroups;
+ *                       0: whole lists; -1 (default): as autotuned, else 0 */
 enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3, RBQ_OPT_ROTATION = 4,
-       RBQ_OPT_GROUP_SIZE = 5, RBQ_OPT_ESTIMATOR = 6 };
+       RBQ_OPT_GROUP_SIZE = 5, RBQ_OPT_ESTIMATOR = 6, RBQ_OPT_BLOCK = 7 };
 rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
 
 /*
@@ -397,6 +416,8 @@ typedef struct {
   int32_t early_form;    /* chunks before the list-major ones, in batches of >= 128
                             queries: 0 one workgroup per query scans and selects;
                             1 popcount scan per (query, probe), then a merge */
+  int32_t block;         /* list-major items cover index blocks of this many
+                            micro-blocks (0: whole lists), tuned last */
 } rbq_tune_result;
 
 rbq_status rbq_autotune(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,

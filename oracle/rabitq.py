@@ -101,7 +101,8 @@ def lloyd_update(T, a, C_prev, dmin):
 
 
 def kmeans(X: np.ndarray, nlist: int, rng: np.random.Generator, iters: int = 25,
-           restarts: int = 3, train_n: int | None = None, trace: list | None = None):
+           restarts: int = 3, train_n: int | None = None, trace: list | None = None,
+           seed_rows: int | None = None, init: str = "kmeans++"):
     """IVF centroids by k-means on a training subset (Sec. 2.1.2, Sec. 3.1.1).
 
     The paper fixes neither the initialisation, the subset, the iteration limit
@@ -110,6 +111,16 @@ def kmeans(X: np.ndarray, nlist: int, rng: np.random.Generator, iters: int = 25,
     no assignment changes or ``iters`` is reached, ``restarts`` runs keeping the
     lowest objective. Returns FP64 centroids. ``trace`` (if a list) receives the
     objective after every assignment step of every restart.
+
+    ``seed_rows`` (the reading the GPU library takes to keep seeding cheap at
+    large nlist): k-means++ draws its centres from the evenly strided subset of
+    at most ``seed_rows`` training rows (row t * T // S of the T training rows,
+    t < S = min(T, seed_rows)) instead of from all of them; the Lloyd steps
+    still use every training row. None: all training rows.
+
+    ``init="random"``: the initial centroids are nlist distinct training rows
+    drawn uniformly (the random initial centroids of Sec. 3.1.1 Phase 1)
+    instead of k-means++ seeds.
     """
     X = np.asarray(X)
     n = len(X)
@@ -118,9 +129,15 @@ def kmeans(X: np.ndarray, nlist: int, rng: np.random.Generator, iters: int = 25,
         T = np.asarray(X[np.sort(rng.choice(n, tn, replace=False))], np.float64)
     else:
         T = np.asarray(X, np.float64)
+    S_rows = T
+    if seed_rows is not None and seed_rows < len(T):
+        S_rows = T[(np.arange(seed_rows, dtype=np.int64) * len(T)) // seed_rows]
     best_obj, best_C = None, None
     for _ in range(restarts):
-        C = kmeanspp_init(T, nlist, rng)
+        if init == "random":
+            C = T[rng.choice(len(T), nlist, replace=False)].copy()
+        else:
+            C = kmeanspp_init(S_rows, nlist, rng)
         prev = None
         run = []
         for _it in range(iters):

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librbq.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["kernels.hip", "kernels_group.hip", "build.cpp", "search.cpp", "server.cpp", "api.cpp",
-           "host_math.cpp", "host_rerank.cpp", "tune.cpp", "noalloc.hip"]
+           "host_math.cpp", "host_rerank.cpp", "tune.cpp", "noalloc.hip", "kernels_flat.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -298,6 +298,9 @@ rbq_status rbq_build_index(const float* x, int64_t n, int32_t d, const rbq_build
     return invalid("k-means parameters must be >= 0");
   if (p->vectors_on_host < -1 || p->vectors_on_host > 1) return invalid("vectors_on_host must be -1, 0 or 1");
   if (p->borrow_vectors != 0 && p->borrow_vectors != 1) return invalid("borrow_vectors must be 0 or 1");
+  if (p->ivf_flat != 0 && p->ivf_flat != 1) return invalid("ivf_flat must be 0 or 1");
+  if (p->kmeans_init != 0 && p->kmeans_init != 1) return invalid("kmeans_init must be 0 or 1");
+  if (p->ivf_flat && d > 256) return invalid("ivf_flat supports d <= 256");
   if (p->borrow_vectors) {
     if (p->vectors_on_host == 0) return invalid("borrow_vectors needs the vectors on the host (vectors_on_host 1 or -1)");
     if (!rbq::is_pinned_host_ptr(x)) return invalid("borrow_vectors needs x in pinned host memory");
@@ -336,7 +339,7 @@ rbq_status rbq_get_info(const rbq_index* idx, rbq_index_info* info) {
   info->device_bytes = (int64_t)(idx->X.bytes + idx->X8.bytes + idx->C.bytes + idx->Crot.bytes + idx->cnorm.bytes +
                                  idx->Pt.bytes + idx->blocks.bytes + idx->list_mb.bytes +
                                  idx->list_len.bytes + idx->pos2id.bytes + idx->nx.bytes +
-                                 idx->alpha.bytes);
+                                 idx->alpha.bytes + idx->flat.bytes);
   return RBQ_OK;
 }
 
@@ -504,10 +507,15 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value) {
       idx->opt_rotation.store((int)value);
       return RBQ_OK;
     case RBQ_OPT_ESTIMATOR:
-      if (value < 0 || value > 1) return invalid("RBQ_OPT_ESTIMATOR must be 0 or 1");
+      if (value < 0 || value > 2) return invalid("RBQ_OPT_ESTIMATOR must be 0, 1 or 2");
       if (value == 1 && idx->d > rbq::scan_lut_max_d())
         return invalid("RBQ_OPT_ESTIMATOR 1 supports d <= 1024");
+      if (value == 2 && !idx->flat.p) return invalid("RBQ_OPT_ESTIMATOR 2 needs an index built with ivf_flat");
       idx->opt_estimator.store((int)value);
+      return RBQ_OK;
+    case RBQ_OPT_BLOCK:
+      if (value < -1 || value > (1 << 20)) return invalid("RBQ_OPT_BLOCK must be in [-1, 2^20]");
+      idx->opt_block.store((int)value);
       return RBQ_OK;
     case RBQ_OPT_GROUP_SIZE:
       if (value < 0 || value > 64) return invalid("RBQ_OPT_GROUP_SIZE must be in [0, 64]");

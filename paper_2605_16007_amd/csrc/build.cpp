@@ -211,7 +211,7 @@ std::vector<float> kmeans_gpu(const float* Xd, int64_t n, int d, int ld, int nli
 
   // k-means++ seeding runs on an evenly strided subset of at most 32 nlist
   // training rows (the training rows are already a uniform random sample)
-  const int64_t sn = std::min<int64_t>(tn, (int64_t)32 * nlist);
+  const int64_t sn = p.kmeans_init == 1 ? tn : std::min<int64_t>(tn, (int64_t)32 * nlist);
   DevBuf S;
   const float* Sd = T.as<float>();
   if (sn < tn) {
@@ -226,19 +226,27 @@ std::vector<float> kmeans_gpu(const float* Xd, int64_t n, int d, int ld, int nli
     Sd = S.as<float>();
   }
   for (int rs = 0; rs < restarts; ++rs) {
-    // k-means++ seeding on the device: first centre uniform, then D(x)^2 sampling
-    RBQ_HIP(hipMemsetAsync(dC.p, 0, dC.bytes, s));
-    const int64_t first = (int64_t)rng.below((uint64_t)sn);
-    RBQ_HIP(hipMemcpyAsync(pick.p, &first, sizeof(int64_t), hipMemcpyHostToDevice, s));
-    launch_copy_row(s, Sd, ld, pick.as<int64_t>(), dC.as<float>(), d);
-    launch_kpp_update(s, Sd, ld, sn, d, pick.as<int64_t>(), mind.as<float>(), bsum.as<double>(), 1);
-    for (int j = 1; j < nlist; ++j) {
-      launch_kpp_choose(s, mind.as<float>(), bsum.as<double>(), sn, rng.uniform(), pick.as<int64_t>());
-      launch_copy_row(s, Sd, ld, pick.as<int64_t>(), dC.as<float>() + (size_t)j * ld, d);
-      launch_kpp_update(s, Sd, ld, sn, d, pick.as<int64_t>(), mind.as<float>(), bsum.as<double>(), 0);
+    if (p.kmeans_init == 1) {
+      // random initial centroids (Sec. 3.1.1 Phase 1): nlist distinct
+      // training rows, uniformly
+      const std::vector<int64_t> rows = sample_without_replacement(tn, nlist, rng);
+      for (int j = 0; j < nlist; ++j)
+        std::memcpy(&hC[(size_t)j * ld], &hT[(size_t)rows[j] * ld], (size_t)ld * sizeof(float));
+    } else {
+      // k-means++ seeding on the device: first centre uniform, then D(x)^2 sampling
+      RBQ_HIP(hipMemsetAsync(dC.p, 0, dC.bytes, s));
+      const int64_t first = (int64_t)rng.below((uint64_t)sn);
+      RBQ_HIP(hipMemcpyAsync(pick.p, &first, sizeof(int64_t), hipMemcpyHostToDevice, s));
+      launch_copy_row(s, Sd, ld, pick.as<int64_t>(), dC.as<float>(), d);
+      launch_kpp_update(s, Sd, ld, sn, d, pick.as<int64_t>(), mind.as<float>(), bsum.as<double>(), 1);
+      for (int j = 1; j < nlist; ++j) {
+        launch_kpp_choose(s, mind.as<float>(), bsum.as<double>(), sn, rng.uniform(), pick.as<int64_t>());
+        launch_copy_row(s, Sd, ld, pick.as<int64_t>(), dC.as<float>() + (size_t)j * ld, d);
+        launch_kpp_update(s, Sd, ld, sn, d, pick.as<int64_t>(), mind.as<float>(), bsum.as<double>(), 0);
+      }
+      RBQ_HIP(hipMemcpyAsync(hC.data(), dC.p, hC.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+      RBQ_HIP(hipStreamSynchronize(s));
     }
-    RBQ_HIP(hipMemcpyAsync(hC.data(), dC.p, hC.size() * sizeof(float), hipMemcpyDeviceToHost, s));
-    RBQ_HIP(hipStreamSynchronize(s));
     prev.clear();
     for (int it = 0; it < iters; ++it) {
       assign_train();
@@ -402,6 +410,10 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
                   idx->pos2id.as<int32_t>(), dmb.as<int32_t>(), m0, std::min(nmb, m0 + step), d, W,
                   idx->blocks.as<uint32_t>(), idx->nx.as<float>(), idx->alpha.as<float>());
 
+  if (p.ivf_flat) {  // the lists' full-precision rows, for the IVF-Flat scan
+    idx->flat.alloc(std::max<int64_t>(1, nmb) * (int64_t)(flat_dp(d) + 1) * MB * sizeof(float));
+    launch_flat_fill(s, Xd.as<float>(), ld, idx->pos2id.as<int32_t>(), nmb, d, idx->flat.as<float>());
+  }
   RBQ_HIP(hipStreamSynchronize(s));
   if (idx->vectors_on_host < 0) {
     // automatic placement: HBM if the raw vectors (already resident) leave

@@ -38,6 +38,7 @@ struct TimingRec {
 struct TuneCfg {
   int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2, gm = 4, growth = 2;
   int early = 0;  // chunks before the list-major ones: 0 fused scan+select, 1 popcount scan + merge
+  int B = 0;      // list-major items over index blocks of B micro-blocks (0: whole lists)
 };
 
 // A device scratch area reused across calls. `done` is recorded on the stream
@@ -99,6 +100,7 @@ struct rbq_index {
   rbq::DevBuf blocks;  // nmb micro-block records
   rbq::DevBuf list_mb, list_len, pos2id;
   rbq::DevBuf nx, alpha;  // per position, for export
+  rbq::DevBuf flat;       // IVF-Flat records: per micro-block dp rows of 64 floats + 64 ||x||^2
 
   // host copies
   std::vector<float> hC;          // nlist x d
@@ -114,7 +116,8 @@ struct rbq_index {
   std::atomic<int64_t> opt_pool_cap{0};
   std::atomic<int> opt_rotation{0};  // 0 FP32, 1 BF16 inputs (FP32 accumulation)
   std::atomic<int> opt_group_size{0};  // queries per list-major item (0: tuned or built-in)
-  std::atomic<int> opt_estimator{0};   // 0 B_q-bit query, 1 unquantised FP32 residual
+  std::atomic<int> opt_estimator{0};   // 0 B_q-bit query, 1 unquantised FP32 residual, 2 IVF-Flat
+  std::atomic<int> opt_block{-1};      // micro-blocks per list-major index block (-1: tuned or built-in)
   // autotuned launch choices per batch-shape bucket (rbq_autotune)
   std::mutex tune_mu;
   std::map<uint64_t, rbq::TuneCfg> tune;

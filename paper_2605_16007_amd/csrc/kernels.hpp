@@ -152,6 +152,7 @@ struct GroupArgs {
   uint32_t* pcnt;          // [nq] pool fill
   uint32_t* overflow;      // [nq] set when a query's pool overflowed
   uint32_t* any_overflow;  // set with any overflow flag
+  const int32_t* probes = nullptr;  // [nq][nprobe] (the debug dumps place positions by list)
   int32_t* dump_ip = nullptr;  // debug: [pairs][maxlen] ip and d_hat^2 of every estimate (or null)
   float* dump_est = nullptr;
   int64_t maxlen = 0;
@@ -182,18 +183,59 @@ struct GroupChunks {
   int nb = 0;
   int bound[kMaxGroupChunks + 1] = {};
 };
-// Pairs of every list-major chunk grouped by (chunk, list), queries ascending
-// within a bin: rank is an nlist x nq int16 table, all -1 on entry; cnt holds
-// nb * nlist counts; wpart 2 * nb * group_map_workgroups(nlist) words of
-// scratch; chunk_items[c .. c+1] the item range of chunk c (nb + 1 words);
-// items[i] = (the list's first micro-block, first slot, pairs, list length).
+// Pairs of every list-major chunk grouped by (chunk, list) and cut into items:
+// item = (first micro-block of its index block, first slot, pairs, vectors of
+// the block), an index block being B micro-blocks of the list (B = 0: the
+// whole list) and an item up to G pairs. Buffers: cnt, fill and bbase hold
+// nb * nlist words (cnt and fill zero on entry); wpart 2 * nb *
+// group_map_workgroups(nlist) words; chunk_items nb + 1 words (the item range
+// of chunk c is [chunk_items[c], chunk_items[c + 1])); slots one word per
+// pair; items at most group_map_item_bound(...) entries.
+struct GroupMap {
+  int32_t* cnt;
+  int32_t* fill;
+  int32_t* bbase;
+  int32_t* wpart;
+  int32_t* chunk_items;
+  int32_t* slots;
+  int4* items;
+};
 int group_map_workgroups(int nlist);
+int64_t group_map_item_bound(int64_t pairs, int G, int nb, int nlist, int64_t nmb, int64_t max_list_len, int B);
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
-                      int nlist, int G, const int32_t* list_mb, const int32_t* list_len, int16_t* rank,
-                      int32_t* cnt, int32_t* wpart, int32_t* chunk_items, int32_t* slots, int4* items);
+                      int nlist, int G, int B, const int32_t* list_mb, const int32_t* list_len,
+                      const GroupMap& m);
 void launch_scan_group(hipStream_t s, const GroupArgs& a, int workgroups);
 void launch_reset_masked(hipStream_t s, const uint32_t* mask, uint64_t* rows, int64_t ld, int R,
                          uint32_t* qthr, uint32_t* pcnt, int nq);
+
+// IVF-Flat list-major scan (kernels_flat.hip): exact squared distances
+// ||q||^2 + ||x||^2 - 2 <q, x> of full-precision vectors on the FP32 matrix
+// cores, items and pools as the list-major code scan's.
+struct FlatArgs {
+  const float* blocks;     // per micro-block: dp rows of 64 floats, then 64 squared norms
+  const int32_t* pos2id;
+  int d;
+  const float* q;          // queries, row stride ldq
+  int ldq;
+  int nq, nprobe, R, G;
+  const int32_t* slots;
+  const int32_t* item_off;
+  const int4* items;
+  uint32_t* item_counter;
+  const uint32_t* qthr;
+  uint64_t* pool;
+  int64_t pool_ld;
+  int cap;
+  uint32_t* pcnt;
+  uint32_t* overflow;
+  uint32_t* any_overflow;
+};
+int flat_dp(int d);  // rows per flat record: round_up(d, 4)
+// Fills the flat records of micro-blocks [0, nmb) from id-ordered rows of X.
+void launch_flat_fill(hipStream_t s, const float* X, int ldx, const int32_t* pos2id, int64_t nmb, int d,
+                      float* out);
+void launch_scan_flat(hipStream_t s, const FlatArgs& a, int workgroups);
 
 // Exact re-rank: per query, gather the candidates' raw vectors, exact squared
 // L2 in FP32, top-k by (distance, id). Output rows have stride k; with rowk

@@ -30,32 +30,22 @@ constexpr int STAGE = 512; // survivors staged per wave before a flush
 
 // ---- inverted map of the list-major chunks' pairs: list -> pairs ----------
 // Built once per search for all list-major chunks (a suffix of the probe
-// ranks): bin c * nlist + j holds the pairs of chunk c that probe list j.
-
-// rank[j * nq + i] = the probe rank p at which query i probes list j within
-// the list-major ranks (-1 otherwise; cleared by the search's state
-// initialisation). Then, without atomics, queries ascending within a bin:
-//   count: one wave per list counts its pairs per chunk (64 queries per
-//          step, one lane each, counted with one ballot per chunk); each
-//          workgroup of 16 lists adds up its pairs and items (ceil(count /
-//          G)) per chunk;
+// ranks): bin c * nlist + j holds the pairs of chunk c that probe list j. The
+// work grows with the pairs, not with nlist x nq:
+//   count: each pair adds one to its bin (atomic);
+//   sums:  each workgroup of 16 lists adds up its bins' pairs and items per
+//          chunk, an item being one index block of the list (B micro-blocks;
+//          B = 0: the whole list) and up to G of its pairs;
 //   scan:  one workgroup turns the workgroup sums (chunk-major) into bases,
 //          and the item range of every chunk;
-//   fill:  one wave per list places its pairs (the same steps: a pair's
-//          slot is its chunk's running base plus its rank in the ballot)
-//          and writes its items.
-// (x: 256 probe ranks per workgroup; y: queries, striding by gridDim.y)
-__global__ void k_grp_mark(const int32_t* __restrict__ probes, int nq, int nprobe, int r0,
-                           int16_t* __restrict__ rank) {
-  const int p = r0 + (int)blockIdx.x * 256 + (int)threadIdx.x;
-  if (p >= nprobe) return;
-  for (int64_t i = blockIdx.y; i < nq; i += gridDim.y) {
-    const int j = probes[i * nprobe + p];
-    if (j >= 0) rank[(int64_t)j * nq + i] = (int16_t)p;
-  }
-}
+//   bins:  one wave per bin finds its pair and item bases and writes its
+//          items, block-major (the query groups of one block are consecutive
+//          items, so they run close together and share its reads);
+//   fill:  each pair takes the next slot of its bin (atomic). The order of
+//          the pairs inside a bin is not fixed, and nothing depends on it: a
+//          scan's survivors are merged by an exact selection.
 
-constexpr int kMapLists = 16;  // lists (waves) per map workgroup
+constexpr int kMapLists = 16;  // lists per workgroup of the map's sums
 
 // chunk of list-major probe rank p (-1 for no pair): bounds are ascending
 __device__ inline int map_chunk(const GroupChunks& gc, int p) {
@@ -78,54 +68,47 @@ __device__ inline uint32_t lane_prefix(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
-constexpr int kMapUnroll = 4;  // 64-query steps whose ranks are loaded together
+// index blocks of a list of `len` vectors (B micro-blocks each; 0: one block)
+__device__ inline int map_blocks(int len, int B) {
+  return B > 0 ? max(1, (((len + 63) >> 6) + B - 1) / B) : 1;
+}
 
-__global__ __launch_bounds__(1024) void k_grp_count(const int16_t* __restrict__ rank, int nq, GroupChunks gc,
-                                                    int nlist, int G, int nwg, int32_t* __restrict__ cnt,
-                                                    int32_t* __restrict__ wpart) {
-  __shared__ int32_t sc[kMaxGroupChunks][kMapLists];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wg = blockIdx.x;
-  const int j = wg * kMapLists + wave;
-  int32_t c[kMaxGroupChunks];  // wave-uniform pair counts per chunk
-#pragma unroll
-  for (int b = 0; b < kMaxGroupChunks; ++b) c[b] = 0;
-  if (j < nlist) {
-    const int16_t* rj = rank + (int64_t)j * nq;
-    for (int i0 = 0; i0 < nq; i0 += 64 * kMapUnroll) {
-      int ch[kMapUnroll];
-#pragma unroll
-      for (int u = 0; u < kMapUnroll; ++u) {
-        const int i = i0 + 64 * u + lane;
-        ch[u] = map_chunk(gc, i < nq ? (int)rj[i] : -1);
-      }
-#pragma unroll
-      for (int u = 0; u < kMapUnroll; ++u)
-#pragma unroll
-        for (int b = 0; b < kMaxGroupChunks; ++b) {
-          if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
-          c[b] += (int32_t)__popcll(__ballot(ch[u] == b));
-        }
-    }
+// (x: 256 probe ranks per workgroup from the first list-major rank; y:
+// queries, striding by gridDim.y)
+template <bool FILL>
+__global__ void k_map_pairs(const int32_t* __restrict__ probes, int nq, int nprobe, GroupChunks gc,
+                            int nlist, int32_t* __restrict__ cnt, const int32_t* __restrict__ bbase,
+                            int32_t* __restrict__ fillc, int32_t* __restrict__ slots) {
+  const int p = gc.bound[0] + (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (p >= nprobe) return;
+  const int c = map_chunk(gc, p);
+  for (int64_t i = blockIdx.y; i < nq; i += gridDim.y) {
+    const int64_t pair = i * nprobe + p;
+    const int j = probes[pair];
+    if (j < 0) continue;
+    const int64_t bin = (int64_t)c * nlist + j;
+    if (FILL)
+      slots[bbase[bin] + atomicAdd(&fillc[bin], 1)] = (int32_t)pair;
+    else
+      atomicAdd(&cnt[bin], 1);
   }
-#pragma unroll
-  for (int b = 0; b < kMaxGroupChunks; ++b) {
-    if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
-    const int32_t tot = c[b];
-    if (lane == 0) {
-      sc[b][wave] = tot;
-      if (j < nlist) cnt[b * nlist + j] = tot;
-    }
+}
+
+// per (chunk, workgroup of 16 lists): pairs and items (one wave, grid (nwg, nb))
+__global__ void k_map_sums(const int32_t* __restrict__ cnt, const int32_t* __restrict__ list_len, int nlist,
+                           int G, int B, int nwg, int nb, int32_t* __restrict__ wpart) {
+  const int wg = blockIdx.x, c = blockIdx.y, lane = threadIdx.x;
+  const int j = wg * kMapLists + lane;
+  int32_t pc = 0, ic = 0;
+  if (lane < kMapLists && j < nlist) {
+    pc = cnt[(int64_t)c * nlist + j];
+    ic = ((pc + G - 1) / G) * map_blocks(list_len[j], B);
   }
-  __syncthreads();
-  if ((int)threadIdx.x < gc.nb) {
-    const int b = threadIdx.x;
-    int32_t pairs = 0, items = 0;
-    for (int w = 0; w < kMapLists; ++w) {
-      pairs += sc[b][w];
-      items += (sc[b][w] + G - 1) / G;
-    }
-    wpart[b * nwg + wg] = pairs;
-    wpart[(gc.nb + b) * nwg + wg] = items;
+  pc = wave_sum(pc);
+  ic = wave_sum(ic);
+  if (lane == 0) {
+    wpart[c * nwg + wg] = pc;
+    wpart[(nb + c) * nwg + wg] = ic;
   }
 }
 
@@ -174,53 +157,35 @@ __global__ __launch_bounds__(1024) void k_grp_scan(int32_t* __restrict__ wpart, 
   if (tid == 0) chunk_items[nb] = carry_i;
 }
 
-__global__ __launch_bounds__(1024) void k_grp_fill(const int16_t* __restrict__ rank, int nq, int nprobe,
-                                                   GroupChunks gc, int nlist, int G, int nwg,
-                                                   const int32_t* __restrict__ list_mb,
-                                                   const int32_t* __restrict__ list_len,
-                                                   const int32_t* __restrict__ cnt,
-                                                   const int32_t* __restrict__ wpart,
-                                                   int32_t* __restrict__ slots, int4* __restrict__ items) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, wg = blockIdx.x;
-  const int j = wg * kMapLists + wave;
-  if (j >= nlist) return;
-  const int V = gc.nb * nwg;
-  // this list's bases per chunk: the workgroup's base plus the lists before it
-  int32_t pos[kMaxGroupChunks];
-#pragma unroll
-  for (int b = 0; b < kMaxGroupChunks; ++b) {
-    if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
-    const int jl = wg * kMapLists + lane;
-    const int32_t cl = lane < wave && jl < nlist ? cnt[b * nlist + jl] : 0;
-    const int32_t pb = wpart[b * nwg + wg] + wave_sum(cl);
-    const int32_t ib = wpart[V + b * nwg + wg] + wave_sum((cl + G - 1) / G);
-    const int32_t cn = cnt[b * nlist + j];
-    const int mbj = list_mb[j], lenj = list_len[j];
-    for (int g = lane; g * G < cn; g += 64) items[ib + g] = make_int4(mbj, pb + g * G, min(G, cn - g * G), lenj);
-    pos[b] = pb;
+// one wave per bin (c, j): its pair base (kept for the fill) and its items
+__global__ void k_map_bins(const int32_t* __restrict__ cnt, const int32_t* __restrict__ list_mb,
+                           const int32_t* __restrict__ list_len, int nlist, int G, int B, int nwg, int nb,
+                           const int32_t* __restrict__ wpart, int32_t* __restrict__ bbase,
+                           int4* __restrict__ items) {
+  const int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (bin >= (int64_t)nb * nlist) return;
+  const int c = (int)(bin / nlist), j = (int)(bin - (int64_t)c * nlist);
+  const int wg = j / kMapLists, j0 = wg * kMapLists;
+  // the lists of this workgroup before j
+  int32_t pc = 0, ic = 0;
+  if (lane < j - j0) {
+    const int jl = j0 + lane;
+    pc = cnt[(int64_t)c * nlist + jl];
+    ic = ((pc + G - 1) / G) * map_blocks(list_len[jl], B);
   }
-  const int16_t* rj = rank + (int64_t)j * nq;
-  for (int i0 = 0; i0 < nq; i0 += 64 * kMapUnroll) {
-    int pr[kMapUnroll];
-#pragma unroll
-    for (int u = 0; u < kMapUnroll; ++u) {
-      const int i = i0 + 64 * u + lane;
-      pr[u] = i < nq ? (int)rj[i] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < kMapUnroll; ++u) {
-      const int i = i0 + 64 * u + lane;
-      const int ch = map_chunk(gc, pr[u]);
-      int32_t o = 0;
-#pragma unroll
-      for (int b = 0; b < kMaxGroupChunks; ++b) {
-        if (b >= gc.nb) continue;  // (the bound is uniform: every later b too)
-        const uint64_t m = __ballot(ch == b);
-        if (ch == b) o = pos[b] + (int32_t)lane_prefix(m);
-        pos[b] += (int32_t)__popcll(m);
-      }
-      if (ch >= 0) slots[o] = (int32_t)((int64_t)i * nprobe + pr[u]);
-    }
+  const int32_t pb = wpart[c * nwg + wg] + wave_sum(pc);
+  const int32_t ib = wpart[(nb + c) * nwg + wg] + wave_sum(ic);
+  const int32_t cn = cnt[bin];
+  if (lane == 0) bbase[bin] = pb;
+  if (cn == 0) return;
+  const int len = list_len[j], mb = list_mb[j];
+  const int nblk = map_blocks(len, B), ng = (cn + G - 1) / G;
+  const int bl = B > 0 ? B * 64 : len;  // vectors per block
+  for (int t = lane; t < nblk * ng; t += 64) {
+    const int blk = t / ng, g = t - blk * ng;
+    items[ib + t] = make_int4(mb + (B > 0 ? blk * B : 0), pb + g * G, min(G, cn - g * G),
+                              min(bl, len - blk * bl));
   }
 }
 
@@ -331,6 +296,8 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     const int mb0 = it.x, len = it.w;
     const int nmb = (len + 63) >> 6;
     list_pos0 = mb0 << 6;
+    // (debug dumps: the item's index block starts this many vectors into its list)
+    const int blk_off = DUMP ? list_pos0 - (a.L.list_mb[a.probes[a.slots[first]]] << 6) : 0;
     const size_t rec = (size_t)(W + 2) * 64;
     // lane = vector of the micro-block; the next micro-block's words and
     // factors are loaded into registers while the current one is computed
@@ -516,7 +483,7 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
                   ip = (acc[n][r] + sq) >> 1;
                 else
                   ip = acc[n][r];
-                const int64_t o = (int64_t)sPair[q] * a.maxlen + pos;
+                const int64_t o = (int64_t)sPair[q] * a.maxlen + blk_off + pos;
                 a.dump_ip[o] = ip;
                 a.dump_est[o] = F8 ? part[r] + qrn2[n] : part[r];
               }
@@ -556,25 +523,39 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
 }
 
 void launch_group_map(hipStream_t s, const int32_t* probes, int nq, int nprobe, const GroupChunks& gc,
-                      int nlist, int G, const int32_t* list_mb, const int32_t* list_len, int16_t* rank,
-                      int32_t* cnt, int32_t* wpart, int32_t* chunk_items, int32_t* slots, int4* items) {
+                      int nlist, int G, int B, const int32_t* list_mb, const int32_t* list_len,
+                      const GroupMap& m) {
   RBQ_CHECK(gc.nb >= 1 && gc.nb <= kMaxGroupChunks && gc.bound[gc.nb] == nprobe,
             "list-major chunk bounds");
-  RBQ_CHECK(nprobe <= 32767, "list-major map: nprobe out of range");
+  RBQ_CHECK(G >= 1 && B >= 0, "list-major map: item shape");
   const int64_t pairs = (int64_t)nq * (nprobe - gc.bound[0]);
   if (pairs <= 0) return;
   const int nwg = group_map_workgroups(nlist);
   const int span = nprobe - gc.bound[0];
-  hipLaunchKernelGGL(k_grp_mark, dim3((unsigned)((span + 255) / 256), (unsigned)std::min(nq, 65535)), dim3(256),
-                     0, s, probes, nq, nprobe, gc.bound[0], rank);
+  const dim3 pg((unsigned)((span + 255) / 256), (unsigned)std::min(nq, 65535));
+  // (cnt and fill are zero: the search's state initialisation clears them)
+  hipLaunchKernelGGL(k_map_pairs<false>, pg, dim3(256), 0, s, probes, nq, nprobe, gc, nlist, m.cnt, nullptr,
+                     nullptr, nullptr);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_count, dim3(nwg), dim3(1024), 0, s, rank, nq, gc, nlist, G, nwg, cnt, wpart);
+  hipLaunchKernelGGL(k_map_sums, dim3(nwg, gc.nb), dim3(64), 0, s, m.cnt, list_len, nlist, G, B, nwg, gc.nb,
+                     m.wpart);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_scan, dim3(1), dim3(1024), 0, s, wpart, gc.nb * nwg, nwg, gc.nb, chunk_items);
+  hipLaunchKernelGGL(k_grp_scan, dim3(1), dim3(1024), 0, s, m.wpart, gc.nb * nwg, nwg, gc.nb, m.chunk_items);
   RBQ_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_grp_fill, dim3(nwg), dim3(1024), 0, s, rank, nq, nprobe, gc, nlist, G, nwg, list_mb,
-                     list_len, cnt, wpart, slots, items);
+  const int64_t bins = (int64_t)gc.nb * nlist;
+  hipLaunchKernelGGL(k_map_bins, dim3((unsigned)((bins + 3) / 4)), dim3(256), 0, s, m.cnt, list_mb, list_len,
+                     nlist, G, B, nwg, gc.nb, m.wpart, m.bbase, m.items);
   RBQ_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_map_pairs<true>, pg, dim3(256), 0, s, probes, nq, nprobe, gc, nlist, m.cnt, m.bbase,
+                     m.fill, m.slots);
+  RBQ_HIP(hipGetLastError());
+}
+
+int64_t group_map_item_bound(int64_t pairs, int G, int nb, int nlist, int64_t nmb, int64_t max_list_len, int B) {
+  if (B <= 0) return pairs / G + (int64_t)nb * nlist + 1;
+  const int64_t maxblk = std::max<int64_t>(1, (ceil_div(max_list_len, 64) + B - 1) / B);
+  const int64_t sumblk = ceil_div(nmb, B) + nlist;
+  return ceil_div(pairs, G) * maxblk + (int64_t)nb * sumblk + 1;
 }
 
 int group_map_workgroups(int nlist) { return (nlist + kMapLists - 1) / kMapLists; }

@@ -74,8 +74,9 @@ struct Bufs {
   float* inj_scal = nullptr;
   uint32_t* qthr = nullptr;
   uint32_t* pcnt = nullptr;
-  int32_t* gcnt = nullptr;
-  int16_t* rankmat = nullptr;  // nlist x nq probe ranks (list-major map)
+  int32_t* gcnt = nullptr;         // list-major map: pairs per (chunk, list) bin
+  int32_t* gfill = nullptr;        // list-major map: fill cursor per bin
+  int32_t* gbase = nullptr;        // list-major map: first slot per bin
   int32_t* wpart = nullptr;        // list-major map: workgroup sums, then bases
   int32_t* chunk_items = nullptr;  // list-major map: item range of every chunk
   int32_t* slots = nullptr;
@@ -104,8 +105,11 @@ struct Plan {
   int64_t cand_ld = 0, pool_cap = 0;
   bool need_qcopy = true, ids_dev = false, dist_dev = false;
   bool inj_probes = false, inj_qu = false, dumps = false, mixed = false, any_group = false;
+  bool unq = false;   // unquantised residual (table-lookup query-major scan)
+  bool flat = false;  // IVF-Flat: exact distances of the lists' raw rows (list-major)
   GroupChunks gc;  // the list-major chunks (a suffix of the probe ranks)
   int G = 64, wg_per_cu = 8;
+  int B = 0;       // micro-blocks per index block of a list-major item (0: whole lists)
   const rbq_debug_io* dbg = nullptr;
   std::vector<Chunk> chunks, qm_chunks;
 };
@@ -144,8 +148,10 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   P.dbg = dbg;
   P.maxlen = std::max<int64_t>(1, idx->max_list_len);
   P.inj_probes = dbg && dbg->inject_probes;
-  P.inj_qu = dbg && dbg->inject_qu;
+  P.inj_qu = dbg && dbg->inject_qu && idx->opt_estimator.load() != 1;
   P.dumps = dbg && (dbg->ip || dbg->est);
+  P.unq = idx->opt_estimator.load() == 1;
+  P.flat = idx->opt_estimator.load() == 2 && idx->flat.p != nullptr;
   const int64_t budget = pool_budget > 0 ? pool_budget : kDefaultPoolBudget;
   P.pch = (int)std::max<int64_t>(
       1, std::min<int64_t>(nprobe, budget / std::max<int64_t>(1, nq * R * 8) - 1));
@@ -163,6 +169,8 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
     tuned = tune_lookup(const_cast<rbq_index*>(idx), nq, nprobe, R, &cfg);
   }
   P.G = idx->opt_group_size.load() > 0 ? idx->opt_group_size.load() : cfg.G;
+  if (P.flat) P.G = std::min(P.G, 32);  // two 16-query tiles per IVF-Flat item
+  P.B = idx->opt_block.load() >= 0 ? idx->opt_block.load() : cfg.B;
   P.wg_per_cu = cfg.wg_per_cu;
   // scan form per chunk of probe ranks: query-major (1) everywhere, or the
   // list-major MFMA scan for every chunk whose (query, probe) pairs number at
@@ -183,6 +191,8 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   // fits) when the budget allows
   P.pool_cap = (int64_t)R * P.pch;
   if (P.maxlen > P.pool_cap && nq * (R + P.maxlen) * 8 <= budget) P.pool_cap = P.maxlen;
+  if (P.flat)  // (no redo for IVF-Flat: as large a pool as the budget holds)
+    P.pool_cap = std::max<int64_t>(P.pool_cap, std::max<int64_t>(P.maxlen, budget / (8 * std::max<int64_t>(1, nq)) - R));
   P.cand_ld = R + P.pool_cap;
   if (idx->opt_pool_cap.load() > 0) P.pool_cap = std::min<int64_t>(P.pool_cap, idx->opt_pool_cap.load());
   for (int p0 = 0, pn = P.first; p0 < nprobe; p0 += pn, pn = std::min(2 * pn, P.pch)) {
@@ -190,6 +200,11 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
     P.qm_chunks.push_back({p0, pn, false, false});
   }
   // (list-major survivors carry their position in the list in 26 bits)
+  if (P.unq) scan_mode = 1;  // the unquantised estimator has the query-major scan only
+  if (P.flat) {              // IVF-Flat: the list-major scan for every chunk
+    scan_mode = 2;
+    gm = 0;
+  }
   const bool lm_ok = scan_mode == 2 && group_k_steps(idx->d) <= 4 &&
                      idx->max_list_len < (int64_t(1) << 26);
   if (lm_ok) {
@@ -259,20 +274,24 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   b.probes = c.take<int32_t>(pairs);
   if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
   b.qrot = c.take<float>((size_t)nq * ld);
-  b.planes = c.take<uint32_t>((size_t)pairs * W * idx->bqs);
-  const bool f8 = P.any_group && group_uses_f8(idx->bq, d);
-  if ((dbg && dbg->qu) || (P.any_group && !f8)) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
+  const bool codes = !P.unq && !P.flat;  // the quantised query's buffers
+  if (codes) b.planes = c.take<uint32_t>((size_t)pairs * W * idx->bqs);
+  const bool f8 = codes && P.any_group && group_uses_f8(idx->bq, d);
+  if (codes && ((dbg && dbg->qu) || (P.any_group && !f8))) b.qu = c.take<uint8_t>((size_t)pairs * W * 32);
   if (f8) b.qu8 = c.take<uint8_t>((size_t)pairs * 128 * group_f8_steps(d));
   if (P.any_group) {
     const int64_t bins = (int64_t)P.gc.nb * nlist;
-    b.gcnt = c.take<int32_t>(bins);
+    // cleared together at the start of a search: the overflow flag, the
+    // chunks' item cursors, the bins' pair counts and fill cursors
+    b.counter = c.take<uint32_t>(1 + kMaxGroupChunks + 2 * bins);
+    b.gcnt = reinterpret_cast<int32_t*>(b.counter + 1 + kMaxGroupChunks);
+    b.gfill = b.gcnt + bins;
+    b.gbase = c.take<int32_t>(bins);
     b.wpart = c.take<int32_t>((size_t)2 * P.gc.nb * group_map_workgroups(nlist));
     b.chunk_items = c.take<int32_t>(kMaxGroupChunks + 1);
     b.slots = c.take<int32_t>(pairs);
-    b.items = c.take<int4>(pairs / P.G + bins + 1);
+    b.items = c.take<int4>(group_map_item_bound(pairs, P.G, P.gc.nb, nlist, idx->nmb, idx->max_list_len, P.B));
     b.overflow = c.take<uint32_t>(nq);
-    b.counter = c.take<uint32_t>(1 + kMaxGroupChunks);  // overflow flag, item cursors
-    b.rankmat = c.take<int16_t>(((size_t)nlist * nq + 1) & ~size_t(1));
   }
   b.scal = c.take<float4>(pairs);
   if (P.inj_qu) {
@@ -397,7 +416,9 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
   const bool inj_probes = P.inj_probes, inj_qu = P.inj_qu, dumps = P.dumps;
   const int64_t maxlen = P.maxlen;
   const bool timed = !io.untimed && idx->timing.load() != 0;
-  const int rec_bytes = W * 4 + 8;  // code words and two factors per vector
+  // bytes of one vector's record: code words and two factors, or for
+  // IVF-Flat its full-precision row and squared norm
+  const int rec_bytes = P.flat ? (flat_dp(d) + 1) * 4 : W * 4 + 8;
   const int64_t cand_ld = P.cand_ld;
   const int64_t pool_cap = P.pool_cap;
   const bool any_group = P.any_group;
@@ -477,6 +498,9 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       launch_gemm_tn_bf16(s, qd, ld, idx->Pt.as<float>(), ld, b.qrot, ld, (int)nq, d, ld);
     else
       launch_gemm_tn(s, 0, qd, ld, idx->Pt.as<float>(), ld, b.qrot, ld, (int)nq, d, ld, nullptr);
+    if (dbg && dbg->inject_qrot)  // (rows of d floats into rows of ld; the padding stays zero)
+      RBQ_HIP(hipMemcpy2DAsync(b.qrot, ld * sizeof(float), dbg->inject_qrot, d * sizeof(float),
+                               d * sizeof(float), nq, hipMemcpyHostToDevice, s));
     mark(2);
     // residual quantisation per (query, probe)
     if (inj_qu) {
@@ -489,8 +513,9 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       RBQ_HIP(hipMemsetAsync(b.dump_ip, 0, (size_t)pairs * maxlen * sizeof(int32_t), s));
       RBQ_HIP(hipMemsetAsync(b.dump_est, 0, (size_t)pairs * maxlen * sizeof(float), s));
     }
-    launch_quant(s, b.qrot, ld, idx->Crot.as<float>(), ld, b.probes, (int)nq, nprobe, d, W, idx->bq,
-                 bqs, b.planes, b.qu, b.qu8, 128 * group_f8_steps(d), b.scal, b.inj_qu, b.inj_scal);
+    if (!P.unq && !P.flat)  // (the unquantised and IVF-Flat scans need no quantised query)
+      launch_quant(s, b.qrot, ld, idx->Crot.as<float>(), ld, b.probes, (int)nq, nprobe, d, W, idx->bq,
+                   bqs, b.planes, b.qu, b.qu8, 128 * group_f8_steps(d), b.scal, b.inj_qu, b.inj_scal);
     mark(3);
     // Phase 3 + Phase 4: code scan with the estimator and per-item top-R,
     // then the per-query merge, one chunk of probe ranks at a time
@@ -508,6 +533,10 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     sa.dump_ip = b.dump_ip;
     sa.dump_est = b.dump_est;
     sa.maxlen = maxlen;
+    sa.qrot = b.qrot;
+    sa.ldq = ld;
+    sa.crot = idx->Crot.as<float>();
+    sa.ldc = ld;
     {
       // running top-R rows empty, thresholds open, pools empty; the list-major
       // bins and cursors cleared
@@ -521,17 +550,15 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       if (any_group) {
         si.overflow = b.overflow;
         si.z0 = b.counter;
-        si.n0 = 1 + kMaxGroupChunks;
-        si.f2 = reinterpret_cast<uint32_t*>(b.rankmat);  // every rank -1
-        si.n2 = ((int64_t)nlist * nq + 1) / 2;
+        si.n0 = 1 + kMaxGroupChunks + 2 * (int64_t)P.gc.nb * nlist;
       }
       launch_search_init(s, si);
     }
     // the (chunk, list) -> pairs map of every list-major chunk
     if (any_group)
-      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, idx->list_mb.as<int32_t>(),
-                       idx->list_len.as<int32_t>(), b.rankmat, b.gcnt, b.wpart,
-                       b.chunk_items, b.slots, b.items);
+      launch_group_map(s, b.probes, (int)nq, nprobe, P.gc, nlist, P.G, P.B, idx->list_mb.as<int32_t>(),
+                       idx->list_len.as<int32_t>(),
+                       GroupMap{b.gcnt, b.gfill, b.gbase, b.wpart, b.chunk_items, b.slots, b.items});
     sa.pcnt = b.pcnt;
     sa.qmask = nullptr;
     GroupArgs ga;
@@ -555,6 +582,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     ga.cap = (int)pool_cap;
     ga.pcnt = b.pcnt;
     ga.overflow = b.overflow;
+    ga.probes = b.probes;
     ga.dump_ip = b.dump_ip;
     ga.dump_est = b.dump_est;
     ga.maxlen = maxlen;
@@ -579,7 +607,10 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         tr.scan.push_back(e1);
         RBQ_HIP(hipEventRecord(e0, s));
       }
-      launch_scan_popc(s, sa);
+      if (P.unq)
+        launch_scan_lut(s, sa);
+      else
+        launch_scan_popc(s, sa);
       if (timed) {
         RBQ_HIP(hipEventRecord(e1, s));
         tr.scan_lm.push_back(0);
@@ -608,7 +639,32 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         tr.scan.push_back(e1);
         RBQ_HIP(hipEventRecord(e0, s));
       }
-      launch_scan_group(s, ga, P.wg_per_cu * idx->num_cus);
+      if (P.flat) {
+        FlatArgs fl;
+        fl.blocks = idx->flat.as<float>();
+        fl.pos2id = idx->pos2id.as<int32_t>();
+        fl.d = d;
+        fl.q = qd;
+        fl.ldq = need_qcopy ? ld : d;
+        fl.nq = (int)nq;
+        fl.nprobe = nprobe;
+        fl.R = R;
+        fl.G = P.G;
+        fl.slots = ga.slots;
+        fl.item_off = ga.item_off;
+        fl.items = ga.items;
+        fl.item_counter = ga.item_counter;
+        fl.qthr = ga.qthr;
+        fl.pool = ga.pool;
+        fl.pool_ld = ga.pool_ld;
+        fl.cap = ga.cap;
+        fl.pcnt = ga.pcnt;
+        fl.overflow = ga.overflow;
+        fl.any_overflow = ga.any_overflow;
+        launch_scan_flat(s, fl, P.wg_per_cu * idx->num_cus);
+      } else {
+        launch_scan_group(s, ga, P.wg_per_cu * idx->num_cus);
+      }
       if (timed) {
         RBQ_HIP(hipEventRecord(e1, s));
         tr.scan_lm.push_back(1);
@@ -678,7 +734,15 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
     // once, so nothing waits for the host. Otherwise their rows are reset and
     // the host reads one flag and, if it is set, the query-major scan redoes
     // them.
-    if (any_group) {
+    if (any_group && P.flat) {
+      // IVF-Flat has no second scan form to redo a query with: a pool that
+      // overflowed fails the search rather than returning a wrong result
+      uint32_t any = 0;
+      RBQ_HIP(hipMemcpyAsync(&any, b.counter, sizeof(any), hipMemcpyDeviceToHost, s));
+      RBQ_HIP(hipStreamSynchronize(s));
+      if (any)
+        fail(RBQ_ENOMEM, "IVF-Flat: a query's candidate pool overflowed; search fewer queries per batch");
+    } else if (any_group) {
       if (idx->W <= 32) {
         FusedArgs ra = fa;
         ra.p0 = 0;
@@ -747,9 +811,9 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       if (dbg->qrot)
         RBQ_HIP(hipMemcpy2DAsync(dbg->qrot, d * sizeof(float), b.qrot, ld * sizeof(float),
                                  d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
-      if (dbg->qu)
+      if (dbg->qu && !P.unq)
         RBQ_HIP(hipMemcpy2DAsync(dbg->qu, d, b.qu, W * 32, d, pairs, hipMemcpyDeviceToHost, s));
-      if (dbg->scalars)
+      if (dbg->scalars && !P.unq)
         RBQ_HIP(hipMemcpyAsync(dbg->scalars, b.scal, pairs * sizeof(float4), hipMemcpyDeviceToHost, s));
       if (dbg->ip)
         RBQ_HIP(hipMemcpyAsync(dbg->ip, b.dump_ip, (size_t)pairs * maxlen * sizeof(int32_t),

@@ -5,6 +5,7 @@
 // shape falls in a tuned bucket uses the stored choices. The table can be saved
 // to and loaded from a text cache, whose entries are keyed by a signature of
 // the device architecture, D, B_q, nlist, n and the list-size histogram.
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -130,6 +131,8 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
         std::vector<uint64_t>& oc = &oi == &ref_ids ? ref_c : got_c;
         search_candidates(idx, dq.as<float>(), nq, nprobe, k, R, hc, hq, s, io);
         std::memcpy(oc.data(), hc, oc.size() * sizeof(uint64_t));
+        // (a query's candidates come in no particular order: compare them sorted)
+        for (int64_t i = 0; i < nq; ++i) std::sort(oc.begin() + i * R, oc.begin() + (i + 1) * R);
         const auto t0 = std::chrono::steady_clock::now();
         for (int r = 0; r < reps; ++r) search_candidates(idx, dq.as<float>(), nq, nprobe, k, R, hc, hq, s, io);
         return std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
@@ -170,6 +173,27 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
         have = true;
       }
     }
+    // then the index-block size of the best list-major choice (Sec. 3.3.1:
+    // long lists shared out over several workgroups), results checked alike
+    int trials = (int)cands.size();
+    if (best.scan == 2) {
+      const TuneCfg base = best;
+      for (int B : {8, 16, 32, 64}) {
+        TuneCfg c = base;
+        c.B = B;
+        const float ms = time_cfg(&c, got_ids, got_d);
+        ++trials;
+        const bool differs = host_rr ? got_c != ref_c
+                                     : (got_ids != ref_ids ||
+                                        std::memcmp(got_d.data(), ref_d.data(), got_d.size() * 4) != 0);
+        if (differs) fail(RBQ_EDEVICE, "autotune: index blocks of " + std::to_string(B) +
+                                           " micro-blocks returned different results");
+        if (ms < best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+    }
     {
       std::lock_guard<std::mutex> g(idx->tune_mu);
       idx->tune[tune_key(nq, nprobe, R)] = best;
@@ -183,9 +207,10 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
       out->chunk_group_min = best.gm;
       out->growth = best.growth;
       out->early_form = best.early;
+      out->block = best.B;
       out->ms = best_ms;
       out->ms_default = ms_default;
-      out->trials = (int32_t)cands.size();
+      out->trials = (int32_t)trials;
     }
   } catch (...) {
     (void)hipStreamSynchronize(s);
@@ -219,13 +244,13 @@ void tune_save(rbq_index* idx, const char* path) {
   {
     std::ofstream o(tmp, std::ios::trunc);
     RBQ_CHECK(o.good(), "cannot write the autotune cache");
-    o << "# librbq autotune cache v4: signature key scan G wg_per_cu first_factor gm growth early\n";
+    o << "# librbq autotune cache v5: signature key scan G wg_per_cu first_factor gm growth early block\n";
     for (const auto& l : keep) o << l << "\n";
     std::lock_guard<std::mutex> g(idx->tune_mu);
     for (const auto& kv : idx->tune)
       o << sig << " " << kv.first << " " << kv.second.scan << " " << kv.second.G << " "
         << kv.second.wg_per_cu << " " << kv.second.first_factor << " " << kv.second.gm << " "
-        << kv.second.growth << " " << kv.second.early << "\n";
+        << kv.second.growth << " " << kv.second.early << " " << kv.second.B << "\n";
     RBQ_CHECK(o.good(), "writing the autotune cache failed");
   }
   RBQ_CHECK(std::rename(tmp.c_str(), path) == 0, "cannot replace the autotune cache");
@@ -244,13 +269,14 @@ int tune_load(rbq_index* idx, const char* path) {
     std::string s;
     uint64_t key = 0;
     TuneCfg c;
-    if (!(ls >> s >> key >> c.scan >> c.G >> c.wg_per_cu >> c.first_factor >> c.gm >> c.growth >> c.early))
+    if (!(ls >> s >> key >> c.scan >> c.G >> c.wg_per_cu >> c.first_factor >> c.gm >> c.growth >> c.early >>
+          c.B))
       continue;
     if (s != sig) continue;
     const bool ok = (c.scan == 1 || c.scan == 2) && c.G >= 1 && c.G <= 64 && c.wg_per_cu >= 1 &&
                     c.wg_per_cu <= 64 && c.first_factor >= 1 && c.first_factor <= 64 &&
                     c.gm >= 0 && c.gm <= (1 << 20) && c.growth >= 2 && c.growth <= 16 &&
-                    (c.early == 0 || c.early == 1);
+                    (c.early == 0 || c.early == 1) && c.B >= 0 && c.B <= (1 << 20);
     RBQ_CHECK(ok, "autotune cache entry out of range");
     got[key] = c;
     ++loaded;

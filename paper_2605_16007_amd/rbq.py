@@ -27,7 +27,8 @@ SYMBOLS = [
     "rbq_server_get_stats", "rbq_server_destroy", "rbq_server_replay", "rbq_replay_plain",
     "rbq_autotune", "rbq_tune_save", "rbq_tune_load", "rbq_tune_clear", "rbq_search_noalloc",
 ]
-OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4, "group_size": 5, "estimator": 6}
+OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4, "group_size": 5, "estimator": 6,
+           "block": 7}
 
 
 class BuildParams(C.Structure):
@@ -36,7 +37,7 @@ class BuildParams(C.Structure):
                 ("train_n", C.c_int64), ("rotation", C.c_void_p), ("centroids", C.c_void_p),
                 ("assignment", C.c_void_p), ("vectors_on_host", C.c_int32),
                 ("host_threads", C.c_int32), ("borrow_vectors", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("ivf_flat", C.c_int32), ("kmeans_init", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class IndexInfo(C.Structure):
@@ -88,7 +89,7 @@ class TuneResult(C.Structure):
     _fields_ = [("scan", C.c_int32), ("group_size", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("first_factor", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
                 ("trials", C.c_int32), ("chunk_group_min", C.c_int32),
-                ("growth", C.c_int32), ("early_form", C.c_int32)]
+                ("growth", C.c_int32), ("early_form", C.c_int32), ("block", C.c_int32)]
 
 
 class RbqError(RuntimeError):
@@ -193,7 +194,7 @@ class Index:
     @classmethod
     def build(cls, x, nlist, *, bq=4, seed=0, kmeans_iters=25, kmeans_restarts=3, train_n=0,
               rotation=None, centroids=None, assignment=None, vectors_on_host=None,
-              host_threads=0, borrow_vectors=False):
+              host_threads=0, borrow_vectors=False, ivf_flat=False, kmeans_init="kmeans++"):
         """Build an index over x (NumPy array or torch tensor, n x d float32).
         vectors_on_host: False (HBM), True (pinned host memory, host re-rank) or
         None (automatic). borrow_vectors: keep x itself (pinned host memory,
@@ -224,6 +225,8 @@ class Index:
         p.vectors_on_host = -1 if vectors_on_host is None else int(bool(vectors_on_host))
         p.host_threads = int(host_threads)
         p.borrow_vectors = int(bool(borrow_vectors))
+        p.ivf_flat = int(bool(ivf_flat))
+        p.kmeans_init = {"kmeans++": 0, "random": 1}[kmeans_init]
         h = C.c_void_p()
         _check(lib().rbq_build_index(_ptr(x), n, d, C.byref(p), C.byref(h)))
         ix = cls(h.value)

@@ -55,6 +55,8 @@ def test_params_defaults():
     (10, 8, {"vectors_on_host": 2}, "vectors_on_host"),
     (10, 8, {"vectors_on_host": -2}, "vectors_on_host"),
     (10, 8, {"borrow_vectors": 2}, "borrow_vectors"),
+    (10, 8, {"kmeans_init": 2}, "kmeans_init"),
+    (10, 8, {"ivf_flat": 2}, "ivf_flat"),
     (10, 8, {"borrow_vectors": 1, "vectors_on_host": 0}, "borrow_vectors needs the vectors on the host"),
     # a NumPy array is pageable memory: it cannot be borrowed
     (10, 8, {"borrow_vectors": 1, "vectors_on_host": 1}, "pinned host memory"),
@@ -75,7 +77,7 @@ def test_build_rejects_nonzero_reserved():
     L = rbq.lib()
     x = np.zeros((10, 8), np.float32)
     p = _params()
-    p.reserved[3] = 1
+    p.reserved[2] = 1
     h = C.c_void_p()
     assert L.rbq_build_index(x.ctypes.data, 10, 8, C.byref(p), C.byref(h)) == rbq.RBQ_EINVAL
 
@@ -105,14 +107,14 @@ def test_null_arguments():
 
 def test_struct_sizes_match_header_layout():
     # natural C layout of the public structs (x86-64 / LP64)
-    assert C.sizeof(rbq.BuildParams) == 4 + 4 + 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4 + 4 + 5 * 4
+    assert C.sizeof(rbq.BuildParams) == 4 + 4 + 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4 + 4 + 4 + 4 + 3 * 4
     assert C.sizeof(rbq.DebugIO) == 14 * 8 + 8 + 8
     assert C.sizeof(rbq.Timings) == 8 + 7 * 4 + 4 + 5 * 8 + 4 + 4 + 2 * 8 + 8 + 4 + 4 + 2 * 8
     assert C.sizeof(rbq.IndexInfo) == 8 + 4 * 4 + 3 * 8 + 4 + 4
     assert C.sizeof(rbq.ServerParams) == 6 * 4 + 8 + 8 * 4
     assert C.sizeof(rbq.ServerStats) == 8 * 8
     assert C.sizeof(rbq.ReplayIO) == 8 * 8 + 8 + 4 + 4
-    assert C.sizeof(rbq.TuneResult) == 4 * 4 + 2 * 4 + 4 + 4 + 4 + 4
+    assert C.sizeof(rbq.TuneResult) == 4 * 4 + 2 * 4 + 4 + 4 + 4 + 4 + 4
 
 
 def test_tuning_null_arguments():

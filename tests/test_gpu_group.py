@@ -140,6 +140,31 @@ def test_group_candidates_match_oracle(gcase):
     _say(f"[group {gcase['name']}] P4 exact, P5 worst {worst:.2e} S")
 
 
+@pytest.mark.parametrize("block", [1, 2, 16])
+def test_group_index_blocks_invariant(gcase, block):
+    """Items over index blocks of `block` micro-blocks (a long list shared out
+    over several workgroups, Sec. 3.3.1): candidates and results equal the
+    query-major scan's, and every estimate written out equals that of
+    whole-list items (each vector's dump lands at its position in its list)."""
+    lib, Q = gcase["lib"], gcase["Q"]
+    nprobe, k, R = gcase["nprobe"], gcase["k"], gcase["R"]
+    a = _run(lib, Q, nprobe, k, R, scan=1)
+    lib.set_option("block", block)
+    try:
+        b = _run(lib, Q, nprobe, k, R, scan=2, lm_only=True, want_extra={"ip", "est"})
+    finally:
+        lib.set_option("block", -1)
+    for key in WANT:
+        np.testing.assert_array_equal(b[key], a[key], err_msg=f"{key} block {block}")
+    lib.set_option("block", 0)
+    try:
+        c = _run(lib, Q, nprobe, k, R, scan=2, lm_only=True, want_extra={"ip", "est"})
+    finally:
+        lib.set_option("block", -1)
+    np.testing.assert_array_equal(b["ip"], c["ip"])
+    np.testing.assert_array_equal(b["est"], c["est"])
+
+
 def test_fused_buffer_shrinks_mid_chunk():
     """Lists of ~10k vectors: the first fused chunk holds more candidates than
     the fused kernel's LDS buffer, so it keeps only the best R and lowers the

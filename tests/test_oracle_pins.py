@@ -146,6 +146,42 @@ def test_kmeans_keeps_lowest_objective_restart():
     assert objective(C) == min(objs)
 
 
+def test_kmeans_seed_rows_subset():
+    """With seed_rows the k-means++ centres come only from the evenly strided
+    subset (row t * T // S, written out here with integer loops), and
+    seed_rows >= T is the default procedure."""
+    rng = np.random.default_rng(6)
+    X = rng.normal(size=(300, 3)).astype(np.float32)
+    T = X.astype(np.float64)
+    S = 37
+    sub = [T[(t * len(T)) // S] for t in range(S)]
+    for seed in range(5):
+        C = O.kmeanspp_init(np.array(sub), 5, np.random.default_rng(seed))
+        for c in C:
+            assert any(np.array_equal(c, r) for r in sub)
+        a = O.kmeans(X, 5, np.random.default_rng(seed), iters=0, restarts=1, seed_rows=S)
+        np.testing.assert_array_equal(a, C)  # zero Lloyd steps: the seeds themselves
+    a = O.kmeans(X, 5, np.random.default_rng(9), iters=4, restarts=2, seed_rows=10_000)
+    b = O.kmeans(X, 5, np.random.default_rng(9), iters=4, restarts=2)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_kmeans_random_init_rows():
+    """init="random": the starting centroids are distinct training rows (zero
+    Lloyd steps return them), and Lloyd steps from them never raise the
+    objective."""
+    rng = np.random.default_rng(8)
+    X = rng.integers(0, 50, size=(200, 2)).astype(np.float32)
+    C = O.kmeans(X, 7, np.random.default_rng(1), iters=0, restarts=1, init="random")
+    rows = {tuple(r) for r in X.astype(np.float64).tolist()}
+    assert len({tuple(c) for c in C.tolist()}) == 7
+    assert all(tuple(c) in rows for c in C.tolist())
+    trace = []
+    O.kmeans(X, 7, np.random.default_rng(1), iters=20, restarts=2, init="random", trace=trace)
+    for run in trace:
+        assert all(b <= a * (1 + 1e-12) for a, b in zip(run, run[1:]))
+
+
 def test_kmeans_empty_cluster_reseed():
     """An empty cluster is moved onto the point farthest from its centroid."""
     T = np.array([[0.0], [1.0], [10.0]])
