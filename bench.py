@@ -1,13 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of batched IVF-RaBitQ search on one MI355X.
 
-Workload (default ``sift10m``): 10M x 128 integer-valued skewed vectors,
-nlist 4096, batches of 1024 queries, B_q 4, k 10. A step is one pass of the
-whole search path over one batch: probe GEMM + top-nprobe, query rotation,
-residual quantisation, code scan with the fused estimator, per-query top-R,
-exact re-rank. The operating point (nprobe, rerank_n) is the fastest measured
-point whose recall@10 against exact kNN reaches 0.95: the workload's listed
-points first, then a wider grid; ``--nprobe``/``--rerank`` fix it instead.
+Headline workload (default): the 400M x 96 unit-vector mixture, as its 50M-row
+shard unless ``--full`` (nlist 8192 for the shard, 65,536 for the whole set,
+lists of about 6,100 vectors either way), batches of 10,000 queries, B_q 4,
+k 10; the raw vectors live in pinned host memory that the index borrows and
+the exact re-rank runs on host cores, overlapped with the GPU search of the
+next sub-batch. A step is one pass of the whole search path over one batch:
+probe GEMM + top-nprobe, query rotation, residual quantisation, code scan with
+the fused estimator, per-query top-R, exact re-rank. The operating point
+(nprobe, rerank_n) is the fastest measured point whose recall@10 against exact
+kNN reaches 0.95: the workload's listed points first, then longer re-rank
+lists and wider probes; ``--nprobe``/``--rerank`` fix it instead.
+
+Secondary workload (default ``sift10m``: 10M x 128 integer-valued vectors,
+nlist 4096, batches of 1024, raw vectors in HBM, GPU re-rank): the same
+measurement, an ablation of GPU against host re-rank, and the serving
+comparison (continuous batching against one query at a time).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -33,15 +42,16 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # a sum for E, (||r||^2 + n_x^2), the factor product and its sum, the threshold
 # compare
 EPILOGUE_OPS = 9
-# PMC summaries (HBM bytes per launch of a scan kernel at one operating point)
+# rows of the 400M x 96 workload's shard (one eighth: nlist 8192)
+SHARD_ROWS = 50_000_000
+# PMC summaries: profiles/<kernel>_<workload>_pmc.md record the HBM bytes per
+# launch of one scan kernel at one operating point, with the sha256 of the
+# kernel's source file and the two headers it includes
 _CSRC = os.path.join(ROOT, "paper_2605_16007_amd", "csrc")
-# kernel -> (its PMC summary, the sources whose concatenation's sha256 the
-# summary records: the kernel's file and the two headers it includes)
-PMC_SUMMARIES = {
-    "k_scan_group": (os.path.join(ROOT, "profiles", "k_scan_group_sift10m_pmc.md"),
-                     [os.path.join(_CSRC, f) for f in ("kernels_group.hip", "kernels.hpp", "common.hpp")]),
-    "k_scan_popc": (os.path.join(ROOT, "profiles", "k_scan_popc_unit96_50m.md"),
-                    [os.path.join(_CSRC, f) for f in ("kernels.hip", "kernels.hpp", "common.hpp")]),
+KERNEL_SOURCES = {
+    "k_scan_group": [os.path.join(_CSRC, f) for f in ("kernels_group.hip", "kernels.hpp", "common.hpp")],
+    "k_scan_popc": [os.path.join(_CSRC, f) for f in ("kernels.hip", "kernels.hpp", "common.hpp")],
+    "k_scan_fused": [os.path.join(_CSRC, f) for f in ("kernels.hip", "kernels.hpp", "common.hpp")],
 }
 
 
@@ -55,22 +65,23 @@ def source_sha(paths):
 
 
 def pmc_traffic(kernel, point):
-    """HBM bytes per launch of `kernel` from its committed PMC summary, if the
-    kernel source has not changed since the counters were taken and they were
-    taken at this operating point (e.g. "sift10m nprobe=512 rerank=3840")."""
+    """HBM bytes per launch of `kernel` from a committed PMC summary taken at
+    this operating point (e.g. "sift10m nprobe=512 rerank=3840") for the
+    current kernel source; None if there is none."""
+    import glob
     import re
-    summary, srcs = PMC_SUMMARIES[kernel]
     try:
+        sha = source_sha(KERNEL_SOURCES[kernel])
+    except (KeyError, OSError):
+        return None
+    for summary in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*_pmc.md"))):
         text = open(summary).read()
-        sha = source_sha(srcs)
-    except OSError:
-        return None
-    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
-    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    o = re.search(r"operating_point:\s*(.+)", text)
-    if not m or not t or not o or m.group(1) != sha or o.group(1).strip() != point:
-        return None
-    return float(t.group(1))
+        m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+        t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+        o = re.search(r"operating_point:\s*(.+)", text)
+        if m and t and o and m.group(1) == sha and o.group(1).strip() == point:
+            return float(t.group(1))
+    return None
 
 
 def log(*a):
@@ -195,137 +206,169 @@ def serve_compare(idx, w, args):
     """Open-loop Poisson traces on the resident index: the continuous-batching
     server against plain one-query-at-a-time search (rbq_search, nq = 1, in
     arrival order), both driven by the library's native replay. Per request
-    nprobe ~ U{8, 16, ..., 256}, k ~ U{10, 100}, rerank_n = 10 k. The two return
-    identical results (checked here), so their recall is equal."""
+    nprobe ~ U{8, 16, ..., 256}, k ~ U{10, 100}, rerank_n = 10 k. Each rate's
+    trace starts with ``serve_warmup_s`` seconds of arrivals that are served but
+    not counted. The plain form replays the first ``plain_max`` requests of the
+    same trace (it saturates far below the offered rates). Both forms return
+    identical results on the requests they share (checked here), so their
+    recall is equal."""
     from paper_2605_16007_amd import Server
     from synth import arrivals, queries
     rates = [float(r) for r in args.serve_rates.split(",") if r]
     counts = [max(64, min(args.serve_max, int(r * args.serve_seconds))) for r in rates]
-    Qs = queries(w, max(counts))
+    warms = [int(r * args.serve_warmup_s) for r in rates]
+    Qs = queries(w, max(c + m for c, m in zip(counts, warms)))
     out = {"workload": f"{w.name} index, Poisson arrivals, nprobe U{{8..256 step 8}}, "
                        f"k U{{10,100}}, rerank_n 10k",
            "server": {"lanes": 2, "max_batch": 1024, "mem_budget_gib": 1.0}, "rates": {}}
 
-    def summary(n, arr, lat):
+    def summary(arr, lat):
         done = arr + lat
-        return {"qps": n / float(done.max() - arr[0]), "p50_ms": float(np.percentile(lat, 50)) * 1e3,
+        return {"requests": len(arr), "qps": len(arr) / float(done.max() - arr[0]),
+                "p50_ms": float(np.percentile(lat, 50)) * 1e3,
                 "p99_ms": float(np.percentile(lat, 99)) * 1e3}
 
     with Server(idx, lanes=2, max_batch=1024, max_nprobe=256, max_k=100, max_rerank=1000,
                 mem_budget=1 << 30) as srv:
         t, npb, kk = arrivals(rates[0], 256, seed=99)
-        srv.replay(Qs[:256], npb, kk, 10 * kk, np.zeros(256))  # warm-up
+        srv.replay(Qs[:256], npb, kk, 10 * kk, np.zeros(256))  # first-use warm-up
         idx.replay_plain(Qs[:32], npb[:32], kk[:32], 10 * kk[:32], np.zeros(32))
-        for ri, (rate, n) in enumerate(zip(rates, counts)):
-            t, npb, kk = arrivals(rate, n, seed=ri)
+        for ri, (rate, n, wm) in enumerate(zip(rates, counts, warms)):
+            tot = n + wm
+            t, npb, kk = arrivals(rate, tot, seed=ri)
             t = t - t[0]
             before = srv.stats()
-            ids_s, d_s, lat_s = srv.replay(Qs[:n], npb, kk, 10 * kk, t)
+            ids_s, d_s, lat_s = srv.replay(Qs[:tot], npb, kk, 10 * kk, t)
             after = srv.stats()
-            ids_p, d_p, lat_p = idx.replay_plain(Qs[:n], npb, kk, 10 * kk, t)
+            m = min(tot, args.plain_max)
+            ids_p, d_p, lat_p = idx.replay_plain(Qs[:m], npb[:m], kk[:m], 10 * kk[:m], t[:m])
             batches = after["batches"] - before["batches"]
-            rec = {"requests": n, "trace_s": float(t[-1]),
-                   "server": dict(summary(n, t, lat_s), mean_batch=n / max(1, batches)),
-                   "plain": summary(n, t, lat_p),
-                   "identical_results": bool(np.array_equal(ids_s, ids_p) and np.array_equal(d_s, d_p))}
+            pw = min(wm, m // 2)
+            rec = {"offered_qps": rate, "warmup_requests": wm, "trace_s": float(t[-1] - t[wm]),
+                   "server": dict(summary(t[wm:], lat_s[wm:]), mean_batch=tot / max(1, batches)),
+                   "plain": summary(t[pw:m], lat_p[pw:]),
+                   "identical_results": bool(np.array_equal(ids_s[:m], ids_p) and np.array_equal(d_s[:m], d_p))}
             out["rates"][str(int(rate))] = rec
-            log(f"[serving] {rate:.0f} q/s x {n}: server {rec['server']['qps']:.0f} q/s "
-                f"p50 {rec['server']['p50_ms']:.2f} p99 {rec['server']['p99_ms']:.2f} ms "
-                f"(batch {rec['server']['mean_batch']:.1f}); plain {rec['plain']['qps']:.0f} q/s "
-                f"p50 {rec['plain']['p50_ms']:.2f} p99 {rec['plain']['p99_ms']:.2f} ms; "
-                f"identical {rec['identical_results']}")
+            log(f"[serving] {rate:.0f} q/s, {n} requests after {wm} warm-up: server "
+                f"{rec['server']['qps']:.0f} q/s p50 {rec['server']['p50_ms']:.2f} p99 "
+                f"{rec['server']['p99_ms']:.2f} ms (batch {rec['server']['mean_batch']:.1f}); plain "
+                f"({m} requests) {rec['plain']['qps']:.0f} q/s p50 {rec['plain']['p50_ms']:.2f} "
+                f"p99 {rec['plain']['p99_ms']:.2f} ms; identical {rec['identical_results']}")
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--streams", type=int, default=1,
-                    help="HIP streams the timed batches alternate over (each batch whole on one)")
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sift10m")
-    ap.add_argument("--nprobe", type=int, default=0,
-                    help="fix nprobe (default: the fastest point reaching recall@10 >= 0.95)")
-    ap.add_argument("--rerank", type=int, default=0, help="fix rerank_n (with --nprobe)")
-    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
-                    help="finish with one device-to-device copy of this size (PMC calibration)")
-    ap.add_argument("--n", type=int, default=0, help="database rows (default: the workload's)")
-    ap.add_argument("--batches", type=int, default=4, help="distinct query batches cycled")
-    ap.add_argument("--latency-iters", type=int, default=50)
-    ap.add_argument("--cpu-queries", type=int, default=128)
-    ap.add_argument("--cpu-cores", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--rotation", choices=("fp32", "bf16"), default="fp32",
-                    help="query rotation precision (bf16: BF16 inputs, FP32 accumulation)")
-    ap.add_argument("--vectors-on-host", action="store_true",
-                    help="keep the raw vectors in pinned host memory and re-rank on host cores")
-    ap.add_argument("--no-autotune", action="store_true", help="time the built-in launch rule")
-    ap.add_argument("--tune-cache", default="",
-                    help="autotune cache file: loaded if it exists (no tuning runs), else written")
-    ap.add_argument("--no-variants", action="store_true",
-                    help="skip the timing of both scan forms at the chosen point")
-    ap.add_argument("--scan", choices=("auto", "popcount", "mfma"), default="auto",
-                    help="force the scan form of the timed loop (auto: tuned per chunk)")
-    ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
-                    help="Poisson arrival rates (queries/s) of the serving comparison; '' skips it")
-    ap.add_argument("--serve-seconds", type=float, default=0.5,
-                    help="seconds of arrivals per rate (capped by --serve-max)")
-    ap.add_argument("--serve-max", type=int, default=8000, help="most requests per rate")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures the search path on one GPU only; this build runs no "
-              "multi-GPU configuration (--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
+# ----------------------------------------------------------------- one workload
 
-    from synth import get, database, queries
-    w = get(args.workload)
-    if args.n:
-        w = w.with_(n=args.n, nlist=max(1, int(round(w.nlist * args.n / w.n))))
-    nb = args.batches
-    t = time.perf_counter()
-    X = database(w)
-    Qall = queries(w, w.nq * nb)
-    log(f"[data] {w.name}: {w.n} x {w.d} + {nb} x {w.nq} queries in {time.perf_counter() - t:.1f}s")
+def roofline_of(tm, w, wname, nprobe, R, scan):
+    """Per-launch figures of the scan kernels from one instrumented pass.
 
-    cpu_pool = None
-    if not args.no_cpu_baseline:
-        # forked before the GPU is touched
-        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
-        cpu_pool = CpuBaseline(w, Qall[:w.nq], args.cpu_queries, cores)
+    Achieved bandwidth counts the bytes each kernel's item schedule reads at
+    least once (the code and factor records: a list-major item reads its list
+    once for its group of queries, a query-major item once for its query)
+    divided by that kernel's HIP-event time. The dominant kernel (the most scan
+    time per batch) is the one reported; the others sit under "forms"."""
+    ns = max(1, tm["searches"])
+    rec = 4 * ((w.d + 31) // 32) + 8
+    forms = {}
+    g_ms = tm["group_scan_ms"] / ns
+    f_ms = tm["fused_scan_ms"] / ns
+    p_ms = tm["scan_ms"] / ns - g_ms - f_ms
+    g_l = tm["group_launches"] / ns
+    f_l = tm["fused_launches"] / ns
+    p_l = (tm["popc_launches"] - tm["fused_launches"]) / ns
+    parts = {
+        "k_scan_group": (g_l, g_ms, tm["group_read_bytes"] / ns, tm["group_vectors"] / ns),
+        "k_scan_fused": (f_l, f_ms, tm["fused_read_bytes"] / ns, tm["fused_vectors"] / ns),
+        "k_scan_popc": (p_l, p_ms, (tm["read_bytes"] - tm["group_read_bytes"] - tm["fused_read_bytes"]) / ns,
+                        (tm["scanned_vectors"] - tm["group_vectors"] - tm["fused_vectors"]) / ns),
+    }
+    for name, (launches, ms, byts, vecs) in parts.items():
+        if launches <= 0 or ms <= 0:
+            continue
+        gbs = byts / (ms * 1e-3) / 1e9
+        f = {"launches_per_step": launches, "avg_launch_ms": ms / launches,
+             "schedule_bytes_per_launch": byts / launches, "achieved_gbs": gbs,
+             "frac_hbm": gbs / HBM_PEAK_GBS, "estimates_per_launch": vecs / launches,
+             "ms_per_step": ms}
+        if name == "k_scan_group":
+            alu = vecs * EPILOGUE_OPS / (ms * 1e-3) / 1e12
+            f["alu"] = {"ops_per_estimate": EPILOGUE_OPS, "achieved_tops": alu, "peak_tops": VALU_PEAK_TOPS,
+                        "frac": alu / VALU_PEAK_TOPS}
+            # every (query, vector) pair as if each read its own record
+            f["pair_bytes_gbs_effective"] = vecs * rec / (ms * 1e-3) / 1e9
+        forms[name] = f
+    if not forms:
+        return None
+    dom = max(forms, key=lambda n: forms[n]["ms_per_step"])
+    d = forms[dom]
+    point = f"{wname} nprobe={nprobe} rerank={R}" + ("" if dom == "k_scan_group" else f" scan={scan}")
+    return {"kernel": dom, "bound": "hbm", "achieved": d["achieved_gbs"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d["frac_hbm"], "traffic": pmc_traffic(dom, point),
+            "launches_per_step": d["launches_per_step"], "avg_launch_ms": d["avg_launch_ms"],
+            "bytes_per_launch": d["schedule_bytes_per_launch"], "forms": forms}
 
+
+def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
+    """Build the index of workload ``w``, choose its operating point, time it.
+    Returns the fields of one result line (``role`` names it in the log)."""
     import torch
     from paper_2605_16007_amd import Index
+    from synth import database, get, queries
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    nb = args.batches
     t = time.perf_counter()
-    idx = Index.build(X, w.nlist, bq=w.bq, seed=w.seed, vectors_on_host=args.vectors_on_host)
+    xt = None
+    if host_vectors:
+        # raw vectors drawn straight into pinned host memory that the index
+        # borrows (no second host copy)
+        xt = torch.empty((w.n, w.d), dtype=torch.float32, pin_memory=True)
+        X = xt.numpy()
+        database(w, out=X)
+    else:
+        X = database(w)
+    Qall = queries(w, w.nq * nb)
+    gen_s = time.perf_counter() - t
+    log(f"[{role}] {w.name}: {w.n} x {w.d} + {nb} x {w.nq} queries in {gen_s:.1f}s")
+    t = time.perf_counter()
+    kw = {}
+    if args.kmeans_iters:
+        kw["kmeans_iters"] = args.kmeans_iters
+    if args.kmeans_restarts:
+        kw["kmeans_restarts"] = args.kmeans_restarts
+    if args.train_n:
+        kw["train_n"] = args.train_n
+    if args.kmeans_init:
+        kw["kmeans_init"] = args.kmeans_init
+    idx = Index.build(xt if host_vectors else X, w.nlist, bq=w.bq, seed=w.seed,
+                      vectors_on_host=host_vectors, borrow_vectors=host_vectors,
+                      ivf_flat=not args.no_flat and w.d <= 256, **kw)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t
     info = idx.info()
     idx.set_option("rotation", 1 if args.rotation == "bf16" else 0)
-    log(f"[build] {build_s:.1f}s, max list {info['max_list_len']}, codes {info['code_bytes'] / 1e6:.1f} MB")
+    log(f"[{role}] build {build_s:.1f}s, max list {info['max_list_len']}, codes "
+        f"{info['code_bytes'] / 1e6:.1f} MB, vectors on host {info['vectors_on_host']} "
+        f"(borrowed {info['vectors_borrowed']})")
 
     Qb = [torch.from_numpy(Qall[i * w.nq:(i + 1) * w.nq]).to(dev) for i in range(nb)]
+    gt_n = min(w.nq, args.gt_queries)
+    t = time.perf_counter()
     Xt = torch.from_numpy(X).to(dev)
-    gt = exact_knn_gpu(Xt, Qb[0], X, Qall[:w.nq], w.k)
+    gt = exact_knn_gpu(Xt, Qb[0][:gt_n], X, Qall[:gt_n], w.k)
     del Xt
     torch.cuda.empty_cache()
-
-    # Operating point: the listed (nprobe, rerank_n) first; if none reaches
-    # recall@10 >= 0.95, wider probes and longer re-rank lists are tried, and
-    # the fastest point that reaches it is timed.
+    log(f"[{role}] exact kNN of {gt_n} queries in {time.perf_counter() - t:.1f}s")
     assign = idx.export("assign")
     gt_lists = assign[gt]
 
     def probe_recall(npb):
-        pr = idx.search_debug(Qall[:w.nq], npb, w.k, w.rerank_n, want={"probes"})["probes"]
+        pr = idx.search_debug(Qall[:gt_n], npb, w.k, w.rerank_n, want={"probes"})["probes"]
         return float(np.mean([np.isin(gl, p).mean() for gl, p in zip(gt_lists, pr)]))
 
     def eval_point(npb, R):
         ids, _ = idx.search(Qb[0], npb, w.k, R)
         torch.cuda.synchronize()
-        return recall(ids.cpu().numpy(), gt)
+        return recall(ids[:gt_n].cpu().numpy(), gt)
 
     def quick_qps(npb, R, steps=8):
         ids_ = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
@@ -338,17 +381,20 @@ def main():
         torch.cuda.synchronize()
         return w.nq * steps / (time.perf_counter() - t)
 
+    # Operating point: the listed (nprobe, rerank_n) first; if none reaches
+    # recall@10 >= 0.95, longer re-rank lists at every probe count whose probed
+    # lists hold >= 95% of the true neighbours, and the fastest point reaching
+    # it is timed.
     rec, prec = {}, {}
-    points = [(p, args.rerank or w.rerank_n) for p in ((args.nprobe,) if args.nprobe else w.nprobe)]
-    for pt in points:
+    fixed = args.nprobe and role == "headline"
+    points = [(args.nprobe, args.rerank or w.rerank_n)] if fixed else [(p, w.rerank_n) for p in w.nprobe]
+    for pt in points + (points_hint or []):
         rec[pt] = eval_point(*pt)
-        prec[pt[0]] = probe_recall(pt[0])
-        log(f"[recall] nprobe {pt[0]} rerank {pt[1]}: recall@{w.k} = {rec[pt]:.4f} "
+        prec.setdefault(pt[0], probe_recall(pt[0]))
+        log(f"[{role}] nprobe {pt[0]} rerank {pt[1]}: recall@{w.k} = {rec[pt]:.4f} "
             f"(probe recall {prec[pt[0]]:.4f})")
-    ok = [pt for pt in points if rec[pt] >= 0.95]
-    if not ok and not args.nprobe:
-        # longer re-rank lists at every probe count whose probed lists hold
-        # >= 95% of the true neighbours (listed counts first, then wider ones)
+    ok = [pt for pt in rec if rec[pt] >= 0.95]
+    if not ok and not fixed:
         top = min(w.nlist, 4096)
         wider = [p for p in (256, 512, 1024, 2048) if max(w.nprobe) < p <= top]
         for npb in list(w.nprobe) + wider:
@@ -356,45 +402,43 @@ def main():
                 prec[npb] = probe_recall(npb)
             if prec[npb] < 0.95:
                 continue
-            for R in sorted({min(3840, f * w.rerank_n) for f in (2, 5, 10, 20, 40)}):
+            for R in sorted({min(3840, f * w.rerank_n) for f in (2, 3, 4, 5, 7, 10, 15, 20, 40)}):
                 pt = (npb, R)
                 rec[pt] = eval_point(*pt)
-                log(f"[recall] nprobe {npb} rerank {R}: recall@{w.k} = {rec[pt]:.4f} "
+                log(f"[{role}] nprobe {npb} rerank {R}: recall@{w.k} = {rec[pt]:.4f} "
                     f"(probe recall {prec[npb]:.4f})")
                 if rec[pt] >= 0.95:
                     ok.append(pt)
                     break
-    if args.nprobe:
+    if fixed:
         nprobe, R = points[0]
     elif ok:
         qq = {pt: quick_qps(*pt) for pt in ok}
         nprobe, R = max(ok, key=lambda pt: qq[pt])
-        log("[choose] " + ", ".join(f"{pt}: {q:.0f} q/s" for pt, q in qq.items()))
+        log(f"[{role}] choose " + ", ".join(f"{pt}: {q:.0f} q/s" for pt, q in qq.items()))
     else:
         nprobe, R = max(rec, key=lambda pt: rec[pt])
-        log(f"[choose] no point reached recall 0.95; timing the best one {(nprobe, R)}")
+        log(f"[{role}] no point reached recall 0.95; timing the best one {(nprobe, R)}")
+
     # the autotuner picks the launch choices of each timed shape (results are
     # unchanged by construction and checked by the library)
     tuned = {}
-    loaded = 0
-    if args.tune_cache and os.path.exists(args.tune_cache):
-        loaded = idx.tune_load(args.tune_cache)
-        log(f"[autotune] {loaded} tuned shapes loaded from {args.tune_cache}")
+    cache = f"{args.tune_cache}.{role}" if args.tune_cache else ""
+    loaded = idx.tune_load(cache) if cache and os.path.exists(cache) else 0
+    if loaded:
+        log(f"[{role}] {loaded} tuned shapes loaded from {cache}")
         tuned = {"loaded_from_cache": loaded}
-    if not args.no_autotune and not loaded:
-        for pt in ([(p, w.rerank_n) for p in w.nprobe] if not args.nprobe else []) + [(nprobe, R)]:
+    elif not args.no_autotune:
+        for pt in ([(p, w.rerank_n) for p in w.nprobe] if not fixed else []) + [(nprobe, R)]:
             tuned[f"nprobe={pt[0]},rerank={pt[1]}"] = idx.autotune(Qb[0], pt[0], w.k, pt[1])
-            log(f"[autotune] {pt}: {tuned[f'nprobe={pt[0]},rerank={pt[1]}']}")
-        if args.tune_cache:
-            idx.tune_save(args.tune_cache)
-    listed_qps = {f"{p}": quick_qps(p, w.rerank_n) for p in w.nprobe} if not args.nprobe else {}
+            log(f"[{role}] autotune {pt}: {tuned[f'nprobe={pt[0]},rerank={pt[1]}']}")
+        if cache:
+            idx.tune_save(cache)
+    listed_qps = {f"{p}": quick_qps(p, w.rerank_n) for p in w.nprobe} if not fixed else {}
 
     idx.set_option("scan", {"auto": 0, "popcount": 1, "mfma": 2}[args.scan])
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
     dd = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
-    # consecutive batches alternate over a few streams (a search never waits
-    # for the host, so one batch's kernels can fill the CUs another's leave
-    # idle); each stream has its own outputs
     nst = max(1, args.streams)
     streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
     outs = [(torch.empty((w.nq, w.k), dtype=torch.int64, device=dev),
@@ -405,28 +449,28 @@ def main():
         oi, od = outs[s % nst]
         idx.search(Qb[s % nb], nprobe, w.k, R, ids=oi, dists=od, stream=st.cuda_stream)
 
+    steps = args.steps if role == "headline" else args.secondary_steps
     torch.cuda.synchronize()
     for s in range(args.warmup):
         step(s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         step(s)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_step = elapsed * 1e3 / args.steps
-    qps = w.nq * args.steps / elapsed
+    ms_step = elapsed * 1e3 / steps
+    qps = w.nq * steps / elapsed
+    log(f"[{role}] timed {steps} steps: {qps:.0f} queries/s, {ms_step:.3f} ms per batch")
     # stage times, scanned work and per-launch kernel times: the same searches
-    # again with the library's instrumentation on (events and counting kernels
-    # of their own, kept out of the timed steps above)
+    # again with the library's instrumentation on (kept out of the timed steps)
     idx.set_timing(True)
-    for s in range(min(args.steps, 10)):
+    for s in range(min(steps, 10)):
         idx.search(Qb[s % nb], nprobe, w.k, R, ids=ids, dists=dd)
     torch.cuda.synchronize()
     tm = idx.timings()
     idx.set_timing(False)
 
-    # latency per batch (one synchronised batch at a time)
     lat = []
     for s in range(args.latency_iters):
         torch.cuda.synchronize()
@@ -436,69 +480,249 @@ def main():
         lat.append((time.perf_counter() - t) * 1e3)
     p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
-    # the two scan forms at the chosen point
+    # the scan forms at the chosen point (the in-house ablation of the work
+    # schedule and of fused versus separate selection)
     variants = {}
     if not args.no_variants:
-        for name, mode in (("popcount_query_major", 1), ("mfma_list_major", 2)):
+        for name, mode in (("tuned", 0), ("query_list_items_popcount_then_merge", 1),
+                           ("list_major_work_queue", 2), ("one_item_per_query_fused_select", 3)):
             idx.set_option("scan", mode)
-            variants[name] = quick_qps(nprobe, R, steps=10)
+            variants[name] = quick_qps(nprobe, R, steps=6)
         idx.set_option("scan", 0)
-        log("[variants] " + ", ".join(f"{k_}: {v:.0f} q/s" for k_, v in variants.items()))
+        log(f"[{role}] scan forms: " + ", ".join(f"{k_}: {v:.0f} q/s" for k_, v in variants.items()))
 
-    serving = serve_compare(idx, w, args) if args.serve_rates else None
-
-    cpu = cpu_pool.run(nprobe, w.k, R) if cpu_pool else None
-    if cpu_pool:
-        cpu_pool.close()
+    # the same lists under the other estimators: the unquantised query (the
+    # paper's own precision point) and IVF-Flat (its comparison system), each
+    # at the smallest re-rank list / probe count reaching recall 0.95
+    estimators = {}
+    if not args.no_estimators:
+        grid = sorted({min(3840, f * w.rerank_n) for f in (1, 2, 3, 4, 5, 7, 10, 15, 20, 40)})
+        if w.d <= 1024:
+            idx.set_option("estimator", 1)
+            row = {"nprobe": nprobe, "points": {}}
+            for R1 in grid:
+                r1 = eval_point(nprobe, R1)
+                row["points"][str(R1)] = r1
+                if r1 >= 0.95:
+                    row.update(rerank_n=R1, recall_at_10=r1, qps=quick_qps(nprobe, R1, steps=4))
+                    break
+            estimators["unquantised_fp32_query"] = row
+            log(f"[{role}] unquantised query at nprobe {nprobe}: {row}")
+        if info["device_bytes"] and not args.no_flat and w.d <= 256:
+            idx.set_option("estimator", 2)
+            row = {"rerank_n": w.k, "points": {}}
+            top = min(w.nlist, 4096)
+            for npb in sorted({p for p in list(w.nprobe) + [256, 512, 1024, 2048] if p <= top}):
+                rf = eval_point(npb, w.k)
+                row["points"][str(npb)] = rf
+                if rf >= 0.95:
+                    row.update(nprobe=npb, recall_at_10=rf, qps=quick_qps(npb, w.k, steps=4))
+                    break
+            row["flat_bytes"] = (w.d + 3) // 4 * 4 * 4 * w.n + 4 * w.n
+            if "qps" in row:
+                row["rabitq_speedup_at_equal_recall"] = qps / row["qps"]
+            estimators["ivf_flat"] = row
+            log(f"[{role}] IVF-Flat: {row}")
+        idx.set_option("estimator", 0)
 
     ns = max(1, tm["searches"])
-    wname = w.name if not args.n else f"{w.name}/n={w.n}"  # the workload as the PMC summaries name it
-    scan_s = tm["scan_ms"] / ns * 1e-3
-    if tm["group_launches"] > 0:
-        # list-major matrix-core scan (the dominant kernel): bound by the VALU epilogue
-        launches = tm["group_launches"] / ns
-        gscan_s = tm["group_scan_ms"] / ns * 1e-3
-        gvec = tm["group_vectors"] / ns
-        achieved = gvec * EPILOGUE_OPS / gscan_s / 1e12
-        traffic = pmc_traffic("k_scan_group", f"{wname} nprobe={nprobe} rerank={R}")
-        roofline = {"kernel": "k_scan_group", "bound": "alu", "achieved": achieved,
-                    "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                    "traffic": traffic,
-                    "launches_per_step": launches,
-                    "avg_launch_ms": gscan_s * 1e3 / launches,
-                    "estimates_per_launch": gvec / launches,
-                    "read_bytes_per_launch": tm["group_read_bytes"] / ns / launches,
-                    "read_gbs": tm["group_read_bytes"] / ns / gscan_s / 1e9,
-                    "schedule_gbs_effective": gvec * (4 * ((w.d + 31) // 32) + 8) / gscan_s / 1e9,
-                    "other_scan_ms_per_step": (scan_s - gscan_s) * 1e3}
-    else:
-        launches = max(1, tm["popc_launches"]) / ns
-        achieved = tm["read_bytes"] / ns / scan_s / 1e9
-        roofline = {"kernel": "k_scan_popc", "bound": "hbm", "achieved": achieved,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": pmc_traffic("k_scan_popc",
-                                           f"{wname} nprobe={nprobe} rerank={R} scan={args.scan}"),
-                    "launches_per_step": launches,
-                    "avg_launch_ms": scan_s * 1e3 / launches,
-                    "bytes_per_launch": tm["read_bytes"] / ns / launches}
+    wname = w.name if w.n == get(w.name).n else f"{w.name}/n={w.n}"
+    roofline = roofline_of(tm, w, wname, nprobe, R, args.scan)
+    cpu = cpu_pool.run(nprobe, w.k, R) if cpu_pool else None
+    out = {
+        "value": qps, "ms_per_step": ms_step, "steps": steps,
+        "config": {"workload": wname, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,
+                   "batch": w.nq, "k": w.k, "rerank_n": R, "bq": w.bq, "rotation": args.rotation,
+                   "rerank_on": "host" if host_vectors else "gpu",
+                   "raw_vectors": "pinned host, borrowed" if host_vectors else "HBM",
+                   "streams": nst, "parallelism": "none (1 GPU)"},
+        "recall_at_10": rec[(nprobe, R)], "recall_queries": gt_n,
+        "recall_by_point": {f"nprobe={p},rerank={r}": v for (p, r), v in rec.items()},
+        "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
+        "qps_at_listed_nprobe": listed_qps, "qps_by_scan_form": variants, "autotune": tuned,
+        "p50_ms": p50, "p99_ms": p99,
+        "stage_ms": {s: tm[f"{s}_ms"] / ns for s in
+                     ("probe", "rotate", "quant", "scan", "merge", "rerank", "total")},
+        "roofline": roofline, "estimators": estimators, "cpu_baseline": cpu, "gen_s": gen_s,
+        "build_s": build_s,
+        "index_info": info,
+    }
+    return idx, X, Qall, out, (nprobe, R)
+
+
+def rerank_ablation(w, X, Qall, dev_idx, args):
+    """GPU versus host re-rank at one probe count over several rerank_n: the
+    same lists, once with the raw vectors in HBM (gather kernel) and once in
+    pinned host memory (host cores, overlapped with the GPU search)."""
+    import torch
+    from paper_2605_16007_amd import Index
+    xt = torch.empty(X.shape, dtype=torch.float32, pin_memory=True)
+    xt.numpy()[:] = X
+    c = dev_idx.export("centroids")
+    a = dev_idx.export("assign")
+    P = dev_idx.export("rotation")
+    host = Index.build(xt, w.nlist, bq=w.bq, centroids=c, rotation=P, assignment=a,
+                       vectors_on_host=True, borrow_vectors=True)
+    q = torch.from_numpy(Qall[:w.nq]).cuda()
+    out = {}
+    try:
+        for R in (100, 200, 500, 1000):
+            row = {}
+            for name, ix in (("gpu", dev_idx), ("host", host)):
+                ix.search(q, args.ablation_nprobe, w.k, R)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(5):
+                    ix.search(q, args.ablation_nprobe, w.k, R)
+                torch.cuda.synchronize()
+                row[name] = w.nq * 5 / (time.perf_counter() - t)
+            out[str(R)] = row
+            log(f"[ablation] rerank {R} at nprobe {args.ablation_nprobe}: GPU {row['gpu']:.0f} q/s, "
+                f"host {row['host']:.0f} q/s")
+    finally:
+        host.close()
+    return {"nprobe": args.ablation_nprobe, "qps_by_rerank_n": out}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--streams", type=int, default=1,
+                    help="HIP streams the timed batches alternate over (each batch whole on one)")
+    ap.add_argument("--workload", default="unit96_400m")
+    ap.add_argument("--full", action="store_true",
+                    help="the whole 400M-row workload instead of its 50M-row shard")
+    ap.add_argument("--n", type=int, default=0, help="database rows (nlist scales with them)")
+    ap.add_argument("--vectors-on-device", action="store_true",
+                    help="keep the raw vectors in HBM even where the workload puts them on the host")
+    ap.add_argument("--nprobe", type=int, default=0,
+                    help="fix nprobe (default: the fastest point reaching recall@10 >= 0.95)")
+    ap.add_argument("--rerank", type=int, default=0, help="fix rerank_n (with --nprobe)")
+    ap.add_argument("--batches", type=int, default=4, help="distinct query batches cycled")
+    ap.add_argument("--gt-queries", type=int, default=10000, help="queries with exact kNN for recall")
+    ap.add_argument("--latency-iters", type=int, default=30)
+    ap.add_argument("--kmeans-iters", type=int, default=0)
+    ap.add_argument("--kmeans-restarts", type=int, default=0)
+    ap.add_argument("--train-n", type=int, default=0)
+    ap.add_argument("--kmeans-init", choices=("kmeans++", "random"), default="",
+                    help="initial centroids of the library's k-means (default: its own, k-means++)")
+    ap.add_argument("--cpu-queries", type=int, default=128)
+    ap.add_argument("--cpu-cores", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rotation", choices=("fp32", "bf16"), default="fp32")
+    ap.add_argument("--no-autotune", action="store_true", help="time the built-in launch rule")
+    ap.add_argument("--tune-cache", default="",
+                    help="autotune cache prefix: <prefix>.<role> is loaded if it exists, else written")
+    ap.add_argument("--no-variants", action="store_true", help="skip the scan-form ablation")
+    ap.add_argument("--no-estimators", action="store_true",
+                    help="skip the unquantised-query and IVF-Flat comparisons")
+    ap.add_argument("--no-flat", action="store_true", help="build no IVF-Flat copy of the lists")
+    ap.add_argument("--scan", choices=("auto", "popcount", "mfma"), default="auto",
+                    help="force the scan form of the timed loop (auto: tuned per chunk)")
+    ap.add_argument("--secondary", default="sift10m",
+                    help="a second workload measured after the headline ('' skips it)")
+    ap.add_argument("--secondary-steps", type=int, default=20)
+    ap.add_argument("--ablation-nprobe", type=int, default=512,
+                    help="probe count of the GPU-versus-host re-rank ablation on the secondary workload")
+    ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
+                    help="Poisson arrival rates (queries/s) of the serving comparison on the "
+                         "secondary workload's index ('' skips it)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="seconds of arrivals per rate")
+    ap.add_argument("--serve-max", type=int, default=20000, help="most requests per rate")
+    ap.add_argument("--serve-warmup-s", type=float, default=0.2,
+                    help="seconds of arrivals served before each rate's measured trace")
+    ap.add_argument("--plain-max", type=int, default=3000,
+                    help="most requests of each trace replayed one query at a time")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="finish with one device-to-device copy of this size (PMC calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures the search path on one GPU only; this build runs no "
+              "multi-GPU configuration (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    from synth import get, queries
+    w = get(args.workload)
+    shard_note = None
+    n = args.n or (SHARD_ROWS if (w.name == "unit96_400m" and not args.full) else 0)
+    if n and n != w.n:
+        w = w.with_(n=n, nlist=max(1, int(round(w.nlist * n / w.n))))
+        if w.name == "unit96_400m":
+            shard_note = True
+    host_vectors = w.kind == "unit_mixture" and not args.vectors_on_device
+
+    cpu_pool = None
+    if not args.no_cpu_baseline:
+        # forked before the GPU is touched
+        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+        cpu_pool = CpuBaseline(w, queries(w, w.nq), args.cpu_queries, cores)
+
+    import torch
+    torch.cuda.set_device(0)
+    idx, X, Qall, head, (nprobe, R) = measure(w, args, host_vectors=host_vectors, role="headline",
+                                              cpu_pool=cpu_pool)
+    if cpu_pool:
+        cpu_pool.close()
+    if shard_note:
+        import psutil
+        full = get("unit96_400m")
+        ram = psutil.virtual_memory().total
+        # k-means (training rows 256 nlist) and the assignment both grow as
+        # rows x lists: x8 rows and x8 lists from the shard to the whole set
+        scale = (full.n / w.n) * (full.nlist / w.nlist)
+        head["shard"] = {
+            "of": f"{full.name}: {full.n} x {full.d}, nlist {full.nlist}",
+            "rows": w.n, "nlist": w.nlist, "host_ram_bytes": ram,
+            "full_raw_vector_bytes": full.n * full.d * 4,
+            "shard_build_s": head["build_s"],
+            "full_build_s_estimate": head["build_s"] * scale,
+            "reason": (f"the whole set needs {full.n * full.d * 4 / 1e9:.0f} GB of pinned host rows "
+                       f"(host RAM {ram / 1e9:.0f} GB) and an index build of about "
+                       f"{head['build_s'] * scale / 60:.0f} min (shard build {head['build_s']:.0f} s "
+                       f"x {scale:.0f}: k-means and assignment scale as rows x lists), beyond this "
+                       f"benchmark's few-minute budget; the shard keeps the lists' length "
+                       f"({w.n // w.nlist} vectors on average) and the batch shape"),
+        }
+        log(f"[headline] shard: {head['shard']['reason']}")
+    del X
+    idx.close()
+
+    secondary = None
+    if args.secondary:
+        w2 = get(args.secondary)
+        sargs = argparse.Namespace(**vars(args))
+        sargs.nprobe = 0
+        sargs.rerank = 0
+        sargs.gt_queries = min(args.gt_queries, w2.nq)
+        hint = [(512, 3840)] if w2.name == "sift10m" else None
+        idx2, X2, Q2, sec, _ = measure(w2, sargs, host_vectors=False, role="secondary", points_hint=hint)
+        if args.ablation_nprobe and w2.kind != "unit_mixture":
+            sec["rerank_ablation"] = rerank_ablation(w2, X2, Q2, idx2, args)
+        if args.serve_rates:
+            sec["serving"] = serve_compare(idx2, w2, args)
+        secondary = sec
+        idx2.close()
+
     if args.calibrate_copy_gib > 0:
-        nb = int(args.calibrate_copy_gib * (1 << 30)) // 4
-        a = torch.ones(nb, dtype=torch.float32, device=dev)
+        nbytes = int(args.calibrate_copy_gib * (1 << 30)) // 4
+        a = torch.ones(nbytes, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        log(f"[calibrate] copied {nb * 4} bytes device to device")
+        log(f"[calibrate] copied {nbytes * 4} bytes device to device")
         del a, b
 
     line = {
         "metric": METRIC,
-        "value": qps,
+        "value": head["value"],
         "unit": "queries/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": head["steps"],
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -509,26 +733,9 @@ def main():
                  + " / u32 popcount + fp32",
         "scan_form": args.scan,
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,
-                   "batch": w.nq, "k": w.k, "rerank_n": R, "bq": w.bq,
-                   "rotation": args.rotation,
-                   "rerank_on": "host" if args.vectors_on_host else "gpu",
-                   "streams": nst, "parallelism": "none (1 GPU)"},
-        "recall_at_10": rec[(nprobe, R)],
-        "recall_by_point": {f"nprobe={p},rerank={r}": v for (p, r), v in rec.items()},
-        "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
-        "qps_at_listed_nprobe": listed_qps,
-        "qps_by_scan_form": variants,
-        "autotune": tuned,
-        "p50_ms": p50,
-        "p99_ms": p99,
-        "stage_ms": {s: tm[f"{s}_ms"] / ns for s in
-                     ("probe", "rotate", "quant", "scan", "merge", "rerank", "total")},
-        "roofline": roofline,
-        "serving": serving,
-        "cpu_baseline": cpu,
-        "build_s": build_s,
     }
+    line.update({k_: v for k_, v in head.items() if k_ not in ("value", "ms_per_step", "steps")})
+    line["secondary"] = secondary
     print(json.dumps(line), flush=True)
 
 

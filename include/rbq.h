@@ -398,7 +398,10 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
  * RBQ_OPT_SCAN still fixes the scan form). Blocks the calling thread.
  * The table can be saved to / loaded from a text cache; its entries are keyed
  * by device architecture, d, B_q, nlist, n and the list-size histogram, and
- * only matching entries load.
+ * only matching entries load. For an index whose raw vectors are on the host,
+ * where a search runs on the GPU in sub-batches of up to a quarter of the
+ * batch while host cores re-rank the previous one, the choices are tuned
+ * (on the GPU phases alone) and stored for that sub-batch size.
  */
 typedef struct {
   int32_t scan;          /* 1 query-major popcount only; 2 list-major matrix core for the
@@ -417,7 +420,10 @@ typedef struct {
                             queries: 0 one workgroup per query scans and selects;
                             1 popcount scan per (query, probe), then a merge */
   int32_t block;         /* list-major items cover index blocks of this many
-                            micro-blocks (0: whole lists), tuned last */
+                            micro-blocks (0: whole lists), tuned after the above */
+  int32_t merge_form;    /* pool merges on 256-thread workgroups instead of 512:
+                            0 none, 1 all but the first list-major chunk's, 2 all;
+                            tuned last */
 } rbq_tune_result;
 
 rbq_status rbq_autotune(rbq_index* idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,

@@ -39,6 +39,7 @@ struct TuneCfg {
   int scan = 0, G = 64, wg_per_cu = 8, first_factor = 2, gm = 4, growth = 2;
   int early = 0;  // chunks before the list-major ones: 0 fused scan+select, 1 popcount scan + merge
   int B = 0;      // list-major items over index blocks of B micro-blocks (0: whole lists)
+  int merge = 0;  // pool merges on 256-thread workgroups: 0 none, 1 after the first list-major chunk, 2 all
 };
 
 // A device scratch area reused across calls. `done` is recorded on the stream
@@ -186,6 +187,9 @@ int64_t fit_pool_budget(const rbq_index* idx, int64_t nq, int nprobe, int k, int
                         int64_t scanned_pairs, size_t cap, int64_t lo);
 void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R, int64_t* ids,
             float* dist, hipStream_t s, const SearchIO& io);
+// Sub-batches a search with the re-rank on host cores is cut into: while the
+// host re-ranks one, the GPU searches the next.
+int host_rerank_parts(int64_t nq);
 // Phases 1-4 only: the coarse top-R of every query (nq x R sort keys) is
 // copied into cand_host, and the queries into q_host when q is on the device
 // (both pinned host memory); returns when they are there. The re-rank's input.

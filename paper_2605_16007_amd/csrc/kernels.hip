@@ -702,8 +702,9 @@ static int pow2_at_least(int n) {
 constexpr size_t kTopkLdsMax = 150u << 10;  // dynamic LDS of one selection workgroup
 
 // Sorted top-k of float scores with the row in registers (rows of up to
-// kScoreTopkCols scores); defined with the register-resident selection.
-constexpr int kScoreTopkCols = 256 * 16;
+// kScoreTopkCols scores: 16 per thread, 256 threads up to 4096 columns, 512
+// above); defined with the register-resident selection.
+constexpr int kScoreTopkCols = 512 * 16;
 static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows);
 
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
@@ -735,9 +736,14 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   });
   // pool merges: the register-resident kernel
   if (a.rowcnt && !a.sorted) {
-    RBQ_CHECK(a.k <= 512 * 32, "pool merge: running keys exceed one piece");
+    // (a row longer than one piece of NT x 32 keys is merged piece by piece)
+    const int nt = a.merge_threads == 256 ? 256 : 512;
+    RBQ_CHECK(a.k <= nt * 32, "pool merge: running keys exceed one piece");
     const size_t stage = a.k <= kMergeStageKeys ? (size_t)a.k * sizeof(uint64_t) : 0;
-    hipLaunchKernelGGL((k_pool_merge<512, 32>), dim3(rows), dim3(512), stage, s, a);
+    if (nt == 256)
+      hipLaunchKernelGGL((k_pool_merge<256, 32>), dim3(rows), dim3(256), stage, s, a);
+    else
+      hipLaunchKernelGGL((k_pool_merge<512, 32>), dim3(rows), dim3(512), stage, s, a);
     RBQ_HIP(hipGetLastError());
     return;
   }
@@ -1022,18 +1028,29 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
     uint64_t key = KEY_NONE;
     if (m < nmb) {
       const uint32_t* blk = a.L.blocks + (size_t)(mb0 + m) * rec;
-      int acc[BQT > 0 ? BQT : 8];
-      for (int t = 0; t < BQ; ++t) acc[t] = 0;
-      int pop = 0;
+      // (bit-plane counts in registers: the plane loops run over the
+      // instance's plane count, or all 8 with a guard)
+      constexpr int NBQ = BQT > 0 ? BQT : 8;
+      int acc[NBQ];
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
+      for (int t = 0; t < NBQ; ++t) acc[t] = 0;
+      int pop = 0;
+      auto word = [&](int w) __attribute__((always_inline)) {
         const uint32_t c = blk[w * 64 + lane];
         pop += __popc(c);
 #pragma unroll
-        for (int t = 0; t < BQ; ++t) acc[t] += __popc(c & planes[w * bqs + t]);
+        for (int t = 0; t < NBQ; ++t)
+          if (t < BQ) acc[t] += __popc(c & planes[w * bqs + t]);
+      };
+      if constexpr (WT > 0) {
+#pragma unroll
+        for (int w = 0; w < WT; ++w) word(w);
+      } else {
+        for (int w = 0; w < W; ++w) word(w);
       }
       int ip = 0;
-      for (int t = 0; t < BQ; ++t) ip += acc[t] << t;
+#pragma unroll
+      for (int t = 0; t < NBQ; ++t) ip += t < BQ ? acc[t] << t : 0;
       const float fadd = __uint_as_float(blk[W * 64 + lane]);
       const float fmul = __uint_as_float(blk[(W + 1) * 64 + lane]);
       const float est = rbq_estimate(rn2, vl, delta, -sumqu, ip, fadd, fmul, rbq_vx(fmul, pop, D));
@@ -1434,7 +1451,10 @@ __global__ __launch_bounds__(NT) void k_score_topk(TopkArgs a) {
 
 static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows) {
   RBQ_CHECK(a.ncols <= kScoreTopkCols && a.KP >= a.k, "score top-k: row too long");
-  hipLaunchKernelGGL((k_score_topk<256, 16>), dim3(rows), dim3(256), (size_t)a.KP * sizeof(uint64_t), s, a);
+  if (a.ncols <= 256 * 16)
+    hipLaunchKernelGGL((k_score_topk<256, 16>), dim3(rows), dim3(256), (size_t)a.KP * sizeof(uint64_t), s, a);
+  else
+    hipLaunchKernelGGL((k_score_topk<512, 16>), dim3(rows), dim3(512), (size_t)a.KP * sizeof(uint64_t), s, a);
   RBQ_HIP(hipGetLastError());
 }
 

@@ -64,6 +64,7 @@ struct TopkArgs {
   uint32_t* qthr = nullptr;
   const int32_t* rowk = nullptr;  // per-row selection size (<= k); slots past it are untouched
   bool sorted = true;          // false: the k keys in any order (pool merges)
+  int merge_threads = 512;     // pool merges: 512 or 256 threads per row (32 keys per thread)
   int KP = 0, cache_cap = 0;   // set by the launcher
 };
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows);

@@ -110,6 +110,7 @@ struct Plan {
   GroupChunks gc;  // the list-major chunks (a suffix of the probe ranks)
   int G = 64, wg_per_cu = 8;
   int B = 0;       // micro-blocks per index block of a list-major item (0: whole lists)
+  int merge = 0;   // which pool merges run on 256-thread workgroups (TuneCfg::merge)
   const rbq_debug_io* dbg = nullptr;
   std::vector<Chunk> chunks, qm_chunks;
 };
@@ -171,6 +172,7 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   P.G = idx->opt_group_size.load() > 0 ? idx->opt_group_size.load() : cfg.G;
   if (P.flat) P.G = std::min(P.G, 32);  // two 16-query tiles per IVF-Flat item
   P.B = idx->opt_block.load() >= 0 ? idx->opt_block.load() : cfg.B;
+  P.merge = cfg.merge;
   P.wg_per_cu = cfg.wg_per_cu;
   // scan form per chunk of probe ranks: query-major (1) everywhere, or the
   // list-major MFMA scan for every chunk whose (query, probe) pairs number at
@@ -623,6 +625,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         }
       }
       ma.max_extra = R * ch.pn;
+      ma.merge_threads = P.merge == 2 ? 256 : 512;
       launch_row_topk(s, ma, (int)nq);
     };
     int lm_chunk = 0;  // index of the next list-major chunk
@@ -680,6 +683,9 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         RBQ_HIP(hipGetLastError());
       }
       ma.max_extra = (int)pool_cap;
+      // (the first list-major chunk's pools, filled before any threshold,
+      // are the long rows; later ones mostly fit one 256-thread piece)
+      ma.merge_threads = (P.merge == 2 || (P.merge == 1 && c > 0)) ? 256 : 512;
       launch_row_topk(s, ma, (int)nq);
     };
     FusedArgs fa;
@@ -869,7 +875,7 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
   const bool qdev = is_device_ptr(q);
   const bool ids_dev = ids && is_device_ptr(ids), dist_dev = dist && is_device_ptr(dist);
   const rbq_debug_io* dbg = io.dbg;
-  const int parts = dbg ? 1 : (nq >= 2048 ? 4 : (nq >= 256 ? 2 : 1));
+  const int parts = dbg ? 1 : host_rerank_parts(nq);
   const int64_t sb = ceil_div(nq, (int64_t)parts);
   const bool stage_out = !ids || !dist || ids_dev || dist_dev;
   size_t off = 0;
@@ -957,6 +963,8 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
 }
 
 }  // namespace
+
+int host_rerank_parts(int64_t nq) { return nq >= 2048 ? 4 : (nq >= 256 ? 2 : 1); }
 
 void search_candidates(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
                        uint64_t* cand_host, float* q_host, hipStream_t s, const SearchIO& io) {

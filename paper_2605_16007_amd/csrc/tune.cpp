@@ -69,6 +69,9 @@ bool tune_lookup(rbq_index* idx, int64_t nq, int nprobe, int R, TuneCfg* out) {
 void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
               rbq_tune_result* out) {
   RBQ_HIP(hipSetDevice(idx->device));
+  // With the re-rank on host cores a search runs on the GPU in sub-batches:
+  // the choices are tuned, and stored, for the sub-batch (its first queries)
+  if (idx->vectors_on_host) nq = ceil_div(nq, (int64_t)host_rerank_parts(nq));
   const int d = idx->d;
   std::vector<TuneCfg> cands;
   cands.push_back(TuneCfg{1, 64, 8, 2, 4, 2, 0});
@@ -194,6 +197,24 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
         }
       }
     }
+    // then which pool merges run on 256-thread workgroups
+    {
+      const TuneCfg base = best;
+      for (int mg : {1, 2}) {
+        TuneCfg c = base;
+        c.merge = mg;
+        const float ms = time_cfg(&c, got_ids, got_d);
+        ++trials;
+        const bool differs = host_rr ? got_c != ref_c
+                                     : (got_ids != ref_ids ||
+                                        std::memcmp(got_d.data(), ref_d.data(), got_d.size() * 4) != 0);
+        if (differs) fail(RBQ_EDEVICE, "autotune: 256-thread pool merges returned different results");
+        if (ms < best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+    }
     {
       std::lock_guard<std::mutex> g(idx->tune_mu);
       idx->tune[tune_key(nq, nprobe, R)] = best;
@@ -208,6 +229,7 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
       out->growth = best.growth;
       out->early_form = best.early;
       out->block = best.B;
+      out->merge_form = best.merge;
       out->ms = best_ms;
       out->ms_default = ms_default;
       out->trials = (int32_t)trials;
@@ -244,13 +266,13 @@ void tune_save(rbq_index* idx, const char* path) {
   {
     std::ofstream o(tmp, std::ios::trunc);
     RBQ_CHECK(o.good(), "cannot write the autotune cache");
-    o << "# librbq autotune cache v5: signature key scan G wg_per_cu first_factor gm growth early block\n";
+    o << "# librbq autotune cache v6: signature key scan G wg_per_cu first_factor gm growth early block merge\n";
     for (const auto& l : keep) o << l << "\n";
     std::lock_guard<std::mutex> g(idx->tune_mu);
     for (const auto& kv : idx->tune)
       o << sig << " " << kv.first << " " << kv.second.scan << " " << kv.second.G << " "
         << kv.second.wg_per_cu << " " << kv.second.first_factor << " " << kv.second.gm << " "
-        << kv.second.growth << " " << kv.second.early << " " << kv.second.B << "\n";
+        << kv.second.growth << " " << kv.second.early << " " << kv.second.B << " " << kv.second.merge << "\n";
     RBQ_CHECK(o.good(), "writing the autotune cache failed");
   }
   RBQ_CHECK(std::rename(tmp.c_str(), path) == 0, "cannot replace the autotune cache");
@@ -270,13 +292,14 @@ int tune_load(rbq_index* idx, const char* path) {
     uint64_t key = 0;
     TuneCfg c;
     if (!(ls >> s >> key >> c.scan >> c.G >> c.wg_per_cu >> c.first_factor >> c.gm >> c.growth >> c.early >>
-          c.B))
+          c.B >> c.merge))
       continue;
     if (s != sig) continue;
     const bool ok = (c.scan == 1 || c.scan == 2) && c.G >= 1 && c.G <= 64 && c.wg_per_cu >= 1 &&
                     c.wg_per_cu <= 64 && c.first_factor >= 1 && c.first_factor <= 64 &&
                     c.gm >= 0 && c.gm <= (1 << 20) && c.growth >= 2 && c.growth <= 16 &&
-                    (c.early == 0 || c.early == 1) && c.B >= 0 && c.B <= (1 << 20);
+                    (c.early == 0 || c.early == 1) && c.B >= 0 && c.B <= (1 << 20) && c.merge >= 0 &&
+                    c.merge <= 2;
     RBQ_CHECK(ok, "autotune cache entry out of range");
     got[key] = c;
     ++loaded;

@@ -89,7 +89,8 @@ class TuneResult(C.Structure):
     _fields_ = [("scan", C.c_int32), ("group_size", C.c_int32), ("wg_per_cu", C.c_int32),
                 ("first_factor", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
                 ("trials", C.c_int32), ("chunk_group_min", C.c_int32),
-                ("growth", C.c_int32), ("early_form", C.c_int32), ("block", C.c_int32)]
+                ("growth", C.c_int32), ("early_form", C.c_int32), ("block", C.c_int32),
+                ("merge_form", C.c_int32)]
 
 
 class RbqError(RuntimeError):

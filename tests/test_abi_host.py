@@ -114,7 +114,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(rbq.ServerParams) == 6 * 4 + 8 + 8 * 4
     assert C.sizeof(rbq.ServerStats) == 8 * 8
     assert C.sizeof(rbq.ReplayIO) == 8 * 8 + 8 + 4 + 4
-    assert C.sizeof(rbq.TuneResult) == 4 * 4 + 2 * 4 + 4 + 4 + 4 + 4 + 4
+    assert C.sizeof(rbq.TuneResult) == 4 * 4 + 2 * 4 + 4 + 4 + 4 + 4 + 4 + 4
 
 
 def test_tuning_null_arguments():

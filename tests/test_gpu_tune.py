@@ -38,7 +38,8 @@ def test_autotune_keeps_results(tcase, nprobe, R):
     _say(f"[tune] chose {r}")
     # 361 launch choices, then four index-block sizes for a list-major winner
     assert r["scan"] in (1, 2) and r["chunk_group_min"] in (0, 4, 16, 64)
-    assert r["trials"] == 361 + (4 if r["scan"] == 2 else 0)
+    assert r["trials"] == 361 + (4 if r["scan"] == 2 else 0) + 2
+    assert r["merge_form"] in (0, 1, 2)
     assert r["block"] in (0, 8, 16, 32, 64) and (r["scan"] == 2 or r["block"] == 0)
     assert r["growth"] in (2, 3, 4, 6, 8)
     assert r["early_form"] in (0, 1)
@@ -81,8 +82,9 @@ def test_tune_cache_round_trip(tcase):
         finally:
             diff.close()
         with open(path, "a") as f:
-            # signature, key, scan 7 (out of range), G, wg_per_cu, first_factor, gm, growth, early, block
-            f.write(lines[0].rsplit(" ", 10)[0] + " 5 7 32 8 2 4 2 0 0\n")
+            # signature, key, scan 7 (out of range), G, wg_per_cu, first_factor, gm, growth, early,
+            # block, merge
+            f.write(lines[0].rsplit(" ", 11)[0] + " 5 7 32 8 2 4 2 0 0 0\n")
         with pytest.raises(RbqError):
             lib.tune_load(path)
     lib.tune_clear()
