@@ -39,7 +39,7 @@ extern "C" {
 typedef enum {
   RBQ_OK = 0,
   RBQ_EINVAL = -1,   /* bad argument; nothing was changed */
-  RBQ_ENOMEM = -2,   /* device or pinned host allocation failed */
+  RBQ_ENOMEM = -2,   /* device or host allocation failed */
   RBQ_EDEVICE = -3,  /* a HIP runtime call failed */
   RBQ_ESTATE = -4,   /* object in the wrong state (e.g. server stopped) */
   RBQ_EAGAIN = -5    /* try again later (serving queue full) */
@@ -61,18 +61,21 @@ typedef struct {
   const int32_t* assignment; /* optional host n list ids in [0,nlist); NULL:
                               nearest centroid */
   int32_t vectors_on_host; /* where the raw vectors of the exact re-rank live
-                              (Sec. 3.3.4): 0 HBM (GPU re-rank); 1 pinned host
-                              memory (re-rank on host cores); -1 (default)
-                              automatic: HBM when, with the index built, they
-                              leave at least max(8 GiB, 1/8 of the device) of
-                              device memory free, else pinned host memory */
+                              (Sec. 3.3.4): 0 HBM (GPU re-rank); 1 host memory
+                              (re-rank on host cores; the index's own copy is
+                              2 MiB-aligned and advised for transparent huge
+                              pages, not pinned: only host threads read it);
+                              -1 (default) automatic: HBM when, with the index
+                              built, they leave at least max(8 GiB, 1/8 of the
+                              device) of device memory free, else host memory */
   int32_t host_threads;    /* host re-rank threads (0 = hardware concurrency) */
   int32_t borrow_vectors;  /* 1: when the vectors end on the host, the index
                               keeps the caller's rows instead of a copy: x must
-                              then be pinned host memory (hipHostMalloc) holding
+                              then be host memory (pageable or pinned) holding
                               n*d float32, and the caller keeps it unchanged
-                              until rbq_free_index. EINVAL with
-                              vectors_on_host = 0 or a pageable or device x */
+                              until rbq_free_index. Rows backed by 2 MiB pages
+                              (madvise MADV_HUGEPAGE) re-rank fastest. EINVAL
+                              with vectors_on_host = 0 or a device x */
   int32_t ivf_flat;        /* 1: also keep every list's full-precision vectors
                               in HBM, in list order (d <= 256), for the IVF-Flat
                               scan (RBQ_OPT_ESTIMATOR 2, the comparison system

@@ -260,8 +260,8 @@ rbq_index* load_index(const char* path) {
   launch_rotate_rows_f64(nullptr, idx->C.as<float>(), ld, idx->Pt.as<float>(), ld, nlist, d,
                          idx->Crot.as<float>(), ld, idx->cnorm.as<float>());
   if (idx->vectors_on_host) {
-    RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&idx->hostX), X.size() * 4, hipHostMallocDefault));
-    std::memcpy(idx->hostX, X.data(), X.size() * 4);
+    idx->hostX = host_rows_alloc(X.size() * 4, &idx->hostX_mapped);
+    host_rows_fill(idx->hostX, X.data(), X.size(), 8);
   } else {
     idx->X.alloc((size_t)h.n * ld * 4);
     if (ld != d) RBQ_HIP(hipMemset(idx->X.p, 0, idx->X.bytes));
@@ -303,7 +303,7 @@ rbq_status rbq_build_index(const float* x, int64_t n, int32_t d, const rbq_build
   if (p->ivf_flat && d > 256) return invalid("ivf_flat supports d <= 256");
   if (p->borrow_vectors) {
     if (p->vectors_on_host == 0) return invalid("borrow_vectors needs the vectors on the host (vectors_on_host 1 or -1)");
-    if (!rbq::is_pinned_host_ptr(x)) return invalid("borrow_vectors needs x in pinned host memory");
+    if (rbq::is_device_ptr(x)) return invalid("borrow_vectors needs x in host memory, not device memory");
   }
   for (int r : p->reserved)
     if (r != 0) return invalid("reserved fields must be zero");

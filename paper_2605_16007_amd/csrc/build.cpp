@@ -1,8 +1,14 @@
 // Index construction (Sec. 3.1.1): k-means centroids (Phases 1-2: random
 // k-means++ seeding, GPU assignment, host centroid update), assignment of every
 // vector, random orthogonal P, list layout, and the RaBitQ encoding (Phase 3).
+#include <sys/mman.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 
@@ -41,14 +47,38 @@ bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-bool is_pinned_host_ptr(const void* p) {
-  if (!p) return false;
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
+// The host re-rank gathers one random row per candidate, so its rate is set by
+// TLB reach more than by bandwidth: the rows live in anonymous memory aligned
+// to and advised for 2 MiB transparent huge pages. Only host threads read
+// them, so they are not pinned (pinned pages stay 4 KiB).
+constexpr size_t kHugePage = size_t(2) << 20;
+
+float* host_rows_alloc(size_t bytes, size_t* mapped) {
+  const size_t len = (std::max<size_t>(bytes, 1) + kHugePage - 1) / kHugePage * kHugePage;
+  void* raw = mmap(nullptr, len + kHugePage, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+  if (raw == MAP_FAILED) fail(RBQ_ENOMEM, "host rows: mmap of " + std::to_string(len) + " bytes failed");
+  const uintptr_t b = reinterpret_cast<uintptr_t>(raw);
+  const uintptr_t a = (b + kHugePage - 1) & ~(uintptr_t)(kHugePage - 1);
+  if (a > b) munmap(raw, a - b);  // trim to a 2 MiB-aligned range of len bytes
+  if (a + len < b + len + kHugePage) munmap(reinterpret_cast<void*>(a + len), b + kHugePage - a);
+  (void)madvise(reinterpret_cast<void*>(a), len, MADV_HUGEPAGE);  // advice only
+  *mapped = len;
+  return reinterpret_cast<float*>(a);
+}
+
+void host_rows_free(float* p, size_t mapped) {
+  if (p && mapped) munmap(p, mapped);
+}
+
+void host_rows_fill(float* dst, const float* src, size_t count, int threads) {
+  const size_t nt = (size_t)std::max(1, threads);
+  const size_t per = std::max<size_t>(1 << 20, (count + nt - 1) / nt);
+  std::vector<std::thread> ts;
+  for (size_t o = 0; o < count; o += per) {
+    const size_t m = std::min(per, count - o);
+    ts.emplace_back([=] { std::memcpy(dst + o, src + o, m * sizeof(float)); });
   }
-  return a.type == hipMemoryTypeHost;
+  for (auto& t : ts) t.join();
 }
 
 std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes) {
@@ -125,6 +155,29 @@ void upload_rows(float* dst, int ld, const float* src, int d, int64_t n, hipStre
 }
 
 namespace {
+
+// Build progress on stderr when the environment sets RBQ_LOG to a value other
+// than 0 (a 400M-row build runs for minutes inside one call).
+bool build_log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("RBQ_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+void build_log(const char* fmt, ...) {
+  if (!build_log_on()) return;
+  static const auto t0 = std::chrono::steady_clock::now();
+  const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  char msg[256];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[rbq build %8.1fs] %s\n", t, msg);
+  std::fflush(stderr);
+}
 
 struct StreamGuard {
   hipStream_t s = nullptr;
@@ -247,9 +300,12 @@ std::vector<float> kmeans_gpu(const float* Xd, int64_t n, int d, int ld, int nli
       RBQ_HIP(hipMemcpyAsync(hC.data(), dC.p, hC.size() * sizeof(float), hipMemcpyDeviceToHost, s));
       RBQ_HIP(hipStreamSynchronize(s));
     }
+    build_log("k-means restart %d of %d: %lld training rows, %d lists, initial centroids set", rs + 1, restarts,
+              (long long)tn, nlist);
     prev.clear();
     for (int it = 0; it < iters; ++it) {
-      assign_train();
+      const double o = assign_train();
+      build_log("k-means restart %d iteration %d of %d: objective %.6g", rs + 1, it + 1, iters, o);
       if (!prev.empty() && prev == a) break;
       lloyd_update(hT.data(), tn, d, ld, a.data(), dist.data(), nlist, hC.data());
       prev = a;
@@ -289,6 +345,7 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
   Xd.alloc((size_t)n * ld * sizeof(float));
   if (ld != d) RBQ_HIP(hipMemsetAsync(Xd.p, 0, Xd.bytes, s));
   upload_rows(Xd.as<float>(), ld, x, d, n, s);
+  build_log("%lld x %d rows staged on the device", (long long)n, d);
   {
     DevBuf bad;
     bad.alloc(sizeof(unsigned));
@@ -355,8 +412,17 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
   } else {
     DevBuf keys;
     keys.alloc(n * sizeof(uint64_t));
-    launch_assign_argmin(s, Xd.as<float>(), ld, idx->C.as<float>(), ld, idx->cnorm.as<float>(),
-                         (int)n, nlist, ld, keys.as<uint64_t>());
+    // in launches of 16M rows (each a few seconds at the largest list counts)
+    const int64_t step = int64_t(1) << 24;
+    for (int64_t r0 = 0; r0 < n; r0 += step) {
+      const int64_t m = std::min(step, n - r0);
+      launch_assign_argmin(s, Xd.as<float>() + (size_t)r0 * ld, ld, idx->C.as<float>(), ld,
+                           idx->cnorm.as<float>(), (int)m, nlist, ld, keys.as<uint64_t>() + r0);
+      if (build_log_on()) {
+        RBQ_HIP(hipStreamSynchronize(s));
+        build_log("assignment: %lld of %lld rows", (long long)(r0 + m), (long long)n);
+      }
+    }
     std::vector<uint64_t> hk(n);
     RBQ_HIP(hipMemcpyAsync(hk.data(), keys.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     RBQ_HIP(hipStreamSynchronize(s));
@@ -410,6 +476,10 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
                   idx->pos2id.as<int32_t>(), dmb.as<int32_t>(), m0, std::min(nmb, m0 + step), d, W,
                   idx->blocks.as<uint32_t>(), idx->nx.as<float>(), idx->alpha.as<float>());
 
+  if (build_log_on()) {
+    RBQ_HIP(hipStreamSynchronize(s));
+    build_log("encoded %lld micro-blocks", (long long)nmb);
+  }
   if (p.ivf_flat) {  // the lists' full-precision rows, for the IVF-Flat scan
     idx->flat.alloc(std::max<int64_t>(1, nmb) * (int64_t)(flat_dp(d) + 1) * MB * sizeof(float));
     launch_flat_fill(s, Xd.as<float>(), ld, idx->pos2id.as<int32_t>(), nmb, d, idx->flat.as<float>());
@@ -425,16 +495,20 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
   }
   if (idx->vectors_on_host) {
     if (p.borrow_vectors) {
-      idx->hostX = const_cast<float*>(x);  // the caller's pinned rows
+      idx->hostX = const_cast<float*>(x);  // the caller's host rows
       idx->hostX_owned = false;
     } else {
-      RBQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&idx->hostX), (size_t)n * d * sizeof(float),
-                            hipHostMallocDefault));
-      if (ld == d)
-        RBQ_HIP(hipMemcpyAsync(idx->hostX, Xd.p, (size_t)n * d * sizeof(float), hipMemcpyDeviceToHost, s));
-      else
+      const size_t count = (size_t)n * d;
+      idx->hostX = host_rows_alloc(count * sizeof(float), &idx->hostX_mapped);
+      if (!is_device_ptr(x)) {
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        host_rows_fill(idx->hostX, x, count, std::min(hw, 16));
+      } else if (ld == d) {
+        RBQ_HIP(hipMemcpyAsync(idx->hostX, Xd.p, count * sizeof(float), hipMemcpyDeviceToHost, s));
+      } else {
         RBQ_HIP(hipMemcpy2DAsync(idx->hostX, d * sizeof(float), Xd.p, ld * sizeof(float),
                                  d * sizeof(float), n, hipMemcpyDeviceToHost, s));
+      }
       RBQ_HIP(hipStreamSynchronize(s));
     }
     Xd.reset();
@@ -464,5 +538,5 @@ void compact_raw_vectors(rbq_index* idx, hipStream_t s) {
 rbq_index::~rbq_index() {
   pool.reset();
   for (auto& pf : pinned_free) (void)hipHostFree(pf.first);
-  if (hostX && hostX_owned) (void)hipHostFree(hostX);
+  if (hostX && hostX_owned) rbq::host_rows_free(hostX, hostX_mapped);
 }

@@ -108,7 +108,8 @@ struct rbq_index {
   std::vector<float> hP;          // d x d row-major
   std::vector<int32_t> h_assign;  // n
   std::vector<int32_t> h_list_len, h_list_mb, h_pos2id;
-  float* hostX = nullptr;         // pinned n x d when vectors_on_host
+  float* hostX = nullptr;         // n x d host rows when vectors_on_host
+  size_t hostX_mapped = 0;        // bytes mapped for the index's own rows
   bool hostX_owned = true;        // false: the caller's rows (borrow_vectors)
 
   // options (rbq_set_option) and device facts
@@ -153,7 +154,11 @@ std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes);
 void ws_release(rbq_index* idx, std::unique_ptr<Workspace> ws, hipStream_t s);
 
 bool is_device_ptr(const void* p);
-bool is_pinned_host_ptr(const void* p);
+// Host rows of the CPU re-rank: 2 MiB-aligned anonymous memory advised for
+// transparent huge pages (not pinned); filled by several threads.
+float* host_rows_alloc(size_t bytes, size_t* mapped);
+void host_rows_free(float* p, size_t mapped);
+void host_rows_fill(float* dst, const float* src, size_t count, int threads);
 void upload_rows(float* dst, int ld, const float* src, int d, int64_t n, hipStream_t s);
 
 rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params& p);

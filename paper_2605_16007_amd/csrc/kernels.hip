@@ -997,8 +997,7 @@ __device__ void sel_compact(uint64_t* sel, int cap, int R, int* s_n, uint64_t* s
 template <int WT, int BQT, bool DUMP>
 __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
   extern __shared__ uint64_t sel[];
-  __shared__ int s_n;
-  __shared__ uint64_t s_thr;
+  __shared__ uint32_t s_cnt[3];  // appends of round r counted in s_cnt[r % 3]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int W = WT > 0 ? WT : a.L.W;
   const int BQ = BQT > 0 ? BQT : a.Q.bqs;
@@ -1017,17 +1016,42 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
   const float rn2 = sc.x, vl = sc.y, delta = sc.z;
   const int sumqu = (int)sc.w;
   const int D = a.L.d;
-  if (tid == 0) {
-    s_n = 0;
-    s_thr = a.qthr ? ((static_cast<uint64_t>(a.qthr[i]) << 32) | 0xFFFFFFFFull) : KEY_NONE;
-  }
-  __syncthreads();
+  if (tid == 0) s_cnt[0] = s_cnt[1] = s_cnt[2] = 0u;
+  // the threshold key (the same in every thread; lowered by each compaction)
+  uint64_t thr = a.qthr ? ((static_cast<uint64_t>(a.qthr[i]) << 32) | 0xFFFFFFFFull) : KEY_NONE;
   const size_t rec = (size_t)(W + 2) * 64;
+  // For the fixed word counts a micro-block's words (codes, then the two
+  // factor rows) are loaded into registers one round ahead, so the next
+  // block's loads are in flight while this one is computed.
+  constexpr bool PF = WT > 0 && WT <= 8;
+  constexpr int NR = PF ? WT + 2 : 1;
+  uint32_t nx[NR];
+  auto fetch = [&](int m) __attribute__((always_inline)) {
+    const uint32_t* blk = a.L.blocks + (size_t)(mb0 + m) * rec;
+#pragma unroll
+    for (int w = 0; w < NR; ++w) nx[w] = blk[w * 64 + lane];
+  };
+  if (PF && wave < nmb) fetch(wave);
+  __syncthreads();  // s_cnt cleared
+  // buffer fill (the same value in every thread) and round number: round r
+  // appends behind the fill through s_cnt[r % 3]; the counter of round r + 1
+  // is cleared during round r (its last readers, after round r - 2's
+  // barrier, are all past round r - 1's), so one barrier per round gives
+  // every thread the same fill
+  int fill = 0, rr = 0;
   for (int base = 0; base < nmb; base += 4) {
     const int m = base + wave;
+    const int par = rr % 3;
+    if (tid == 0) s_cnt[(rr + 1) % 3] = 0u;
     uint64_t key = KEY_NONE;
     if (m < nmb) {
       const uint32_t* blk = a.L.blocks + (size_t)(mb0 + m) * rec;
+      uint32_t cur[NR];
+      if constexpr (PF) {
+#pragma unroll
+        for (int w = 0; w < NR; ++w) cur[w] = nx[w];
+        if (m + 4 < nmb) fetch(m + 4);
+      }
       // (bit-plane counts in registers: the plane loops run over the
       // instance's plane count, or all 8 with a guard)
       constexpr int NBQ = BQT > 0 ? BQT : 8;
@@ -1036,7 +1060,7 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
       for (int t = 0; t < NBQ; ++t) acc[t] = 0;
       int pop = 0;
       auto word = [&](int w) __attribute__((always_inline)) {
-        const uint32_t c = blk[w * 64 + lane];
+        const uint32_t c = PF ? cur[w] : blk[w * 64 + lane];
         pop += __popc(c);
 #pragma unroll
         for (int t = 0; t < NBQ; ++t)
@@ -1051,8 +1075,8 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
       int ip = 0;
 #pragma unroll
       for (int t = 0; t < NBQ; ++t) ip += t < BQ ? acc[t] << t : 0;
-      const float fadd = __uint_as_float(blk[W * 64 + lane]);
-      const float fmul = __uint_as_float(blk[(W + 1) * 64 + lane]);
+      const float fadd = __uint_as_float(PF ? cur[NR - 2] : blk[W * 64 + lane]);
+      const float fmul = __uint_as_float(PF ? cur[NR - 1] : blk[(W + 1) * 64 + lane]);
       const float est = rbq_estimate(rn2, vl, delta, -sumqu, ip, fadd, fmul, rbq_vx(fmul, pop, D));
       const int v = (m << 6) + lane;
       if (v < len) {
@@ -1063,22 +1087,28 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
         }
       }
     }
-    const uint64_t thr = s_thr;
     const bool pass = key < thr;
     const uint64_t mask = __ballot(pass);
     if (mask) {
-      int off = 0;
-      if (lane == 0) off = atomicAdd(&s_n, (int)__popcll(mask));
+      uint32_t off = 0;
+      if (lane == 0) off = (uint32_t)fill + atomicAdd(&s_cnt[par], (uint32_t)__popcll(mask));
       off = __shfl(off, 0);
-      if (pass) sel[off + (int)lane_prefix(mask)] = key;
+      if (pass) sel[off + lane_prefix(mask)] = key;
     }
     __syncthreads();
-    const int nn = s_n;
-    __syncthreads();  // every thread has read the count before the next appends
-    if (nn > cap - 256) sel_compact(sel, cap, R, &s_n, &s_thr);
+    fill += (int)s_cnt[par];
+    ++rr;
+    if (fill > cap - 256) {  // the next round could overflow: keep the best R
+      for (int t = fill + tid; t < cap; t += 256) sel[t] = KEY_NONE;
+      __syncthreads();
+      bitonic_sort_lds(sel, cap);  // (ends with a barrier)
+      if (fill >= R) {
+        thr = sel[R - 1];
+        fill = R;
+      }
+    }
   }
-  __syncthreads();
-  const int n = s_n;
+  const int n = fill;
   if (n > R) {  // keep the best R (an item with at most R survivors keeps them all, unsorted)
     int P = 2;
     while (P < n) P <<= 1;

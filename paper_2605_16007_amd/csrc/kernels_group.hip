@@ -26,7 +26,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int GMAX = 64;   // queries per item (four 16-query MFMA tiles)
 constexpr int KSMAX = 4;   // 64-dimension MFMA steps (D <= 256)
-constexpr int STAGE = 512; // survivors staged per wave before a flush
+constexpr int STAGE = 512; // candidates staged per wave before a flush
 
 // ---- inverted map of the list-major chunks' pairs: list -> pairs ----------
 // Built once per search for all list-major chunks (a suffix of the probe
@@ -233,8 +233,8 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   __shared__ uint32_t sCode[4][CW][64];      // per wave: the micro-block's code words
   __shared__ __align__(16) float sVx[4][64], sAdd[4][64], sMul[4][64];
   __shared__ __align__(16) int32_t sPop[QB == QB_OFFSET ? 4 : 1][64];  // 128 pop per vector
-  // per wave: survivors as (float bits of d_hat^2 << 32) | (query slot << 26 |
-  // position in the list)
+  // per wave: candidates that passed the scan's test, as (float bits of the
+  // tested value << 32) | (query slot << 26 | position in the list)
   __shared__ uint64_t sStage[4][STAGE];
   __shared__ uint32_t sFcnt[4][GMAX], sFbase[4][GMAX];  // per wave: flush counts and bases
   __shared__ int32_t sItem;
@@ -246,16 +246,29 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
   const int D = a.L.d;
   const int Wq = W * 32;  // qu bytes per pair
   int stage_n = 0;  // wave-uniform fill of this wave's stage
-  // Moves the staged survivors to their queries' pools: the entries are
-  // counted per query slot in LDS, each slot reserves its range with one
-  // global atomic, and every entry is written at its slot's base plus its
-  // rank (ids looked up lane-parallel).
+  // Moves the staged candidates to their queries' pools. First each entry
+  // forms d_hat^2 (QB_F8 staged the value without ||r||^2) and takes the
+  // exact test against its query's threshold; the passing entries are counted
+  // per query slot in LDS, each slot reserves its range with one global
+  // atomic, and every entry is written at its slot's base plus its rank (ids
+  // looked up lane-parallel).
   int list_pos0 = 0;  // first position of the item's list
   auto flush = [&](int nst) {
-    if (nst == 0) return;
     sFcnt[wave][lane] = 0u;
     __builtin_amdgcn_wave_barrier();
-    for (int e = lane; e < nst; e += 64) atomicAdd(&sFcnt[wave][(uint32_t)sStage[wave][e] >> 26], 1u);
+    for (int e = lane; e < nst; e += 64) {
+      const uint64_t kp = sStage[wave][e];
+      const uint32_t lo = (uint32_t)kp;
+      const int q = (int)(lo >> 26);
+      const float v = __uint_as_float((uint32_t)(kp >> 32));
+      const float est = F8 ? v + sSc[q].x : v;  // d_hat^2, as every scan forms it
+      if (est <= sThr[q]) {
+        atomicAdd(&sFcnt[wave][q], 1u);
+        sStage[wave][e] = ((uint64_t)__float_as_uint(est) << 32) | lo;
+      } else {
+        sStage[wave][e] = ~0ull;
+      }
+    }
     __builtin_amdgcn_wave_barrier();
     const uint32_t c = sFcnt[wave][lane];
     sFbase[wave][lane] = c ? atomicAdd(&a.pcnt[sQ[lane]], c) : 0u;
@@ -263,17 +276,19 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
     __builtin_amdgcn_wave_barrier();
     for (int e = lane; e < nst; e += 64) {
       const uint64_t kp = sStage[wave][e];
-      const uint32_t lo = (uint32_t)kp;
-      const int q = (int)(lo >> 26);
-      const int qi = sQ[q];
-      const uint32_t slot = sFbase[wave][q] + atomicAdd(&sFcnt[wave][q], 1u);
-      const int id = a.L.pos2id[list_pos0 + (int)(lo & 0x3FFFFFFu)];
-      const uint64_t key = ((uint64_t)ord_f32(__uint_as_float((uint32_t)(kp >> 32))) << 32) | (uint32_t)id;
-      if (slot < (uint32_t)a.cap) {
-        a.pool[(int64_t)qi * a.pool_ld + a.R + slot] = key;
-      } else {
-        a.overflow[qi] = 1u;
-        *a.any_overflow = 1u;
+      if (kp != ~0ull) {
+        const uint32_t lo = (uint32_t)kp;
+        const int q = (int)(lo >> 26);
+        const int qi = sQ[q];
+        const uint32_t slot = sFbase[wave][q] + atomicAdd(&sFcnt[wave][q], 1u);
+        const int id = a.L.pos2id[list_pos0 + (int)(lo & 0x3FFFFFFu)];
+        const uint64_t key = ((uint64_t)ord_f32(__uint_as_float((uint32_t)(kp >> 32))) << 32) | (uint32_t)id;
+        if (slot < (uint32_t)a.cap) {
+          a.pool[(int64_t)qi * a.pool_ld + a.R + slot] = key;
+        } else {
+          a.overflow[qi] = 1u;
+          *a.any_overflow = 1u;
+        }
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -455,21 +470,23 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
         for (int n = 0; n < GT; ++n) {
           if (n >= nt) break;
           // QB_F8: the estimate without ||r||^2 is tested against the
-          // query's bound on it; the lanes that pass form the estimate and
-          // test it exactly
+          // query's bound on it; the lanes that pass are staged, and the
+          // flush forms the estimate and tests it exactly
           float part[4];
+          bool ok[4];      // this lane's value may pass, per result row
           uint64_t pm[4];  // the lanes that may pass, per result row
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             if constexpr (F8) {
               part[r] = rbq_estimate_part(qvl[n], qdelta[n], acc[n][r], fadd[r], fmul[r], vxr[r]);
               // NaN (padding lanes, empty slots) never passes
-              pm[r] = __builtin_amdgcn_ballot_w64(part[r] <= qbound[n]);
+              ok[r] = part[r] <= qbound[n];
             } else {  // (the signed-byte forms test the estimate itself: fewer registers)
               const int g = QB == QB_DOUBLE ? acc[n][r] : (acc[n][r] << 1) + qneg[n];
               part[r] = rbq_estimate_g(qrn2[n], qvl[n], qdelta[n], g, fadd[r], fmul[r], vxr[r]);
-              pm[r] = __builtin_amdgcn_ballot_w64(part[r] <= qthr[n]);
+              ok[r] = part[r] <= qthr[n];
             }
+            pm[r] = __builtin_amdgcn_ballot_w64(ok[r]);
             if constexpr (DUMP) {
               const int q = 16 * n + (lane & 15);
               const uint32_t pos = rel0 + (uint32_t)r;
@@ -489,20 +506,17 @@ __global__ __launch_bounds__(256) void k_scan_group(GroupArgs a) {
               }
             }
           }
-          if (pm[0] | pm[1] | pm[2] | pm[3]) {  // stage the survivors of this tile
+          if (pm[0] | pm[1] | pm[2] | pm[3]) {  // stage this tile's candidates
             const uint32_t tag = rel0 | ((uint32_t)(16 * n + (lane & 15)) << 26);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               if (pm[r]) {
-                const float est = F8 ? part[r] + qrn2[n] : part[r];  // d_hat^2, as every scan forms it
-                const bool pass = est <= qthr[n];
-                const uint64_t me = __builtin_amdgcn_ballot_w64(pass);
-                if (pass) {
+                if (ok[r]) {
                   const uint32_t e = __builtin_amdgcn_mbcnt_hi(
-                      (uint32_t)(me >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)me, (uint32_t)stage_n));
-                  sStage[wave][e] = ((uint64_t)__float_as_uint(est) << 32) | (tag + (uint32_t)r);
+                      (uint32_t)(pm[r] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pm[r], (uint32_t)stage_n));
+                  sStage[wave][e] = ((uint64_t)__float_as_uint(part[r]) << 32) | (tag + (uint32_t)r);
                 }
-                stage_n += (int)__popcll(me);
+                stage_n += (int)__popcll(pm[r]);
               }
             }
             if (stage_n > STAGE - 256) {

@@ -866,7 +866,7 @@ ThreadPool& host_pool(rbq_index* idx) {
   return *idx->pool;
 }
 
-// Search with the re-rank on host cores (raw vectors in pinned host memory).
+// Search with the re-rank on host cores (raw vectors in host memory).
 // The batch is cut into sub-batches: while the host threads re-rank one, the
 // GPU already searches the next (the overlap of Sec. 3.3.4).
 void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,

@@ -58,9 +58,6 @@ def test_params_defaults():
     (10, 8, {"kmeans_init": 2}, "kmeans_init"),
     (10, 8, {"ivf_flat": 2}, "ivf_flat"),
     (10, 8, {"borrow_vectors": 1, "vectors_on_host": 0}, "borrow_vectors needs the vectors on the host"),
-    # a NumPy array is pageable memory: it cannot be borrowed
-    (10, 8, {"borrow_vectors": 1, "vectors_on_host": 1}, "pinned host memory"),
-    (10, 8, {"borrow_vectors": 1}, "pinned host memory"),
 ])
 def test_build_rejects_bad_arguments(n, d, kw, msg):
     L = rbq.lib()

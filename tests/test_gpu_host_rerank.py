@@ -1,4 +1,4 @@
-"""GPU tests of the host re-rank path (raw vectors in pinned host memory,
+"""GPU tests of the host re-rank path (raw vectors in host memory,
 Sec. 3.3.4): the same index built with the vectors on the device and on the
 host returns the same candidates; the host path re-ranks them in FP64, so its
 final results follow the oracle's exact distances (P7) and differ from the
@@ -117,9 +117,9 @@ def test_host_rerank_device_inputs_and_mixed(pair):
 
 
 def test_borrowed_and_automatic_placement(pair):
-    """borrow_vectors keeps the caller's pinned rows (no copy) and returns the
-    copied host index's results; automatic placement keeps a small index's
-    vectors in HBM; pageable memory cannot be borrowed."""
+    """borrow_vectors keeps the caller's rows (pinned or pageable, no copy) and
+    returns the copied host index's results; automatic placement keeps a small
+    index's vectors in HBM; device memory cannot be borrowed."""
     import torch
     from paper_2605_16007_amd.rbq import RbqError
     X, Q, idx, dev, host = pair
@@ -127,22 +127,60 @@ def test_borrowed_and_automatic_placement(pair):
     xp.numpy()[:] = X
     kw = dict(centroids=idx.centroids, rotation=idx.P, assignment=idx.assign.astype(np.int32))
     b = Index.build(xp, idx.nlist, vectors_on_host=True, borrow_vectors=True, host_threads=4, **kw)
+    xpage = np.array(X, np.float32, copy=True)
+    bp = Index.build(xpage, idx.nlist, vectors_on_host=True, borrow_vectors=True, host_threads=4, **kw)
     auto = Index.build(X, idx.nlist, **kw)
     try:
         assert b.info()["vectors_borrowed"] == 1 and b.info()["vectors_on_host"] == 1
+        assert bp.info()["vectors_borrowed"] == 1
         assert host.info()["vectors_borrowed"] == 0
         assert auto.info()["vectors_on_host"] == 0
         for nq in (1, 700, 2100):
             x_ids, x_d = host.search(Q[:nq], 6, 10, 100)
-            y_ids, y_d = b.search(Q[:nq], 6, 10, 100)
-            np.testing.assert_array_equal(x_ids, y_ids)
-            np.testing.assert_array_equal(x_d, y_d)
+            for ix in (b, bp):
+                y_ids, y_d = ix.search(Q[:nq], 6, 10, 100)
+                np.testing.assert_array_equal(x_ids, y_ids)
+                np.testing.assert_array_equal(x_d, y_d)
         a_ids, a_d = auto.search(Q[:300], 6, 10, 100)
         d_ids, d_d = dev.search(Q[:300], 6, 10, 100)
         np.testing.assert_array_equal(a_ids, d_ids)
         np.testing.assert_array_equal(a_d, d_d)
-        with pytest.raises(RbqError, match="pinned host memory"):
-            Index.build(X, idx.nlist, vectors_on_host=True, borrow_vectors=True, **kw)
+        with pytest.raises(RbqError, match="not device memory"):
+            Index.build(torch.from_numpy(X).cuda(), idx.nlist, vectors_on_host=True,
+                        borrow_vectors=True, **kw)
     finally:
         b.close()
+        bp.close()
         auto.close()
+
+
+def test_host_copy_gets_huge_pages(pair):
+    """The index's own host rows are private anonymous memory advised for
+    transparent huge pages: building a host index of 96 MiB of rows raises the
+    process's AnonHugePages by at least half of that."""
+    import re
+    try:
+        mode = re.search(r"\[(\w+)\]", open("/sys/kernel/mm/transparent_hugepage/enabled").read()).group(1)
+    except (OSError, AttributeError):
+        mode = None
+    if mode not in ("always", "madvise"):
+        pytest.skip("transparent huge pages are off on this host")
+    X, Q, idx, dev, host = pair
+
+    def huge_kb():
+        return int(re.search(r"AnonHugePages:\s+(\d+)", open("/proc/self/smaps_rollup").read()).group(1))
+
+    reps = 96 * 2**20 // X.nbytes + 1
+    big = np.ascontiguousarray(np.tile(X, (reps, 1)))
+    _say(f"[host rerank] host copy of {big.nbytes >> 20} MiB")
+    before = huge_kb()
+    ix = Index.build(big, idx.nlist, centroids=idx.centroids, rotation=idx.P, vectors_on_host=True,
+                     host_threads=4)
+    try:
+        after = huge_kb()
+        assert after - before >= 48 * 1024, (before, after)
+        ids, _ = ix.search(Q[:8], 6, 10, 100)
+        assert (ids >= 0).all()
+    finally:
+        ix.close()
+
