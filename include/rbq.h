@@ -383,9 +383,16 @@ rbq_status rbq_replay_plain(rbq_index* idx, const rbq_replay_io* io);
  *   RBQ_OPT_BLOCK       list-major work items cover index blocks of this many
  *                       64-vector micro-blocks of a list (Sec. 3.3.1), so a
  *                       long list is shared out over several workgroups;
- *                       0: whole lists; -1 (default): as autotuned, else 0 */
+ *                       0: whole lists; -1 (default): as autotuned, else 0
+ *   RBQ_OPT_HOST_PARTS  sub-batches of a search whose re-rank runs on host
+ *                       cores (Sec. 3.3.4: the host re-ranks one while the GPU
+ *                       searches the next), 1..64; 0 (default): 4 for batches
+ *                       of >= 2048 queries, 2 for >= 256, else 1, halved while
+ *                       a sub-batch would probe each list fewer than 8 times
+ *                       on average. rbq_autotune tunes for the sub-batch size
+ *                       in force when it runs */
 enum { RBQ_OPT_SCAN = 1, RBQ_OPT_GROUP_MIN = 2, RBQ_OPT_POOL_CAP = 3, RBQ_OPT_ROTATION = 4,
-       RBQ_OPT_GROUP_SIZE = 5, RBQ_OPT_ESTIMATOR = 6, RBQ_OPT_BLOCK = 7 };
+       RBQ_OPT_GROUP_SIZE = 5, RBQ_OPT_ESTIMATOR = 6, RBQ_OPT_BLOCK = 7, RBQ_OPT_HOST_PARTS = 8 };
 rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
 
 /*

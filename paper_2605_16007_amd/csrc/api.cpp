@@ -517,6 +517,10 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value) {
       if (value < -1 || value > (1 << 20)) return invalid("RBQ_OPT_BLOCK must be in [-1, 2^20]");
       idx->opt_block.store((int)value);
       return RBQ_OK;
+    case RBQ_OPT_HOST_PARTS:
+      if (value < 0 || value > 64) return invalid("RBQ_OPT_HOST_PARTS must be in [0, 64]");
+      idx->opt_host_parts.store((int)value);
+      return RBQ_OK;
     case RBQ_OPT_GROUP_SIZE:
       if (value < 0 || value > 64) return invalid("RBQ_OPT_GROUP_SIZE must be in [0, 64]");
       idx->opt_group_size.store((int)value);

@@ -120,6 +120,7 @@ struct rbq_index {
   std::atomic<int> opt_group_size{0};  // queries per list-major item (0: tuned or built-in)
   std::atomic<int> opt_estimator{0};   // 0 B_q-bit query, 1 unquantised FP32 residual, 2 IVF-Flat
   std::atomic<int> opt_block{-1};      // micro-blocks per list-major index block (-1: tuned or built-in)
+  std::atomic<int> opt_host_parts{0};  // sub-batches of a host re-rank search (0: automatic)
   // autotuned launch choices per batch-shape bucket (rbq_autotune)
   std::mutex tune_mu;
   std::map<uint64_t, rbq::TuneCfg> tune;
@@ -194,7 +195,7 @@ void search(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R
             float* dist, hipStream_t s, const SearchIO& io);
 // Sub-batches a search with the re-rank on host cores is cut into: while the
 // host re-ranks one, the GPU searches the next.
-int host_rerank_parts(int64_t nq);
+int host_rerank_parts(const rbq_index* idx, int64_t nq, int nprobe);
 // Phases 1-4 only: the coarse top-R of every query (nq x R sort keys) is
 // copied into cand_host, and the queries into q_host when q is on the device
 // (both pinned host memory); returns when they are there. The re-rank's input.

@@ -703,9 +703,16 @@ constexpr size_t kTopkLdsMax = 150u << 10;  // dynamic LDS of one selection work
 
 // Sorted top-k of float scores with the row in registers (rows of up to
 // kScoreTopkCols scores: 16 per thread, 256 threads up to 4096 columns, 512
-// above); defined with the register-resident selection.
+// above); defined with the register-resident selection. Longer rows are cut
+// into pieces of kScoreTopkCols scores whose k smallest are selected first.
 constexpr int kScoreTopkCols = 512 * 16;
 static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows);
+static void launch_score_topk_pieces(hipStream_t s, const TopkArgs& a, int rows, int pieces);
+
+int64_t row_topk_scratch_keys(int ncols, int k, int64_t rows) {
+  if (ncols <= kScoreTopkCols) return 0;
+  return rows * ((ncols + kScoreTopkCols - 1) / kScoreTopkCols) * (int64_t)k;
+}
 
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   if (rows <= 0) return;
@@ -749,6 +756,22 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   }
   if (a.score && a.sorted && a.ncols <= kScoreTopkCols && !a.rowcnt) {
     launch_score_topk(s, a, rows);
+    return;
+  }
+  if (a.score && a.sorted && !a.rowcnt && !a.rowk && a.scratch) {
+    // two stages: the k smallest of every piece, then of the pieces' keys
+    // (the row's k smallest are among its pieces' k smallest: the same keys)
+    const int pieces = (a.ncols + kScoreTopkCols - 1) / kScoreTopkCols;
+    RBQ_CHECK(pieces <= 65535, "score top-k: row too long");
+    launch_score_topk_pieces(s, a, rows, pieces);
+    TopkArgs b = a;
+    b.score = nullptr;
+    b.keys = a.scratch;
+    b.ld = (int64_t)pieces * a.k;
+    b.ncols = pieces * a.k;
+    b.scratch = nullptr;
+    b.KP = b.cache_cap = 0;
+    launch_row_topk(s, b, rows);
     return;
   }
   if (a.score)
@@ -1477,6 +1500,36 @@ __global__ __launch_bounds__(NT) void k_score_topk(TopkArgs a) {
     if (a.out_low) a.out_low[row * k + t] = x == KEY_NONE ? -1 : (int32_t)(uint32_t)x;
     if (a.out_val) a.out_val[row * k + t] = x == KEY_NONE ? INFINITY : f32_ord((uint32_t)(x >> 32));
   }
+}
+
+// One piece of a long score row: the k smallest of its (up to NT x KPT)
+// scores as keys with the row's column in the low word, in any order, at
+// cand[(row x pieces + piece) x k]; a piece shorter than k is padded with
+// KEY_NONE.
+template <int NT, int KPT>
+__global__ __launch_bounds__(NT) void k_score_topk_piece(TopkArgs a) {
+  __shared__ SelRegShared<NT> sh;
+  const int tid = threadIdx.x;
+  const int64_t row = blockIdx.x;
+  const int piece = blockIdx.y;
+  const int c0 = piece * NT * KPT;
+  const int n = min(NT * KPT, a.ncols - c0);
+  const int k = a.k;
+  uint64_t v[KPT];
+#pragma unroll
+  for (int u = 0; u < KPT; ++u) {
+    const int c = u * NT + tid;
+    v[u] = c < n ? key64(a.score[row * a.ld + c0 + c], (uint32_t)(c0 + c)) : KEY_NONE;
+  }
+  uint64_t* dst = a.scratch + (row * (int64_t)gridDim.y + piece) * k;
+  (void)select_regs<NT, KPT>(v, n, k, dst, sh);
+  for (int t = min(n, k) + tid; t < k; t += NT) dst[t] = KEY_NONE;
+}
+
+static void launch_score_topk_pieces(hipStream_t s, const TopkArgs& a, int rows, int pieces) {
+  static_assert(kScoreTopkCols == 512 * 16, "piece width");
+  hipLaunchKernelGGL((k_score_topk_piece<512, 16>), dim3((unsigned)rows, (unsigned)pieces), dim3(512), 0, s, a);
+  RBQ_HIP(hipGetLastError());
 }
 
 static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows) {

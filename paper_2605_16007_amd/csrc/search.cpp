@@ -63,6 +63,7 @@ __global__ void k_count_group_bytes(const int32_t* cnt, const int32_t* list_len,
 struct Bufs {
   float* qpad = nullptr;
   float* score = nullptr;
+  uint64_t* pcand = nullptr;  // the probe selection's per-piece keys (nlist > 8192)
   int32_t* probes = nullptr;
   float* pscore = nullptr;
   float* qrot = nullptr;
@@ -272,7 +273,11 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   const int ld = idx->ld, nlist = idx->nlist, W = idx->W, d = idx->d;
   const rbq_debug_io* dbg = P.dbg;
   if (P.need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
-  if (!P.inj_probes) b.score = c.take<float>((size_t)nq * nlist);
+  if (!P.inj_probes) {
+    b.score = c.take<float>((size_t)nq * nlist);
+    const int64_t pk = row_topk_scratch_keys(nlist, P.nprobe, nq);
+    if (pk) b.pcand = c.take<uint64_t>(pk);
+  }
   b.probes = c.take<int32_t>(pairs);
   if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
   b.qrot = c.take<float>((size_t)nq * ld);
@@ -491,6 +496,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       ta.k = nprobe;
       ta.out_low = b.probes;
       ta.out_val = b.pscore;
+      ta.scratch = b.pcand;
       launch_row_topk(s, ta, (int)nq);
     }
     if (mixed) launch_mask_probes(s, b.probes, (int)nq, nprobe, d_np);
@@ -875,7 +881,7 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
   const bool qdev = is_device_ptr(q);
   const bool ids_dev = ids && is_device_ptr(ids), dist_dev = dist && is_device_ptr(dist);
   const rbq_debug_io* dbg = io.dbg;
-  const int parts = dbg ? 1 : host_rerank_parts(nq);
+  const int parts = dbg ? 1 : host_rerank_parts(idx, nq, nprobe);
   const int64_t sb = ceil_div(nq, (int64_t)parts);
   const bool stage_out = !ids || !dist || ids_dev || dist_dev;
   size_t off = 0;
@@ -964,7 +970,17 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
 
 }  // namespace
 
-int host_rerank_parts(int64_t nq) { return nq >= 2048 ? 4 : (nq >= 256 ? 2 : 1); }
+// Sub-batches of a host re-rank search: more of them overlap more of the
+// host's work with the GPU's, but each list-major item then groups fewer
+// queries, so the automatic rule keeps at least 8 (query, list) pairs per
+// list in each sub-batch on average.
+int host_rerank_parts(const rbq_index* idx, int64_t nq, int nprobe) {
+  const int fixed = idx->opt_host_parts.load();
+  if (fixed > 0) return (int)std::min<int64_t>(fixed, std::max<int64_t>(1, nq));
+  int parts = nq >= 2048 ? 4 : (nq >= 256 ? 2 : 1);
+  while (parts > 1 && nq * (int64_t)nprobe < (int64_t)8 * parts * idx->nlist) parts /= 2;
+  return parts;
+}
 
 void search_candidates(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int R,
                        uint64_t* cand_host, float* q_host, hipStream_t s, const SearchIO& io) {

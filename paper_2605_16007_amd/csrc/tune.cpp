@@ -71,7 +71,7 @@ void autotune(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, int
   RBQ_HIP(hipSetDevice(idx->device));
   // With the re-rank on host cores a search runs on the GPU in sub-batches:
   // the choices are tuned, and stored, for the sub-batch (its first queries)
-  if (idx->vectors_on_host) nq = ceil_div(nq, (int64_t)host_rerank_parts(nq));
+  if (idx->vectors_on_host) nq = ceil_div(nq, (int64_t)host_rerank_parts(idx, nq, nprobe));
   const int d = idx->d;
   std::vector<TuneCfg> cands;
   cands.push_back(TuneCfg{1, 64, 8, 2, 4, 2, 0});

@@ -28,7 +28,7 @@ SYMBOLS = [
     "rbq_autotune", "rbq_tune_save", "rbq_tune_load", "rbq_tune_clear", "rbq_search_noalloc",
 ]
 OPTIONS = {"scan": 1, "group_min": 2, "pool_cap": 3, "rotation": 4, "group_size": 5, "estimator": 6,
-           "block": 7}
+           "block": 7, "host_parts": 8}
 
 
 class BuildParams(C.Structure):
@@ -413,8 +413,8 @@ class Index:
     def set_option(self, name: str, value: int):
         """Tuning knobs: scan (0 auto, 1 query-major popcount, 2 list-major
         MFMA, 3 one item per query), group_min, pool_cap, rotation,
-        group_size, estimator (0 B_q-bit query, 1 unquantised); see
-        rbq_set_option in include/rbq.h."""
+        group_size, estimator (0 B_q-bit query, 1 unquantised, 2 IVF-Flat),
+        block, host_parts; see rbq_set_option in include/rbq.h."""
         _check(lib().rbq_set_option(self._h, OPTIONS[name], int(value)))
 
     # ---------------------------------------------------------------- timing

@@ -184,3 +184,21 @@ def test_host_copy_gets_huge_pages(pair):
     finally:
         ix.close()
 
+
+
+def test_host_parts_leave_results_unchanged(pair):
+    """RBQ_OPT_HOST_PARTS (sub-batches overlapped with the host re-rank) and
+    its automatic rule return the same results for every split."""
+    from paper_2605_16007_amd.rbq import RbqError
+    X, Q, idx, dev, host = pair
+    ref_ids, ref_d = host.search(Q[:2100], 6, 10, 100)
+    try:
+        for parts in (1, 2, 3, 7, 64):
+            host.set_option("host_parts", parts)
+            ids, dd = host.search(Q[:2100], 6, 10, 100)
+            np.testing.assert_array_equal(ids, ref_ids)
+            np.testing.assert_array_equal(dd, ref_d)
+        with pytest.raises(RbqError):
+            host.set_option("host_parts", 65)
+    finally:
+        host.set_option("host_parts", 0)
