@@ -445,8 +445,10 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
         tuned = {"loaded_from_cache": loaded}
     elif not args.no_autotune:
         for pt in ([(p, w.rerank_n) for p in w.nprobe] if not fixed else []) + [(nprobe, R)]:
+            t_ = time.perf_counter()
             tuned[f"nprobe={pt[0]},rerank={pt[1]}"] = idx.autotune(Qb[0], pt[0], w.k, pt[1])
-            log(f"[{role}] autotune {pt}: {tuned[f'nprobe={pt[0]},rerank={pt[1]}']}")
+            log(f"[{role}] autotune {pt} ({time.perf_counter() - t_:.0f}s): "
+                f"{tuned[f'nprobe={pt[0]},rerank={pt[1]}']}")
         if cache:
             idx.tune_save(cache)
     listed_qps = {f"{p}": quick_qps(p, w.rerank_n) for p in w.nprobe} if not fixed else {}
@@ -457,8 +459,12 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
         for p in (1, 2, 4):
             idx.set_option("host_parts", p)
             if not loaded and not args.no_autotune:
-                idx.autotune(Qb[0], nprobe, w.k, R)
+                t_ = time.perf_counter()
+                r_ = idx.autotune(Qb[0], nprobe, w.k, R)
+                log(f"[{role}] {p} host sub-batch(es): autotuned in {time.perf_counter() - t_:.0f}s, "
+                    f"{r_['ms']:.2f} ms per sub-batch")
             parts_qps[str(p)] = quick_qps(nprobe, R)
+            log(f"[{role}] {p} host sub-batch(es): {parts_qps[str(p)]:.0f} q/s")
         best = int(max(parts_qps, key=parts_qps.get))
         idx.set_option("host_parts", best)
         log(f"[{role}] host sub-batches: " + ", ".join(f"{p}: {q:.0f} q/s" for p, q in parts_qps.items())

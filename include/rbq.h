@@ -402,16 +402,17 @@ rbq_status rbq_set_option(rbq_index* idx, int32_t option, int64_t value);
  * matrix-core scan), the queries grouped per list-major work item (G), the persistent
  * workgroups per compute unit, and the sizes of the chunks. rbq_autotune times every
  * candidate on the given queries (host or device, nq x d; representative of
- * later batches), checks that each returns the same results, and stores the
+ * later batches) over three searches (one when the first already takes 1.5x
+ * the best time so far), checks that each returns the same results, and stores the
  * fastest for the bucket of (nq, nprobe, rerank_n) rounded up to powers of
  * two. Later searches of any shape in a tuned bucket use it (an explicit
  * RBQ_OPT_SCAN still fixes the scan form). Blocks the calling thread.
  * The table can be saved to / loaded from a text cache; its entries are keyed
  * by device architecture, d, B_q, nlist, n and the list-size histogram, and
  * only matching entries load. For an index whose raw vectors are on the host,
- * where a search runs on the GPU in sub-batches of up to a quarter of the
- * batch while host cores re-rank the previous one, the choices are tuned
- * (on the GPU phases alone) and stored for that sub-batch size.
+ * where a search runs on the GPU in sub-batches (RBQ_OPT_HOST_PARTS) while
+ * host cores re-rank the previous one, the choices are tuned (on the GPU
+ * phases alone) and stored for the sub-batch size in force.
  */
 typedef struct {
   int32_t scan;          /* 1 query-major popcount only; 2 list-major matrix core for the
