@@ -370,14 +370,35 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
         torch.cuda.synchronize()
         return recall(ids[:gt_n].cpu().numpy(), gt)
 
-    def quick_qps(npb, R, steps=8):
-        ids_ = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
-        dd_ = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
-        idx.search(Qb[0], npb, w.k, R, ids=ids_, dists=dd_)
+    # batches in flight at once: with the re-rank on host cores a search
+    # returns only when its host re-rank is done, so a second caller thread
+    # (own stream, own workspace) keeps the GPU busy meanwhile
+    conc = args.concurrency if args.concurrency > 0 else (2 if host_vectors else 1)
+
+    def quick_qps(npb, R, steps=8, threads=1):
+        """Queries/s of `steps` searches issued from `threads` caller threads,
+        each on its own stream."""
+        import threading
+        sts = [torch.cuda.Stream(device=dev) for _ in range(threads)]
+        bufs = [(torch.empty((w.nq, w.k), dtype=torch.int64, device=dev),
+                 torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)) for _ in range(threads)]
+
+        def run(t, first, count):
+            torch.cuda.set_device(dev)
+            for s in range(first + t, first + count, threads):
+                idx.search(Qb[s % nb], npb, w.k, R, ids=bufs[t][0], dists=bufs[t][1],
+                           stream=sts[t].cuda_stream)
+
+        def all_threads(first, count):
+            th = [threading.Thread(target=run, args=(t, first, count)) for t in range(threads)]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join()
+        all_threads(0, threads)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for s in range(steps):
-            idx.search(Qb[s % nb], npb, w.k, R, ids=ids_, dists=dd_)
+        all_threads(0, steps)
         torch.cuda.synchronize()
         return w.nq * steps / (time.perf_counter() - t)
 
@@ -463,8 +484,8 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
                 r_ = idx.autotune(Qb[0], nprobe, w.k, R)
                 log(f"[{role}] {p} host sub-batch(es): autotuned in {time.perf_counter() - t_:.0f}s, "
                     f"{r_['ms']:.2f} ms per sub-batch")
-            parts_qps[str(p)] = quick_qps(nprobe, R)
-            log(f"[{role}] {p} host sub-batch(es): {parts_qps[str(p)]:.0f} q/s")
+            parts_qps[str(p)] = quick_qps(nprobe, R, steps=8, threads=conc)
+            log(f"[{role}] {p} host sub-batch(es), {conc} in flight: {parts_qps[str(p)]:.0f} q/s")
         best = int(max(parts_qps, key=parts_qps.get))
         idx.set_option("host_parts", best)
         log(f"[{role}] host sub-batches: " + ", ".join(f"{p}: {q:.0f} q/s" for p, q in parts_qps.items())
@@ -488,18 +509,40 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
         idx.search(Qb[s % nb], nprobe, w.k, R, ids=oi, dists=od, stream=st.cuda_stream)
 
     steps = args.steps if role == "headline" else args.secondary_steps
+    conc = min(conc, nst) if nst > 1 else conc
+    if conc > 1 and nst < conc:
+        streams += [torch.cuda.Stream(device=dev) for _ in range(conc - nst)]
+        outs += [(torch.empty((w.nq, w.k), dtype=torch.int64, device=dev),
+                  torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)) for _ in range(conc - nst)]
+        nst = conc
+
+    def run_steps(first, count):
+        if conc == 1:
+            for s in range(first, first + count):
+                step(s)
+            return
+        import threading
+
+        def worker(t):
+            torch.cuda.set_device(dev)
+            for s in range(first + t, first + count, conc):
+                step(s)
+        th = [threading.Thread(target=worker, args=(t,)) for t in range(conc)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+
     torch.cuda.synchronize()
-    for s in range(args.warmup):
-        step(s)
+    run_steps(0, max(args.warmup, conc))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(steps):
-        step(s)
+    run_steps(0, steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_step = elapsed * 1e3 / steps
     qps = w.nq * steps / elapsed
-    log(f"[{role}] timed {steps} steps: {qps:.0f} queries/s, {ms_step:.3f} ms per batch")
+    log(f"[{role}] timed {steps} steps ({conc} in flight): {qps:.0f} queries/s, {ms_step:.3f} ms per batch")
     # stage times, scanned work and per-launch kernel times: the same searches
     # again with the library's instrumentation on (kept out of the timed steps)
     idx.set_timing(True)
@@ -575,7 +618,7 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
                    "host_parts": (int(max(parts_qps, key=parts_qps.get)) if parts_qps else args.host_parts)
                    if host_vectors else None,
                    "raw_vectors": "host (2 MiB pages), borrowed" if host_vectors else "HBM",
-                   "streams": nst, "parallelism": "none (1 GPU)"},
+                   "streams": nst, "batches_in_flight": conc, "parallelism": "none (1 GPU)"},
         "recall_at_10": rec[(nprobe, R)], "recall_queries": gt_n,
         "recall_by_point": {f"nprobe={p},rerank={r}": v for (p, r), v in rec.items()},
         "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
@@ -592,7 +635,7 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
     return idx, X, Qall, out, (nprobe, R)
 
 
-def hbm_placement(w, X, Qall, host_idx, gt, nprobe, R, args):
+def hbm_placement(w, X, Qall, parts, gt, nprobe, R, args):
     """The headline index with its raw vectors in HBM instead (GPU gather
     re-rank), from the same centroids, rotation and lists, at the same point.
     One MI355X holds the whole 400M x 96 set (154 GB of rows plus 8 GB of
@@ -602,9 +645,8 @@ def hbm_placement(w, X, Qall, host_idx, gt, nprobe, R, args):
     from paper_2605_16007_amd import Index
     dev = torch.device("cuda:0")
     t = time.perf_counter()
-    ix = Index.build(X, w.nlist, bq=w.bq, centroids=host_idx.export("centroids"),
-                     rotation=host_idx.export("rotation"), assignment=host_idx.export("assign"),
-                     vectors_on_host=False)
+    ix = Index.build(X, w.nlist, bq=w.bq, centroids=parts["centroids"], rotation=parts["rotation"],
+                     assignment=parts["assign"], vectors_on_host=False)
     build_s = time.perf_counter() - t
     try:
         Qb = [torch.from_numpy(Qall[i * w.nq:(i + 1) * w.nq]).to(dev) for i in range(args.batches)]
@@ -702,6 +744,9 @@ def main():
     ap.add_argument("--no-estimators", action="store_true",
                     help="skip the unquantised-query and IVF-Flat comparisons")
     ap.add_argument("--no-flat", action="store_true", help="build no IVF-Flat copy of the lists")
+    ap.add_argument("--concurrency", type=int, default=0,
+                    help="batches in flight from as many caller threads (default: 2 with the "
+                         "re-rank on host cores, else 1)")
     ap.add_argument("--host-parts", type=int, default=-1,
                     help="sub-batches of a host re-rank search (0: the library's rule; default: "
                          "the fastest of 1, 2 and 4, each autotuned)")
@@ -767,15 +812,15 @@ def main():
     gt = head.pop("_gt")
     if cpu_pool:
         cpu_pool.close()
+    hbm_parts = None
     if host_vectors and not args.no_hbm_variant:
-        head["vectors_in_hbm"] = hbm_placement(w, X, Qall, idx, gt, nprobe, R, args)
+        # (the host-vector index and its workspaces are freed first: the whole
+        # set's rows then fill 154 GB of HBM)
+        hbm_parts = {what: idx.export(what) for what in ("centroids", "rotation", "assign")}
     if shard_note:
         import psutil
         full = get("unit96_400m")
         ram = psutil.virtual_memory().total
-        # k-means (training rows 256 nlist) and the assignment both grow as
-        # rows x lists: x8 rows and x8 lists from the shard to the whole set
-        scale = (full.n / w.n) * (full.nlist / w.nlist)
         head["shard"] = {
             "of": f"{full.name}: {full.n} x {full.d}, nlist {full.nlist}",
             "rows": w.n, "nlist": w.nlist, "host_ram_bytes": ram,
@@ -787,8 +832,12 @@ def main():
                        f"whole set, so list-major items are fuller than there"),
         }
         log(f"[headline] shard: {head['shard']['reason']}")
-    del X
     idx.close()
+    if hbm_parts is not None:
+        torch.cuda.empty_cache()
+        head["vectors_in_hbm"] = hbm_placement(w, X, Qall, hbm_parts, gt, nprobe, R, args)
+        hbm_parts = None
+    del X
 
     secondary = None
     if args.secondary:

@@ -202,6 +202,11 @@ rbq_index* load_index(const char* path) {
   auto idx = std::make_unique<rbq_index>();
   RBQ_HIP(hipGetDevice(&idx->device));
   RBQ_HIP(hipDeviceGetAttribute(&idx->num_cus, hipDeviceAttributeMultiprocessorCount, idx->device));
+  {
+    size_t free_b = 0, total_b = 0;
+    RBQ_HIP(hipMemGetInfo(&free_b, &total_b));
+    idx->device_mem = (int64_t)total_b;
+  }
   idx->n = h.n;
   idx->d = h.d;
   idx->ld = (int)round_up(h.d, 4);

@@ -325,6 +325,11 @@ rbq_index* build_index(const float* x, int64_t n, int d, const rbq_build_params&
   auto idx = std::make_unique<rbq_index>();
   RBQ_HIP(hipGetDevice(&idx->device));
   RBQ_HIP(hipDeviceGetAttribute(&idx->num_cus, hipDeviceAttributeMultiprocessorCount, idx->device));
+  {
+    size_t free_b = 0, total_b = 0;
+    RBQ_HIP(hipMemGetInfo(&free_b, &total_b));
+    idx->device_mem = (int64_t)total_b;
+  }
   idx->n = n;
   idx->d = d;
   idx->ld = (int)round_up(d, 4);

@@ -125,6 +125,7 @@ struct rbq_index {
   std::mutex tune_mu;
   std::map<uint64_t, rbq::TuneCfg> tune;
   int num_cus = 256;
+  int64_t device_mem = 0;  // bytes of device memory (sizes the default pool budget)
 
   // per-call scratch
   std::mutex ws_mu;

@@ -116,7 +116,13 @@ struct Plan {
   std::vector<Chunk> chunks, qm_chunks;
 };
 
-constexpr int64_t kDefaultPoolBudget = (int64_t)512 << 20;
+// Candidate pools of a search without a memory budget: 1/64 of the device's
+// memory, from 512 MiB to 8 GiB (4.5 GB on a 288 GB MI355X). A pool that
+// overflows sends its query to an exact redo from scratch, so room is cheaper
+// than a redo.
+int64_t default_pool_budget(const rbq_index* idx) {
+  return std::min<int64_t>((int64_t)8 << 30, std::max<int64_t>((int64_t)512 << 20, idx->device_mem / 64));
+}
 // batches at least this large scan their query-major chunks with the fused
 // one-workgroup-per-query kernel (enough workgroups to fill the GPU)
 constexpr int64_t kFusedMinQueries = 128;
@@ -154,7 +160,7 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   P.dumps = dbg && (dbg->ip || dbg->est);
   P.unq = idx->opt_estimator.load() == 1;
   P.flat = idx->opt_estimator.load() == 2 && idx->flat.p != nullptr;
-  const int64_t budget = pool_budget > 0 ? pool_budget : kDefaultPoolBudget;
+  const int64_t budget = pool_budget > 0 ? pool_budget : default_pool_budget(idx);
   P.pch = (int)std::max<int64_t>(
       1, std::min<int64_t>(nprobe, budget / std::max<int64_t>(1, nq * R * 8) - 1));
   P.first = (int)std::min<int64_t>(P.pch, std::max<int64_t>(1, (2048 + nq - 1) / nq));
