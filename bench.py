@@ -483,7 +483,7 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
                 t_ = time.perf_counter()
                 r_ = idx.autotune(Qb[0], nprobe, w.k, R)
                 log(f"[{role}] {p} host sub-batch(es): autotuned in {time.perf_counter() - t_:.0f}s, "
-                    f"{r_['ms']:.2f} ms per sub-batch")
+                    f"{r_['ms']:.2f} ms per sub-batch (built-in rule {r_['ms_default']:.2f}): {r_}")
             parts_qps[str(p)] = quick_qps(nprobe, R, steps=8, threads=conc)
             log(f"[{role}] {p} host sub-batch(es), {conc} in flight: {parts_qps[str(p)]:.0f} q/s")
         best = int(max(parts_qps, key=parts_qps.get))
@@ -649,8 +649,13 @@ def hbm_placement(w, X, Qall, parts, gt, nprobe, R, args):
                      assignment=parts["assign"], vectors_on_host=False)
     build_s = time.perf_counter() - t
     try:
+        free_b, _ = torch.cuda.mem_get_info()
+        log(f"[headline] HBM placement built in {build_s:.0f}s ({ix.info()['device_bytes'] / 1e9:.1f} GB); "
+            f"{free_b / 1e9:.1f} GB free")
         Qb = [torch.from_numpy(Qall[i * w.nq:(i + 1) * w.nq]).to(dev) for i in range(args.batches)]
         tuned = ix.autotune(Qb[0], nprobe, w.k, R) if not args.no_autotune else None
+        free_b, _ = torch.cuda.mem_get_info()
+        log(f"[headline] HBM placement tuned; {free_b / 1e9:.1f} GB free")
         ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
         dd = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
         for s in range(args.warmup):
@@ -757,6 +762,8 @@ def main():
     ap.add_argument("--secondary", default="sift10m",
                     help="a second workload measured after the headline ('' skips it)")
     ap.add_argument("--secondary-steps", type=int, default=20)
+    ap.add_argument("--others", default="mixture128,embed960",
+                    help="further workloads measured briefly (comma-separated; empty: none)")
     ap.add_argument("--ablation-nprobe", type=int, default=512,
                     help="probe count of the GPU-versus-host re-rank ablation on the secondary workload")
     ap.add_argument("--serve-rates", default="5000,10000,20000,50000",
@@ -834,8 +841,17 @@ def main():
         log(f"[headline] shard: {head['shard']['reason']}")
     idx.close()
     if hbm_parts is not None:
+        from paper_2605_16007_amd import RbqError
         torch.cuda.empty_cache()
-        head["vectors_in_hbm"] = hbm_placement(w, X, Qall, hbm_parts, gt, nprobe, R, args)
+        free_b, total_b = torch.cuda.mem_get_info()
+        log(f"[headline] device memory before the HBM placement: {free_b / 1e9:.1f} GB free of "
+            f"{total_b / 1e9:.1f} GB (torch holds {torch.cuda.memory_reserved() / 1e9:.1f} GB)")
+        try:
+            head["vectors_in_hbm"] = hbm_placement(w, X, Qall, hbm_parts, gt, nprobe, R, args)
+        except RbqError as e:
+            free_b, _ = torch.cuda.mem_get_info()
+            log(f"[headline] HBM placement failed ({e}); {free_b / 1e9:.1f} GB free")
+            head["vectors_in_hbm"] = {"error": str(e)}
         hbm_parts = None
     del X
 
@@ -857,6 +873,44 @@ def main():
             sec["serving"] = serve_compare(idx2, w2, args)
         secondary = sec
         idx2.close()
+
+    # the remaining workloads, briefly: the small mixture (the paper's plain
+    # IVF-RaBitQ configuration) and the 960-dimension features with FP32
+    # against BF16 query rotation
+    others = {}
+    for name in [x for x in args.others.split(",") if x]:
+        w3 = get(name)
+        oargs = argparse.Namespace(**vars(args))
+        oargs.nprobe = oargs.rerank = 0
+        oargs.gt_queries = w3.nq
+        oargs.no_variants = oargs.no_estimators = True
+        oargs.no_flat = True
+        oargs.cpu_queries = 0
+        for k_, v in given.items():
+            setattr(oargs, k_, v)
+        oargs.no_flat = True
+        idx3, X3, Q3, o3, (np3, R3) = measure(w3, oargs, host_vectors=False, role=name)
+        gt3 = o3.pop("_gt")
+        row = {k_: o3[k_] for k_ in ("value", "ms_per_step", "recall_at_10", "recall_by_point",
+                                     "p50_ms", "p99_ms", "build_s")}
+        row["config"] = o3["config"]
+        if w3.d >= 512:
+            # BF16 inputs to the query rotation (FP32 accumulation) at the same point
+            idx3.set_option("rotation", 1)
+            q3 = torch.from_numpy(Q3[:w3.nq]).cuda()
+            ids3, _ = idx3.search(q3, np3, w3.k, R3)
+            torch.cuda.synchronize()
+            rb = recall(ids3[:len(gt3)].cpu().numpy(), gt3)
+            t_ = time.perf_counter()
+            for _ in range(10):
+                idx3.search(q3, np3, w3.k, R3)
+            torch.cuda.synchronize()
+            row["bf16_rotation"] = {"recall_at_10": rb, "qps": w3.nq * 10 / (time.perf_counter() - t_)}
+            idx3.set_option("rotation", 0)
+            log(f"[{name}] BF16 rotation: recall {rb:.4f}, {row['bf16_rotation']['qps']:.0f} q/s")
+        others[name] = row
+        idx3.close()
+        del X3
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30)) // 4
@@ -889,6 +943,7 @@ def main():
     }
     line.update({k_: v for k_, v in head.items() if k_ not in ("value", "ms_per_step", "steps")})
     line["secondary"] = secondary
+    line["other_workloads"] = others
     print(json.dumps(line), flush=True)
 
 
