@@ -22,12 +22,17 @@ rbq_status guarded(F&& f) {
     return RBQ_OK;
   } catch (const rbq::Error& e) {
     g_err = e.what();
+    // (a failed runtime call, such as an allocation that did not fit, also
+    // stays as the thread's last HIP error: clear it so that the next call's
+    // launch checks do not report it again)
+    (void)hipGetLastError();
     return e.status;
   } catch (const std::bad_alloc&) {
     g_err = "host allocation failed";
     return RBQ_ENOMEM;
   } catch (const std::exception& e) {
     g_err = e.what();
+    (void)hipGetLastError();
     return RBQ_EDEVICE;
   }
 }

@@ -17,6 +17,32 @@
 
 namespace rbq {
 
+namespace {
+// Progress on stderr when the environment sets RBQ_LOG to a value other than
+// 0 (a 400M-row build runs for minutes inside one call; workspace sizes).
+bool build_log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("RBQ_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+void build_log(const char* fmt, ...) {
+  if (!build_log_on()) return;
+  static const auto t0 = std::chrono::steady_clock::now();
+  const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  char msg[256];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[rbq %8.1fs] %s\n", t, msg);
+  std::fflush(stderr);
+}
+
+}  // namespace
+
 Workspace::~Workspace() {
   if (done) (void)hipEventDestroy(done);
   if (base) (void)hipFree(base);
@@ -81,8 +107,15 @@ void host_rows_fill(float* dst, const float* src, size_t count, int threads) {
   for (auto& t : ts) t.join();
 }
 
+// Searches enqueue their work and hand their workspace back at once, so a
+// caller that issues searches faster than the GPU completes them would keep
+// allocating: once kMaxIdleWorkspaces are held back, the oldest one is waited
+// for and reused instead.
+constexpr size_t kMaxIdleWorkspaces = 4;
+
 std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes) {
   std::unique_ptr<Workspace> got;
+  bool wait = false;
   {
     std::lock_guard<std::mutex> g(idx->ws_mu);
     // prefer the smallest idle workspace that is big enough
@@ -103,13 +136,19 @@ std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes) {
         }
       (void)hipGetLastError();
     }
+    if (best == (size_t)-1 && idx->ws_free.size() >= kMaxIdleWorkspaces) {
+      best = 0;  // every held workspace is still in use: the oldest
+      wait = true;
+    }
     if (best != (size_t)-1) {
       got = std::move(idx->ws_free[best]);
       idx->ws_free.erase(idx->ws_free.begin() + best);
     }
   }
+  if (wait) RBQ_HIP(hipEventSynchronize(got->done));
   if (got && got->cap >= bytes) return got;
   got.reset();  // idle but too small: its last use has completed
+  build_log("search workspace: allocating %.3f GB", (double)bytes / 1e9);
   got = std::make_unique<Workspace>();
   RBQ_HIP(hipMalloc(reinterpret_cast<void**>(&got->base), bytes));
   got->cap = bytes;
@@ -155,29 +194,6 @@ void upload_rows(float* dst, int ld, const float* src, int d, int64_t n, hipStre
 }
 
 namespace {
-
-// Build progress on stderr when the environment sets RBQ_LOG to a value other
-// than 0 (a 400M-row build runs for minutes inside one call).
-bool build_log_on() {
-  static const bool on = [] {
-    const char* v = std::getenv("RBQ_LOG");
-    return v && *v && std::strcmp(v, "0") != 0;
-  }();
-  return on;
-}
-
-void build_log(const char* fmt, ...) {
-  if (!build_log_on()) return;
-  static const auto t0 = std::chrono::steady_clock::now();
-  const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  char msg[256];
-  va_list ap;
-  va_start(ap, fmt);
-  std::vsnprintf(msg, sizeof msg, fmt, ap);
-  va_end(ap);
-  std::fprintf(stderr, "[rbq build %8.1fs] %s\n", t, msg);
-  std::fflush(stderr);
-}
 
 struct StreamGuard {
   hipStream_t s = nullptr;

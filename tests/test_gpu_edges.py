@@ -190,3 +190,28 @@ def test_large_k_rerank():
             assert np.all(np.diff(dd[qi][g >= 0]) >= 0)
             common = len(set(g.tolist()) & set(ref_ids[qi].tolist()))
             assert common >= k - 5, (k, qi, common)
+
+
+def test_many_searches_in_flight_reuse_workspaces():
+    """Searches that only enqueue (raw vectors in HBM, device outputs) can be
+    issued faster than the GPU completes them; past a few held workspaces a
+    search waits for the oldest instead of allocating another. Sixteen
+    back-to-back searches on one stream equal the same search run alone."""
+    import torch
+    _say("[edge] 16 searches in flight n=20000 d=64 nlist=64")
+    X, Q, idx = make_case(20_000, 64, 64, 400, seed=13)
+    lib = lib_index(X, idx)
+    try:
+        q = torch.from_numpy(Q).cuda()
+        ref_ids, ref_d = lib.search(q, 16, 10, 200)
+        torch.cuda.synchronize()
+        outs = [(torch.empty((len(Q), 10), dtype=torch.int64, device="cuda"),
+                 torch.empty((len(Q), 10), dtype=torch.float32, device="cuda")) for _ in range(16)]
+        st = torch.cuda.Stream()
+        for oi, od in outs:
+            lib.search(q, 16, 10, 200, ids=oi, dists=od, stream=st.cuda_stream)
+        torch.cuda.synchronize()
+        for oi, od in outs:
+            assert torch.equal(oi, ref_ids) and torch.equal(od, ref_d)
+    finally:
+        lib.close()
