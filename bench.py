@@ -624,6 +624,8 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
         "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
         "qps_at_listed_nprobe": listed_qps, "qps_by_scan_form": variants, "autotune": tuned,
         "qps_by_host_parts": parts_qps,
+        # queries whose list-major pool overflowed and were searched again
+        "redo_queries_per_batch": tm["redo_queries"] / max(1, tm["searches"]),
         "p50_ms": p50, "p99_ms": p99,
         "stage_ms": {s: tm[f"{s}_ms"] / ns for s in
                      ("probe", "rotate", "quant", "scan", "merge", "rerank", "total")},

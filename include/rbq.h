@@ -241,6 +241,8 @@ typedef struct {
   int32_t reserved;
   int64_t fused_vectors;     /* scanned_vectors of the fused launches */
   int64_t fused_read_bytes;  /* read_bytes of the fused launches */
+  int64_t redo_queries;      /* queries whose list-major pool overflowed and
+                                were searched again from scratch (exact) */
 } rbq_timings;
 
 rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled);

@@ -440,8 +440,8 @@ rbq_status rbq_set_timing(rbq_index* idx, int32_t enabled) {
     idx->pending.clear();
     idx->last = rbq_timings{};
     if (enabled) {
-      if (!idx->tcounter.p) idx->tcounter.alloc(6 * sizeof(unsigned long long));
-      RBQ_HIP(hipMemset(idx->tcounter.p, 0, 6 * sizeof(unsigned long long)));
+      if (!idx->tcounter.p) idx->tcounter.alloc(7 * sizeof(unsigned long long));
+      RBQ_HIP(hipMemset(idx->tcounter.p, 0, 7 * sizeof(unsigned long long)));
     }
     idx->timing.store(enabled ? 1 : 0);
   });
@@ -482,7 +482,7 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
     }
     idx->pending.clear();
     if (idx->tcounter.p) {
-      unsigned long long c[6] = {0, 0, 0, 0, 0, 0};
+      unsigned long long c[7] = {0, 0, 0, 0, 0, 0, 0};
       RBQ_HIP(hipDeviceSynchronize());
       RBQ_HIP(hipMemcpy(c, idx->tcounter.p, sizeof(c), hipMemcpyDeviceToHost));
       idx->last.scanned_vectors = (int64_t)c[0];
@@ -492,6 +492,7 @@ rbq_status rbq_get_timings(rbq_index* idx, rbq_timings* t) {
       idx->last.group_read_bytes = (int64_t)c[3];
       idx->last.fused_vectors = (int64_t)c[4];
       idx->last.fused_read_bytes = (int64_t)c[5];
+      idx->last.redo_queries = (int64_t)c[6];
     }
     *t = idx->last;
   });

@@ -152,7 +152,9 @@ std::unique_ptr<Workspace> ws_acquire(rbq_index* idx, size_t bytes) {
   got = std::make_unique<Workspace>();
   RBQ_HIP(hipMalloc(reinterpret_cast<void**>(&got->base), bytes));
   got->cap = bytes;
-  RBQ_HIP(hipEventCreateWithFlags(&got->done, hipEventDisableTiming));
+  // (blocking: a search that must wait for a workspace sleeps, leaving the
+  // host cores to the re-rank threads)
+  RBQ_HIP(hipEventCreateWithFlags(&got->done, hipEventDisableTiming | hipEventBlockingSync));
   return got;
 }
 

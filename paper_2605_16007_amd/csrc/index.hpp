@@ -139,7 +139,8 @@ struct rbq_index {
   rbq_timings last{};
   std::vector<rbq::TimingRec> pending;
   rbq::DevBuf tcounter;  // device sums: scanned vectors, record bytes read; the same two
-                         // for the list-major launches alone, then for the fused ones
+                         // for the list-major launches alone, then for the fused ones;
+                         // then the queries redone after a pool overflow
 
   // host re-rank (vectors_on_host): worker threads and pinned staging, made on
   // first use and kept with the index

@@ -16,6 +16,20 @@ namespace {
 // Timing counters: acc[0] += sum of list sizes over the pairs of probe ranks
 // [p0, p0 + pn); acc[1] += their padded record bytes when `qm` (each
 // query-major item reads its whole list).
+// (instrumented searches) the queries flagged for a redo
+__global__ void k_count_flags(const uint32_t* flags, int n, unsigned long long* acc) {
+  __shared__ unsigned long long part[256];
+  unsigned long long c = 0;
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < n; t += gridDim.x * 256) c += flags[t] ? 1u : 0u;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(acc, part[0]);
+}
+
 __global__ void k_count_scanned(const int32_t* probes, const int32_t* list_len, int nq, int nprobe,
                                 int p0, int pn, int rec_bytes, int qm, unsigned long long* acc) {
   __shared__ unsigned long long part[2][256];
@@ -200,6 +214,12 @@ Plan make_plan(const rbq_index* idx, int64_t nq, int nprobe, int k, int R, int64
   // fits) when the budget allows
   P.pool_cap = (int64_t)R * P.pch;
   if (P.maxlen > P.pool_cap && nq * (R + P.maxlen) * 8 <= budget) P.pool_cap = P.maxlen;
+  // the rest of the budget goes to the pools too: a list-major chunk's
+  // survivors may exceed R per probe rank (queries whose first lists leave a
+  // loose threshold), and an overflowing query is searched again from
+  // scratch by one workgroup
+  P.pool_cap = std::max<int64_t>(P.pool_cap, std::min<int64_t>(budget / (8 * std::max<int64_t>(1, nq)) - R,
+                                                               (int64_t)1 << 28));
   if (P.flat)  // (no redo for IVF-Flat: as large a pool as the budget holds)
     P.pool_cap = std::max<int64_t>(P.pool_cap, std::max<int64_t>(P.maxlen, budget / (8 * std::max<int64_t>(1, nq)) - R));
   P.cand_ld = R + P.pool_cap;
@@ -768,6 +788,11 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         ra.qmask = b.overflow;
         ra.reset = 1;
         launch_scan_fused(s, ra);
+        if (timed) {
+          hipLaunchKernelGGL(k_count_flags, dim3(16), dim3(256), 0, s, b.overflow, (int)nq,
+                             idx->tcounter.as<unsigned long long>() + 6);
+          RBQ_HIP(hipGetLastError());
+        }
       } else {
         launch_reset_masked(s, b.overflow, b.cand, cand_ld, R, b.qthr, b.pcnt, (int)nq);
         uint32_t any = 0;
@@ -919,13 +944,18 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
     events.clear();
   };
   try {
+    // every sub-batch's GPU work is queued first; then, as each completes
+    // (the caller sleeps on its event rather than spinning), its re-rank
+    // goes to the host threads, so they only ever hold work that is ready
+    std::vector<std::pair<int64_t, int64_t>> ranges;
     for (int64_t q0 = 0; q0 < nq; q0 += sb) {
       const int64_t q1 = std::min(nq, q0 + sb);
       HostJob job;
       job.cand = hc + q0 * R;
       job.qh = hq + q0 * d;
-      RBQ_HIP(hipEventCreateWithFlags(&job.ready, hipEventDisableTiming));
+      RBQ_HIP(hipEventCreateWithFlags(&job.ready, hipEventDisableTiming | hipEventBlockingSync));
       events.push_back(job.ready);
+      ranges.emplace_back(q0, q1);
       SearchIO sub = io;
       sub.continues_search = q0 > 0;
       if (io.q_nprobe) {
@@ -935,15 +965,17 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
       }
       const float* qsrc = q + q0 * d;
       search_part(idx, qsrc, q1 - q0, nprobe, k, R, nullptr, nullptr, s, sub, &job);
+    }
+    for (size_t pi = 0; pi < ranges.size(); ++pi) {
+      RBQ_HIP(hipEventSynchronize(events[pi]));
+      const int64_t q0 = ranges[pi].first, q1 = ranges[pi].second;
       const int tasks = std::max(1, std::min<int>(pool.size(), (int)ceil_div(q1 - q0, (int64_t)8)));
       const int64_t per = ceil_div(q1 - q0, (int64_t)tasks);
       for (int64_t r0 = q0; r0 < q1; r0 += per) {
         const int64_t r1 = std::min(q1, r0 + per);
         latch.add(1);
-        const hipEvent_t ready = job.ready;
         pool.submit([=, &latch, &emu, &err, &est]() {
           try {
-            RBQ_HIP(hipEventSynchronize(ready));
             host_rerank_rows(idx->hostX, idx->n, d, hq, hc, R, io.q_k, k, r0, r1, hids, hdist);
           } catch (const Error& e) {
             std::lock_guard<std::mutex> g(emu);

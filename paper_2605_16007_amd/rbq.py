@@ -64,7 +64,7 @@ class Timings(C.Structure):
                 ("group_vectors", C.c_int64), ("group_read_bytes", C.c_int64),
                 ("fused_launches", C.c_int64), ("fused_scan_ms", C.c_float),
                 ("reserved", C.c_int32), ("fused_vectors", C.c_int64),
-                ("fused_read_bytes", C.c_int64)]
+                ("fused_read_bytes", C.c_int64), ("redo_queries", C.c_int64)]
 
 
 class ServerParams(C.Structure):

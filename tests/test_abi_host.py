@@ -106,7 +106,7 @@ def test_struct_sizes_match_header_layout():
     # natural C layout of the public structs (x86-64 / LP64)
     assert C.sizeof(rbq.BuildParams) == 4 + 4 + 8 + 4 + 4 + 8 + 3 * 8 + 4 + 4 + 4 + 4 + 4 + 3 * 4
     assert C.sizeof(rbq.DebugIO) == 14 * 8 + 8 + 8
-    assert C.sizeof(rbq.Timings) == 8 + 7 * 4 + 4 + 5 * 8 + 4 + 4 + 2 * 8 + 8 + 4 + 4 + 2 * 8
+    assert C.sizeof(rbq.Timings) == 8 + 7 * 4 + 4 + 5 * 8 + 4 + 4 + 2 * 8 + 8 + 4 + 4 + 2 * 8 + 8
     assert C.sizeof(rbq.IndexInfo) == 8 + 4 * 4 + 3 * 8 + 4 + 4
     assert C.sizeof(rbq.ServerParams) == 6 * 4 + 8 + 8 * 4
     assert C.sizeof(rbq.ServerStats) == 8 * 8

@@ -215,3 +215,28 @@ def test_many_searches_in_flight_reuse_workspaces():
             assert torch.equal(oi, ref_ids) and torch.equal(od, ref_d)
     finally:
         lib.close()
+
+
+def test_overflow_redo_is_counted_and_exact():
+    """A tiny list-major pool makes queries overflow: they are searched again
+    from scratch, the instrumented pass counts them, and the results equal
+    those of an ample pool."""
+    _say("[edge] pool overflow redo n=20000 d=64 nlist=32")
+    X, Q, idx = make_case(20_000, 64, 32, 300, seed=17)
+    lib = lib_index(X, idx)
+    try:
+        lib.set_option("scan", 2)
+        ref = lib.search(Q, 8, 10, 100)
+        lib.set_timing(True)
+        lib.search(Q, 8, 10, 100)
+        assert lib.timings()["redo_queries"] == 0
+        lib.set_option("pool_cap", 64)
+        lib.set_timing(True)
+        got = lib.search(Q, 8, 10, 100)
+        t = lib.timings()
+        lib.set_timing(False)
+        assert t["redo_queries"] > 0, t
+        np.testing.assert_array_equal(got[0], ref[0])
+        np.testing.assert_array_equal(got[1], ref[1])
+    finally:
+        lib.close()
