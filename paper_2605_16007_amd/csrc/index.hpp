@@ -146,6 +146,12 @@ struct rbq_index {
   // first use and kept with the index
   std::mutex host_mu;
   std::unique_ptr<rbq::ThreadPool> pool;
+  // the GPU parts of host re-rank searches run on one stream of the index,
+  // each search's parts queued whole (host_gpu_mu): concurrent callers then
+  // take turns on the GPU and one's host re-rank overlaps the next one's
+  // GPU work instead of both halves running side by side at half speed
+  hipStream_t host_gpu_stream = nullptr;
+  std::mutex host_gpu_mu;
   std::vector<std::pair<void*, size_t>> pinned_free;
 
   ~rbq_index();

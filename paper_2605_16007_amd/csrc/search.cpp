@@ -943,11 +943,24 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
   };
+  hipStream_t gs = nullptr;
+  {
+    std::lock_guard<std::mutex> g(idx->host_mu);
+    if (!idx->host_gpu_stream) RBQ_HIP(hipStreamCreateWithFlags(&idx->host_gpu_stream, hipStreamNonBlocking));
+    gs = idx->host_gpu_stream;
+  }
+  hipEvent_t inputs = nullptr;  // the caller's stream has its queries ready
+  RBQ_HIP(hipEventCreateWithFlags(&inputs, hipEventDisableTiming));
+  events.push_back(inputs);
+  RBQ_HIP(hipEventRecord(inputs, s));
   try {
-    // every sub-batch's GPU work is queued first; then, as each completes
-    // (the caller sleeps on its event rather than spinning), its re-rank
-    // goes to the host threads, so they only ever hold work that is ready
+    // every sub-batch's GPU work is queued first, on the index's host-path
+    // stream and as one block; then, as each completes (the caller sleeps on
+    // its event rather than spinning), its re-rank goes to the host threads,
+    // so they only ever hold work that is ready
     std::vector<std::pair<int64_t, int64_t>> ranges;
+    std::unique_lock<std::mutex> enqueue(idx->host_gpu_mu);
+    RBQ_HIP(hipStreamWaitEvent(gs, inputs, 0));
     for (int64_t q0 = 0; q0 < nq; q0 += sb) {
       const int64_t q1 = std::min(nq, q0 + sb);
       HostJob job;
@@ -964,10 +977,11 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
         sub.q_R = io.q_R + q0;
       }
       const float* qsrc = q + q0 * d;
-      search_part(idx, qsrc, q1 - q0, nprobe, k, R, nullptr, nullptr, s, sub, &job);
+      search_part(idx, qsrc, q1 - q0, nprobe, k, R, nullptr, nullptr, gs, sub, &job);
     }
+    enqueue.unlock();
     for (size_t pi = 0; pi < ranges.size(); ++pi) {
-      RBQ_HIP(hipEventSynchronize(events[pi]));
+      RBQ_HIP(hipEventSynchronize(events[pi + 1]));
       const int64_t q0 = ranges[pi].first, q1 = ranges[pi].second;
       const int tasks = std::max(1, std::min<int>(pool.size(), (int)ceil_div(q1 - q0, (int64_t)8)));
       const int64_t per = ceil_div(q1 - q0, (int64_t)tasks);
@@ -991,6 +1005,7 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
       }
     }
   } catch (...) {
+    (void)hipStreamSynchronize(gs);
     (void)hipStreamSynchronize(s);
     wait_all();
     throw;

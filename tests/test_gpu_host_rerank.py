@@ -202,3 +202,39 @@ def test_host_parts_leave_results_unchanged(pair):
             host.set_option("host_parts", 65)
     finally:
         host.set_option("host_parts", 0)
+
+
+def test_concurrent_callers_match_sequential(pair):
+    """Several caller threads searching the host index at once (each on its own
+    stream; their GPU parts take turns on the index's host-path stream) get
+    the results of the same searches run one after another."""
+    import threading
+    import torch
+    X, Q, idx, dev, host = pair
+    slices = [Q[i * 500:(i + 1) * 500] for i in range(4)]
+    ref = [host.search(qs, 6, 10, 100) for qs in slices]
+    got = [None] * len(slices)
+    errs = []
+
+    def run(t):
+        try:
+            torch.cuda.set_device(0)
+            st = torch.cuda.Stream()
+            q = torch.from_numpy(slices[t]).cuda()
+            torch.cuda.synchronize()
+            for _ in range(3):
+                ids, dd = host.search(q, 6, 10, 100, stream=st.cuda_stream)
+            st.synchronize()
+            got[t] = (ids.cpu().numpy(), dd.cpu().numpy())
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=run, args=(t,)) for t in range(len(slices))]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errs, errs
+    for (a_ids, a_d), (b_ids, b_d) in zip(ref, got):
+        np.testing.assert_array_equal(a_ids, b_ids)
+        np.testing.assert_array_equal(a_d, b_d)
