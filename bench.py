@@ -46,7 +46,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 EPILOGUE_OPS = 9
 # rows of the 400M x 96 workload's shard (one eighth: nlist 8192)
 SHARD_ROWS = 50_000_000
-# PMC summaries: profiles/<kernel>_<workload>_pmc.md record the HBM bytes per
+# PMC summaries: profiles/<kernel>_<workload>.md record the HBM bytes per
 # launch of one scan kernel at one operating point, with the sha256 of the
 # kernel's source file and the two headers it includes
 _CSRC = os.path.join(ROOT, "paper_2605_16007_amd", "csrc")
@@ -76,7 +76,7 @@ def pmc_traffic(kernel, point):
         sha = source_sha(KERNEL_SOURCES[kernel])
     except (KeyError, OSError):
         return None
-    for summary in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*_pmc.md"))):
+    for summary in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{kernel}_*.md"))):
         text = open(summary).read()
         m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
         t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
