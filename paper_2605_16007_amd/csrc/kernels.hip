@@ -703,16 +703,11 @@ constexpr size_t kTopkLdsMax = 150u << 10;  // dynamic LDS of one selection work
 
 // Sorted top-k of float scores with the row in registers (rows of up to
 // kScoreTopkCols scores: 16 per thread, 256 threads up to 4096 columns, 512
-// above); defined with the register-resident selection. Longer rows are cut
-// into pieces of kScoreTopkCols scores whose k smallest are selected first.
+// above); defined with the register-resident selection. Longer rows stream
+// past a bound set by their first kScoreTopkCols scores.
 constexpr int kScoreTopkCols = 512 * 16;
 static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows);
-static void launch_score_topk_pieces(hipStream_t s, const TopkArgs& a, int rows, int pieces);
-
-int64_t row_topk_scratch_keys(int ncols, int k, int64_t rows) {
-  if (ncols <= kScoreTopkCols) return 0;
-  return rows * ((ncols + kScoreTopkCols - 1) / kScoreTopkCols) * (int64_t)k;
-}
+static void launch_score_topk_long(hipStream_t s, const TopkArgs& a, int rows);
 
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
   if (rows <= 0) return;
@@ -758,20 +753,8 @@ void launch_row_topk(hipStream_t s, TopkArgs a, int rows) {
     launch_score_topk(s, a, rows);
     return;
   }
-  if (a.score && a.sorted && !a.rowcnt && !a.rowk && a.scratch) {
-    // two stages: the k smallest of every piece, then of the pieces' keys
-    // (the row's k smallest are among its pieces' k smallest: the same keys)
-    const int pieces = (a.ncols + kScoreTopkCols - 1) / kScoreTopkCols;
-    RBQ_CHECK(pieces <= 65535, "score top-k: row too long");
-    launch_score_topk_pieces(s, a, rows, pieces);
-    TopkArgs b = a;
-    b.score = nullptr;
-    b.keys = a.scratch;
-    b.ld = (int64_t)pieces * a.k;
-    b.ncols = pieces * a.k;
-    b.scratch = nullptr;
-    b.KP = b.cache_cap = 0;
-    launch_row_topk(s, b, rows);
+  if (a.score && a.sorted && !a.rowcnt && !a.rowk) {
+    launch_score_topk_long(s, a, rows);
     return;
   }
   if (a.score)
@@ -1502,33 +1485,112 @@ __global__ __launch_bounds__(NT) void k_score_topk(TopkArgs a) {
   }
 }
 
-// One piece of a long score row: the k smallest of its (up to NT x KPT)
-// scores as keys with the row's column in the low word, in any order, at
-// cand[(row x pieces + piece) x k]; a piece shorter than k is padded with
-// KEY_NONE.
-template <int NT, int KPT>
-__global__ __launch_bounds__(NT) void k_score_topk_piece(TopkArgs a) {
+// Sorted top-k of a score row longer than one register-resident piece, one
+// workgroup per row. The first NT x KPT scores are selected in registers and
+// their k-th key becomes the bound; the rest of the row streams past in tiles
+// of NT x U scores and only keys below the bound are kept (in LDS, after the k
+// selected ones). A key above the bound has k smaller keys before it, so the
+// kept keys hold the row's k smallest. When the next tile might not fit, the
+// kept keys are cut back to their k smallest and the bound drops to the new
+// k-th key. LDS: NT x KPT keys (dynamic), which must leave room for k keys
+// plus one tile.
+template <int NT, int KPT, int U>
+__global__ __launch_bounds__(NT) void k_score_topk_long(TopkArgs a) {
+  constexpr int CAP = NT * KPT, TILE = NT * U;
+  extern __shared__ uint64_t kept[];  // CAP keys
   __shared__ SelRegShared<NT> sh;
-  const int tid = threadIdx.x;
+  __shared__ uint32_t s_cnt;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int64_t row = blockIdx.x;
-  const int piece = blockIdx.y;
-  const int c0 = piece * NT * KPT;
-  const int n = min(NT * KPT, a.ncols - c0);
-  const int k = a.k;
+  const float* src = a.score + row * a.ld;
+  const int n = a.ncols, k = a.k;  // n > CAP and k <= CAP - TILE (launcher)
   uint64_t v[KPT];
 #pragma unroll
   for (int u = 0; u < KPT; ++u) {
     const int c = u * NT + tid;
-    v[u] = c < n ? key64(a.score[row * a.ld + c0 + c], (uint32_t)(c0 + c)) : KEY_NONE;
+    v[u] = key64(src[c], (uint32_t)c);
   }
-  uint64_t* dst = a.scratch + (row * (int64_t)gridDim.y + piece) * k;
-  (void)select_regs<NT, KPT>(v, n, k, dst, sh);
-  for (int t = min(n, k) + tid; t < k; t += NT) dst[t] = KEY_NONE;
+  uint64_t bound = select_regs<NT, KPT>(v, CAP, k, kept, sh);
+  uint32_t cnt = (uint32_t)k;
+  if (tid == 0) s_cnt = cnt;
+  __syncthreads();
+  for (int c0 = CAP; c0 < n; c0 += TILE) {
+    if (cnt > (uint32_t)(CAP - TILE)) {  // (uniform) cut back to the k smallest
+#pragma unroll
+      for (int u = 0; u < KPT; ++u) {
+        const int i = u * NT + tid;
+        v[u] = i < (int)cnt ? kept[i] : KEY_NONE;
+      }
+      bound = select_regs<NT, KPT>(v, (int)cnt, k, kept, sh);
+      cnt = (uint32_t)k;
+      if (tid == 0) s_cnt = cnt;
+      __syncthreads();
+    }
+    float f[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * NT + tid;
+      f[u] = c < n ? src[c] : 0.f;
+    }
+    uint64_t key[U];
+    uint64_t bal[U];
+    uint32_t wtot = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * NT + tid;
+      key[u] = key64(f[u], (uint32_t)c);
+      bal[u] = __ballot(c < n && key[u] < bound);
+      wtot += (uint32_t)__popcll(bal[u]);
+    }
+    if (wtot) {  // (uniform per wave) one LDS atomic per wave and tile
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(&s_cnt, wtot);
+      base = (uint32_t)__shfl(base, 0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if ((bal[u] >> lane) & 1ull)
+          kept[base + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[u] >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal[u], 0u))] = key[u];
+        base += (uint32_t)__popcll(bal[u]);
+      }
+    }
+    __syncthreads();
+    cnt = s_cnt;
+    __syncthreads();  // (every thread has read the count before the next tile adds to it)
+  }
+  if (cnt > (uint32_t)k) {
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+      const int i = u * NT + tid;
+      v[u] = i < (int)cnt ? kept[i] : KEY_NONE;
+    }
+    (void)select_regs<NT, KPT>(v, (int)cnt, k, kept, sh);
+  }
+  for (int t = k + tid; t < a.KP; t += NT) kept[t] = KEY_NONE;
+  __syncthreads();
+  bitonic_sort_lds(kept, a.KP);
+  for (int t = tid; t < k; t += NT) {
+    const uint64_t x = kept[t];
+    if (a.out_keys) a.out_keys[row * a.ldo + t] = x;
+    if (a.out_low) a.out_low[row * k + t] = x == KEY_NONE ? -1 : (int32_t)(uint32_t)x;
+    if (a.out_val) a.out_val[row * k + t] = x == KEY_NONE ? INFINITY : f32_ord((uint32_t)(x >> 32));
+  }
 }
 
-static void launch_score_topk_pieces(hipStream_t s, const TopkArgs& a, int rows, int pieces) {
-  static_assert(kScoreTopkCols == 512 * 16, "piece width");
-  hipLaunchKernelGGL((k_score_topk_piece<512, 16>), dim3((unsigned)rows, (unsigned)pieces), dim3(512), 0, s, a);
+constexpr int kLongTopkThreads = 512, kLongTopkKpt = 16, kLongTopkU = 8;
+constexpr int kLongTopkMaxK = kLongTopkThreads * (kLongTopkKpt - kLongTopkU);
+
+static void launch_score_topk_long(hipStream_t s, const TopkArgs& a, int rows) {
+  constexpr int cap = kLongTopkThreads * kLongTopkKpt;
+  RBQ_CHECK(a.ncols > cap && a.k <= kLongTopkMaxK && a.KP <= cap, "long score top-k: shape");
+  const size_t lds = (size_t)cap * sizeof(uint64_t);
+  auto kern = k_score_topk_long<kLongTopkThreads, kLongTopkKpt, kLongTopkU>;
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [&] {
+    RBQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  });
+  hipLaunchKernelGGL(kern, dim3((unsigned)rows), dim3(kLongTopkThreads), lds, s, a);
   RBQ_HIP(hipGetLastError());
 }
 

@@ -65,14 +65,9 @@ struct TopkArgs {
   const int32_t* rowk = nullptr;  // per-row selection size (<= k); slots past it are untouched
   bool sorted = true;          // false: the k keys in any order (pool merges)
   int merge_threads = 512;     // pool merges: 512 or 256 threads per row (32 keys per thread)
-  // sorted score rows longer than one register-resident piece: device buffer
-  // of row_topk_scratch_keys(ncols, k, rows) keys for the pieces' selections
-  uint64_t* scratch = nullptr;
   int KP = 0, cache_cap = 0;   // set by the launcher
 };
 void launch_row_topk(hipStream_t s, TopkArgs a, int rows);
-// Keys of scratch a sorted score selection of k of ncols needs (0: none).
-int64_t row_topk_scratch_keys(int ncols, int k, int64_t rows);
 
 // Residual r = qrot_i - crot_j for every (query, probe) pair, B_q-bit
 // quantisation, bit-planes and scalars; or pack injected qu / scalars.

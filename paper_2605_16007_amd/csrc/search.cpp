@@ -77,7 +77,6 @@ __global__ void k_count_group_bytes(const int32_t* cnt, const int32_t* list_len,
 struct Bufs {
   float* qpad = nullptr;
   float* score = nullptr;
-  uint64_t* pcand = nullptr;  // the probe selection's per-piece keys (nlist > 8192)
   int32_t* probes = nullptr;
   float* pscore = nullptr;
   float* qrot = nullptr;
@@ -301,8 +300,6 @@ void layout(const rbq_index* idx, const Plan& P, Carver& c, Bufs& b) {
   if (P.need_qcopy) b.qpad = c.take<float>((size_t)nq * ld);
   if (!P.inj_probes) {
     b.score = c.take<float>((size_t)nq * nlist);
-    const int64_t pk = row_topk_scratch_keys(nlist, P.nprobe, nq);
-    if (pk) b.pcand = c.take<uint64_t>(pk);
   }
   b.probes = c.take<int32_t>(pairs);
   if (dbg && dbg->probe_score) b.pscore = c.take<float>(pairs);
@@ -522,7 +519,6 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       ta.k = nprobe;
       ta.out_low = b.probes;
       ta.out_val = b.pscore;
-      ta.scratch = b.pcand;
       launch_row_topk(s, ta, (int)nq);
     }
     if (mixed) launch_mask_probes(s, b.probes, (int)nq, nprobe, d_np);
@@ -897,7 +893,13 @@ ThreadPool& host_pool(rbq_index* idx) {
   std::lock_guard<std::mutex> g(idx->host_mu);
   if (!idx->pool) {
     int t = idx->host_threads;
-    if (t <= 0) t = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+    // automatic: up to 16, less two when there are 8 or more: the threads
+    // that queue GPU work must not wait for a core (a queue left idle stalls
+    // the GPU), nor may the process exceed its share of the host
+    if (t <= 0) {
+      t = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+      if (t >= 8) t -= 2;
+    }
     idx->pool.reset(new ThreadPool(t));
   }
   return *idx->pool;

@@ -1,9 +1,11 @@
 """Probe selection for more lists than one register-resident row holds
-(nlist > 8192, as at 400M x 96 with 65,536 lists): each 8192-list piece of a
-query's score row gives its nprobe best, and those keys are selected again.
-Checked against the oracle's FP64 probe ranking (lists whose exact distances
-lie within FP32 rounding of the boundary may swap), with ragged last pieces
-and nprobe larger than the last piece."""
+(nlist > 8192, as at 400M x 96 with 65,536 lists): the first 8192 scores of a
+query's row set a bound that the rest of the row streams past, the keys below
+it being cut back to the nprobe best whenever they might overflow. Checked
+against the oracle's FP64 probe ranking (lists whose exact distances lie
+within FP32 rounding of the boundary may swap), with a ragged last tile,
+nprobe up to 4000 and lists ordered far-to-near (every later score passes a
+loose first bound, so the cut-back runs many times per row)."""
 import math
 import sys
 
@@ -23,17 +25,22 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("nlist,nprobe", [(20_000, 128), (20_000, 4000), (65_536, 128), (65_536, 1000)])
-def test_probes_over_pieces(nlist, nprobe):
+@pytest.mark.parametrize("nlist,nprobe,order", [(20_000, 128, "random"), (20_000, 4000, "random"),
+                                                (65_536, 128, "random"), (65_536, 1000, "random"),
+                                                (20_000, 128, "far_first"), (20_000, 4000, "far_first")])
+def test_probes_over_pieces(nlist, nprobe, order):
     from synth import database, get, queries
     from paper_2605_16007_amd import Index
     n = nlist + 5000
     w = get("unit96_400m", n=n, nlist=nlist, nq=NQ, centres=4096)
-    _say(f"[probe pieces] n={n} d={D} nlist={nlist} nprobe={nprobe} queries={NQ}")
+    _say(f"[probe pieces] n={n} d={D} nlist={nlist} nprobe={nprobe} order={order} queries={NQ}")
     X = database(w)
     Q = queries(w)
     rng = np.random.default_rng(nlist + nprobe)
     C = np.asarray(X[np.sort(rng.choice(n, nlist, replace=False))], np.float32)
+    if order == "far_first":  # descending distance to the mean query
+        far = np.sum((C.astype(np.float64) - Q.astype(np.float64).mean(axis=0)) ** 2, axis=1)
+        C = np.ascontiguousarray(C[np.argsort(-far, kind="stable")])
     ix = Index.build(X, nlist, centroids=C, vectors_on_host=False)
     try:
         got = ix.search_debug(Q, nprobe, 10, 100, want={"probes"})["probes"]
