@@ -68,7 +68,9 @@ typedef struct {
                               -1 (default) automatic: HBM when, with the index
                               built, they leave at least max(8 GiB, 1/8 of the
                               device) of device memory free, else host memory */
-  int32_t host_threads;    /* host re-rank threads (0 = hardware concurrency) */
+  int32_t host_threads;    /* host re-rank threads (0: min(16, hardware
+                              threads), less two from 8 up, leaving cores to
+                              the threads that queue GPU work) */
   int32_t borrow_vectors;  /* 1: when the vectors end on the host, the index
                               keeps the caller's rows instead of a copy: x must
                               then be host memory (pageable or pinned) holding
