@@ -476,6 +476,7 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
     # host re-rank: the batch's split into sub-batches (overlap of host and GPU
     # against fuller list-major items), each split tuned for its sub-batch size
     parts_qps = {}
+    hp_used = None  # host sub-batches per batch (-1: the library's rule)
     if host_vectors and args.host_parts < 0:
         for p in (1, 2, 4):
             idx.set_option("host_parts", p)
@@ -488,17 +489,26 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
             log(f"[{role}] {p} host sub-batch(es), {conc} in flight: {parts_qps[str(p)]:.0f} q/s")
         best = int(max(parts_qps, key=parts_qps.get))
         idx.set_option("host_parts", best)
+        hp_used = best
         log(f"[{role}] host sub-batches: " + ", ".join(f"{p}: {q:.0f} q/s" for p, q in parts_qps.items())
             + f"; using {best}")
         if cache and not loaded:
             idx.tune_save(cache)
+        if args.concurrency <= 0:
+            # one batch more in flight, kept if it is faster by more than noise
+            q3 = quick_qps(nprobe, R, steps=9, threads=conc + 1)
+            log(f"[{role}] {best} host sub-batch(es), {conc + 1} in flight: {q3:.0f} q/s")
+            parts_qps[f"{best}@{conc + 1}"] = q3
+            if q3 > 1.02 * parts_qps[str(best)]:
+                conc += 1
     elif host_vectors:
         idx.set_option("host_parts", args.host_parts)
+        hp_used = args.host_parts
 
     idx.set_option("scan", {"auto": 0, "popcount": 1, "mfma": 2}[args.scan])
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
     dd = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
-    nst = max(1, args.streams)
+    nst = args.streams if args.streams > 0 else (1 if host_vectors else 2)
     streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
     outs = [(torch.empty((w.nq, w.k), dtype=torch.int64, device=dev),
              torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)) for _ in range(nst)]
@@ -615,8 +625,7 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
         "config": {"workload": wname, "n": w.n, "d": w.d, "nlist": w.nlist, "nprobe": nprobe,
                    "batch": w.nq, "k": w.k, "rerank_n": R, "bq": w.bq, "rotation": args.rotation,
                    "rerank_on": "host" if host_vectors else "gpu",
-                   "host_parts": (int(max(parts_qps, key=parts_qps.get)) if parts_qps else args.host_parts)
-                   if host_vectors else None,
+                   "host_parts": hp_used,
                    "raw_vectors": "host (2 MiB pages), borrowed" if host_vectors else "HBM",
                    "streams": nst, "batches_in_flight": conc, "parallelism": "none (1 GPU)"},
         "recall_at_10": rec[(nprobe, R)], "recall_queries": gt_n,
@@ -658,14 +667,22 @@ def hbm_placement(w, X, Qall, parts, gt, nprobe, R, args):
         tuned = ix.autotune(Qb[0], nprobe, w.k, R) if not args.no_autotune else None
         free_b, _ = torch.cuda.mem_get_info()
         log(f"[headline] HBM placement tuned; {free_b / 1e9:.1f} GB free")
-        ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
-        dd = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
-        for s in range(args.warmup):
-            ix.search(Qb[s % len(Qb)], nprobe, w.k, R, ids=ids, dists=dd)
+        # batches alternate over two streams from this thread, as in the
+        # device-resident timing of measure()
+        nst = args.streams if args.streams > 0 else 2
+        sts = [torch.cuda.Stream(device=dev) for _ in range(nst)]
+        outs = [(torch.empty((w.nq, w.k), dtype=torch.int64, device=dev),
+                 torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)) for _ in range(nst)]
+
+        def step(s):
+            ix.search(Qb[s % len(Qb)], nprobe, w.k, R, ids=outs[s % nst][0], dists=outs[s % nst][1],
+                      stream=sts[s % nst].cuda_stream)
+        for s in range(max(args.warmup, nst)):
+            step(s)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(args.steps):
-            ix.search(Qb[s % len(Qb)], nprobe, w.k, R, ids=ids, dists=dd)
+            step(s)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         r_ids, _ = ix.search(Qb[0], nprobe, w.k, R)
@@ -674,6 +691,7 @@ def hbm_placement(w, X, Qall, parts, gt, nprobe, R, args):
         out = {"qps": w.nq * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
                "recall_at_10": rec, "nprobe": nprobe, "rerank_n": R, "rerank_on": "gpu",
                "raw_vectors": "HBM", "device_bytes": ix.info()["device_bytes"], "build_s": build_s,
+               "streams": nst,
                "autotune": tuned}
     finally:
         ix.close()
@@ -720,8 +738,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--streams", type=int, default=1,
-                    help="HIP streams the timed batches alternate over (each batch whole on one)")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="HIP streams the timed batches alternate over from one caller thread (each "
+                         "batch whole on one); 0: two when the raw vectors are in HBM, else one")
     ap.add_argument("--workload", default="unit96_400m")
     ap.add_argument("--shard", action="store_true",
                     help="the 400M-row workload's first 50M rows (nlist 8192) instead of the whole set")
