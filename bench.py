@@ -310,6 +310,27 @@ def roofline_of(tm, w, wname, nprobe, R, scan):
             "bytes_per_launch": d["schedule_bytes_per_launch"], "forms": forms}
 
 
+def alternating_qps(idx, Qb, nprobe, k, R, n_streams, steps):
+    """Queries/s of `steps` searches issued from this thread, batch s on
+    stream s mod n_streams (each stream with its own outputs)."""
+    import torch
+    dev = Qb[0].device
+    sts = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
+    outs = [(torch.empty((Qb[0].shape[0], k), dtype=torch.int64, device=dev),
+             torch.empty((Qb[0].shape[0], k), dtype=torch.float32, device=dev)) for _ in range(n_streams)]
+
+    def go(count):
+        for s in range(count):
+            idx.search(Qb[s % len(Qb)], nprobe, k, R, ids=outs[s % n_streams][0],
+                       dists=outs[s % n_streams][1], stream=sts[s % n_streams].cuda_stream)
+    go(n_streams)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    go(steps)
+    torch.cuda.synchronize()
+    return Qb[0].shape[0] * steps / (time.perf_counter() - t)
+
+
 def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
     """Build the index of workload ``w``, choose its operating point, time it.
     Returns the fields of one result line (``role`` names it in the log)."""
@@ -509,6 +530,14 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
     dd = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
     nst = args.streams if args.streams > 0 else (1 if host_vectors else 2)
+    streams_qps = {}
+    if args.streams <= 0 and not host_vectors:
+        # device-resident batches: two or three in flight from this thread
+        # (the faster is timed)
+        streams_qps = {str(n_): alternating_qps(idx, Qb, nprobe, w.k, R, n_, 12) for n_ in (2, 3)}
+        nst = int(max(streams_qps, key=streams_qps.get))
+        log(f"[{role}] streams: " + ", ".join(f"{k_}: {v_:.0f} q/s" for k_, v_ in streams_qps.items())
+            + f"; using {nst}")
     streams = [torch.cuda.Stream(device=dev) for _ in range(nst)]
     outs = [(torch.empty((w.nq, w.k), dtype=torch.int64, device=dev),
              torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)) for _ in range(nst)]
@@ -632,7 +661,7 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
         "recall_by_point": {f"nprobe={p},rerank={r}": v for (p, r), v in rec.items()},
         "probe_recall_by_nprobe": {str(p): v for p, v in prec.items()},
         "qps_at_listed_nprobe": listed_qps, "qps_by_scan_form": variants, "autotune": tuned,
-        "qps_by_host_parts": parts_qps,
+        "qps_by_host_parts": parts_qps, "qps_by_streams": streams_qps,
         # queries whose list-major pool overflowed and were searched again
         "redo_queries_per_batch": tm["redo_queries"] / max(1, tm["searches"]),
         "p50_ms": p50, "p99_ms": p99,
@@ -667,9 +696,14 @@ def hbm_placement(w, X, Qall, parts, gt, nprobe, R, args):
         tuned = ix.autotune(Qb[0], nprobe, w.k, R) if not args.no_autotune else None
         free_b, _ = torch.cuda.mem_get_info()
         log(f"[headline] HBM placement tuned; {free_b / 1e9:.1f} GB free")
-        # batches alternate over two streams from this thread, as in the
-        # device-resident timing of measure()
-        nst = args.streams if args.streams > 0 else 2
+        # batches alternate over two or three streams from this thread, as in
+        # the device-resident timing of measure()
+        streams_qps = {}
+        if args.streams > 0:
+            nst = args.streams
+        else:
+            streams_qps = {str(n_): alternating_qps(ix, Qb, nprobe, w.k, R, n_, 8) for n_ in (2, 3)}
+            nst = int(max(streams_qps, key=streams_qps.get))
         sts = [torch.cuda.Stream(device=dev) for _ in range(nst)]
         outs = [(torch.empty((w.nq, w.k), dtype=torch.int64, device=dev),
                  torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)) for _ in range(nst)]
@@ -691,7 +725,7 @@ def hbm_placement(w, X, Qall, parts, gt, nprobe, R, args):
         out = {"qps": w.nq * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
                "recall_at_10": rec, "nprobe": nprobe, "rerank_n": R, "rerank_on": "gpu",
                "raw_vectors": "HBM", "device_bytes": ix.info()["device_bytes"], "build_s": build_s,
-               "streams": nst,
+               "streams": nst, "qps_by_streams": streams_qps,
                "autotune": tuned}
     finally:
         ix.close()
@@ -740,7 +774,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--streams", type=int, default=0,
                     help="HIP streams the timed batches alternate over from one caller thread (each "
-                         "batch whole on one); 0: two when the raw vectors are in HBM, else one")
+                         "batch whole on one); 0: two or three (the faster) when the raw vectors are "
+                         "in HBM, else one")
     ap.add_argument("--workload", default="unit96_400m")
     ap.add_argument("--shard", action="store_true",
                     help="the 400M-row workload's first 50M rows (nlist 8192) instead of the whole set")
