@@ -974,6 +974,132 @@ void launch_quant(hipStream_t s, const float* qrot, int ldq, const float* crot, 
   RBQ_HIP(hipGetLastError());
 }
 
+// LDS of a register-resident selection (select_regs) by NT threads.
+template <int NT>
+struct SelRegShared {
+  uint32_t hist[4][256];
+  uint32_t wsum[NT / 64 > 4 ? NT / 64 : 4];
+  uint32_t digit, rem, bucket;
+  uint64_t lo[NT / 64], hi[NT / 64];
+};
+
+// The k smallest of the n keys held KPT per thread (key u of thread t is key
+// u * NT + t; keys at n and beyond are ignored) written to dst[0..k) in any
+// order; returns the k-th smallest, or KEY_NONE when n <= k (then every key is
+// written). Every thread must call it; the keys must not live in dst's range
+// of memory except in these registers (all reads are done before the first
+// write, behind a barrier). Ends with a barrier.
+template <int NT, int KPT>
+__device__ uint64_t select_regs(const uint64_t (&v)[KPT], int n, int k, uint64_t* dst, SelRegShared<NT>& sh) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto valid = [&](int u) { return u * NT + tid < n; };
+  uint64_t lo = ~0ull, hi = 0;
+#pragma unroll
+  for (int u = 0; u < KPT; ++u)
+    if (valid(u)) {
+      lo = v[u] < lo ? v[u] : lo;
+      hi = v[u] > hi ? v[u] : hi;
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (lane == 0) {
+    sh.lo[wave] = lo;
+    sh.hi[wave] = hi;
+  }
+  __syncthreads();
+  lo = sh.lo[0];
+  hi = sh.hi[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    lo = sh.lo[w] < lo ? sh.lo[w] : lo;
+    hi = sh.hi[w] > hi ? sh.hi[w] : hi;
+  }
+  const bool take_all = n <= k;
+  uint64_t prefix = 0, pmask = 0;
+  uint32_t rem = (uint32_t)(take_all ? n : k);
+  if (!take_all) {
+    const uint64_t diff = lo ^ hi;
+    const int top = diff ? 63 - __clzll((long long)diff) : -1;
+    if (top < 63) {
+      pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
+      prefix = lo & pmask;
+    }
+    for (int hb = top; hb >= 0;) {
+      const int lb = hb >= 7 ? hb - 7 : 0;
+      const uint64_t dmask = (2ull << (hb - lb)) - 1ull;
+      for (int t = tid; t < 4 * 256; t += NT) (&sh.hist[0][0])[t] = 0u;
+      __syncthreads();
+      uint32_t* hw = sh.hist[wave & 3];
+#pragma unroll
+      for (int u = 0; u < KPT; ++u)
+        if (valid(u) && (v[u] & pmask) == prefix) atomicAdd(&hw[(v[u] >> lb) & dmask], 1u);
+      __syncthreads();
+      uint32_t h = 0;
+      if (tid < 256) h = sh.hist[0][tid] + sh.hist[1][tid] + sh.hist[2][tid] + sh.hist[3][tid];
+      const uint32_t incl = hist_incl_scan<NT>(h, sh.wsum);
+      const uint32_t excl = incl - h;
+      if (tid < 256 && excl < rem && rem <= incl) {
+        sh.digit = (uint32_t)tid;
+        sh.rem = rem - excl;
+        sh.bucket = h;
+      }
+      __syncthreads();
+      prefix |= (uint64_t)sh.digit << lb;
+      pmask |= dmask << lb;
+      rem = sh.rem;
+      const uint32_t bucket = sh.bucket;
+      __syncthreads();
+      if (bucket == rem) break;
+      hb = lb - 1;
+    }
+  }
+  // keys below the boundary bucket fill [0, k - rem), boundary keys fill
+  // [k - rem, k) until rem are taken (take_all: every key)
+  const uint64_t hi_key = take_all ? ~0ull : (prefix | ~pmask);
+  const uint64_t lt_key = take_all ? 0ull : prefix;
+  const uint32_t nlt = take_all ? 0u : (uint32_t)k - rem;
+  uint32_t clt = 0, ceq = 0;
+#pragma unroll
+  for (int u = 0; u < KPT; ++u)
+    if (valid(u)) {
+      clt += v[u] < lt_key ? 1u : 0u;
+      ceq += (v[u] >= lt_key && v[u] <= hi_key) ? 1u : 0u;
+    }
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan<NT>((clt << 16) | ceq, sh.wsum, &tot);
+  uint32_t plt = ex >> 16, peq = ex & 0xFFFFu;
+  uint64_t mx = 0;
+#pragma unroll
+  for (int u = 0; u < KPT; ++u)
+    if (valid(u)) {
+      if (v[u] < lt_key) {
+        dst[plt++] = v[u];
+        mx = v[u] > mx ? v[u] : mx;
+      } else if (v[u] <= hi_key) {
+        if (peq < rem) {
+          dst[nlt + peq] = v[u];
+          mx = v[u] > mx ? v[u] : mx;
+        }
+        ++peq;
+      }
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if (lane == 0) sh.hi[wave] = mx;
+  __syncthreads();
+  uint64_t kth = sh.hi[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) kth = sh.hi[w] > kth ? sh.hi[w] : kth;
+  __syncthreads();
+  return take_all ? KEY_NONE : kth;
+}
+
 // ---------------------------------------------------------------------------
 // Code scan (query-major popcount form). One workgroup per (query, probe)
 // item, ordered probe-rank-major so that every query's nearest lists are
@@ -1331,131 +1457,6 @@ constexpr int kFusedNT = 512;                 // threads per workgroup
 constexpr int kFusedKPT = 16;                 // buffer keys per thread in a selection
 constexpr int kFusedCap = kFusedNT * kFusedKPT;  // LDS buffer keys (64 KB)
 
-template <int NT>
-struct SelRegShared {
-  uint32_t hist[4][256];
-  uint32_t wsum[NT / 64 > 4 ? NT / 64 : 4];
-  uint32_t digit, rem, bucket;
-  uint64_t lo[NT / 64], hi[NT / 64];
-};
-
-// The k smallest of the n keys held KPT per thread (key u of thread t is key
-// u * NT + t; keys at n and beyond are ignored) written to dst[0..k) in any
-// order; returns the k-th smallest, or KEY_NONE when n <= k (then every key is
-// written). Every thread must call it; the keys must not live in dst's range
-// of memory except in these registers (all reads are done before the first
-// write, behind a barrier). Ends with a barrier.
-template <int NT, int KPT>
-__device__ uint64_t select_regs(const uint64_t (&v)[KPT], int n, int k, uint64_t* dst, SelRegShared<NT>& sh) {
-  constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  auto valid = [&](int u) { return u * NT + tid < n; };
-  uint64_t lo = ~0ull, hi = 0;
-#pragma unroll
-  for (int u = 0; u < KPT; ++u)
-    if (valid(u)) {
-      lo = v[u] < lo ? v[u] : lo;
-      hi = v[u] > hi ? v[u] : hi;
-    }
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
-    lo = l2 < lo ? l2 : lo;
-    hi = h2 > hi ? h2 : hi;
-  }
-  if (lane == 0) {
-    sh.lo[wave] = lo;
-    sh.hi[wave] = hi;
-  }
-  __syncthreads();
-  lo = sh.lo[0];
-  hi = sh.hi[0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) {
-    lo = sh.lo[w] < lo ? sh.lo[w] : lo;
-    hi = sh.hi[w] > hi ? sh.hi[w] : hi;
-  }
-  const bool take_all = n <= k;
-  uint64_t prefix = 0, pmask = 0;
-  uint32_t rem = (uint32_t)(take_all ? n : k);
-  if (!take_all) {
-    const uint64_t diff = lo ^ hi;
-    const int top = diff ? 63 - __clzll((long long)diff) : -1;
-    if (top < 63) {
-      pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
-      prefix = lo & pmask;
-    }
-    for (int hb = top; hb >= 0;) {
-      const int lb = hb >= 7 ? hb - 7 : 0;
-      const uint64_t dmask = (2ull << (hb - lb)) - 1ull;
-      for (int t = tid; t < 4 * 256; t += NT) (&sh.hist[0][0])[t] = 0u;
-      __syncthreads();
-      uint32_t* hw = sh.hist[wave & 3];
-#pragma unroll
-      for (int u = 0; u < KPT; ++u)
-        if (valid(u) && (v[u] & pmask) == prefix) atomicAdd(&hw[(v[u] >> lb) & dmask], 1u);
-      __syncthreads();
-      uint32_t h = 0;
-      if (tid < 256) h = sh.hist[0][tid] + sh.hist[1][tid] + sh.hist[2][tid] + sh.hist[3][tid];
-      const uint32_t incl = hist_incl_scan<NT>(h, sh.wsum);
-      const uint32_t excl = incl - h;
-      if (tid < 256 && excl < rem && rem <= incl) {
-        sh.digit = (uint32_t)tid;
-        sh.rem = rem - excl;
-        sh.bucket = h;
-      }
-      __syncthreads();
-      prefix |= (uint64_t)sh.digit << lb;
-      pmask |= dmask << lb;
-      rem = sh.rem;
-      const uint32_t bucket = sh.bucket;
-      __syncthreads();
-      if (bucket == rem) break;
-      hb = lb - 1;
-    }
-  }
-  // keys below the boundary bucket fill [0, k - rem), boundary keys fill
-  // [k - rem, k) until rem are taken (take_all: every key)
-  const uint64_t hi_key = take_all ? ~0ull : (prefix | ~pmask);
-  const uint64_t lt_key = take_all ? 0ull : prefix;
-  const uint32_t nlt = take_all ? 0u : (uint32_t)k - rem;
-  uint32_t clt = 0, ceq = 0;
-#pragma unroll
-  for (int u = 0; u < KPT; ++u)
-    if (valid(u)) {
-      clt += v[u] < lt_key ? 1u : 0u;
-      ceq += (v[u] >= lt_key && v[u] <= hi_key) ? 1u : 0u;
-    }
-  uint32_t tot;
-  const uint32_t ex = block_excl_scan<NT>((clt << 16) | ceq, sh.wsum, &tot);
-  uint32_t plt = ex >> 16, peq = ex & 0xFFFFu;
-  uint64_t mx = 0;
-#pragma unroll
-  for (int u = 0; u < KPT; ++u)
-    if (valid(u)) {
-      if (v[u] < lt_key) {
-        dst[plt++] = v[u];
-        mx = v[u] > mx ? v[u] : mx;
-      } else if (v[u] <= hi_key) {
-        if (peq < rem) {
-          dst[nlt + peq] = v[u];
-          mx = v[u] > mx ? v[u] : mx;
-        }
-        ++peq;
-      }
-    }
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t o = __shfl_xor(mx, off);
-    mx = o > mx ? o : mx;
-  }
-  if (lane == 0) sh.hi[wave] = mx;
-  __syncthreads();
-  uint64_t kth = sh.hi[0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) kth = sh.hi[w] > kth ? sh.hi[w] : kth;
-  __syncthreads();
-  return take_all ? KEY_NONE : kth;
-}
-
 // Sorted top-k of a row of float scores (key = ordered score << 32 | column):
 // the row in registers (16 per thread), the k smallest selected, then an LDS
 // bitonic sort of those k.
@@ -1485,22 +1486,49 @@ __global__ __launch_bounds__(NT) void k_score_topk(TopkArgs a) {
   }
 }
 
+// Appends the keys whose pass flag is set to kept[] at the running count
+// *cnt (LDS): one ballot per key slot and one LDS atomic per wave.
+template <int U>
+__device__ inline void append_kept(const uint64_t (&key)[U], const bool (&pass)[U], uint64_t* kept,
+                                   uint32_t* cnt) {
+  const int lane = threadIdx.x & 63;
+  uint64_t bal[U];
+  uint32_t wtot = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    bal[u] = __ballot(pass[u]);
+    wtot += (uint32_t)__popcll(bal[u]);
+  }
+  if (wtot == 0) return;  // (uniform per wave)
+  uint32_t base = 0;
+  if (lane == 0) base = atomicAdd(cnt, wtot);
+  base = (uint32_t)__shfl(base, 0);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (pass[u])
+      kept[base + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[u] >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal[u], 0u))] = key[u];
+    base += (uint32_t)__popcll(bal[u]);
+  }
+}
+
 // Sorted top-k of a score row longer than one register-resident piece, one
-// workgroup per row. The first NT x KPT scores are selected in registers and
-// their k-th key becomes the bound; the rest of the row streams past in tiles
-// of NT x U scores and only keys below the bound are kept (in LDS, after the k
-// selected ones). A key above the bound has k smaller keys before it, so the
-// kept keys hold the row's k smallest. When the next tile might not fit, the
-// kept keys are cut back to their k smallest and the bound drops to the new
-// k-th key. LDS: NT x KPT keys (dynamic), which must leave room for k keys
-// plus one tile.
-template <int NT, int KPT, int U>
-__global__ __launch_bounds__(NT) void k_score_topk_long(TopkArgs a) {
+// workgroup per row. A bound comes from the first NT x KPT scores: for
+// k <= NT / 2 the k-th smallest of the threads' minima (k distinct keys lie
+// at or below it), else the k-th smallest of all of them. The first piece's
+// keys up to the bound are kept (in LDS); the rest of the row streams past in
+// tiles of NT x U scores and only keys below the bound are kept. A key above
+// the bound has k smaller keys before it, so the kept keys hold the row's k
+// smallest. When the next tile might not fit, the kept keys are cut back to
+// their k smallest and the bound drops to the new k-th key. LDS: NT x KPT keys
+// (dynamic), which must leave room for k keys plus one tile.
+template <int NT, int KPT, int U, int PD, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_score_topk_long(TopkArgs a) {
   constexpr int CAP = NT * KPT, TILE = NT * U;
   extern __shared__ uint64_t kept[];  // CAP keys
   __shared__ SelRegShared<NT> sh;
   __shared__ uint32_t s_cnt;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x;
   const int64_t row = blockIdx.x;
   const float* src = a.score + row * a.ld;
   const int n = a.ncols, k = a.k;  // n > CAP and k <= CAP - TILE (launcher)
@@ -1510,10 +1538,39 @@ __global__ __launch_bounds__(NT) void k_score_topk_long(TopkArgs a) {
     const int c = u * NT + tid;
     v[u] = key64(src[c], (uint32_t)c);
   }
-  uint64_t bound = select_regs<NT, KPT>(v, CAP, k, kept, sh);
-  uint32_t cnt = (uint32_t)k;
-  if (tid == 0) s_cnt = cnt;
-  __syncthreads();
+  // the scores of the next PD tiles are loaded ahead, so their loads are in
+  // flight during the selection, the appends and the barriers before them
+  float f[PD][U];
+  auto load_tile = [&](int c0, float (&dst)[U]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * NT + tid;
+      dst[u] = c < n ? src[c] : 0.f;
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < PD; ++p) load_tile(CAP + p * TILE, f[p]);
+  uint64_t bound;
+  uint32_t cnt;
+  if (k <= NT / 2) {
+    uint64_t m[1] = {v[0]};
+#pragma unroll
+    for (int u = 1; u < KPT; ++u) m[0] = v[u] < m[0] ? v[u] : m[0];
+    bound = select_regs<NT, 1>(m, NT, k, kept, sh);  // (kept[] as scratch; ends with a barrier)
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+    bool pass[KPT];
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) pass[u] = v[u] <= bound;
+    append_kept<KPT>(v, pass, kept, &s_cnt);
+    __syncthreads();
+    cnt = s_cnt;
+  } else {
+    bound = select_regs<NT, KPT>(v, CAP, k, kept, sh);
+    cnt = (uint32_t)k;
+    if (tid == 0) s_cnt = cnt;
+  }
+  __syncthreads();  // (every thread has the count before the next change to it)
   for (int c0 = CAP; c0 < n; c0 += TILE) {
     if (cnt > (uint32_t)(CAP - TILE)) {  // (uniform) cut back to the k smallest
 #pragma unroll
@@ -1526,34 +1583,23 @@ __global__ __launch_bounds__(NT) void k_score_topk_long(TopkArgs a) {
       if (tid == 0) s_cnt = cnt;
       __syncthreads();
     }
-    float f[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = c0 + u * NT + tid;
-      f[u] = c < n ? src[c] : 0.f;
-    }
+    float fn[U];
+    load_tile(c0 + PD * TILE, fn);
     uint64_t key[U];
-    uint64_t bal[U];
-    uint32_t wtot = 0;
+    bool pass[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * NT + tid;
-      key[u] = key64(f[u], (uint32_t)c);
-      bal[u] = __ballot(c < n && key[u] < bound);
-      wtot += (uint32_t)__popcll(bal[u]);
+      key[u] = key64(f[0][u], (uint32_t)c);
+      pass[u] = c < n && key[u] < bound;
     }
-    if (wtot) {  // (uniform per wave) one LDS atomic per wave and tile
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(&s_cnt, wtot);
-      base = (uint32_t)__shfl(base, 0);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if ((bal[u] >> lane) & 1ull)
-          kept[base + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[u] >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal[u], 0u))] = key[u];
-        base += (uint32_t)__popcll(bal[u]);
-      }
-    }
+    for (int p = 0; p + 1 < PD; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) f[p][u] = f[p + 1][u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) f[PD - 1][u] = fn[u];
+    append_kept<U>(key, pass, kept, &s_cnt);
     __syncthreads();
     cnt = s_cnt;
     __syncthreads();  // (every thread has read the count before the next tile adds to it)
@@ -1577,21 +1623,31 @@ __global__ __launch_bounds__(NT) void k_score_topk_long(TopkArgs a) {
   }
 }
 
-constexpr int kLongTopkThreads = 512, kLongTopkKpt = 16, kLongTopkU = 8;
-constexpr int kLongTopkMaxK = kLongTopkThreads * (kLongTopkKpt - kLongTopkU);
-
-static void launch_score_topk_long(hipStream_t s, const TopkArgs& a, int rows) {
-  constexpr int cap = kLongTopkThreads * kLongTopkKpt;
-  RBQ_CHECK(a.ncols > cap && a.k <= kLongTopkMaxK && a.KP <= cap, "long score top-k: shape");
+// Two shapes: up to 4096 selected keys from a first piece of 8192 scores
+// (512 threads, 64 KB of LDS, two rows per CU, one tile of 4096 loaded
+// ahead), and for k <= 256 a first piece of 2048 scores (256 threads, 16 KB,
+// five rows per CU, two tiles of 1024 ahead), so that more score bytes are in
+// flight per CU.
+template <int NT, int KPT, int U, int PD, int WPE>
+static void launch_score_topk_long_as(hipStream_t s, const TopkArgs& a, int rows) {
+  constexpr int cap = NT * KPT;
+  RBQ_CHECK(a.ncols > cap && a.k <= cap - NT * U && a.KP <= cap, "long score top-k: shape");
   const size_t lds = (size_t)cap * sizeof(uint64_t);
-  auto kern = k_score_topk_long<kLongTopkThreads, kLongTopkKpt, kLongTopkU>;
+  auto kern = k_score_topk_long<NT, KPT, U, PD, WPE>;
   static std::once_flag attr_once;
   std::call_once(attr_once, [&] {
     RBQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   });
-  hipLaunchKernelGGL(kern, dim3((unsigned)rows), dim3(kLongTopkThreads), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)rows), dim3(NT), lds, s, a);
   RBQ_HIP(hipGetLastError());
+}
+
+static void launch_score_topk_long(hipStream_t s, const TopkArgs& a, int rows) {
+  if (a.k <= 256)
+    launch_score_topk_long_as<256, 8, 4, 2, 5>(s, a, rows);
+  else
+    launch_score_topk_long_as<512, 16, 8, 1, 4>(s, a, rows);
 }
 
 static void launch_score_topk(hipStream_t s, const TopkArgs& a, int rows) {

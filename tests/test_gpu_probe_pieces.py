@@ -1,11 +1,12 @@
 """Probe selection for more lists than one register-resident row holds
-(nlist > 8192, as at 400M x 96 with 65,536 lists): the first 8192 scores of a
-query's row set a bound that the rest of the row streams past, the keys below
-it being cut back to the nprobe best whenever they might overflow. Checked
-against the oracle's FP64 probe ranking (lists whose exact distances lie
-within FP32 rounding of the boundary may swap), with a ragged last tile,
-nprobe up to 4000 and lists ordered far-to-near (every later score passes a
-loose first bound, so the cut-back runs many times per row)."""
+(nlist > 8192, as at 400M x 96 with 65,536 lists): the first 2048 scores
+(nprobe <= 256) or 8192 of a query's row set a bound that the rest of the row
+streams past, the keys below it being cut back to the nprobe best whenever
+they might overflow. Checked against the oracle's FP64 probe ranking (lists
+whose exact distances lie within FP32 rounding of the boundary may swap),
+with a ragged last tile, nprobe on both sides of 256 and up to 4000, and
+lists ordered far-to-near (every later score passes a loose first bound, so
+the cut-back runs many times per row)."""
 import math
 import sys
 
@@ -27,7 +28,8 @@ def _say(*a):
 
 @pytest.mark.parametrize("nlist,nprobe,order", [(20_000, 128, "random"), (20_000, 4000, "random"),
                                                 (65_536, 128, "random"), (65_536, 1000, "random"),
-                                                (20_000, 128, "far_first"), (20_000, 4000, "far_first")])
+                                                (20_000, 128, "far_first"), (20_000, 4000, "far_first"),
+                                                (65_536, 256, "far_first"), (20_000, 257, "random")])
 def test_probes_over_pieces(nlist, nprobe, order):
     from synth import database, get, queries
     from paper_2605_16007_amd import Index
