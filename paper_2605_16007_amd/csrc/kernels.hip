@@ -1126,10 +1126,136 @@ __device__ void sel_compact(uint64_t* sel, int cap, int R, int* s_n, uint64_t* s
   __syncthreads();
 }
 
+// LDS of the popcount scan's radix cut-back.
+struct PopcCutShared {
+  uint32_t hist[256];
+  uint32_t wsum[4];
+  uint32_t digit, rem, bucket, nlt, neq;
+  uint64_t lo[4], hi[4];
+};
+
+// The k smallest of the unique keys src[0..n) (k < n) written to dst[0..k)
+// in any order by a 256-thread workgroup; returns the k-th smallest. An
+// MSB-first radix select whose passes read the keys from LDS (8-bit digits
+// from the highest bit in which the keys differ), so the caller's registers
+// stay free; keys below the boundary digit and the boundary bucket (taken
+// whole) are then appended with one LDS atomic per wave. src and dst must not
+// overlap. Ends with a barrier.
+__device__ uint64_t popc_radix_cut(const uint64_t* src, int n, int k, uint64_t* dst, PopcCutShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t lo = ~0ull, hi = 0;
+  for (int t = tid; t < n; t += 256) {
+    const uint64_t x = src[t];
+    lo = x < lo ? x : lo;
+    hi = x > hi ? x : hi;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (lane == 0) {
+    sh.lo[wave] = lo;
+    sh.hi[wave] = hi;
+  }
+  if (tid == 0) sh.nlt = sh.neq = 0u;
+  __syncthreads();
+  lo = sh.lo[0];
+  hi = sh.hi[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) {
+    lo = sh.lo[w] < lo ? sh.lo[w] : lo;
+    hi = sh.hi[w] > hi ? sh.hi[w] : hi;
+  }
+  const uint64_t diff = lo ^ hi;
+  const int top = diff ? 63 - __clzll((long long)diff) : -1;
+  uint64_t prefix = 0, pmask = 0;
+  if (top < 63) {
+    pmask = top < 0 ? ~0ull : ~((2ull << top) - 1ull);
+    prefix = lo & pmask;
+  }
+  uint32_t rem = (uint32_t)k;
+  for (int hb = top; hb >= 0;) {
+    const int lb = hb >= 7 ? hb - 7 : 0;
+    const uint64_t dmask = (2ull << (hb - lb)) - 1ull;
+    sh.hist[tid] = 0u;
+    __syncthreads();
+    for (int t = tid; t < n; t += 256) {
+      const uint64_t x = src[t];
+      if ((x & pmask) == prefix) atomicAdd(&sh.hist[(x >> lb) & dmask], 1u);
+    }
+    __syncthreads();
+    const uint32_t h = sh.hist[tid];
+    const uint32_t incl = hist_incl_scan<256>(h, sh.wsum);
+    const uint32_t excl = incl - h;
+    if (excl < rem && rem <= incl) {
+      sh.digit = (uint32_t)tid;
+      sh.rem = rem - excl;
+      sh.bucket = h;
+    }
+    __syncthreads();
+    prefix |= (uint64_t)sh.digit << lb;
+    pmask |= dmask << lb;
+    rem = sh.rem;
+    const uint32_t bucket = sh.bucket;
+    __syncthreads();
+    if (bucket == rem) break;
+    hb = lb - 1;
+  }
+  // keys below the prefix fill [0, k - rem), boundary keys [k - rem, k)
+  const uint64_t hi_key = prefix | ~pmask;
+  const uint32_t nlt = (uint32_t)k - rem;
+  uint64_t mx = 0;
+  for (int t0 = 0; t0 < n; t0 += 256) {
+    const int t = t0 + tid;
+    const uint64_t x = t < n ? src[t] : KEY_NONE;
+    const bool blt = t < n && x < prefix;
+    const bool beq = t < n && x >= prefix && x <= hi_key;
+    const uint64_t mlt = __ballot(blt), meq = __ballot(beq);
+    uint32_t b0 = 0, e0 = 0;
+    if (lane == 0) {
+      if (mlt) b0 = atomicAdd(&sh.nlt, (uint32_t)__popcll(mlt));
+      if (meq) e0 = atomicAdd(&sh.neq, (uint32_t)__popcll(meq));
+    }
+    b0 = (uint32_t)__shfl(b0, 0);
+    e0 = (uint32_t)__shfl(e0, 0);
+    if (blt) {
+      dst[b0 + lane_prefix(mlt)] = x;
+      mx = x > mx ? x : mx;
+    }
+    if (beq) {
+      const uint32_t q = e0 + lane_prefix(meq);
+      if (q < rem) {
+        dst[nlt + q] = x;
+        mx = x > mx ? x : mx;
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  if (lane == 0) sh.hi[wave] = mx;
+  __syncthreads();
+  uint64_t kth = sh.hi[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) kth = sh.hi[w] > kth ? sh.hi[w] : kth;
+  __syncthreads();
+  return kth;
+}
+
+// Buffers of up to this many keys are cut back by popc_radix_cut into a
+// second buffer of the same size; longer ones by an LDS bitonic sort in place.
+constexpr int kPopcRadixCap = 1024;
+
 template <int WT, int BQT, bool DUMP>
 __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
-  extern __shared__ uint64_t sel[];
+  extern __shared__ uint64_t sel[];  // cap keys (two buffers of cap when cap <= kPopcRadixCap)
   __shared__ uint32_t s_cnt[3];  // appends of round r counted in s_cnt[r % 3]
+  __shared__ PopcCutShared cs;
+  const bool radix = cap <= kPopcRadixCap;
+  uint64_t* buf = sel;          // the buffer being filled
+  uint64_t* spare = sel + cap;  // (radix) the other one
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int W = WT > 0 ? WT : a.L.W;
   const int BQ = BQT > 0 ? BQT : a.Q.bqs;
@@ -1225,28 +1351,42 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
       uint32_t off = 0;
       if (lane == 0) off = (uint32_t)fill + atomicAdd(&s_cnt[par], (uint32_t)__popcll(mask));
       off = __shfl(off, 0);
-      if (pass) sel[off + lane_prefix(mask)] = key;
+      if (pass) buf[off + lane_prefix(mask)] = key;
     }
     __syncthreads();
     fill += (int)s_cnt[par];
     ++rr;
     if (fill > cap - 256) {  // the next round could overflow: keep the best R
-      for (int t = fill + tid; t < cap; t += 256) sel[t] = KEY_NONE;
-      __syncthreads();
-      bitonic_sort_lds(sel, cap);  // (ends with a barrier)
-      if (fill >= R) {
-        thr = sel[R - 1];
+      if (radix) {  // (fill > cap - 256 >= R)
+        thr = popc_radix_cut(buf, fill, R, spare, cs);
+        uint64_t* t = buf;
+        buf = spare;
+        spare = t;
         fill = R;
+      } else {
+        for (int t = fill + tid; t < cap; t += 256) buf[t] = KEY_NONE;
+        __syncthreads();
+        bitonic_sort_lds(buf, cap);  // (ends with a barrier)
+        if (fill >= R) {
+          thr = buf[R - 1];
+          fill = R;
+        }
       }
     }
   }
   const int n = fill;
-  if (n > R) {  // keep the best R (an item with at most R survivors keeps them all, unsorted)
+  // keep the best R (an item with at most R survivors keeps them all, unsorted)
+  uint64_t rth = KEY_NONE;  // the R-th smallest key when n > R
+  if (n > R && radix) {
+    rth = popc_radix_cut(buf, n, R, spare, cs);
+    buf = spare;
+  } else if (n > R) {
     int P = 2;
     while (P < n) P <<= 1;
-    for (int t = n + tid; t < P; t += 256) sel[t] = KEY_NONE;
+    for (int t = n + tid; t < P; t += 256) buf[t] = KEY_NONE;
     __syncthreads();
-    bitonic_sort_lds(sel, P);
+    bitonic_sort_lds(buf, P);
+    rth = buf[R - 1];
   }
   // append this item's survivors (at most R) to the query's pool; the pool
   // holds R * (probe ranks in this launch) keys, so it cannot overflow
@@ -1256,17 +1396,17 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
   __syncthreads();
   uint64_t* dst = a.out + (int64_t)i * a.out_ld + R + s_base;
   for (int r = tid; r < nout; r += 256) {
-    const uint64_t sv = sel[r];
+    const uint64_t sv = buf[r];
     const int id = a.L.pos2id[(uint32_t)sv];
     dst[r] = (sv & 0xFFFFFFFF00000000ull) | (uint32_t)id;
   }
-  if (a.qthr && tid == 0 && n > R) atomicMin(&a.qthr[i], (uint32_t)(sel[R - 1] >> 32));
+  if (a.qthr && tid == 0 && n > R) atomicMin(&a.qthr[i], (uint32_t)(rth >> 32));
 }
 
 template <int WT, int BQT>
 static void scan_dispatch(hipStream_t s, const ScanArgs& a, int cap, bool dump) {
   const unsigned items = (unsigned)((int64_t)a.nq * a.pn);
-  const size_t lds = (size_t)cap * sizeof(uint64_t);
+  const size_t lds = (size_t)(cap <= kPopcRadixCap ? 2 : 1) * cap * sizeof(uint64_t);
   if (dump)
     hipLaunchKernelGGL((k_scan_popc<WT, BQT, true>), dim3(items), dim3(256), lds, s, a, cap);
   else
