@@ -506,22 +506,18 @@ def measure(w, args, *, host_vectors, role, points_hint=None, cpu_pool=None):
                 r_ = idx.autotune(Qb[0], nprobe, w.k, R)
                 log(f"[{role}] {p} host sub-batch(es): autotuned in {time.perf_counter() - t_:.0f}s, "
                     f"{r_['ms']:.2f} ms per sub-batch (built-in rule {r_['ms_default']:.2f}): {r_}")
-            parts_qps[str(p)] = quick_qps(nprobe, R, steps=8, threads=conc)
-            log(f"[{role}] {p} host sub-batch(es), {conc} in flight: {parts_qps[str(p)]:.0f} q/s")
-        best = int(max(parts_qps, key=parts_qps.get))
+            # batches in flight: the given number, else two and three
+            for c in ([conc] if args.concurrency > 0 else [2, 3]):
+                parts_qps[f"{p}@{c}"] = quick_qps(nprobe, R, steps=12, threads=c)
+                log(f"[{role}] {p} host sub-batch(es), {c} in flight: {parts_qps[f'{p}@{c}']:.0f} q/s")
+        best_key = max(parts_qps, key=parts_qps.get)
+        best, conc = (int(x) for x in best_key.split("@"))
         idx.set_option("host_parts", best)
         hp_used = best
-        log(f"[{role}] host sub-batches: " + ", ".join(f"{p}: {q:.0f} q/s" for p, q in parts_qps.items())
-            + f"; using {best}")
+        log(f"[{role}] host sub-batches @ batches in flight: "
+            + ", ".join(f"{k}: {q:.0f} q/s" for k, q in parts_qps.items()) + f"; using {best_key}")
         if cache and not loaded:
             idx.tune_save(cache)
-        if args.concurrency <= 0:
-            # one batch more in flight, kept if it is faster by more than noise
-            q3 = quick_qps(nprobe, R, steps=9, threads=conc + 1)
-            log(f"[{role}] {best} host sub-batch(es), {conc + 1} in flight: {q3:.0f} q/s")
-            parts_qps[f"{best}@{conc + 1}"] = q3
-            if q3 > 1.02 * parts_qps[str(best)]:
-                conc += 1
     elif host_vectors:
         idx.set_option("host_parts", args.host_parts)
         hp_used = args.host_parts

@@ -1245,15 +1245,19 @@ __device__ uint64_t popc_radix_cut(const uint64_t* src, int n, int k, uint64_t* 
 }
 
 // Buffers of up to this many keys are cut back by popc_radix_cut into a
-// second buffer of the same size; longer ones by an LDS bitonic sort in place.
+// second buffer of the same size, in the instances with a fixed word count of
+// at most 8 (D <= 256); longer buffers and the wide instances use an LDS
+// bitonic sort in place.
 constexpr int kPopcRadixCap = 1024;
+template <int WT>
+__host__ __device__ constexpr bool popc_radix_form() { return WT > 0 && WT <= 8; }
 
 template <int WT, int BQT, bool DUMP>
 __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
-  extern __shared__ uint64_t sel[];  // cap keys (two buffers of cap when cap <= kPopcRadixCap)
+  extern __shared__ uint64_t sel[];  // cap keys (two buffers of cap in the radix form)
   __shared__ uint32_t s_cnt[3];  // appends of round r counted in s_cnt[r % 3]
   __shared__ PopcCutShared cs;
-  const bool radix = cap <= kPopcRadixCap;
+  const bool radix = popc_radix_form<WT>() && cap <= kPopcRadixCap;
   uint64_t* buf = sel;          // the buffer being filled
   uint64_t* spare = sel + cap;  // (radix) the other one
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1406,7 +1410,7 @@ __global__ __launch_bounds__(256) void k_scan_popc(ScanArgs a, int cap) {
 template <int WT, int BQT>
 static void scan_dispatch(hipStream_t s, const ScanArgs& a, int cap, bool dump) {
   const unsigned items = (unsigned)((int64_t)a.nq * a.pn);
-  const size_t lds = (size_t)(cap <= kPopcRadixCap ? 2 : 1) * cap * sizeof(uint64_t);
+  const size_t lds = (size_t)(popc_radix_form<WT>() && cap <= kPopcRadixCap ? 2 : 1) * cap * sizeof(uint64_t);
   if (dump)
     hipLaunchKernelGGL((k_scan_popc<WT, BQT, true>), dim3(items), dim3(256), lds, s, a, cap);
   else
