@@ -561,6 +561,7 @@ void compact_raw_vectors(rbq_index* idx, hipStream_t s) {
 rbq_index::~rbq_index() {
   pool.reset();
   if (host_gpu_stream) (void)hipStreamDestroy(host_gpu_stream);
+  if (host_copy_stream) (void)hipStreamDestroy(host_copy_stream);
   for (auto& pf : pinned_free) (void)hipHostFree(pf.first);
   if (hostX && hostX_owned) rbq::host_rows_free(hostX, hostX_mapped);
 }

@@ -151,6 +151,9 @@ struct rbq_index {
   // take turns on the GPU and one's host re-rank overlaps the next one's
   // GPU work instead of both halves running side by side at half speed
   hipStream_t host_gpu_stream = nullptr;
+  // the candidate hand-off of those parts (device to pinned host memory) runs
+  // on a stream of its own, so the next part's kernels do not queue behind it
+  hipStream_t host_copy_stream = nullptr;
   std::mutex host_gpu_mu;
   std::vector<std::pair<void*, size_t>> pinned_free;
 

@@ -386,6 +386,10 @@ struct HostJob {
   uint64_t* cand = nullptr;  // nq x R keys (written by the search)
   float* qh = nullptr;       // nq x d queries (written by the search when it has them on the device)
   hipEvent_t ready = nullptr;
+  // (optional) the stream that copies them out, and an event that orders it
+  // after the search's kernels; the search's workspace is then released on it
+  hipStream_t copy = nullptr;
+  hipEvent_t staged = nullptr;
 };
 
 // Pinned host memory from the index's free list (returned on destruction).
@@ -816,15 +820,24 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       launch_row_topk(s, so, (int)nq);
     }
     mark(4);
+    hipStream_t release_on = s;  // the stream whose last use of the workspace ends it
     if (job) {
       // Phase 5 on host cores: hand the candidates (and the queries, if they
-      // are only on the device) over in pinned memory
+      // are only on the device) over in pinned memory, on the job's copy
+      // stream when it has one (not with debug outputs, which read the
+      // workspace on this stream afterwards)
+      hipStream_t cs = s;
+      if (job->copy && !dbg) {
+        RBQ_HIP(hipEventRecord(job->staged, s));
+        RBQ_HIP(hipStreamWaitEvent(job->copy, job->staged, 0));
+        cs = release_on = job->copy;
+      }
       RBQ_HIP(hipMemcpy2DAsync(job->cand, R * sizeof(uint64_t), top, cand_ld * sizeof(uint64_t),
-                               R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, s));
+                               R * sizeof(uint64_t), nq, hipMemcpyDeviceToHost, cs));
       if (qdev)
         RBQ_HIP(hipMemcpy2DAsync(job->qh, d * sizeof(float), qd, (need_qcopy ? ld : d) * sizeof(float),
-                                 d * sizeof(float), nq, hipMemcpyDeviceToHost, s));
-      RBQ_HIP(hipEventRecord(job->ready, s));
+                                 d * sizeof(float), nq, hipMemcpyDeviceToHost, cs));
+      RBQ_HIP(hipEventRecord(job->ready, cs));
     } else {
       // Phase 5: exact re-rank of the top-R on the GPU
       if (idx->X8.p)
@@ -834,7 +847,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
         launch_rerank(s, qd, ld, idx->X.as<float>(), idx->n, ld, d, top, cand_ld, (int)nq, R, k,
                       ids_out, dist_out, d_k);
     }
-    mark(5);
+    if (timed) RBQ_HIP(hipEventRecord(tr.e[5], release_on));
 
     // host-side outputs
     if (ids && !ids_dev)
@@ -871,7 +884,7 @@ void search_part(rbq_index* idx, const float* q, int64_t nq, int nprobe, int k, 
       if (dbg->sqdist && !job)
         RBQ_HIP(hipMemcpyAsync(dbg->sqdist, dist_out, (size_t)nq * k * sizeof(float), hipMemcpyDeviceToHost, s));
     }
-    if (ws) ws_release(idx, std::move(ws), s);
+    if (ws) ws_release(idx, std::move(ws), release_on);
     if (timed) {
       tr.first_part = !io.continues_search;
       std::lock_guard<std::mutex> g(idx->timing_mu);
@@ -939,17 +952,21 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
   std::mutex emu;
   std::string err;
   rbq_status est = RBQ_OK;
-  std::vector<hipEvent_t> events;
+  std::vector<hipEvent_t> events, staged;
   auto wait_all = [&]() {
     latch.wait();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : staged) (void)hipEventDestroy(e);
     events.clear();
+    staged.clear();
   };
-  hipStream_t gs = nullptr;
+  hipStream_t gs = nullptr, cs = nullptr;
   {
     std::lock_guard<std::mutex> g(idx->host_mu);
     if (!idx->host_gpu_stream) RBQ_HIP(hipStreamCreateWithFlags(&idx->host_gpu_stream, hipStreamNonBlocking));
+    if (!idx->host_copy_stream) RBQ_HIP(hipStreamCreateWithFlags(&idx->host_copy_stream, hipStreamNonBlocking));
     gs = idx->host_gpu_stream;
+    cs = idx->host_copy_stream;
   }
   hipEvent_t inputs = nullptr;  // the caller's stream has its queries ready
   RBQ_HIP(hipEventCreateWithFlags(&inputs, hipEventDisableTiming));
@@ -970,6 +987,9 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
       job.qh = hq + q0 * d;
       RBQ_HIP(hipEventCreateWithFlags(&job.ready, hipEventDisableTiming | hipEventBlockingSync));
       events.push_back(job.ready);
+      RBQ_HIP(hipEventCreateWithFlags(&job.staged, hipEventDisableTiming));
+      staged.push_back(job.staged);
+      job.copy = cs;
       ranges.emplace_back(q0, q1);
       SearchIO sub = io;
       sub.continues_search = q0 > 0;
@@ -1008,6 +1028,7 @@ void search_host_rerank(rbq_index* idx, const float* q, int64_t nq, int nprobe, 
     }
   } catch (...) {
     (void)hipStreamSynchronize(gs);
+    (void)hipStreamSynchronize(cs);
     (void)hipStreamSynchronize(s);
     wait_all();
     throw;
