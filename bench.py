@@ -5,7 +5,9 @@ Headline workload (default): the whole 400M x 96 unit-vector mixture (nlist
 65,536; ``--shard`` takes its first 50M rows with nlist 8192 instead, the same
 list length), batches of 10,000 queries, B_q 4, k 10; the raw vectors live in
 host memory (2 MiB pages) that the index borrows and the exact re-rank runs on
-host cores, overlapped with the GPU search of the next sub-batch. The whole
+host cores, overlapped with the GPU search of the other batches in flight
+(the split into host sub-batches and the number of batches in flight, two
+or three, are picked by a short trial). The whole
 set is built with k-means from nlist random training rows, 10 Lloyd
 iterations and one run (the objective changes by under 1e-4 after the
 seventh), and its recall is measured on 1,000 queries. A step is one pass of the whole search path over one batch:
@@ -802,8 +804,9 @@ def main():
                     help="skip the unquantised-query and IVF-Flat comparisons")
     ap.add_argument("--no-flat", action="store_true", help="build no IVF-Flat copy of the lists")
     ap.add_argument("--concurrency", type=int, default=0,
-                    help="batches in flight from as many caller threads (default: 2 with the "
-                         "re-rank on host cores, else 1)")
+                    help="batches in flight from as many caller threads (default: with the "
+                         "re-rank on host cores the faster of 2 and 3 in a short trial, else 1 "
+                         "caller thread over --streams)")
     ap.add_argument("--host-parts", type=int, default=-1,
                     help="sub-batches of a host re-rank search (0: the library's rule; default: "
                          "the fastest of 1, 2 and 4, each autotuned)")
